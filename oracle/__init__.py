@@ -1,0 +1,366 @@
+"""REED-MD reference oracle (plain FP64 CPU implementation, C + ctypes).
+
+TEST INFRASTRUCTURE ONLY: only the test suite, the smoke check and the CPU
+baseline leg of the benchmark may import this package.  The product library
+(``paper_0810_4737_amd``) never imports, links or loads anything from here, and
+this package never imports the product library.
+
+The arithmetic lives in the C sources next to this file (``oracle.h`` lists
+what each part computes and which passage of the paper it follows); this
+module only builds and loads the shared library and marshals numpy arrays.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = ["or_rng.c", "or_physics.c", "or_track.c", "or_run.c"]
+LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+MAX_SPECIES = 8
+NSLOT = 216
+RECORD_WORDS = 32 + 9 * NSLOT
+
+DIAMOND, ISOLATED = 0, 1
+POT_ZBL, POT_NONE = 0, 1
+STOP_OFF, STOP_UNIFORM, STOP_LOCAL = 0, 1, 2
+ACTIVE, STOPPED, BACKSCATTERED, NONFINITE, STEPCAP = 0, 1, 2, 3, 4
+DIR_TILT, DIR_CONE, DIR_MIXED = 0, 1, 2
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, no FMA contraction, IEEE binary64)."""
+    if not force and os.path.exists(LIB_PATH):
+        return LIB_PATH
+    srcs = [os.path.join(_HERE, s) for s in _SRC]
+    tmp = LIB_PATH + ".tmp"
+    cmd = ["gcc", "-std=gnu11", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+           "-shared", "-pthread", "-Wall", "-Wno-unused-function", "-o", tmp] + srcs + ["-lm"]
+    subprocess.check_call(cmd)
+    os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("a", C.c_double), ("M2", C.c_double), ("sigma", C.c_double),
+        ("Z2", C.c_int32), ("structure", C.c_int32),
+        ("pot_mode", C.c_int32), ("stop_mode", C.c_int32),
+        ("s", C.c_double), ("k", C.c_double),
+        ("dx_max", C.c_double), ("dt_max", C.c_double), ("E_stop", C.c_double),
+        ("z_start", C.c_double), ("max_steps", C.c_int64), ("seed", C.c_uint64),
+        ("n_thresh", C.c_int32), ("n_tables", C.c_int32),
+        ("thresholds", C.POINTER(C.c_double)),
+        ("n_clones", C.c_int32), ("n_bins", C.c_int32), ("bin_width", C.c_double),
+        ("n_species", C.c_int32), ("Z1", C.c_int32 * MAX_SPECIES),
+        ("M1", C.c_double * MAX_SPECIES),
+    ]
+
+
+class Stats(C.Structure):
+    _fields_ = [(n, C.c_int64) for n in (
+        "primaries", "finished", "clones", "track_steps", "pair_evals",
+        "n_stopped", "n_backscattered", "n_nonfinite", "n_stepcap", "reserved0")] + \
+        [(n, C.c_double) for n in (
+            "w_stopped", "w_backscattered", "w_underflow", "w_overflow", "w_quarantined",
+            "sum_wz", "sum_wz2", "reserved1")]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_ if not n.startswith("reserved")}
+
+
+class Result(C.Structure):
+    _fields_ = [("lineage", C.c_int64), ("status", C.c_int32), ("next_k", C.c_int32),
+                ("z_stop", C.c_double), ("w", C.c_double), ("steps", C.c_int64)]
+
+
+class Sampler(C.Structure):
+    _fields_ = [
+        ("n_choice", C.c_int32), ("choice", C.c_int32 * MAX_SPECIES),
+        ("dir_mode", C.c_int32), ("n_energy_tables", C.c_int32),
+        ("E_min", C.c_double), ("E_max", C.c_double), ("tilt", C.c_double),
+        ("axis", C.c_double * 3), ("half_angle", C.c_double), ("n_cone", C.c_int64),
+        ("a", C.c_double), ("z_start", C.c_double),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = C.CDLL(LIB_PATH)
+        P = C.POINTER
+        L.or_philox4x64.argtypes = [P(C.c_uint64), P(C.c_uint64), P(C.c_uint64)]
+        L.or_u01.argtypes = [C.c_uint64]
+        L.or_u01.restype = C.c_double
+        L.or_screening_length.argtypes = [P(Params), C.c_int]
+        L.or_screening_length.restype = C.c_double
+        L.or_unscaled_screening_length.argtypes = [P(Params), C.c_int]
+        L.or_unscaled_screening_length.restype = C.c_double
+        L.or_zbl.argtypes = [P(Params), C.c_int, C.c_double, P(C.c_double), P(C.c_double)]
+        L.or_lss_kL.argtypes = [P(Params), C.c_int]
+        L.or_lss_kL.restype = C.c_double
+        L.or_density_weight.argtypes = [P(Params), C.c_int, C.c_double]
+        L.or_density_weight.restype = C.c_double
+        L.or_sample_primaries.argtypes = [P(Sampler), C.c_uint64, C.c_int64, C.c_int64,
+                                          C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                          C.c_void_p, C.c_void_p]
+        L.or_track_size.restype = C.c_int64
+        L.or_record_words.restype = C.c_int64
+        L.or_track_init.argtypes = [P(Params), C.c_int32, C.c_double, P(C.c_double),
+                                    P(C.c_double), C.c_uint64, C.c_int32, C.c_int64, C.c_void_p]
+        L.or_track_step.argtypes = [P(Params), C.c_void_p]
+        L.or_track_step.restype = C.c_double
+        L.or_track_events.argtypes = [P(Params), C.c_void_p, C.c_double, C.c_double]
+        L.or_track_events.restype = C.c_int32
+        L.or_track_advance.argtypes = [P(Params), C.c_void_p, C.c_int64, C.c_int32]
+        L.or_track_ledger.argtypes = [P(Params), C.c_void_p, P(C.c_double), P(C.c_double)]
+        L.or_track_export.argtypes = [P(Params), C.c_void_p, C.c_void_p]
+        L.or_track_import.argtypes = [P(Params), C.c_void_p, C.c_void_p]
+        L.or_run.argtypes = [P(Params), C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
+                             C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                             C.c_void_p, P(Stats), C.c_void_p, C.c_int64, P(C.c_int64)]
+        L.or_run.restype = C.c_int32
+        assert L.or_record_words() == RECORD_WORDS
+        _lib = L
+    return _lib
+
+
+# ---------------------------------------------------------------------------
+# Python-side configuration
+
+SPECIES = {  # symbol: (Z, mass in amu)
+    "B": (5, 10.81), "P": (15, 30.97), "As": (33, 74.92),
+}
+SI = dict(a=5.431, Z2=14, M2=28.0855, sigma=0.076)
+
+
+@dataclass
+class Config:
+    a: float = SI["a"]
+    Z2: int = SI["Z2"]
+    M2: float = SI["M2"]
+    sigma: float = SI["sigma"]
+    structure: int = DIAMOND
+    pot_mode: int = POT_ZBL
+    stop_mode: int = STOP_LOCAL
+    s: float = 1.0
+    k: float = 1.0
+    dx_max: float = 0.05
+    dt_max: float = 1.0
+    E_stop: float = 5.0
+    z_start: float = -3.0
+    max_steps: int = 0
+    seed: int = 0
+    thresholds: np.ndarray = field(default_factory=lambda: np.zeros((1, 0)))
+    n_clones: int = 2
+    n_bins: int = 1024
+    bin_width: float = 1.0
+    species: tuple = (("B",),)
+
+    def params(self):
+        """Returns (Params, keepalive) where keepalive holds referenced arrays."""
+        thr = np.ascontiguousarray(np.atleast_2d(np.asarray(self.thresholds, dtype=np.float64)))
+        p = Params()
+        p.a, p.M2, p.sigma, p.Z2 = self.a, self.M2, self.sigma, self.Z2
+        p.structure, p.pot_mode, p.stop_mode = self.structure, self.pot_mode, self.stop_mode
+        p.s, p.k = self.s, self.k
+        p.dx_max, p.dt_max, p.E_stop, p.z_start = self.dx_max, self.dt_max, self.E_stop, self.z_start
+        p.max_steps, p.seed = int(self.max_steps), int(self.seed)
+        p.n_tables, p.n_thresh = thr.shape[0], thr.shape[1]
+        p.thresholds = thr.ctypes.data_as(C.POINTER(C.c_double)) if thr.size else None
+        p.n_clones, p.n_bins, p.bin_width = self.n_clones, self.n_bins, self.bin_width
+        sp = [s[0] if isinstance(s, tuple) else s for s in self.species]
+        p.n_species = len(sp)
+        for i, name in enumerate(sp):
+            if isinstance(name, str):
+                Z, M = SPECIES[name]
+            else:
+                Z, M = name
+            p.Z1[i], p.M1[i] = Z, M
+        return p, thr
+
+
+def philox4x64(ctr, key):
+    L = lib()
+    c = (C.c_uint64 * 4)(*[int(x) & (2**64 - 1) for x in ctr])
+    k = (C.c_uint64 * 2)(*[int(x) & (2**64 - 1) for x in key])
+    o = (C.c_uint64 * 4)()
+    L.or_philox4x64(c, k, o)
+    return [int(x) for x in o]
+
+
+def zbl(cfg: Config, species: int, r: float):
+    p, keep = cfg.params()
+    V, dV = C.c_double(), C.c_double()
+    lib().or_zbl(C.byref(p), species, float(r), C.byref(V), C.byref(dV))
+    return V.value, dV.value
+
+
+def screening_length(cfg: Config, species: int = 0, scaled: bool = True) -> float:
+    p, keep = cfg.params()
+    f = lib().or_screening_length if scaled else lib().or_unscaled_screening_length
+    return f(C.byref(p), species)
+
+
+def lss_kL(cfg: Config, species: int = 0) -> float:
+    p, keep = cfg.params()
+    return lib().or_lss_kL(C.byref(p), species)
+
+
+def density_weight(cfg: Config, species: int, r: float) -> float:
+    p, keep = cfg.params()
+    return lib().or_density_weight(C.byref(p), species, float(r))
+
+
+@dataclass
+class SamplerCfg:
+    choice: tuple = (0,)
+    dir_mode: int = DIR_TILT
+    n_energy_tables: int = 1
+    E_min: float = 1000.0
+    E_max: float = 1000.0
+    tilt: float = np.deg2rad(7.0)
+    axis: tuple = (0.0, 0.0, 1.0)
+    half_angle: float = 0.0
+    n_cone: int = 0
+    a: float = SI["a"]
+    z_start: float = -3.0
+
+    def struct(self):
+        s = Sampler()
+        s.n_choice = len(self.choice)
+        for i, c in enumerate(self.choice):
+            s.choice[i] = c
+        s.dir_mode, s.n_energy_tables = self.dir_mode, self.n_energy_tables
+        s.E_min, s.E_max, s.tilt = self.E_min, self.E_max, self.tilt
+        for i in range(3):
+            s.axis[i] = self.axis[i]
+        s.half_angle, s.n_cone, s.a, s.z_start = self.half_angle, self.n_cone, self.a, self.z_start
+        return s
+
+
+def sample_primaries(sc: SamplerCfg, seed: int, n: int, id0: int = 0):
+    s = sc.struct()
+    out = dict(species=np.zeros(n, np.int32), E0=np.zeros(n), pos=np.zeros((3, n)),
+               dir=np.zeros((3, n)), key=np.zeros(n, np.uint64), table=np.zeros(n, np.int32))
+    lib().or_sample_primaries(C.byref(s), seed, id0, n, out["species"].ctypes.data,
+                              out["E0"].ctypes.data, out["pos"].ctypes.data,
+                              out["dir"].ctypes.data, out["key"].ctypes.data,
+                              out["table"].ctypes.data)
+    return out
+
+
+class Track:
+    """One oracle track (opaque C struct held in a byte buffer)."""
+
+    def __init__(self, cfg: Config):
+        self.cfg = cfg
+        self._p, self._keep = cfg.params()
+        self.buf = np.zeros(lib().or_track_size(), np.uint8)
+
+    @classmethod
+    def start(cls, cfg, species, E0, pos, dir, key, table=0, lineage=0):
+        t = cls(cfg)
+        pos = (C.c_double * 3)(*pos)
+        dr = (C.c_double * 3)(*dir)
+        lib().or_track_init(C.byref(t._p), species, E0, pos, dr, int(key), table, lineage,
+                            t.buf.ctypes.data)
+        return t
+
+    @classmethod
+    def from_record(cls, cfg, rec):
+        t = cls(cfg)
+        rec = np.ascontiguousarray(rec, dtype=np.float64)
+        lib().or_track_import(C.byref(t._p), rec.ctypes.data, t.buf.ctypes.data)
+        return t
+
+    def step(self) -> float:
+        return lib().or_track_step(C.byref(self._p), self.buf.ctypes.data)
+
+    def advance(self, nsteps, events=True):
+        lib().or_track_advance(C.byref(self._p), self.buf.ctypes.data, int(nsteps), int(events))
+
+    def record(self):
+        rec = np.zeros(RECORD_WORDS, np.float64)
+        lib().or_track_export(C.byref(self._p), self.buf.ctypes.data, rec.ctypes.data)
+        return rec
+
+    def ledger(self):
+        e = C.c_double()
+        m = (C.c_double * 3)()
+        lib().or_track_ledger(C.byref(self._p), self.buf.ctypes.data, C.byref(e), m)
+        return e.value, np.array(list(m))
+
+    # convenient views of the exchange record
+    def state(self):
+        return unpack_record(self.record())
+
+
+def unpack_record(rec):
+    rec = np.asarray(rec, dtype=np.float64)
+    ir = rec.view(np.int64)
+    atoms = rec[32:].reshape(9, NSLOT)
+    return dict(x=rec[0:3].copy(), v=rec[3:6].copy(), F=rec[6:9].copy(), rho=rec[9], w=rec[10],
+                z_stop=rec[11], center=ir[12:15].copy(), key=int(ir[15]) & (2**64 - 1),
+                steps=int(ir[16]), lineage=int(ir[17]), species=int(ir[18]), next_k=int(ir[19]),
+                table=int(ir[20]), status=int(ir[21]), ax=atoms[0:3].copy(), av=atoms[3:6].copy(),
+                af=atoms[6:9].copy())
+
+
+def slot_exists(center):
+    """Boolean mask over the 216 record slots: True where the slot's cell exists (c_z >= 0)."""
+    ex = np.zeros(NSLOT, bool)
+    for i in (-1, 0, 1):
+        for j in (-1, 0, 1):
+            for k in (-1, 0, 1):
+                c = (center[0] + i, center[1] + j, center[2] + k)
+                base = ((c[0] % 3) * 9 + (c[1] % 3) * 3 + (c[2] % 3)) * 8
+                ex[base:base + 8] = c[2] >= 0
+    return ex
+
+
+def run(cfg: Config, prim: dict, nthreads: int | None = None, log: bool = False,
+        lineage=None):
+    """Runs every primary in `prim` (as returned by sample_primaries) with all clones."""
+    L = lib()
+    p, keep = cfg.params()
+    n = int(prim["E0"].shape[0])
+    hist = np.zeros(cfg.n_bins)
+    st = Stats()
+    species = np.ascontiguousarray(prim["species"], np.int32)
+    E0 = np.ascontiguousarray(prim["E0"], np.float64)
+    pos = np.ascontiguousarray(prim["pos"], np.float64)
+    dr = np.ascontiguousarray(prim["dir"], np.float64)
+    key = np.ascontiguousarray(prim["key"], np.uint64)
+    table = np.ascontiguousarray(prim["table"], np.int32)
+    lin = None if lineage is None else np.ascontiguousarray(lineage, np.int64)
+    cap = 0
+    logbuf = None
+    if log:
+        cap = max(16, n * (1 + cfg.n_clones * max(1, p.n_thresh)) + 16)
+        logbuf = (Result * cap)()
+    cnt = C.c_int64(0)
+    if nthreads is None:
+        nthreads = os.cpu_count() or 1
+    rc = L.or_run(C.byref(p), n, species.ctypes.data, E0.ctypes.data, pos.ctypes.data,
+                  dr.ctypes.data, key.ctypes.data, table.ctypes.data,
+                  None if lin is None else lin.ctypes.data, int(nthreads), hist.ctypes.data,
+                  C.byref(st), C.cast(logbuf, C.c_void_p) if log else None, cap, C.byref(cnt))
+    if rc != 0:
+        raise RuntimeError(f"oracle run failed ({rc})")
+    out = dict(hist=hist, stats=st.as_dict(), nthreads=int(nthreads))
+    if log:
+        m = min(cnt.value, cap)
+        arr = np.ctypeslib.as_array(logbuf)[:m]
+        out["log"] = np.array(arr)
+    return out

@@ -1,0 +1,185 @@
+/*
+ * REED-MD reference oracle: plain, serial-per-track FP64 CPU implementation.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may include, link,
+ * load or call this code; only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark do.  It shares no source, header, constant or
+ * helper with the HIP library: every physical constant and every step below
+ * is written out here on its own.
+ *
+ * What it computes (Jeon & Gronbech-Jensen, "Efficient Parallel Algorithm for
+ * Statistical Ion Track Simulations in Crystalline Materials", Sec. 2 "Review
+ * of the REED-MD Algorithm", and Figs. 1-3):
+ *   - domain following: only the 27 unit cells around the ion exist; the
+ *     ion sits in the centre cell; when it enters a neighbouring cell the
+ *     centre moves, wake cells are discarded and new front cells are created
+ *     from the statistical (thermal) description of the crystal (Sec. 2,
+ *     Fig. 1);
+ *   - nuclear interactions by the ZBL universal screened Coulomb potential
+ *     only (Sec. 2, "First" and "Second");
+ *   - local electronic stopping (Sec. 2, "Third"; the configured Local
+ *     Lindhard-Scharff reading);
+ *   - Verlet-type integration with an adaptive time step derived from the
+ *     kinetic and the collisional energy scale (Sec. 2, Fig. 2);
+ *   - rare-event enhancement: the system is cloned at cloning depths and the
+ *     statistical weight is halved per cloning (Sec. 2, Fig. 3);
+ *   - a weighted range (stopping depth) histogram (Sec. 2).
+ * Where the paper is silent (formulas are deferred to its references) the
+ * readings listed in the design notes are followed; each is named in the
+ * function that implements it.
+ *
+ * Units: length in Angstrom, energy in eV, mass in amu; time in
+ * tau = sqrt(amu * A^2 / eV) = 10.18 fs (the unit quoted with Fig. 2).
+ */
+#ifndef REEDMD_ORACLE_H
+#define REEDMD_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { OR_MAX_SPECIES = 8, OR_NCELL = 27, OR_NBASIS = 8, OR_NSLOT = 216 };
+
+/* structures */
+enum { OR_DIAMOND = 0, OR_ISOLATED = 1 };
+/* potential modes */
+enum { OR_POT_ZBL = 0, OR_POT_NONE = 1 };
+/* stopping modes */
+enum { OR_STOP_OFF = 0, OR_STOP_UNIFORM = 1, OR_STOP_LOCAL = 2 };
+/* track status */
+enum { OR_ACTIVE = 0, OR_STOPPED = 1, OR_BACKSCATTERED = 2, OR_NONFINITE = 3,
+       OR_STEPCAP = 4 };
+
+typedef struct {
+    /* crystal */
+    double a;            /* cubic lattice constant (A) */
+    double M2;           /* target atom mass (amu) */
+    double sigma;        /* thermal rms displacement per axis (A) */
+    int32_t Z2;          /* target atomic number */
+    int32_t structure;   /* OR_DIAMOND, or OR_ISOLATED (one atom at the origin, no domain following) */
+    /* interaction */
+    int32_t pot_mode;    /* OR_POT_ZBL / OR_POT_NONE */
+    int32_t stop_mode;   /* OR_STOP_* */
+    double s;            /* ZBL screening-length scale */
+    double k;            /* electronic stopping scale */
+    /* integration and events */
+    double dx_max;       /* max displacement per step (A) */
+    double dt_max;       /* max time step (tau) */
+    double E_stop;       /* stop below this kinetic energy (eV) */
+    double z_start;      /* start plane; backscatter when z < z_start moving outward */
+    int64_t max_steps;   /* per-track step cap (<=0: none) */
+    uint64_t seed;       /* crystal realisation seed */
+    /* splitting */
+    int32_t n_thresh;    /* thresholds per table */
+    int32_t n_tables;
+    const double* thresholds; /* [n_tables][n_thresh], ascending */
+    int32_t n_clones;    /* copies per cloning (2) */
+    int32_t n_bins;
+    double bin_width;    /* histogram bin width (A), bins cover [0, n_bins*bin_width) */
+    /* species */
+    int32_t n_species;
+    int32_t Z1[OR_MAX_SPECIES];
+    double M1[OR_MAX_SPECIES];
+} or_params;
+
+/* One domain atom. */
+typedef struct {
+    double x[3], v[3], f[3];
+    int64_t cell[3];
+    int32_t basis;
+    int32_t exists;
+} or_atom;
+
+/* One ion track with its 27-cell domain (atoms in canonical offset order:
+ * offset (i,j,k) in {-1,0,1}^3 with i slowest, then basis b). */
+typedef struct {
+    double x[3], v[3], F[3];    /* ion position, velocity, ZBL force */
+    double rho;                 /* local electron-density weight at the ion */
+    double w;                   /* statistical weight */
+    int64_t center[3];          /* centre cell */
+    uint64_t key;               /* crystal-realisation key of this track */
+    int64_t steps;
+    int64_t lineage;            /* primary id */
+    int32_t species, next_k, table, status;
+    double z_stop;
+    int32_t n_atoms;            /* 216 for the lattice, 1 for OR_ISOLATED */
+    int32_t pad;
+    or_atom atom[OR_NSLOT];
+    /* conservation ledger (stopping off): energy and momentum carried out of
+     * the domain by dropped atoms, and potential energy brought in by created atoms */
+    double e_out, e_in, p_out[3];
+} or_track;
+
+typedef struct {
+    int64_t primaries, finished, clones, track_steps, pair_evals;
+    int64_t n_stopped, n_backscattered, n_nonfinite, n_stepcap, reserved0;
+    double w_stopped, w_backscattered, w_underflow, w_overflow, w_quarantined;
+    double sum_wz, sum_wz2, reserved1;
+} or_stats;
+
+/* Finished-track log entry. */
+typedef struct {
+    int64_t lineage;
+    int32_t status, next_k;
+    double z_stop;
+    double w;
+    int64_t steps;
+} or_result;
+
+/* Primary sampler description. */
+enum { OR_DIR_TILT = 0, OR_DIR_CONE = 1, OR_DIR_MIXED = 2 };
+typedef struct {
+    int32_t n_choice;         /* species drawn uniformly from choice[0..n_choice) */
+    int32_t choice[OR_MAX_SPECIES];
+    int32_t dir_mode;         /* OR_DIR_* */
+    int32_t n_energy_tables;  /* threshold tables per species (equal log-energy bands) */
+    double E_min, E_max;      /* log-uniform energy; E_min == E_max gives a fixed energy */
+    double tilt;              /* polar tilt from +z (rad), azimuth uniform */
+    double axis[3];           /* cone axis (unit) */
+    double half_angle;        /* cone half angle (rad) */
+    int64_t n_cone;           /* DIR_MIXED: ids below this use the cone */
+    double a;                 /* entry area is [0,a)^2 */
+    double z_start;
+} or_sampler;
+
+/* RNG (counter-based Philox4x64-10) */
+void or_philox4x64(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);
+double or_u01(uint64_t w);
+
+/* physics primitives */
+double or_screening_length(const or_params* p, int species);
+double or_unscaled_screening_length(const or_params* p, int species);
+void or_zbl(const or_params* p, int species, double r, double* V, double* dVdr);
+double or_lss_kL(const or_params* p, int species);
+double or_density_weight(const or_params* p, int species, double r);
+
+/* sampler */
+void or_sample_primaries(const or_sampler* s, uint64_t seed, int64_t id0, int64_t n,
+                         int32_t* species, double* E0, double* pos, double* dir,
+                         uint64_t* key, int32_t* table);
+
+/* single-track interface */
+int64_t or_track_size(void);
+void or_track_init(const or_params* p, int32_t species, double E0, const double pos[3],
+                   const double dir[3], uint64_t key, int32_t table, int64_t lineage,
+                   or_track* t);
+double or_track_step(const or_params* p, or_track* t);      /* returns dt */
+int32_t or_track_events(const or_params* p, or_track* t, double ke_before, double z_before);
+void or_track_advance(const or_params* p, or_track* t, int64_t nsteps, int32_t with_events);
+void or_track_ledger(const or_params* p, const or_track* t, double* energy, double momentum[3]);
+void or_track_export(const or_params* p, const or_track* t, double* record);
+void or_track_import(const or_params* p, const double* record, or_track* t);
+int64_t or_record_words(void);
+
+/* whole run: every primary with all of its clones, weighted histogram out */
+int32_t or_run(const or_params* p, int64_t n, const int32_t* species, const double* E0,
+               const double* pos, const double* dir, const uint64_t* key,
+               const int32_t* table, const int64_t* lineage, int32_t nthreads,
+               double* hist, or_stats* stats, or_result* log, int64_t log_cap,
+               int64_t* log_count);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
