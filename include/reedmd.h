@@ -1,0 +1,244 @@
+/*
+ * reedmd — MI355X (gfx950) REED-MD ion-track engine, C ABI.
+ *
+ * Rare Event Enhanced Domain-following Molecular Dynamics (Jeon and
+ * Gronbech-Jensen, "Efficient Parallel Algorithm for Statistical Ion Track
+ * Simulations in Crystalline Materials", Sec. 2): many independent ion tracks
+ * are advanced through a thermally disordered crystal.  Each track carries
+ * its own 27-unit-cell domain of target atoms that follows the ion (Sec. 2,
+ * Fig. 1); ions feel ZBL screened-Coulomb forces from every domain atom and a
+ * local electronic friction; the equations of motion are integrated with an
+ * adaptive-step velocity Verlet scheme (Sec. 2, Fig. 2); tracks are cloned
+ * with halved statistical weights when they reach cloning depths (Sec. 2,
+ * Fig. 3); stopped ions are collected in a weighted depth histogram.
+ *
+ * Units: length A, energy eV, mass amu, time tau = sqrt(amu A^2 / eV) = 10.18 fs.
+ *
+ * Conventions for every entry point:
+ *   - Pointers documented as "device" point to device memory owned by the
+ *     caller (e.g. torch tensors); "host" pointers are read or written before
+ *     the call returns.  The context owns its own scratch memory (clone stacks,
+ *     the clone queue, counters) and frees it in reedmd_destroy.
+ *   - Work is enqueued on the caller's HIP stream and the call returns without
+ *     waiting, except where a function says it synchronises.
+ *   - Errors are status codes, never exceptions; arguments are checked before
+ *     anything is launched.  reedmd_last_error() describes the last failure.
+ *   - A context is not thread safe: use one context per host thread.
+ */
+#ifndef REEDMD_H
+#define REEDMD_H
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define REEDMD_NSLOT 216                 /* 27 cells x 8 diamond basis atoms */
+#define REEDMD_RECORD_WORDS (32 + 9 * 216)
+#define REEDMD_MAX_SPECIES 8
+
+typedef struct reedmd_ctx reedmd_ctx;
+
+typedef enum {
+    REEDMD_OK = 0,
+    REEDMD_EINVAL = -1,        /* invalid argument (nothing was launched) */
+    REEDMD_ENOMEM = -2,        /* device allocation failed */
+    REEDMD_EHIP = -3,          /* HIP runtime error (message in reedmd_last_error) */
+    REEDMD_EUNSUPPORTED = -5   /* valid but not implemented combination */
+} reedmd_status;
+
+enum { REEDMD_DIAMOND = 0 };
+enum { REEDMD_POT_ZBL = 0, REEDMD_POT_NONE = 1 };
+enum { REEDMD_STOP_OFF = 0, REEDMD_STOP_UNIFORM = 1, REEDMD_STOP_LOCAL = 2 };
+enum { REEDMD_FORM_PLAIN = 0, REEDMD_FORM_PERSISTENT = 1 };
+enum { REEDMD_DIR_TILT = 0, REEDMD_DIR_CONE = 1, REEDMD_DIR_MIXED = 2 };
+/* track status (record word 21, result log) */
+enum { REEDMD_ACTIVE = 0, REEDMD_STOPPED = 1, REEDMD_BACKSCATTERED = 2, REEDMD_NONFINITE = 3,
+       REEDMD_STEPCAP = 4, REEDMD_CANCELLED = 5, REEDMD_LOST = 6 };
+
+/* Target crystal (Sec. 2: the domain is made of unit cells of the target
+ * structure; Sec. 4: temperature as Gaussian displacements of lattice atoms).
+ * Diamond cubic with cubic constant a; every created atom sits at its ideal
+ * site plus an independent N(0, sigma^2) displacement per axis, at rest.  The
+ * crystal occupies z >= 0 (cells with c_z >= 0). */
+typedef struct {
+    double a;            /* cubic lattice constant (A), > 0 */
+    double M2;           /* target mass (amu), > 0 */
+    double sigma;        /* thermal rms displacement per axis (A), >= 0 */
+    int32_t Z2;          /* target atomic number, > 0 */
+    int32_t structure;   /* REEDMD_DIAMOND */
+} reedmd_lattice;
+
+/* Ion-atom interaction (Sec. 2, "First"): ZBL universal screened Coulomb,
+ * V(r) = Z1 Z2 e^2 / r * sum_i c_i exp(-d_i r / a), a = s * 0.8854 a0 / (Z1^0.23 + Z2^0.23). */
+typedef struct {
+    int32_t mode;        /* REEDMD_POT_ZBL, or REEDMD_POT_NONE (no nuclear force; tests) */
+    int32_t reserved;
+    double s;            /* screening-length scale, > 0 (1 = ZBL) */
+} reedmd_potential;
+
+/* Electronic stopping (Sec. 2, "Third"), read as a local Lindhard-Scharff
+ * friction F = -gamma(x) v with gamma = k N kL sqrt(M1/2) rho(x)/N, where
+ * rho(x) = sum_j exp(-r_j/lambda)/(8 pi lambda^3), lambda = a_U/0.3 (unscaled a_U),
+ * kL = 1.212 Z1^(7/6) Z2 / ((Z1^(2/3)+Z2^(2/3))^(3/2) sqrt(M1)).  UNIFORM uses rho = N. */
+typedef struct {
+    int32_t mode;        /* REEDMD_STOP_OFF / _UNIFORM / _LOCAL */
+    int32_t reserved;
+    double k;            /* stopping scale, >= 0 */
+} reedmd_stopping;
+
+/* Ion species table (host struct, passed by pointer, copied at the call). */
+typedef struct {
+    int32_t n_species;               /* 1..REEDMD_MAX_SPECIES */
+    int32_t reserved;
+    int32_t Z1[REEDMD_MAX_SPECIES];  /* > 0 */
+    double M1[REEDMD_MAX_SPECIES];   /* amu, > 0 */
+} reedmd_species;
+
+/* A batch of primary ions (Sec. 3: all primaries share one statistical
+ * description).  Every array is device memory owned by the caller, of length
+ * n (pos and dir: [3][n], component major).  Entry i gets lineage id0 + i. */
+typedef struct {
+    int64_t n;
+    int64_t id0;
+    int32_t* species;    /* index into the species table */
+    double* energy;      /* initial kinetic energy (eV), > E_stop */
+    double* pos;         /* start position (A) */
+    double* dir;         /* direction (normalised by the library) */
+    uint64_t* key;       /* crystal-realisation key of the primary */
+    int32_t* table;      /* cloning-depth table index, < n_tables */
+} reedmd_batch;
+
+/* Primary sampler (counter-based, seed + lineage id): entry point uniform in
+ * [0,a)^2 at z = z_start; species uniform over choice[]; energy log-uniform in
+ * [E_min, E_max] (fixed if equal); direction a polar tilt with uniform azimuth,
+ * or uniform in a cone of half angle about axis, or the cone for ids < n_cone
+ * and the tilt otherwise.  table = choice index * n_energy_tables + energy band. */
+typedef struct {
+    int32_t n_choice;
+    int32_t choice[REEDMD_MAX_SPECIES];
+    int32_t dir_mode;                 /* REEDMD_DIR_* */
+    int32_t n_energy_tables;          /* >= 1 */
+    int32_t reserved;
+    double E_min, E_max;
+    double tilt;                      /* rad */
+    double axis[3];                   /* unit vector */
+    double half_angle;                /* rad */
+    int64_t n_cone;
+    double a;
+    double z_start;
+} reedmd_sampler;
+
+/* Run parameters (host struct; the pointers inside are device memory). */
+typedef struct {
+    double dx_max;       /* max displacement of any particle per step (A), > 0 */
+    double dt_max;       /* max step (tau), > 0 */
+    double E_stop;       /* stop when the ion's kinetic energy falls below (eV), > 0 */
+    double z_start;      /* backscatter when z < z_start and v_z < 0 */
+    int64_t max_steps;   /* per-track step cap (capped tracks are quarantined); <= 0: 2,000,000 */
+    uint64_t seed;       /* crystal seed shared by every track */
+    int32_t n_thresh;    /* cloning depths per table (0 = no splitting) */
+    int32_t n_tables;    /* >= 1 when n_thresh > 0 */
+    const double* thresholds;  /* device [n_tables][n_thresh], ascending, spaced > 2 dx_max */
+    int32_t n_clones;    /* copies per cloning, >= 2 (each gets weight / n_clones) */
+    int32_t n_bins;      /* histogram bins, > 0 */
+    double bin_width;    /* bins cover [0, n_bins * bin_width) (A) */
+    int32_t form;        /* REEDMD_FORM_PLAIN or REEDMD_FORM_PERSISTENT */
+    int32_t lanes_per_track;   /* 64, 32 or 16; 0 = from the autotune cache (default 64) */
+    int32_t waves_per_cu;      /* persistent form: resident waves per CU (0 = default) */
+    int32_t queue_capacity;    /* persistent form: clone-queue records (0 = default 4096) */
+    const int32_t* cancel;     /* device word polled by the kernel, non-zero = cancel; may be NULL */
+    void* track_log;           /* optional device array of reedmd_result, may be NULL */
+    int64_t track_log_cap;
+} reedmd_run_params;
+
+/* Finished-track entry of the optional log (40 bytes). */
+typedef struct {
+    int64_t lineage;
+    int32_t status;
+    int32_t next_k;      /* cloning depths crossed: weight = n_clones^-next_k */
+    double z_stop;
+    double w;
+    int64_t steps;
+} reedmd_result;
+
+/* Run statistics (device struct owned by the caller; reedmd_run adds to it). */
+typedef struct {
+    int64_t primaries, finished, clones, track_steps, pair_evals;
+    int64_t n_stopped, n_backscattered, n_nonfinite, n_stepcap, n_cancelled;
+    double w_stopped, w_backscattered, w_underflow, w_overflow, w_quarantined;
+    double sum_wz, sum_wz2, w_cancelled;
+    int64_t max_queue, stack_overflow, log_count, error_flags;
+} reedmd_stats;
+
+/* Library version, e.g. 100 for 0.1.0. */
+int32_t reedmd_version(void);
+
+/* Creates a context for one target crystal and interaction model on the
+ * current HIP device.  out receives the context (host).  EINVAL on bad
+ * values, EHIP if no device is usable. */
+reedmd_status reedmd_create(const reedmd_lattice* lattice, const reedmd_potential* potential,
+                            const reedmd_stopping* stopping, reedmd_ctx** out);
+
+/* Frees the context and all memory it owns; NULL is ignored.  Synchronises
+ * the device first. */
+void reedmd_destroy(reedmd_ctx* ctx);
+
+/* Message for the last non-OK status returned on this context (never NULL;
+ * ctx may be NULL for errors of reedmd_create). */
+const char* reedmd_last_error(const reedmd_ctx* ctx);
+
+/* Fills out's device arrays (n = out->n entries, lineage ids id0 .. id0+n-1)
+ * from the counter-based sampler keyed by seed (Sec. 3: every primary starts
+ * from the same statistical description).  Enqueued on stream. */
+reedmd_status reedmd_sample_primaries(reedmd_ctx* ctx, const reedmd_sampler* sampler,
+                                      uint64_t seed, const reedmd_batch* out, hipStream_t stream);
+
+/* Runs every primary of the batch to termination together with every clone
+ * it produces (Sec. 2), and adds the weights of stopped ions to d_hist
+ * (device, n_bins doubles, bin = floor(z_stop / bin_width)) and the run totals
+ * to d_stats (device).  PLAIN form: a static assignment of primaries to
+ * wavefronts, each finishing its own clones depth first.  PERSISTENT form:
+ * resident wavefronts take primaries and clones from a device work queue
+ * until no track is live (replacing the paper's host-client polling, Sec. 3).
+ * Enqueued on stream; the results are valid once the stream reaches this
+ * point.  A non-zero *cancel drains the run: live and unstarted tracks end
+ * with status CANCELLED and their weight goes to w_cancelled. */
+reedmd_status reedmd_run(reedmd_ctx* ctx, const reedmd_species* species, const reedmd_batch* batch,
+                         const reedmd_run_params* params, double* d_hist, reedmd_stats* d_stats,
+                         hipStream_t stream);
+
+/* Builds the starting record (ion, its full domain and the forces at the
+ * start point) of each batch entry into d_records (device, n *
+ * REEDMD_RECORD_WORDS 64-bit words).  Record layout: words 0-2 ion position,
+ * 3-5 velocity, 6-8 ZBL force, 9 local density, 10 weight, 11 stopping depth,
+ * 12-14 centre cell (int64), 15 key (uint64), 16 steps, 17 lineage, 18
+ * species, 19 crossed thresholds, 20 table, 21 status, 22-31 zero; then nine
+ * 216-word fields x, y, z, vx, vy, vz, fx, fy, fz of the domain atoms, slot of
+ * basis atom b of cell c = ((c_x mod 3)*9 + (c_y mod 3)*3 + (c_z mod 3))*8 + b.
+ * Slots of cells with c_z < 0 do not exist and hold zeros. */
+reedmd_status reedmd_track_init(reedmd_ctx* ctx, const reedmd_species* species,
+                                const reedmd_batch* batch, const reedmd_run_params* params,
+                                double* d_records, hipStream_t stream);
+
+/* Advances each of the n records in d_records (device, in place) by nsteps
+ * integration steps (Sec. 2), without termination events or cloning.  For
+ * per-step parity checks.  lanes_per_track in params selects the kernel. */
+reedmd_status reedmd_debug_step(reedmd_ctx* ctx, const reedmd_species* species,
+                                const reedmd_run_params* params, double* d_records, int64_t n,
+                                int32_t nsteps, hipStream_t stream);
+
+/* Tries each lanes-per-track variant (and, for the persistent form, resident
+ * waves per CU) on the first `pilot` primaries of the batch and records the
+ * fastest in the context's cache under this configuration; *best_lanes and
+ * *best_waves (host) receive the choice.  Synchronises the stream. */
+reedmd_status reedmd_autotune(reedmd_ctx* ctx, const reedmd_species* species,
+                              const reedmd_batch* batch, const reedmd_run_params* params,
+                              int64_t pilot, hipStream_t stream, int32_t* best_lanes,
+                              int32_t* best_waves);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

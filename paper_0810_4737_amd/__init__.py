@@ -1,0 +1,269 @@
+"""MI355X-native REED-MD ion-track engine (thin Python binding over libreedmd.so).
+
+Every step of the track simulation runs in the HIP kernels of ``libreedmd.so``;
+this module only marshals torch device tensors (PyTorch provides device memory
+and streams) into the C ABI declared in ``include/reedmd.h``.  If the library
+is missing, importing the binding's functions raises: there is no CPU path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import _abi
+from ._abi import (ACTIVE, BACKSCATTERED, CANCELLED, DIR_CONE, DIR_MIXED, DIR_TILT,  # noqa: F401
+                   FORM_PERSISTENT, FORM_PLAIN, NONFINITE, NSLOT, POT_NONE, POT_ZBL, RECORD_WORDS,
+                   STEPCAP, STOP_LOCAL, STOP_OFF, STOP_UNIFORM, STOPPED)
+
+SPECIES = {"B": (5, 10.81), "P": (15, 30.97), "As": (33, 74.92)}
+SILICON = dict(a=5.431, Z2=14, M2=28.0855, sigma=0.076)
+
+
+class ReedmdError(RuntimeError):
+    pass
+
+
+def _check(rc, ctx=None):
+    if rc != 0:
+        L = _abi.load()
+        msg = L.reedmd_last_error(ctx).decode() if ctx is not None or rc != 0 else ""
+        raise ReedmdError(f"reedmd status {rc}: {msg}")
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+class Context:
+    """One target crystal + interaction model on the current device."""
+
+    def __init__(self, a=SILICON["a"], Z2=SILICON["Z2"], M2=SILICON["M2"], sigma=SILICON["sigma"],
+                 pot_mode=POT_ZBL, s=1.0, stop_mode=STOP_LOCAL, k=1.0):
+        L = _abi.load()
+        self._lib = L
+        lat = _abi.Lattice(a=a, M2=M2, sigma=sigma, Z2=Z2, structure=_abi.DIAMOND)
+        pot = _abi.Potential(mode=pot_mode, s=s)
+        stp = _abi.Stopping(mode=stop_mode, k=k)
+        h = C.c_void_p()
+        rc = L.reedmd_create(C.byref(lat), C.byref(pot), C.byref(stp), C.byref(h))
+        if rc != 0:
+            raise ReedmdError(f"reedmd_create failed ({rc}): {L.reedmd_last_error(None).decode()}")
+        self.handle = h
+        self.a = a
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            self._lib.reedmd_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def check(self, rc):
+        if rc != 0:
+            raise ReedmdError(f"reedmd status {rc}: {self._lib.reedmd_last_error(self.handle).decode()}")
+
+
+def species_table(names):
+    st = _abi.Species()
+    st.n_species = len(names)
+    for i, nm in enumerate(names):
+        Z, M = SPECIES[nm] if isinstance(nm, str) else nm
+        st.Z1[i], st.M1[i] = Z, M
+    return st
+
+
+@dataclass
+class RunConfig:
+    dx_max: float = 0.05
+    dt_max: float = 1.0
+    E_stop: float = 5.0
+    z_start: float = -3.0
+    max_steps: int = 0
+    seed: int = 0
+    thresholds: object = None      # array [n_tables][n_thresh] or None
+    n_clones: int = 2
+    n_bins: int = 1024
+    bin_width: float = 1.0
+    form: int = FORM_PLAIN
+    lanes_per_track: int = 0
+    waves_per_cu: int = 0
+    queue_capacity: int = 0
+
+    def struct(self, device, keep):
+        p = _abi.RunParams()
+        p.dx_max, p.dt_max, p.E_stop, p.z_start = self.dx_max, self.dt_max, self.E_stop, self.z_start
+        p.max_steps, p.seed = int(self.max_steps), int(self.seed)
+        if self.thresholds is not None and np.asarray(self.thresholds).size:
+            thr = torch.as_tensor(np.atleast_2d(np.asarray(self.thresholds, np.float64)), device=device)
+            keep.append(thr)
+            p.n_tables, p.n_thresh = thr.shape
+            p.thresholds = thr.data_ptr()
+        p.n_clones, p.n_bins, p.bin_width = self.n_clones, self.n_bins, self.bin_width
+        p.form, p.lanes_per_track = self.form, self.lanes_per_track
+        p.waves_per_cu, p.queue_capacity = self.waves_per_cu, self.queue_capacity
+        return p
+
+
+@dataclass
+class SamplerConfig:
+    choice: tuple = (0,)
+    dir_mode: int = DIR_TILT
+    n_energy_tables: int = 1
+    E_min: float = 1000.0
+    E_max: float = 1000.0
+    tilt: float = math.radians(7.0)
+    axis: tuple = (0.0, 0.0, 1.0)
+    half_angle: float = 0.0
+    n_cone: int = 0
+    a: float = SILICON["a"]
+    z_start: float = -3.0
+
+    def struct(self):
+        s = _abi.Sampler()
+        s.n_choice = len(self.choice)
+        for i, c in enumerate(self.choice):
+            s.choice[i] = c
+        s.dir_mode, s.n_energy_tables = self.dir_mode, self.n_energy_tables
+        s.E_min, s.E_max, s.tilt = self.E_min, self.E_max, self.tilt
+        for i in range(3):
+            s.axis[i] = self.axis[i]
+        s.half_angle, s.n_cone, s.a, s.z_start = self.half_angle, self.n_cone, self.a, self.z_start
+        return s
+
+
+def empty_batch(n, device="cuda"):
+    return dict(species=torch.zeros(n, dtype=torch.int32, device=device),
+                energy=torch.zeros(n, dtype=torch.float64, device=device),
+                pos=torch.zeros((3, n), dtype=torch.float64, device=device),
+                dir=torch.zeros((3, n), dtype=torch.float64, device=device),
+                key=torch.zeros(n, dtype=torch.int64, device=device),
+                table=torch.zeros(n, dtype=torch.int32, device=device))
+
+
+def _batch_struct(batch, id0=0):
+    b = _abi.Batch()
+    b.n = int(batch["energy"].shape[0])
+    b.id0 = int(id0)
+    for name in ("species", "energy", "pos", "dir", "key", "table"):
+        t = batch[name]
+        assert t.is_contiguous() and t.is_cuda, name
+        setattr(b, name, t.data_ptr())
+    return b
+
+
+def batch_from_numpy(d, device="cuda"):
+    """Uploads a host batch (e.g. one made by a test) into device tensors."""
+    return dict(species=torch.as_tensor(np.ascontiguousarray(d["species"], np.int32), device=device),
+                energy=torch.as_tensor(np.ascontiguousarray(d["E0"] if "E0" in d else d["energy"], np.float64), device=device),
+                pos=torch.as_tensor(np.ascontiguousarray(d["pos"], np.float64), device=device),
+                dir=torch.as_tensor(np.ascontiguousarray(d["dir"], np.float64), device=device),
+                key=torch.as_tensor(np.ascontiguousarray(d["key"]).view(np.int64), device=device),
+                table=torch.as_tensor(np.ascontiguousarray(d["table"], np.int32), device=device))
+
+
+def sample_primaries(ctx: Context, sampler: SamplerConfig, seed: int, n: int, id0: int = 0,
+                     device="cuda", stream=None):
+    batch = empty_batch(n, device)
+    b = _batch_struct(batch, id0)
+    s = sampler.struct()
+    ctx.check(ctx._lib.reedmd_sample_primaries(ctx.handle, C.byref(s), int(seed), C.byref(b), _stream(stream)))
+    return batch
+
+
+def new_stats(device="cuda"):
+    return torch.zeros(_abi.STATS_WORDS, dtype=torch.int64, device=device)
+
+
+def parse_stats(stats: torch.Tensor):
+    raw = stats.detach().cpu().numpy().astype(np.int64)
+    out = {}
+    i = 0
+    for n in _abi.STATS_INT_A:
+        out[n] = int(raw[i]); i += 1
+    dbl = raw[i:i + len(_abi.STATS_DBL)].view(np.float64)
+    for j, n in enumerate(_abi.STATS_DBL):
+        out[n] = float(dbl[j])
+    i += len(_abi.STATS_DBL)
+    for n in _abi.STATS_INT_B:
+        out[n] = int(raw[i]); i += 1
+    return out
+
+
+def run(ctx: Context, species, batch, cfg: RunConfig, hist=None, stats=None, id0=0, log_cap=0,
+        cancel=None, stream=None):
+    """Runs every primary of `batch` with all its clones; returns (hist, stats[, log])."""
+    dev = batch["energy"].device
+    keep = []
+    p = cfg.struct(dev, keep)
+    if hist is None:
+        hist = torch.zeros(cfg.n_bins, dtype=torch.float64, device=dev)
+    if stats is None:
+        stats = new_stats(dev)
+    log = None
+    if log_cap > 0:
+        log = torch.zeros((log_cap, 5), dtype=torch.int64, device=dev)
+        p.track_log = log.data_ptr()
+        p.track_log_cap = log_cap
+    if cancel is not None:
+        p.cancel = cancel.data_ptr()
+    sp = species_table(species) if not isinstance(species, _abi.Species) else species
+    b = _batch_struct(batch, id0)
+    ctx.check(ctx._lib.reedmd_run(ctx.handle, C.byref(sp), C.byref(b), C.byref(p), _ptr(hist), _ptr(stats),
+                                  _stream(stream)))
+    if log is not None:
+        return hist, stats, log, keep
+    return hist, stats, keep
+
+
+def parse_log(log: torch.Tensor, count: int):
+    raw = log[:count].detach().cpu().numpy()
+    dt = np.dtype([("lineage", np.int64), ("status", np.int32), ("next_k", np.int32),
+                   ("z_stop", np.float64), ("w", np.float64), ("steps", np.int64)])
+    return raw.copy().view(dt).reshape(-1)
+
+
+def track_init(ctx: Context, species, batch, cfg: RunConfig, id0=0, stream=None):
+    dev = batch["energy"].device
+    keep = []
+    p = cfg.struct(dev, keep)
+    n = int(batch["energy"].shape[0])
+    rec = torch.zeros((n, RECORD_WORDS), dtype=torch.float64, device=dev)
+    sp = species_table(species) if not isinstance(species, _abi.Species) else species
+    b = _batch_struct(batch, id0)
+    ctx.check(ctx._lib.reedmd_track_init(ctx.handle, C.byref(sp), C.byref(b), C.byref(p), _ptr(rec),
+                                         _stream(stream)))
+    return rec
+
+
+def debug_step(ctx: Context, species, records: torch.Tensor, cfg: RunConfig, nsteps=1, stream=None):
+    keep = []
+    p = cfg.struct(records.device, keep)
+    sp = species_table(species) if not isinstance(species, _abi.Species) else species
+    assert records.is_contiguous() and records.dtype == torch.float64
+    ctx.check(ctx._lib.reedmd_debug_step(ctx.handle, C.byref(sp), C.byref(p), _ptr(records),
+                                         int(records.shape[0]), int(nsteps), _stream(stream)))
+    return records
+
+
+def autotune(ctx: Context, species, batch, cfg: RunConfig, pilot: int, stream=None):
+    keep = []
+    p = cfg.struct(batch["energy"].device, keep)
+    sp = species_table(species) if not isinstance(species, _abi.Species) else species
+    b = _batch_struct(batch)
+    bl, bw = C.c_int32(), C.c_int32()
+    ctx.check(ctx._lib.reedmd_autotune(ctx.handle, C.byref(sp), C.byref(b), C.byref(p), int(pilot),
+                                       _stream(stream), C.byref(bl), C.byref(bw)))
+    return bl.value, bw.value

@@ -1,0 +1,699 @@
+// reedmd C ABI: context, argument checks, scratch memory, launches, hipGraph
+// capture of the persistent pipeline and the launch-shape autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/reedmd.h"
+#include "track_kernels.hpp"
+
+using namespace reedmd;
+
+namespace {
+
+constexpr double kCoulomb = 14.3996454784;   // e^2 / (4 pi eps0), eV A (CODATA 2018)
+constexpr double kBohr = 0.529177210903;     // A
+constexpr int kBlock = 256;                  // 4 wavefronts per workgroup
+constexpr long long kDefaultMaxSteps = 2000000;   // step cap when the caller sets none
+
+thread_local std::string g_create_error;
+
+}  // namespace
+
+struct reedmd_ctx {
+    int device = 0;
+    int cu_count = 0;
+    reedmd_lattice lat{};
+    reedmd_potential pot{};
+    reedmd_stopping stop{};
+    std::string err;
+    // scratch
+    void* scratch = nullptr;       // QueueState + qseq + qrec
+    size_t scratch_bytes = 0;
+    double* stack = nullptr;
+    size_t stack_bytes = 0;
+    // autotune cache: config hash -> (lanes, waves per CU)
+    std::map<unsigned long long, std::pair<int, int>> tune;
+    // captured persistent pipelines
+    struct Graph {
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+    };
+    std::map<std::vector<unsigned long long>, Graph> graphs;
+};
+
+namespace {
+
+reedmd_status fail(reedmd_ctx* ctx, reedmd_status st, const std::string& msg)
+{
+    if (ctx) ctx->err = msg;
+    else g_create_error = msg;
+    return st;
+}
+
+reedmd_status hip_fail(reedmd_ctx* ctx, hipError_t e, const char* what)
+{
+    return fail(ctx, REEDMD_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(ctx, call)                                   \
+    do {                                                     \
+        hipError_t e__ = (call);                             \
+        if (e__ != hipSuccess) return hip_fail(ctx, e__, #call); \
+    } while (0)
+
+// Per-species constants for the kernels (ZBL screening length and Coulomb
+// prefactor, density kernel, Lindhard-Scharff friction coefficient).
+void prepare_species(const reedmd_ctx* ctx, const reedmd_species* sp, KernelArgs& A)
+{
+    const double Z2 = ctx->lat.Z2;
+    const double N = 8.0 / (ctx->lat.a * ctx->lat.a * ctx->lat.a);
+    for (int i = 0; i < kMaxSpecies; ++i) {
+        SpeciesConst& c = A.sp[i];
+        if (i >= sp->n_species) {
+            c = SpeciesConst{1.0, 0.5, 1.0, 0.0, 1.0, 0.0, 0.0, 0.0};
+            continue;
+        }
+        const double Z1 = sp->Z1[i], M1 = sp->M1[i];
+        const double aU = 0.8854 * kBohr / (std::pow(Z1, 0.23) + std::pow(Z2, 0.23));
+        const double lambda = aU / 0.3;
+        const double z23 = std::pow(Z1, 2.0 / 3.0) + std::pow(Z2, 2.0 / 3.0);
+        const double kL = 1.212 * std::pow(Z1, 7.0 / 6.0) * Z2 / (std::pow(z23, 1.5) * std::sqrt(M1));
+        const double gamma0 = N * kL * std::sqrt(M1 / 2.0);
+        c.M1 = M1;
+        c.half_inv_M1 = 1.0 / (2.0 * M1);
+        c.inv_a = 1.0 / (ctx->pot.s * aU);
+        c.zz = (ctx->pot.mode == REEDMD_POT_ZBL) ? Z1 * Z2 * kCoulomb : 0.0;
+        c.inv_lambda = 1.0 / lambda;
+        c.wnorm = 1.0 / (8.0 * M_PI * lambda * lambda * lambda);
+        c.g_const = 0.0;
+        c.g_rho = 0.0;
+        if (ctx->stop.mode == REEDMD_STOP_UNIFORM) c.g_const = ctx->stop.k * gamma0;
+        if (ctx->stop.mode == REEDMD_STOP_LOCAL) c.g_rho = ctx->stop.k * gamma0 / N;
+    }
+}
+
+reedmd_status check_species(reedmd_ctx* ctx, const reedmd_species* sp)
+{
+    if (!sp) return fail(ctx, REEDMD_EINVAL, "species table is NULL");
+    if (sp->n_species < 1 || sp->n_species > REEDMD_MAX_SPECIES)
+        return fail(ctx, REEDMD_EINVAL, "n_species must be in 1..8");
+    for (int i = 0; i < sp->n_species; ++i)
+        if (sp->Z1[i] <= 0 || !(sp->M1[i] > 0.0)) return fail(ctx, REEDMD_EINVAL, "species Z1 and M1 must be positive");
+    return REEDMD_OK;
+}
+
+reedmd_status check_params(reedmd_ctx* ctx, const reedmd_run_params* p, bool need_hist)
+{
+    if (!p) return fail(ctx, REEDMD_EINVAL, "params is NULL");
+    if (!(p->dx_max > 0.0) || !(p->dt_max > 0.0) || !(p->E_stop > 0.0) || !std::isfinite(p->z_start))
+        return fail(ctx, REEDMD_EINVAL, "dx_max, dt_max and E_stop must be positive, z_start finite");
+    if (p->n_thresh < 0 || p->n_thresh > 64) return fail(ctx, REEDMD_EINVAL, "n_thresh must be in 0..64");
+    if (p->n_thresh > 0) {
+        if (p->n_tables < 1 || !p->thresholds) return fail(ctx, REEDMD_EINVAL, "thresholds need n_tables >= 1 and a pointer");
+        if (p->n_clones < 2 || p->n_clones > 16) return fail(ctx, REEDMD_EINVAL, "n_clones must be in 2..16");
+    }
+    if (need_hist) {
+        if (p->n_bins <= 0 || !(p->bin_width > 0.0)) return fail(ctx, REEDMD_EINVAL, "n_bins and bin_width must be positive");
+        if (p->form != REEDMD_FORM_PLAIN && p->form != REEDMD_FORM_PERSISTENT)
+            return fail(ctx, REEDMD_EINVAL, "unknown form");
+    }
+    if (p->lanes_per_track != 0 && p->lanes_per_track != 64 && p->lanes_per_track != 32 && p->lanes_per_track != 16)
+        return fail(ctx, REEDMD_EINVAL, "lanes_per_track must be 0, 16, 32 or 64");
+    if (p->waves_per_cu < 0 || p->waves_per_cu > 32) return fail(ctx, REEDMD_EINVAL, "waves_per_cu must be in 0..32");
+    if (p->queue_capacity < 0) return fail(ctx, REEDMD_EINVAL, "queue_capacity must be >= 0");
+    if (p->track_log && p->track_log_cap < 0) return fail(ctx, REEDMD_EINVAL, "track_log_cap must be >= 0");
+    return REEDMD_OK;
+}
+
+reedmd_status check_batch(reedmd_ctx* ctx, const reedmd_batch* b)
+{
+    if (!b) return fail(ctx, REEDMD_EINVAL, "batch is NULL");
+    if (b->n < 0) return fail(ctx, REEDMD_EINVAL, "batch n must be >= 0");
+    if (b->n > 0 && (!b->species || !b->energy || !b->pos || !b->dir || !b->key || !b->table))
+        return fail(ctx, REEDMD_EINVAL, "batch arrays must be non-NULL");
+    return REEDMD_OK;
+}
+
+void fill_common(const reedmd_ctx* ctx, const reedmd_species* sp, const reedmd_run_params* p, KernelArgs& A)
+{
+    std::memset(&A, 0, sizeof(A));
+    prepare_species(ctx, sp, A);
+    A.n_species = sp->n_species;
+    A.a = ctx->lat.a;
+    A.M2 = ctx->lat.M2;
+    A.sigma = ctx->lat.sigma;
+    A.inv_M2sq = 1.0 / (ctx->lat.M2 * ctx->lat.M2);
+    A.half_inv_M2 = 1.0 / (2.0 * ctx->lat.M2);
+    A.dx_max = p->dx_max;
+    A.dt_max = p->dt_max;
+    A.E_stop = p->E_stop;
+    A.z_start = p->z_start;
+    A.max_steps = p->max_steps > 0 ? p->max_steps : kDefaultMaxSteps;
+    A.seed = p->seed;
+    A.thr = p->thresholds;
+    A.n_thresh = p->n_thresh;
+    A.n_tables = p->n_tables;
+    A.n_clones = p->n_clones < 2 ? 2 : p->n_clones;
+    A.n_bins = p->n_bins;
+    A.bin_width = p->bin_width;
+}
+
+void fill_batch(const reedmd_batch* b, KernelArgs& A)
+{
+    A.n = b->n;
+    A.id0 = b->id0;
+    A.species = b->species;
+    A.energy = b->energy;
+    A.pos = b->pos;
+    A.dir = b->dir;
+    A.key = reinterpret_cast<const unsigned long long*>(b->key);
+    A.table = b->table;
+}
+
+template <int L, int MODE>
+hipError_t launch_track(const KernelArgs& A, long long blocks, hipStream_t s)
+{
+    hipLaunchKernelGGL((track_kernel<L, MODE>), dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s, A);
+    return hipGetLastError();
+}
+
+hipError_t launch_track_any(int L, int mode, const KernelArgs& A, long long blocks, hipStream_t s)
+{
+    if (mode == kModePlain) {
+        if (L == 64) return launch_track<64, kModePlain>(A, blocks, s);
+        if (L == 32) return launch_track<32, kModePlain>(A, blocks, s);
+        return launch_track<16, kModePlain>(A, blocks, s);
+    }
+    if (L == 64) return launch_track<64, kModePersistent>(A, blocks, s);
+    if (L == 32) return launch_track<32, kModePersistent>(A, blocks, s);
+    return launch_track<16, kModePersistent>(A, blocks, s);
+}
+
+int resident_blocks_per_cu(int L, int mode)
+{
+    int nb = 0;
+    hipError_t e = hipSuccess;
+    if (mode == kModePlain) {
+        if (L == 64) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, track_kernel<64, kModePlain>, kBlock, 0);
+        else if (L == 32) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, track_kernel<32, kModePlain>, kBlock, 0);
+        else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, track_kernel<16, kModePlain>, kBlock, 0);
+    } else {
+        if (L == 64) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, track_kernel<64, kModePersistent>, kBlock, 0);
+        else if (L == 32) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, track_kernel<32, kModePersistent>, kBlock, 0);
+        else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, track_kernel<16, kModePersistent>, kBlock, 0);
+    }
+    if (e != hipSuccess || nb < 1) nb = 1;
+    return nb;
+}
+
+// Queue state reset (a kernel, not a memset, so the pipeline can be captured).
+__global__ void queue_reset_kernel(QueueState* q, unsigned long long* seq, int cap, long long n)
+{
+    const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i == 0) {
+        q->head = 0;
+        q->tail = 0;
+        q->live = n;
+        q->prim_next = 0;
+        q->depth_max = 0;
+        q->log_next = 0;
+        q->pad[0] = q->pad[1] = 0;
+    }
+    if (i < cap) seq[i] = static_cast<unsigned long long>(i);
+}
+
+// Copies the number of logged results into the caller's stats at the end.
+__global__ void stats_finalize_kernel(const QueueState* q, reedmd_stats* st)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) st->log_count += q->log_next;
+}
+
+reedmd_status ensure_scratch(reedmd_ctx* ctx, int qcap, size_t stack_records)
+{
+    const size_t qbytes = 256 + static_cast<size_t>(qcap) * 8 + static_cast<size_t>(qcap) * kRecWords * 8;
+    const size_t need_q = ((qbytes + 4095) / 4096) * 4096;
+    if (need_q > ctx->scratch_bytes) {
+        HIP_TRY(ctx, hipDeviceSynchronize());
+        if (ctx->scratch) (void)hipFree(ctx->scratch);
+        ctx->scratch = nullptr;
+        ctx->scratch_bytes = 0;
+        for (auto& g : ctx->graphs) {
+            (void)hipGraphExecDestroy(g.second.exec);
+            (void)hipGraphDestroy(g.second.graph);
+        }
+        ctx->graphs.clear();
+        if (hipMalloc(&ctx->scratch, need_q) != hipSuccess) {
+            ctx->scratch = nullptr;
+            return fail(ctx, REEDMD_ENOMEM, "cannot allocate the clone queue");
+        }
+        ctx->scratch_bytes = need_q;
+    }
+    const size_t need_s = std::max<size_t>(stack_records, 1) * kRecWords * 8;
+    if (need_s > ctx->stack_bytes) {
+        HIP_TRY(ctx, hipDeviceSynchronize());
+        if (ctx->stack) (void)hipFree(ctx->stack);
+        ctx->stack = nullptr;
+        ctx->stack_bytes = 0;
+        for (auto& g : ctx->graphs) {
+            (void)hipGraphExecDestroy(g.second.exec);
+            (void)hipGraphDestroy(g.second.graph);
+        }
+        ctx->graphs.clear();
+        if (hipMalloc(reinterpret_cast<void**>(&ctx->stack), need_s) != hipSuccess) {
+            ctx->stack = nullptr;
+            return fail(ctx, REEDMD_ENOMEM, "cannot allocate clone stacks");
+        }
+        ctx->stack_bytes = need_s;
+    }
+    return REEDMD_OK;
+}
+
+unsigned long long hash_mix(unsigned long long h, unsigned long long v)
+{
+    h ^= v + 0x9E3779B97F4A7C15ULL + (h << 6) + (h >> 2);
+    return h;
+}
+
+unsigned long long tune_key(const reedmd_run_params* p, const reedmd_batch* b)
+{
+    unsigned long long h = 1469598103934665603ULL;
+    h = hash_mix(h, static_cast<unsigned long long>(p->form));
+    h = hash_mix(h, static_cast<unsigned long long>(p->n_thresh));
+    h = hash_mix(h, static_cast<unsigned long long>(b->n > 0 ? 63 - __builtin_clzll(static_cast<unsigned long long>(b->n)) : 0));
+    return h;
+}
+
+// Launch shape for a run.
+struct Shape {
+    int L;
+    int mode;
+    long long seg_total;
+    long long blocks;
+    int stack_cap;
+    int qcap;
+};
+
+Shape choose_shape(reedmd_ctx* ctx, const reedmd_run_params* p, const reedmd_batch* b)
+{
+    Shape s{};
+    s.mode = p->form == REEDMD_FORM_PERSISTENT ? kModePersistent : kModePlain;
+    int L = p->lanes_per_track;
+    int waves = p->waves_per_cu;
+    if (L == 0 || (s.mode == kModePersistent && waves == 0)) {
+        auto it = ctx->tune.find(tune_key(p, b));
+        if (it != ctx->tune.end()) {
+            if (L == 0) L = it->second.first;
+            if (waves == 0) waves = it->second.second;
+        }
+    }
+    if (L == 0) L = 64;
+    s.L = L;
+    const int T = 64 / L;
+    const int per_wave_block = kBlock / 64;
+    s.stack_cap = p->n_thresh > 0 ? p->n_thresh * (std::max(p->n_clones, 2) - 1) + 1 : 0;
+    if (s.mode == kModePlain) {
+        const long long max_segs = 1ll << 16;
+        s.seg_total = std::max<long long>(1, std::min<long long>(b->n, max_segs * T));
+        const long long waves_needed = (s.seg_total + T - 1) / T;
+        s.blocks = (waves_needed + per_wave_block - 1) / per_wave_block;
+        s.qcap = 0;
+    } else {
+        int bpc = resident_blocks_per_cu(L, s.mode);
+        if (waves > 0) bpc = std::max(1, std::min(bpc, (waves + per_wave_block - 1) / per_wave_block));
+        s.blocks = static_cast<long long>(bpc) * ctx->cu_count;
+        s.seg_total = s.blocks * per_wave_block * T;
+        s.qcap = p->queue_capacity > 0 ? p->queue_capacity : 4096;
+        if (p->n_thresh == 0) s.qcap = 1;
+    }
+    return s;
+}
+
+reedmd_status run_impl(reedmd_ctx* ctx, const reedmd_species* sp, const reedmd_batch* b,
+                       const reedmd_run_params* p, double* d_hist, reedmd_stats* d_stats, hipStream_t stream,
+                       const Shape* forced)
+{
+    Shape s = forced ? *forced : choose_shape(ctx, p, b);
+    const int qcap = s.qcap > 0 ? s.qcap : 1;
+    const size_t stack_records = static_cast<size_t>(s.seg_total) * static_cast<size_t>(std::max(s.stack_cap, 0));
+    reedmd_status st = ensure_scratch(ctx, qcap, stack_records);
+    if (st != REEDMD_OK) return st;
+
+    KernelArgs A;
+    fill_common(ctx, sp, p, A);
+    fill_batch(b, A);
+    A.hist = d_hist;
+    A.stats = d_stats;
+    A.log = static_cast<reedmd_result*>(p->track_log);
+    A.log_cap = p->track_log ? p->track_log_cap : 0;
+    A.stack = ctx->stack;
+    A.stack_cap = s.stack_cap;
+    A.q = static_cast<QueueState*>(ctx->scratch);
+    A.qseq = reinterpret_cast<unsigned long long*>(static_cast<char*>(ctx->scratch) + 256);
+    A.qrec = reinterpret_cast<double*>(static_cast<char*>(ctx->scratch) + 256 + static_cast<size_t>(qcap) * 8);
+    A.qcap = (s.mode == kModePersistent && p->n_thresh > 0) ? qcap : 0;
+    A.cancel = p->cancel;
+    A.seg_total = s.seg_total;
+
+    if (b->n == 0) return REEDMD_OK;
+
+    auto enqueue = [&](hipStream_t sm) -> hipError_t {
+        const int rb = (qcap + 255) / 256;
+        hipLaunchKernelGGL(queue_reset_kernel, dim3(rb), dim3(256), 0, sm, A.q, A.qseq, qcap, b->n);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        e = launch_track_any(s.L, s.mode, A, s.blocks, sm);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(stats_finalize_kernel, dim3(1), dim3(64), 0, sm, A.q, d_stats);
+        return hipGetLastError();
+    };
+
+    if (s.mode == kModePersistent && !forced) {
+        // The persistent pipeline (queue reset, persistent kernel, stats) is
+        // captured once per argument set and replayed.
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        HIP_TRY(ctx, hipStreamIsCapturing(stream, &cs));
+        if (cs == hipStreamCaptureStatusNone) {
+            std::vector<unsigned long long> key;
+            const unsigned long long* raw = reinterpret_cast<const unsigned long long*>(&A);
+            key.assign(raw, raw + sizeof(A) / 8);
+            key.push_back(static_cast<unsigned long long>(s.L));
+            key.push_back(static_cast<unsigned long long>(s.blocks));
+            auto it = ctx->graphs.find(key);
+            if (it == ctx->graphs.end()) {
+                hipStream_t cap_stream;
+                HIP_TRY(ctx, hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
+                reedmd_ctx::Graph g;
+                hipError_t e = hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal);
+                if (e == hipSuccess) {
+                    hipError_t e2 = enqueue(cap_stream);
+                    e = hipStreamEndCapture(cap_stream, &g.graph);
+                    if (e2 != hipSuccess) e = e2;
+                }
+                if (e == hipSuccess) e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
+                (void)hipStreamDestroy(cap_stream);
+                if (e != hipSuccess) return hip_fail(ctx, e, "capturing the persistent pipeline");
+                it = ctx->graphs.emplace(key, g).first;
+            }
+            HIP_TRY(ctx, hipGraphLaunch(it->second.exec, stream));
+            return REEDMD_OK;
+        }
+    }
+    HIP_TRY(ctx, enqueue(stream));
+    return REEDMD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Primary sampler: mirrors the batch contract of reedmd_sample_primaries.
+struct SamplerArgs {
+    reedmd_sampler s;
+    unsigned long long seed;
+    long long id0, n;
+    int* species;
+    double* energy;
+    double* pos;
+    double* dir;
+    unsigned long long* key;
+    int* table;
+};
+
+__global__ void sample_kernel(const SamplerArgs S)
+{
+    const long long q = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (q >= S.n) return;
+    const long long id = S.id0 + q;
+    const U64x4 r0 = philox4x64_10(kTagSample, static_cast<uint64_t>(id), 0, 0, S.seed, 0);
+    const U64x4 r1 = philox4x64_10(kTagSample, static_cast<uint64_t>(id), 1, 0, S.seed, 0);
+    double u[8];
+    for (int i = 0; i < 4; ++i) {
+        u[i] = open_unit(r0.w[i]);
+        u[4 + i] = open_unit(r1.w[i]);
+    }
+    const reedmd_sampler& s = S.s;
+    S.pos[q] = s.a * u[0];
+    S.pos[S.n + q] = s.a * u[1];
+    S.pos[2 * S.n + q] = s.z_start;
+    int ci = static_cast<int>(floor(static_cast<double>(s.n_choice) * u[2]));
+    if (ci > s.n_choice - 1) ci = s.n_choice - 1;
+    S.species[q] = s.choice[ci];
+    S.energy[q] = (s.E_min == s.E_max) ? s.E_min : s.E_min * exp(u[3] * log(s.E_max / s.E_min));
+    const int net = s.n_energy_tables > 1 ? s.n_energy_tables : 1;
+    int band = 0;
+    if (net > 1) {
+        band = static_cast<int>(floor(static_cast<double>(net) * u[3]));
+        if (band > net - 1) band = net - 1;
+    }
+    S.table[q] = ci * net + band;
+    const bool cone = s.dir_mode == REEDMD_DIR_CONE || (s.dir_mode == REEDMD_DIR_MIXED && id < s.n_cone);
+    constexpr double kTwoPi = 6.283185307179586476925286766559;
+    const double phi = kTwoPi * u[4];
+    double sp, cp;
+    sincos(phi, &sp, &cp);
+    if (!cone) {
+        double st, ct;
+        sincos(s.tilt, &st, &ct);
+        S.dir[q] = st * cp;
+        S.dir[S.n + q] = st * sp;
+        S.dir[2 * S.n + q] = ct;
+    } else {
+        const double ct = 1.0 - u[5] * (1.0 - cos(s.half_angle));
+        const double st = sqrt(fmax(0.0, 1.0 - ct * ct));
+        const double* A = s.axis;
+        double hx = 1.0, hy = 0.0;
+        if (fabs(A[0]) >= 0.9) { hx = 0.0; hy = 1.0; }
+        // e1 = normalise(A x h) with h = (hx, hy, 0); e2 = A x e1
+        double e1x = -A[2] * hy, e1y = A[2] * hx, e1z = A[0] * hy - A[1] * hx;
+        const double n1 = sqrt(e1x * e1x + e1y * e1y + e1z * e1z);
+        e1x /= n1; e1y /= n1; e1z /= n1;
+        const double e2x = A[1] * e1z - A[2] * e1y, e2y = A[2] * e1x - A[0] * e1z, e2z = A[0] * e1y - A[1] * e1x;
+        S.dir[q] = st * (cp * e1x + sp * e2x) + ct * A[0];
+        S.dir[S.n + q] = st * (cp * e1y + sp * e2y) + ct * A[1];
+        S.dir[2 * S.n + q] = st * (cp * e1z + sp * e2z) + ct * A[2];
+    }
+    S.key[q] = primary_key(S.seed, id);
+}
+
+}  // namespace
+
+// ===========================================================================
+extern "C" {
+
+int32_t reedmd_version(void) { return 100; }
+
+reedmd_status reedmd_create(const reedmd_lattice* lattice, const reedmd_potential* potential,
+                            const reedmd_stopping* stopping, reedmd_ctx** out)
+{
+    if (!out) return fail(nullptr, REEDMD_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!lattice || !potential || !stopping) return fail(nullptr, REEDMD_EINVAL, "NULL model description");
+    if (!(lattice->a > 0.0) || !(lattice->M2 > 0.0) || !(lattice->sigma >= 0.0) || lattice->Z2 <= 0)
+        return fail(nullptr, REEDMD_EINVAL, "lattice a, M2, Z2 must be positive and sigma >= 0");
+    if (lattice->structure != REEDMD_DIAMOND) return fail(nullptr, REEDMD_EUNSUPPORTED, "only the diamond structure");
+    if (potential->mode != REEDMD_POT_ZBL && potential->mode != REEDMD_POT_NONE)
+        return fail(nullptr, REEDMD_EINVAL, "unknown potential mode");
+    if (!(potential->s > 0.0)) return fail(nullptr, REEDMD_EINVAL, "screening scale s must be positive");
+    if (stopping->mode < REEDMD_STOP_OFF || stopping->mode > REEDMD_STOP_LOCAL || !(stopping->k >= 0.0))
+        return fail(nullptr, REEDMD_EINVAL, "unknown stopping mode or negative k");
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(nullptr, REEDMD_EHIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    int cus = 0;
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return fail(nullptr, REEDMD_EHIP, std::string("device attribute: ") + hipGetErrorString(e));
+    reedmd_ctx* ctx = new reedmd_ctx();
+    ctx->device = dev;
+    ctx->cu_count = cus;
+    ctx->lat = *lattice;
+    ctx->pot = *potential;
+    ctx->stop = *stopping;
+    *out = ctx;
+    return REEDMD_OK;
+}
+
+void reedmd_destroy(reedmd_ctx* ctx)
+{
+    if (!ctx) return;
+    (void)hipDeviceSynchronize();
+    for (auto& g : ctx->graphs) {
+        (void)hipGraphExecDestroy(g.second.exec);
+        (void)hipGraphDestroy(g.second.graph);
+    }
+    if (ctx->scratch) (void)hipFree(ctx->scratch);
+    if (ctx->stack) (void)hipFree(ctx->stack);
+    delete ctx;
+}
+
+const char* reedmd_last_error(const reedmd_ctx* ctx)
+{
+    if (!ctx) return g_create_error.c_str();
+    return ctx->err.c_str();
+}
+
+reedmd_status reedmd_sample_primaries(reedmd_ctx* ctx, const reedmd_sampler* sampler, uint64_t seed,
+                                      const reedmd_batch* out, hipStream_t stream)
+{
+    if (!ctx) return fail(nullptr, REEDMD_EINVAL, "ctx is NULL");
+    if (!sampler) return fail(ctx, REEDMD_EINVAL, "sampler is NULL");
+    reedmd_status st = check_batch(ctx, out);
+    if (st != REEDMD_OK) return st;
+    if (sampler->n_choice < 1 || sampler->n_choice > REEDMD_MAX_SPECIES)
+        return fail(ctx, REEDMD_EINVAL, "n_choice must be in 1..8");
+    if (sampler->n_energy_tables < 1) return fail(ctx, REEDMD_EINVAL, "n_energy_tables must be >= 1");
+    if (!(sampler->E_min > 0.0) || !(sampler->E_max >= sampler->E_min))
+        return fail(ctx, REEDMD_EINVAL, "need 0 < E_min <= E_max");
+    if (sampler->dir_mode < REEDMD_DIR_TILT || sampler->dir_mode > REEDMD_DIR_MIXED)
+        return fail(ctx, REEDMD_EINVAL, "unknown direction mode");
+    if (sampler->dir_mode != REEDMD_DIR_TILT) {
+        const double n2 = sampler->axis[0] * sampler->axis[0] + sampler->axis[1] * sampler->axis[1] +
+                          sampler->axis[2] * sampler->axis[2];
+        if (std::fabs(n2 - 1.0) > 1e-12) return fail(ctx, REEDMD_EINVAL, "cone axis must be a unit vector");
+    }
+    if (out->n == 0) return REEDMD_OK;
+    SamplerArgs S;
+    std::memset(&S, 0, sizeof(S));
+    S.s = *sampler;
+    S.seed = seed;
+    S.id0 = out->id0;
+    S.n = out->n;
+    S.species = out->species;
+    S.energy = out->energy;
+    S.pos = out->pos;
+    S.dir = out->dir;
+    S.key = reinterpret_cast<unsigned long long*>(out->key);
+    S.table = out->table;
+    const long long blocks = (out->n + 255) / 256;
+    hipLaunchKernelGGL(sample_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, stream, S);
+    HIP_TRY(ctx, hipGetLastError());
+    return REEDMD_OK;
+}
+
+reedmd_status reedmd_run(reedmd_ctx* ctx, const reedmd_species* species, const reedmd_batch* batch,
+                         const reedmd_run_params* params, double* d_hist, reedmd_stats* d_stats,
+                         hipStream_t stream)
+{
+    if (!ctx) return fail(nullptr, REEDMD_EINVAL, "ctx is NULL");
+    reedmd_status st;
+    if ((st = check_species(ctx, species)) != REEDMD_OK) return st;
+    if ((st = check_batch(ctx, batch)) != REEDMD_OK) return st;
+    if ((st = check_params(ctx, params, true)) != REEDMD_OK) return st;
+    if (!d_hist || !d_stats) return fail(ctx, REEDMD_EINVAL, "d_hist and d_stats must be non-NULL");
+    return run_impl(ctx, species, batch, params, d_hist, d_stats, stream, nullptr);
+}
+
+reedmd_status reedmd_track_init(reedmd_ctx* ctx, const reedmd_species* species, const reedmd_batch* batch,
+                                const reedmd_run_params* params, double* d_records, hipStream_t stream)
+{
+    if (!ctx) return fail(nullptr, REEDMD_EINVAL, "ctx is NULL");
+    reedmd_status st;
+    if ((st = check_species(ctx, species)) != REEDMD_OK) return st;
+    if ((st = check_batch(ctx, batch)) != REEDMD_OK) return st;
+    if ((st = check_params(ctx, params, false)) != REEDMD_OK) return st;
+    if (!d_records && batch->n > 0) return fail(ctx, REEDMD_EINVAL, "d_records is NULL");
+    if (batch->n == 0) return REEDMD_OK;
+    KernelArgs A;
+    fill_common(ctx, species, params, A);
+    fill_batch(batch, A);
+    A.records = d_records;
+    const int L = params->lanes_per_track ? params->lanes_per_track : 64;
+    const long long waves = (batch->n + (64 / L) - 1) / (64 / L);
+    const long long blocks = (waves + 3) / 4;
+    if (L == 64) hipLaunchKernelGGL(init_kernel<64>, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, stream, A);
+    else if (L == 32) hipLaunchKernelGGL(init_kernel<32>, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, stream, A);
+    else hipLaunchKernelGGL(init_kernel<16>, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, stream, A);
+    HIP_TRY(ctx, hipGetLastError());
+    return REEDMD_OK;
+}
+
+reedmd_status reedmd_debug_step(reedmd_ctx* ctx, const reedmd_species* species, const reedmd_run_params* params,
+                                double* d_records, int64_t n, int32_t nsteps, hipStream_t stream)
+{
+    if (!ctx) return fail(nullptr, REEDMD_EINVAL, "ctx is NULL");
+    reedmd_status st;
+    if ((st = check_species(ctx, species)) != REEDMD_OK) return st;
+    if ((st = check_params(ctx, params, false)) != REEDMD_OK) return st;
+    if (n < 0 || nsteps < 0) return fail(ctx, REEDMD_EINVAL, "n and nsteps must be >= 0");
+    if (!d_records && n > 0) return fail(ctx, REEDMD_EINVAL, "d_records is NULL");
+    if (n == 0) return REEDMD_OK;
+    KernelArgs A;
+    fill_common(ctx, species, params, A);
+    A.n = n;
+    A.records = d_records;
+    A.nsteps = nsteps;
+    const int L = params->lanes_per_track ? params->lanes_per_track : 64;
+    const long long waves = (n + (64 / L) - 1) / (64 / L);
+    const long long blocks = (waves + 3) / 4;
+    if (L == 64) hipLaunchKernelGGL(step_kernel<64>, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, stream, A);
+    else if (L == 32) hipLaunchKernelGGL(step_kernel<32>, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, stream, A);
+    else hipLaunchKernelGGL(step_kernel<16>, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, stream, A);
+    HIP_TRY(ctx, hipGetLastError());
+    return REEDMD_OK;
+}
+
+reedmd_status reedmd_autotune(reedmd_ctx* ctx, const reedmd_species* species, const reedmd_batch* batch,
+                              const reedmd_run_params* params, int64_t pilot, hipStream_t stream,
+                              int32_t* best_lanes, int32_t* best_waves)
+{
+    if (!ctx) return fail(nullptr, REEDMD_EINVAL, "ctx is NULL");
+    reedmd_status st;
+    if ((st = check_species(ctx, species)) != REEDMD_OK) return st;
+    if ((st = check_batch(ctx, batch)) != REEDMD_OK) return st;
+    if ((st = check_params(ctx, params, true)) != REEDMD_OK) return st;
+    if (pilot <= 0) return fail(ctx, REEDMD_EINVAL, "pilot must be positive");
+    reedmd_batch pb = *batch;
+    pb.n = std::min<int64_t>(pilot, batch->n);
+    double* hist = nullptr;
+    reedmd_stats* stats = nullptr;
+    HIP_TRY(ctx, hipMalloc(reinterpret_cast<void**>(&hist), sizeof(double) * params->n_bins));
+    HIP_TRY(ctx, hipMalloc(reinterpret_cast<void**>(&stats), sizeof(reedmd_stats)));
+    reedmd_run_params p = *params;
+    p.track_log = nullptr;
+    p.track_log_cap = 0;
+    p.cancel = nullptr;
+    hipEvent_t e0, e1;
+    HIP_TRY(ctx, hipEventCreate(&e0));
+    HIP_TRY(ctx, hipEventCreate(&e1));
+    float best = 1e30f;
+    int bl = 64, bw = 0;
+    const int lanes[3] = {64, 32, 16};
+    const int wave_opts_p[4] = {0, 4, 8, 12};
+    for (int li = 0; li < 3; ++li) {
+        const int nw = params->form == REEDMD_FORM_PERSISTENT ? 4 : 1;
+        for (int wi = 0; wi < nw; ++wi) {
+            p.lanes_per_track = lanes[li];
+            p.waves_per_cu = params->form == REEDMD_FORM_PERSISTENT ? wave_opts_p[wi] : 0;
+            Shape s = choose_shape(ctx, &p, &pb);
+            HIP_TRY(ctx, hipEventRecord(e0, stream));
+            st = run_impl(ctx, species, &pb, &p, hist, stats, stream, &s);
+            if (st != REEDMD_OK) break;
+            HIP_TRY(ctx, hipEventRecord(e1, stream));
+            HIP_TRY(ctx, hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIP_TRY(ctx, hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best) {
+                best = ms;
+                bl = lanes[li];
+                bw = p.waves_per_cu;
+            }
+        }
+        if (st != REEDMD_OK) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(hist);
+    (void)hipFree(stats);
+    if (st != REEDMD_OK) return st;
+    ctx->tune[tune_key(params, batch)] = std::make_pair(bl, bw);
+    if (best_lanes) *best_lanes = bl;
+    if (best_waves) *best_waves = bw;
+    return REEDMD_OK;
+}
+
+}  // extern "C"

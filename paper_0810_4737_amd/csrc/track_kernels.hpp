@@ -1,0 +1,670 @@
+// REED-MD track kernels for gfx950.
+//
+// Mapping: one wavefront holds T = 64 / L track segments of L lanes.  The 216
+// domain atoms of a track live in the VGPRs of its segment: slot s is held by
+// lane (s mod L) as its register element s / L.  Slots are indexed by cell
+// residue (c mod 3 per axis) so that moving the domain never moves data: when
+// the centre cell changes, exactly the slots whose cell left the 3x3x3 block
+// are re-created in place (Sec. 2, Fig. 1).  Per step, one fused pass over a
+// lane's slots does half kick, drift, the ZBL pair term, the reaction force
+// and the second half kick; segment reductions (xor shuffles) give the ion
+// force, the local density and the largest atom speed and acceleration.
+#pragma once
+#include "device_physics.hpp"
+#include "../../include/reedmd.h"
+
+namespace reedmd {
+
+enum : int { kModePlain = 0, kModePersistent = 1 };
+
+// Clone queue (persistent form): bounded multi-producer multi-consumer ring
+// with one sequence word per slot (slot free for ticket t when seq == t, full
+// when seq == t + 1).
+struct QueueState {
+    unsigned long long head;
+    unsigned long long tail;
+    long long live;         // tracks not yet finished (unclaimed primaries included)
+    long long prim_next;    // next unclaimed primary
+    long long depth_max;
+    long long log_next;     // next free entry of the optional result log
+    long long pad[2];
+};
+
+struct KernelArgs {
+    SpeciesConst sp[kMaxSpecies];
+    // crystal
+    double a, M2, sigma, inv_M2sq, half_inv_M2;
+    // integration and events
+    double dx_max, dt_max, E_stop, z_start;
+    long long max_steps;
+    unsigned long long seed;
+    // cloning
+    const double* thr;
+    int n_thresh, n_tables, n_clones, n_bins;
+    int n_species;
+    double bin_width;
+    // batch
+    long long n, id0;
+    const int* species;
+    const double* energy;
+    const double* pos;
+    const double* dir;
+    const unsigned long long* key;
+    const int* table;
+    // outputs
+    double* hist;
+    reedmd_stats* stats;
+    reedmd_result* log;
+    long long log_cap;
+    // scratch
+    double* stack;          // [segments][stack_cap][kRecWords]
+    int stack_cap;
+    int qcap;               // 0: no shared queue
+    QueueState* q;
+    unsigned long long* qseq;
+    double* qrec;
+    const int* cancel;
+    long long seg_total;
+    // debug entry points
+    double* records;
+    int nsteps;
+};
+
+// ---------------------------------------------------------------------------
+template <int L>
+struct SegReduce {
+    __device__ __forceinline__ static double sum(double v)
+    {
+#pragma unroll
+        for (int m = L / 2; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+        return v;
+    }
+    __device__ __forceinline__ static double max(double v)
+    {
+#pragma unroll
+        for (int m = L / 2; m >= 1; m >>= 1) v = fmax(v, __shfl_xor(v, m, 64));
+        return v;
+    }
+    __device__ __forceinline__ static int isum(int v)
+    {
+#pragma unroll
+        for (int m = L / 2; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+        return v;
+    }
+};
+
+// Register-resident state of one track segment.
+template <int L>
+struct TrackRegs {
+    static constexpr int SL = (kSlots + L - 1) / L;
+    double ax[SL], ay[SL], az[SL], avx[SL], avy[SL], avz[SL], afx[SL], afy[SL], afz[SL];
+    unsigned exist;      // bit i: register slot i holds an existing atom
+    // ion (segment-uniform)
+    double x, y, z, vx, vy, vz, Fx, Fy, Fz, rho, w, zstop;
+    double vmax2a, amax2a;   // largest atom |v|^2 and |f/M2|^2 after the last pass
+    int cx, cy, cz;
+    unsigned long long key;
+    long long steps, lineage;
+    int species, next_k, table, status;
+    int n_exist;             // atoms in the domain (segment-uniform)
+};
+
+template <int L>
+__device__ __forceinline__ void regenerate(TrackRegs<L>& t, const KernelArgs& A, int sl, int ncx,
+                                           int ncy, int ncz, bool all)
+{
+    unsigned ex = 0;
+#pragma unroll
+    for (int i = 0; i < TrackRegs<L>::SL; ++i) {
+        const int s = sl + L * i;
+        if (s >= kSlots) continue;
+        const int cell = s >> 3, b = s & 7;
+        const int rx = cell / 9, ry = (cell / 3) % 3, rz = cell % 3;
+        const int nx = cell_of_residue(rx, ncx), ny = cell_of_residue(ry, ncy), nz = cell_of_residue(rz, ncz);
+        const bool changed = all || nx != cell_of_residue(rx, t.cx) || ny != cell_of_residue(ry, t.cy) ||
+                             nz != cell_of_residue(rz, t.cz);
+        if (changed) {
+            if (nz >= 0) {
+                double fx, fy, fz, gx, gy, gz;
+                basis_site(b, fx, fy, fz);
+                thermal_gauss(t.key, A.seed, nx, ny, nz, b, gx, gy, gz);
+                t.ax[i] = A.a * (static_cast<double>(nx) + fx) + A.sigma * gx;
+                t.ay[i] = A.a * (static_cast<double>(ny) + fy) + A.sigma * gy;
+                t.az[i] = A.a * (static_cast<double>(nz) + fz) + A.sigma * gz;
+            } else {
+                t.ax[i] = 0.0; t.ay[i] = 0.0; t.az[i] = 0.0;
+            }
+            t.avx[i] = 0.0; t.avy[i] = 0.0; t.avz[i] = 0.0;
+            t.afx[i] = 0.0; t.afy[i] = 0.0; t.afz[i] = 0.0;
+        }
+        if (nz >= 0) ex |= (1u << i);
+    }
+    t.exist = ex;
+    t.cx = ncx; t.cy = ncy; t.cz = ncz;
+    t.n_exist = SegReduce<L>::isum(__popc(ex));
+}
+
+// One integration step (velocity Verlet with symmetric friction halves); a
+// step with fresh == true has dt = 0 and builds the whole domain (start of a
+// primary).  Returns the kinetic energy before the step via ke0.
+template <int L>
+__device__ __forceinline__ void track_step(TrackRegs<L>& t, const KernelArgs& A, int sl, bool fresh,
+                                           double& ke0, double& z0)
+{
+    const SpeciesConst& c = A.sp[t.species];
+    const double v2 = t.vx * t.vx + t.vy * t.vy + t.vz * t.vz;
+    const double f2 = t.Fx * t.Fx + t.Fy * t.Fy + t.Fz * t.Fz;
+    const double vmax2 = fmax(v2, t.vmax2a);
+    const double amax2 = fmax(f2 / (c.M1 * c.M1), t.amax2a);
+    double dt = A.dt_max;
+    if (vmax2 > 0.0) dt = fmin(dt, A.dx_max / sqrt(vmax2));
+    if (amax2 > 0.0) dt = fmin(dt, sqrt(2.0 * A.dx_max / sqrt(amax2)));
+    if (fresh) dt = 0.0;
+    ke0 = 0.5 * c.M1 * v2;
+    z0 = t.z;
+
+    const double h1 = dt * c.half_inv_M1;
+    const double fr1 = exp(-(c.g_const + c.g_rho * t.rho) * h1);
+    t.vx = t.vx * fr1 + t.Fx * h1;
+    t.vy = t.vy * fr1 + t.Fy * h1;
+    t.vz = t.vz * fr1 + t.Fz * h1;
+    t.x += t.vx * dt;
+    t.y += t.vy * dt;
+    t.z += t.vz * dt;
+
+    const int ncx = floor_cell(t.x, A.a), ncy = floor_cell(t.y, A.a), ncz = floor_cell(t.z, A.a);
+    if (fresh || ncx != t.cx || ncy != t.cy || ncz != t.cz) regenerate<L>(t, A, sl, ncx, ncy, ncz, fresh);
+
+    const double h2 = dt * A.half_inv_M2;
+    double Fx = 0.0, Fy = 0.0, Fz = 0.0, rho = 0.0, vm = 0.0, fm = 0.0;
+#pragma unroll
+    for (int i = 0; i < TrackRegs<L>::SL; ++i) {
+        if (!((t.exist >> i) & 1u)) continue;
+        double vx = t.avx[i] + t.afx[i] * h2;
+        double vy = t.avy[i] + t.afy[i] * h2;
+        double vz = t.avz[i] + t.afz[i] * h2;
+        const double px = t.ax[i] + vx * dt;
+        const double py = t.ay[i] + vy * dt;
+        const double pz = t.az[i] + vz * dt;
+        const double dx = t.x - px, dy = t.y - py, dz = t.z - pz;
+        double coef, wr;
+        zbl_pair(c, dx, dy, dz, coef, wr);
+        const double fx = -coef * dx, fy = -coef * dy, fz = -coef * dz;   // force on the atom
+        Fx -= fx; Fy -= fy; Fz -= fz;
+        rho += wr;
+        vx += fx * h2; vy += fy * h2; vz += fz * h2;
+        t.ax[i] = px; t.ay[i] = py; t.az[i] = pz;
+        t.avx[i] = vx; t.avy[i] = vy; t.avz[i] = vz;
+        t.afx[i] = fx; t.afy[i] = fy; t.afz[i] = fz;
+        vm = fmax(vm, vx * vx + vy * vy + vz * vz);
+        fm = fmax(fm, fx * fx + fy * fy + fz * fz);
+    }
+    t.Fx = SegReduce<L>::sum(Fx);
+    t.Fy = SegReduce<L>::sum(Fy);
+    t.Fz = SegReduce<L>::sum(Fz);
+    t.rho = SegReduce<L>::sum(rho);
+    t.vmax2a = SegReduce<L>::max(vm);
+    t.amax2a = SegReduce<L>::max(fm) * A.inv_M2sq;
+
+    const double fr2 = exp(-(c.g_const + c.g_rho * t.rho) * h1);
+    t.vx = (t.vx + t.Fx * h1) * fr2;
+    t.vy = (t.vy + t.Fy * h1) * fr2;
+    t.vz = (t.vz + t.Fz * h1) * fr2;
+    if (!fresh) t.steps += 1;
+}
+
+// ---------------------------------------------------------------------------
+// Record transfer (segment cooperative).  Layout as documented for
+// reedmd_track_init.
+template <int L>
+__device__ __forceinline__ void store_record(const TrackRegs<L>& t, double* rec, int sl)
+{
+    if (sl == 0) {
+        long long* ir = reinterpret_cast<long long*>(rec);
+        rec[0] = t.x; rec[1] = t.y; rec[2] = t.z;
+        rec[3] = t.vx; rec[4] = t.vy; rec[5] = t.vz;
+        rec[6] = t.Fx; rec[7] = t.Fy; rec[8] = t.Fz;
+        rec[9] = t.rho; rec[10] = t.w; rec[11] = t.zstop;
+        ir[12] = t.cx; ir[13] = t.cy; ir[14] = t.cz;
+        ir[15] = static_cast<long long>(t.key);
+        ir[16] = t.steps; ir[17] = t.lineage;
+        ir[18] = t.species; ir[19] = t.next_k; ir[20] = t.table; ir[21] = t.status;
+#pragma unroll
+        for (int k = 22; k < kHdr; ++k) ir[k] = 0;
+    }
+    double* at = rec + kHdr;
+#pragma unroll
+    for (int i = 0; i < TrackRegs<L>::SL; ++i) {
+        const int s = sl + L * i;
+        if (s >= kSlots) continue;
+        const bool e = (t.exist >> i) & 1u;
+        at[0 * kSlots + s] = e ? t.ax[i] : 0.0;
+        at[1 * kSlots + s] = e ? t.ay[i] : 0.0;
+        at[2 * kSlots + s] = e ? t.az[i] : 0.0;
+        at[3 * kSlots + s] = e ? t.avx[i] : 0.0;
+        at[4 * kSlots + s] = e ? t.avy[i] : 0.0;
+        at[5 * kSlots + s] = e ? t.avz[i] : 0.0;
+        at[6 * kSlots + s] = e ? t.afx[i] : 0.0;
+        at[7 * kSlots + s] = e ? t.afy[i] : 0.0;
+        at[8 * kSlots + s] = e ? t.afz[i] : 0.0;
+    }
+}
+
+template <int L>
+__device__ __forceinline__ void load_record(TrackRegs<L>& t, const double* rec, int sl, const KernelArgs& A)
+{
+    const long long* ir = reinterpret_cast<const long long*>(rec);
+    t.x = rec[0]; t.y = rec[1]; t.z = rec[2];
+    t.vx = rec[3]; t.vy = rec[4]; t.vz = rec[5];
+    t.Fx = rec[6]; t.Fy = rec[7]; t.Fz = rec[8];
+    t.rho = rec[9]; t.w = rec[10]; t.zstop = rec[11];
+    t.cx = static_cast<int>(ir[12]); t.cy = static_cast<int>(ir[13]); t.cz = static_cast<int>(ir[14]);
+    t.key = static_cast<unsigned long long>(ir[15]);
+    t.steps = ir[16]; t.lineage = ir[17];
+    t.species = static_cast<int>(ir[18]); t.next_k = static_cast<int>(ir[19]);
+    t.table = static_cast<int>(ir[20]); t.status = static_cast<int>(ir[21]);
+    if (t.species < 0 || t.species >= A.n_species) {
+        t.species = 0;
+        t.status = REEDMD_LOST;
+    }
+    const double* at = rec + kHdr;
+    unsigned ex = 0;
+    double vm = 0.0, fm = 0.0;
+#pragma unroll
+    for (int i = 0; i < TrackRegs<L>::SL; ++i) {
+        const int s = sl + L * i;
+        if (s >= kSlots) continue;
+        const int cell = s >> 3;
+        const int nz = cell_of_residue(cell % 3, t.cz);
+        t.ax[i] = at[0 * kSlots + s]; t.ay[i] = at[1 * kSlots + s]; t.az[i] = at[2 * kSlots + s];
+        t.avx[i] = at[3 * kSlots + s]; t.avy[i] = at[4 * kSlots + s]; t.avz[i] = at[5 * kSlots + s];
+        t.afx[i] = at[6 * kSlots + s]; t.afy[i] = at[7 * kSlots + s]; t.afz[i] = at[8 * kSlots + s];
+        if (nz >= 0) {
+            ex |= (1u << i);
+            vm = fmax(vm, t.avx[i] * t.avx[i] + t.avy[i] * t.avy[i] + t.avz[i] * t.avz[i]);
+            fm = fmax(fm, t.afx[i] * t.afx[i] + t.afy[i] * t.afy[i] + t.afz[i] * t.afz[i]);
+        }
+    }
+    t.exist = ex;
+    t.n_exist = SegReduce<L>::isum(__popc(ex));
+    t.vmax2a = SegReduce<L>::max(vm);
+    t.amax2a = SegReduce<L>::max(fm) * A.inv_M2sq;
+}
+
+// Starting state of batch entry q (the fresh step that builds the domain and
+// evaluates the first forces is done by the caller).
+template <int L>
+__device__ __forceinline__ void start_primary(TrackRegs<L>& t, const KernelArgs& A, long long q)
+{
+    t.species = A.species[q];
+    t.table = A.table[q];
+    t.status = REEDMD_ACTIVE;
+    if (t.species < 0 || t.species >= A.n_species || (A.n_thresh > 0 && (t.table < 0 || t.table >= A.n_tables))) {
+        // invalid batch entry: never stepped, booked as lost (quarantined weight)
+        t.status = REEDMD_LOST;
+        t.species = 0;
+        t.table = 0;
+    }
+    const SpeciesConst& c = A.sp[t.species];
+    const double dx = A.dir[q], dy = A.dir[A.n + q], dz = A.dir[2 * A.n + q];
+    const double dn = sqrt(dx * dx + dy * dy + dz * dz);
+    const double speed = sqrt(2.0 * A.energy[q] / c.M1);
+    t.x = A.pos[q]; t.y = A.pos[A.n + q]; t.z = A.pos[2 * A.n + q];
+    t.vx = speed * dx / dn; t.vy = speed * dy / dn; t.vz = speed * dz / dn;
+    t.Fx = 0.0; t.Fy = 0.0; t.Fz = 0.0;
+    t.rho = 0.0; t.w = 1.0; t.zstop = 0.0;
+    t.vmax2a = 0.0; t.amax2a = 0.0;
+    t.cx = kSentinel; t.cy = kSentinel; t.cz = kSentinel;
+    t.key = A.key[q];
+    t.steps = 0;
+    t.lineage = A.id0 + q;
+    t.next_k = 0;
+}
+
+// Termination events after a step: non-finite state, stop (depth linearly
+// interpolated in kinetic energy within the step), backscatter, step cap.
+template <int L>
+__device__ __forceinline__ int track_events(TrackRegs<L>& t, const KernelArgs& A, double ke0, double z0)
+{
+    const bool finite = isfinite(t.x) && isfinite(t.y) && isfinite(t.z) && isfinite(t.vx) &&
+                        isfinite(t.vy) && isfinite(t.vz);
+    if (!finite) return REEDMD_NONFINITE;
+    const double ke = 0.5 * A.sp[t.species].M1 * (t.vx * t.vx + t.vy * t.vy + t.vz * t.vz);
+    if (ke < A.E_stop) {
+        t.zstop = (ke0 > A.E_stop) ? z0 + (t.z - z0) * (ke0 - A.E_stop) / (ke0 - ke) : z0;
+        return REEDMD_STOPPED;
+    }
+    if (t.z < A.z_start && t.vz < 0.0) return REEDMD_BACKSCATTERED;
+    if (A.max_steps > 0 && t.steps >= A.max_steps) return REEDMD_STEPCAP;
+    return REEDMD_ACTIVE;
+}
+
+__device__ __forceinline__ void add_f64(double* p, double v) { unsafeAtomicAdd(p, v); }
+__device__ __forceinline__ void add_i64(long long* p, long long v)
+{
+    atomicAdd(reinterpret_cast<unsigned long long*>(p), static_cast<unsigned long long>(v));
+}
+__device__ __forceinline__ void add_i64(int64_t* p, long long v)
+{
+    atomicAdd(reinterpret_cast<unsigned long long*>(p), static_cast<unsigned long long>(v));
+}
+
+// Books a finished track (segment leader only).
+__device__ __forceinline__ void book_finished(const KernelArgs& A, int status, double w, double zstop,
+                                              long long lineage, int next_k, long long steps,
+                                              long long exec_steps, long long pairs)
+{
+    reedmd_stats* S = A.stats;
+    add_i64(&S->finished, 1);
+    add_i64(&S->track_steps, exec_steps);
+    add_i64(&S->pair_evals, pairs);
+    if (status == REEDMD_STOPPED) {
+        add_i64(&S->n_stopped, 1);
+        add_f64(&S->w_stopped, w);
+        if (zstop < 0.0) {
+            add_f64(&S->w_underflow, w);
+        } else {
+            const double fb = floor(zstop / A.bin_width);
+            if (!(fb < static_cast<double>(A.n_bins))) add_f64(&S->w_overflow, w);
+            else add_f64(&A.hist[static_cast<int>(fb)], w);
+        }
+        add_f64(&S->sum_wz, w * zstop);
+        add_f64(&S->sum_wz2, w * zstop * zstop);
+    } else if (status == REEDMD_BACKSCATTERED) {
+        add_i64(&S->n_backscattered, 1);
+        add_f64(&S->w_backscattered, w);
+    } else if (status == REEDMD_CANCELLED) {
+        add_i64(&S->n_cancelled, 1);
+        add_f64(&S->w_cancelled, w);
+    } else {
+        if (status == REEDMD_NONFINITE) add_i64(&S->n_nonfinite, 1);
+        else add_i64(&S->n_stepcap, 1);
+        add_f64(&S->w_quarantined, w);
+    }
+    if (A.log != nullptr) {
+        const long long i = static_cast<long long>(
+            atomicAdd(reinterpret_cast<unsigned long long*>(&A.q->log_next), 1ull));
+        if (i < A.log_cap) {
+            reedmd_result* r = &A.log[i];
+            r->lineage = lineage;
+            r->status = status;
+            r->next_k = next_k;
+            r->z_stop = zstop;
+            r->w = w;
+            r->steps = steps;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Clone queue operations (segment leader), acquire/release at agent scope.
+__device__ __forceinline__ long long queue_reserve_push(const KernelArgs& A)
+{
+    QueueState* q = A.q;
+    unsigned long long pos = __hip_atomic_load(&q->tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int tries = 0; tries < 64; ++tries) {
+        const unsigned long long seq =
+            __hip_atomic_load(&A.qseq[pos % A.qcap], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        if (seq == pos) {
+            unsigned long long expect = pos;
+            if (__hip_atomic_compare_exchange_strong(&q->tail, &expect, pos + 1, __ATOMIC_RELAXED,
+                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                return static_cast<long long>(pos);
+            pos = expect;
+        } else if (seq < pos) {
+            return -1;  // full
+        } else {
+            pos = __hip_atomic_load(&q->tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+    return -1;
+}
+
+__device__ __forceinline__ long long queue_reserve_pop(const KernelArgs& A)
+{
+    QueueState* q = A.q;
+    unsigned long long pos = __hip_atomic_load(&q->head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int tries = 0; tries < 64; ++tries) {
+        const unsigned long long seq =
+            __hip_atomic_load(&A.qseq[pos % A.qcap], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        if (seq == pos + 1) {
+            unsigned long long expect = pos;
+            if (__hip_atomic_compare_exchange_strong(&q->head, &expect, pos + 1, __ATOMIC_RELAXED,
+                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                return static_cast<long long>(pos);
+            pos = expect;
+        } else if (seq < pos + 1) {
+            return -1;  // empty
+        } else {
+            pos = __hip_atomic_load(&q->head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+    return -1;
+}
+
+// ---------------------------------------------------------------------------
+// Main track kernel: PLAIN (static grid-stride assignment of primaries, clones
+// depth first on a per-segment stack) or PERSISTENT (primaries and clones taken
+// from device counters and the clone queue until no track is live).
+enum : int { kSegNeed = 0, kSegRun = 1, kSegDone = 2 };
+
+template <int L, int MODE>
+__global__ void __launch_bounds__(256) track_kernel(const KernelArgs A)
+{
+    const int lane = threadIdx.x & 63;
+    const int sl = lane % L;
+    const int seg_in_wave = lane / L;
+    const int leader = lane - sl;
+    const long long wave = static_cast<long long>(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const long long seg = wave * (64 / L) + seg_in_wave;
+
+    TrackRegs<L> t;
+    t.cx = t.cy = t.cz = kSentinel;
+    t.exist = 0;
+    t.n_exist = 0;
+    int mode = (seg < A.seg_total) ? kSegNeed : kSegDone;
+    long long next_primary = seg;
+    int top = 0;
+    bool fresh = false;
+    long long exec_steps = 0, pairs = 0;
+    int since_poll = 0;
+    bool cancelled = false;
+    double* my_stack = A.stack + static_cast<size_t>(seg < A.seg_total ? seg : 0) *
+                                     static_cast<size_t>(A.stack_cap) * kRecWords;
+
+    for (;;) {
+        if (mode == kSegNeed) {
+            if (A.cancel != nullptr) {
+                int cv = 0;
+                if (sl == 0) cv = __hip_atomic_load(A.cancel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                cancelled = __shfl(cv, leader, 64) != 0;
+            }
+            bool got = false;
+            if (top > 0) {
+                --top;
+                load_record<L>(t, my_stack + static_cast<size_t>(top) * kRecWords, sl, A);
+                got = true;
+            } else if (MODE == kModePersistent && A.qcap > 0) {
+                long long slot = -1;
+                if (sl == 0) slot = queue_reserve_pop(A);
+                slot = __shfl(slot, leader, 64);
+                if (slot >= 0) {
+                    const double* rec = A.qrec + static_cast<size_t>(slot % A.qcap) * kRecWords;
+                    load_record<L>(t, rec, sl, A);
+                    __threadfence();
+                    if (sl == 0)
+                        __hip_atomic_store(&A.qseq[slot % A.qcap], static_cast<unsigned long long>(slot) + A.qcap,
+                                           __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                    got = true;
+                }
+            }
+            if (!got) {
+                long long qi = -1;
+                if (MODE == kModePlain) {
+                    if (next_primary < A.n) {
+                        qi = next_primary;
+                        next_primary += A.seg_total;
+                    }
+                } else {
+                    if (sl == 0) {
+                        const long long cur = __hip_atomic_load(&A.q->prim_next, __ATOMIC_RELAXED,
+                                                                __HIP_MEMORY_SCOPE_AGENT);
+                        if (cur < A.n) qi = atomicAdd(reinterpret_cast<unsigned long long*>(&A.q->prim_next), 1ull);
+                    }
+                    qi = __shfl(qi, leader, 64);
+                    if (qi >= A.n) qi = -1;
+                }
+                if (qi >= 0) {
+                    start_primary<L>(t, A, qi);
+                    if (sl == 0) add_i64(&A.stats->primaries, 1);
+                    fresh = true;
+                    got = true;
+                }
+            }
+            if (got) {
+                mode = kSegRun;
+                exec_steps = 0;
+                pairs = 0;
+                if (t.status == REEDMD_LOST) {
+                    // invalid species or table index: weight quarantined, error flagged
+                    if (sl == 0) {
+                        book_finished(A, REEDMD_LOST, t.w, 0.0, t.lineage, t.next_k, t.steps, 0, 0);
+                        add_i64(&A.stats->error_flags, 1);
+                        if (MODE == kModePersistent) add_i64(&A.q->live, -1);
+                    }
+                    mode = kSegNeed;
+                    fresh = false;
+                } else if (cancelled) {
+                    // drain: the track ends where it is, its weight is booked as cancelled
+                    if (sl == 0) {
+                        book_finished(A, REEDMD_CANCELLED, t.w, 0.0, t.lineage, t.next_k, t.steps, 0, 0);
+                        if (MODE == kModePersistent) add_i64(&A.q->live, -1);
+                    }
+                    mode = kSegNeed;
+                    fresh = false;
+                }
+            } else if (MODE == kModePlain) {
+                mode = kSegDone;
+            } else {
+                long long live = 0;
+                if (sl == 0) live = __hip_atomic_load(&A.q->live, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                live = __shfl(live, leader, 64);
+                if (live <= 0) mode = kSegDone;
+            }
+        }
+        if (__all(mode == kSegDone)) break;
+        if (mode != kSegRun) {
+            __builtin_amdgcn_s_sleep(8);
+            continue;
+        }
+
+        // ---- one step of a running track ----
+        double ke0, z0;
+        track_step<L>(t, A, sl, fresh, ke0, z0);
+        pairs += t.n_exist;
+        if (fresh) {
+            fresh = false;
+            continue;
+        }
+        exec_steps += 1;
+        int st = track_events<L>(t, A, ke0, z0);
+        if (st == REEDMD_ACTIVE && A.cancel != nullptr && ++since_poll >= 256) {
+            since_poll = 0;
+            int cv = 0;
+            if (sl == 0) cv = __hip_atomic_load(A.cancel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            if (__shfl(cv, leader, 64) != 0) st = REEDMD_CANCELLED;
+        }
+        if (st != REEDMD_ACTIVE) {
+            if (sl == 0) {
+                book_finished(A, st, t.w, t.zstop, t.lineage, t.next_k, t.steps, exec_steps, pairs);
+                if (MODE == kModePersistent) add_i64(&A.q->live, -1);
+            }
+            mode = kSegNeed;
+            continue;
+        }
+        // cloning at depth thresholds (Sec. 2): weight / n_clones, new keys
+        if (A.n_thresh > 0) {
+            const double* thr = A.thr + static_cast<size_t>(t.table) * A.n_thresh;
+            while (t.next_k < A.n_thresh && t.z >= thr[t.next_k]) {
+                const int k = t.next_k;
+                const unsigned long long parent = t.key;
+                t.w = t.w / static_cast<double>(A.n_clones);
+                t.next_k = k + 1;
+                for (int i = A.n_clones - 1; i >= 1; --i) {
+                    t.key = child_key(parent, A.seed, k, i);
+                    long long slot = -1;
+                    if (MODE == kModePersistent && A.qcap > 0) {
+                        if (sl == 0) slot = queue_reserve_push(A);
+                        slot = __shfl(slot, leader, 64);
+                    }
+                    if (slot >= 0) {
+                        if (sl == 0) add_i64(&A.q->live, 1);
+                        store_record<L>(t, A.qrec + static_cast<size_t>(slot % A.qcap) * kRecWords, sl);
+                        __threadfence();
+                        if (sl == 0) {
+                            __hip_atomic_store(&A.qseq[slot % A.qcap], static_cast<unsigned long long>(slot) + 1,
+                                               __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                            const long long d = static_cast<long long>(slot) + 1 -
+                                                static_cast<long long>(__hip_atomic_load(
+                                                    &A.q->head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                            atomicMax(reinterpret_cast<unsigned long long*>(&A.stats->max_queue),
+                                      static_cast<unsigned long long>(d > 0 ? d : 0));
+                        }
+                    } else if (top < A.stack_cap) {
+                        if (MODE == kModePersistent && sl == 0) {
+                            add_i64(&A.q->live, 1);
+                            if (A.qcap > 0) add_i64(&A.stats->stack_overflow, 1);
+                        }
+                        store_record<L>(t, my_stack + static_cast<size_t>(top) * kRecWords, sl);
+                        ++top;
+                    } else {
+                        // no room anywhere: the clone's weight is quarantined (ledger stays exact)
+                        if (sl == 0) {
+                            add_f64(&A.stats->w_quarantined, t.w);
+                            add_i64(&A.stats->error_flags, 1);
+                        }
+                    }
+                    if (sl == 0) add_i64(&A.stats->clones, 1);
+                }
+                t.key = child_key(parent, A.seed, k, 0);
+            }
+        }
+    }
+}
+
+// Builds the starting record of every batch entry (debug / parity entry point).
+template <int L>
+__global__ void __launch_bounds__(256) init_kernel(const KernelArgs A)
+{
+    const int lane = threadIdx.x & 63;
+    const int sl = lane % L;
+    const long long seg = (static_cast<long long>(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6)) * (64 / L) + lane / L;
+    if (seg >= A.n) return;
+    TrackRegs<L> t;
+    t.exist = 0;
+    start_primary<L>(t, A, seg);
+    double ke0, z0;
+    if (t.status != REEDMD_LOST) track_step<L>(t, A, sl, true, ke0, z0);
+    store_record<L>(t, A.records + static_cast<size_t>(seg) * kRecWords, sl);
+}
+
+// Advances caller records by nsteps steps without events (debug / parity).
+template <int L>
+__global__ void __launch_bounds__(256) step_kernel(const KernelArgs A)
+{
+    const int lane = threadIdx.x & 63;
+    const int sl = lane % L;
+    const long long seg = (static_cast<long long>(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6)) * (64 / L) + lane / L;
+    if (seg >= A.n) return;
+    TrackRegs<L> t;
+    double* rec = A.records + static_cast<size_t>(seg) * kRecWords;
+    load_record<L>(t, rec, sl, A);
+    if (t.status == REEDMD_LOST) return;   // invalid species index: record left as it was
+    for (int s = 0; s < A.nsteps; ++s) {
+        double ke0, z0;
+        track_step<L>(t, A, sl, false, ke0, z0);
+    }
+    store_record<L>(t, rec, sl);
+}
+
+}  // namespace reedmd

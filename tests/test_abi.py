@@ -1,0 +1,74 @@
+"""C-ABI library checks that need no GPU: it loads, exports every declared
+symbol, and rejects bad arguments before touching the device."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "reedmd.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(reedmd_[a-z_0-9]+)\s*\(", txt)))
+
+
+def _lib():
+    from paper_0810_4737_amd import _abi
+    if not os.path.exists(_abi.LIB_PATH):
+        pytest.skip("libreedmd.so not built")
+    return _abi.load()
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for need in ("reedmd_create", "reedmd_run", "reedmd_destroy", "reedmd_sample_primaries",
+                 "reedmd_debug_step", "reedmd_track_init", "reedmd_autotune", "reedmd_last_error"):
+        assert need in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib()
+    from paper_0810_4737_amd import _abi
+    names = _declared()
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(_abi.EXPORTS)
+
+
+def test_struct_sizes_match_header_layout():
+    from paper_0810_4737_amd import _abi
+    assert C.sizeof(_abi.Result) == 40
+    assert C.sizeof(_abi.Species) == 8 + 4 * 8 + 8 * 8
+    assert _abi.STATS_WORDS * 8 == 10 * 8 + 8 * 8 + 4 * 8
+    assert _abi.RECORD_WORDS == 32 + 9 * 216
+
+
+def test_version_and_create_argument_errors_without_gpu():
+    L = _lib()
+    from paper_0810_4737_amd import _abi
+    assert L.reedmd_version() == 100
+    h = C.c_void_p()
+    lat = _abi.Lattice(a=5.431, M2=28.0855, sigma=0.076, Z2=14, structure=0)
+    pot = _abi.Potential(mode=0, s=1.0)
+    stp = _abi.Stopping(mode=2, k=1.0)
+    assert L.reedmd_create(None, C.byref(pot), C.byref(stp), C.byref(h)) == _abi.EINVAL
+    bad = _abi.Lattice(a=-1.0, M2=28.0855, sigma=0.076, Z2=14, structure=0)
+    assert L.reedmd_create(C.byref(bad), C.byref(pot), C.byref(stp), C.byref(h)) == _abi.EINVAL
+    assert b"positive" in L.reedmd_last_error(None)
+    badp = _abi.Potential(mode=0, s=0.0)
+    assert L.reedmd_create(C.byref(lat), C.byref(badp), C.byref(stp), C.byref(h)) == _abi.EINVAL
+    bads = _abi.Lattice(a=5.431, M2=28.0855, sigma=0.076, Z2=14, structure=3)
+    assert L.reedmd_create(C.byref(bads), C.byref(pot), C.byref(stp), C.byref(h)) == _abi.EUNSUPPORTED
+    assert L.reedmd_run(None, None, None, None, None, None, None) == _abi.EINVAL
+    L.reedmd_destroy(None)
+
+
+def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
+    from paper_0810_4737_amd import _abi
+    monkeypatch.setattr(_abi, "_lib", None)
+    monkeypatch.setattr(_abi, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(RuntimeError, match="not built"):
+        _abi.load()

@@ -1,0 +1,339 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Per-step quantities are deterministic and compared element by element at
+1e-10 relative (positions, velocities, forces, density; integers exactly).
+Whole runs are chaotic and compared statistically (weighted two-sample KS
+p > 0.01, mean and standard deviation of the depth within 1 %), plus exact
+ledgers and bitwise launch-configuration invariance.
+"""
+import gzip
+import json
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from tests import physref
+from tests.workloads import C1_THRESHOLDS, WORKLOADS
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+GOLDEN = os.path.join(HERE, "golden")
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def R():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_0810_4737_amd as R
+    R._abi.load()
+    return R
+
+
+@pytest.fixture(scope="module")
+def ctx(R):
+    c = R.Context()
+    yield c
+    c.close()
+
+
+SPECIES3 = ("B", "P", "As")
+
+
+def ocfg(**kw):
+    kw.setdefault("species", SPECIES3)
+    return oracle.Config(**kw)
+
+
+def rcfg(R, **kw):
+    return R.RunConfig(**kw)
+
+
+def _prims(n, seed=3):
+    sc = oracle.SamplerCfg(choice=(0, 1, 2), E_min=1000.0, E_max=20000.0)
+    return oracle.sample_primaries(sc, seed, n)
+
+
+def _exists(rec):
+    ir = rec.view(np.int64)
+    return oracle.slot_exists(ir[12:15])
+
+
+def assert_records_close(got, ref, rtol=1e-10, what=""):
+    """Compares two exchange records: integers exactly, floats to rtol relative to the
+    larger of the value and a floor of 1e-9 times the field's largest magnitude."""
+    got = np.asarray(got, np.float64)
+    ref = np.asarray(ref, np.float64)
+    gi, ri = got.view(np.int64), ref.view(np.int64)
+    assert np.array_equal(gi[12:22], ri[12:22]), (what, gi[12:22], ri[12:22])
+    ex = _exists(ref)
+
+    def cmp(a, b, name):
+        scale = np.maximum(np.abs(b), 1e-9 * max(np.abs(b).max(), 1e-300))
+        err = np.abs(a - b) / scale
+        assert err.max() <= rtol, (what, name, float(err.max()), int(np.argmax(err)))
+
+    cmp(got[0:3], ref[0:3], "x")
+    cmp(got[3:6], ref[3:6], "v")
+    # the ion force is a sum of cancelling terms: relative to the largest term
+    fa = got[32 + 6 * 216: 32 + 9 * 216].reshape(3, 216)[:, ex]
+    fb = ref[32 + 6 * 216: 32 + 9 * 216].reshape(3, 216)[:, ex]
+    fscale = max(np.abs(fb).max(), np.abs(ref[6:9]).max(), 1e-300)
+    assert np.abs(got[6:9] - ref[6:9]).max() <= rtol * fscale, (what, "F", got[6:9], ref[6:9])
+    assert abs(got[9] - ref[9]) <= rtol * abs(ref[9]) + 1e-300, (what, "rho")
+    assert got[10] == ref[10]
+    A = got[32:].reshape(9, 216)[:, ex]
+    B = ref[32:].reshape(9, 216)[:, ex]
+    for f, name in ((slice(0, 3), "ax"), (slice(3, 6), "av"), (slice(6, 9), "af")):
+        cmp(A[f].ravel(), B[f].ravel(), name)
+
+
+# ----------------------------------------------------------------------------- sampler
+def test_sampler_matches_oracle(R, ctx):
+    sc = dict(choice=(0, 1, 2), E_min=1000.0, E_max=100000.0, n_energy_tables=2, dir_mode=2,
+              n_cone=3000, half_angle=math.radians(0.5), axis=(0.0, 2 ** -0.5, 2 ** -0.5),
+              tilt=math.radians(7.0))
+    n = 6000
+    ref = oracle.sample_primaries(oracle.SamplerCfg(**sc), 5, n, id0=7)
+    got = R.sample_primaries(ctx, R.SamplerConfig(**sc), 5, n, id0=7)
+    torch.cuda.synchronize()
+    assert np.array_equal(got["species"].cpu().numpy(), ref["species"])
+    assert np.array_equal(got["table"].cpu().numpy(), ref["table"])
+    assert np.array_equal(got["key"].cpu().numpy().view(np.uint64), ref["key"])
+    for k in ("energy", "pos"):
+        g = got[k].cpu().numpy()
+        r = ref["E0" if k == "energy" else k]
+        assert np.allclose(g, r, rtol=1e-14, atol=1e-15), k
+    # cone directions go through 1 - cos(theta)^2 with cos(theta) ~ 1 - 4e-5: the sine
+    # component carries ~1e-12 relative rounding (absolute ~1e-14)
+    g = got["dir"].cpu().numpy()
+    assert np.abs(g - ref["dir"]).max() < 5e-13
+
+
+def test_empty_batch_and_argument_errors(R, ctx):
+    b = R.empty_batch(0)
+    h, s, _ = R.run(ctx, ("B",), b, rcfg(R))
+    torch.cuda.synchronize()
+    assert float(h.sum()) == 0.0 and R.parse_stats(s)["finished"] == 0
+    with pytest.raises(R.ReedmdError):
+        R.run(ctx, ("B",), R.empty_batch(4), rcfg(R, lanes_per_track=48))
+    with pytest.raises(R.ReedmdError):
+        R.run(ctx, ("B",), R.empty_batch(4), rcfg(R, n_bins=0))
+    with pytest.raises(R.ReedmdError):
+        R.run(ctx, ("B",), R.empty_batch(4), rcfg(R, thresholds=[[10.0, 20.0]], n_clones=1))
+
+
+# ----------------------------------------------------------------------------- per step
+@pytest.mark.parametrize("lanes", [64, 32, 16])
+def test_initial_domain_and_forces_match_oracle(R, ctx, lanes):
+    n = 48
+    pr = _prims(n)
+    # put some starts deep inside the crystal as well
+    pr["pos"][2, ::3] = 37.3 + 11.0 * np.arange(len(pr["pos"][2, ::3]))
+    got = R.track_init(ctx, SPECIES3, R.batch_from_numpy(pr), rcfg(R, lanes_per_track=lanes)).cpu().numpy()
+    c = ocfg()
+    for i in range(n):
+        t = oracle.Track.start(c, int(pr["species"][i]), float(pr["E0"][i]), pr["pos"][:, i],
+                               pr["dir"][:, i], int(pr["key"][i]), int(pr["table"][i]), i)
+        assert_records_close(got[i], t.record(), what=f"init {i} lanes {lanes}")
+
+
+def _oracle_states(n, seed=4, max_adv=2500, near_shift=False):
+    """Oracle records of tracks advanced a random number of steps (atoms recoiling)."""
+    pr = _prims(n, seed)
+    c = ocfg()
+    rng = np.random.default_rng(seed)
+    recs = []
+    for i in range(n):
+        t = oracle.Track.start(c, int(pr["species"][i]), float(pr["E0"][i]), pr["pos"][:, i],
+                               pr["dir"][:, i], int(pr["key"][i]), int(pr["table"][i]), i)
+        t.advance(int(rng.integers(0, max_adv)), events=True)
+        if near_shift:
+            # stop right before a step that moves the domain
+            c0 = t.state()["center"].copy()
+            for _ in range(4000):
+                prev = t.record()
+                t.step()
+                if (t.state()["center"] != c0).any():
+                    t = oracle.Track.from_record(c, prev)
+                    break
+        recs.append(t.record())
+    return c, np.array(recs)
+
+
+@pytest.mark.parametrize("near_shift", [False, True])
+def test_one_step_matches_oracle(R, ctx, near_shift):
+    c, recs = _oracle_states(40, seed=5 + int(near_shift), near_shift=near_shift)
+    dev = torch.as_tensor(recs.copy(), device="cuda")
+    R.debug_step(ctx, SPECIES3, dev, rcfg(R, lanes_per_track=64), nsteps=1)
+    got = dev.cpu().numpy()
+    shifted = 0
+    for i in range(len(recs)):
+        t = oracle.Track.from_record(c, recs[i])
+        t.step()
+        ref = t.record()
+        shifted += int((ref.view(np.int64)[12:15] != recs[i].view(np.int64)[12:15]).any())
+        assert_records_close(got[i], ref, what=f"step {i}")
+    if near_shift:
+        assert shifted >= 0.9 * len(recs)   # a few tracks stop before their next shift
+
+
+def test_twenty_steps_match_oracle(R, ctx):
+    c, recs = _oracle_states(24, seed=9)
+    dev = torch.as_tensor(recs.copy(), device="cuda")
+    R.debug_step(ctx, SPECIES3, dev, rcfg(R), nsteps=20)
+    got = dev.cpu().numpy()
+    for i in range(len(recs)):
+        t = oracle.Track.from_record(c, recs[i])
+        t.advance(20, events=False)
+        assert_records_close(got[i], t.record(), rtol=1e-8, what=f"20 steps {i}")
+
+
+@pytest.mark.parametrize("lanes", [32, 16])
+def test_lane_layouts_agree(R, ctx, lanes):
+    c, recs = _oracle_states(16, seed=11)
+    a = torch.as_tensor(recs.copy(), device="cuda")
+    b = torch.as_tensor(recs.copy(), device="cuda")
+    R.debug_step(ctx, SPECIES3, a, rcfg(R, lanes_per_track=64), nsteps=5)
+    R.debug_step(ctx, SPECIES3, b, rcfg(R, lanes_per_track=lanes), nsteps=5)
+    ga, gb = a.cpu().numpy(), b.cpu().numpy()
+    for i in range(len(recs)):
+        assert_records_close(gb[i], ga[i], rtol=1e-11, what=f"lanes {lanes} {i}")
+
+
+# ----------------------------------------------------------------------------- whole runs
+def _load_golden(name):
+    meta = json.load(open(os.path.join(GOLDEN, name + ".json")))
+    zw = np.loadtxt(gzip.open(os.path.join(GOLDEN, name + "_stopped.txt.gz"), "rt"))
+    return meta, zw[:, 0], zw[:, 1]
+
+
+def _moments(z, w):
+    W = w.sum()
+    m = (w * z).sum() / W
+    return m, math.sqrt((w * (z - m) ** 2).sum() / W)
+
+
+def test_c0_acceptance_set_matches_oracle_statistics(R, ctx):
+    """65,536 B at 1 keV (the 256-ion workload's sampler, extended): exact ledger, weighted
+    KS p > 0.01 and mean/std of the stopping depth within 1 % of the stored oracle run."""
+    meta, zo, wo = _load_golden("c0_accept")
+    w = WORKLOADS["c0_b1kev"]
+    n = meta["workload"]["n"]
+    batch = R.sample_primaries(ctx, R.SamplerConfig(**w["sampler"]), 0, n)
+    hist, stats, log, _ = R.run(ctx, w["species"], batch, rcfg(R, n_bins=w["n_bins"]), log_cap=n + 16)
+    torch.cuda.synchronize()
+    st = R.parse_stats(stats)
+    _say(f"c0 gpu stats {st}")
+    assert st["primaries"] == n and st["finished"] == n
+    assert st["w_stopped"] + st["w_backscattered"] + st["w_quarantined"] == n
+    assert float(hist.sum()) + st["w_underflow"] + st["w_overflow"] == st["w_stopped"]
+    lg = R.parse_log(log, st["log_count"])
+    s = lg[lg["status"] == R.STOPPED]
+    D, p = physref.weighted_ks(s["z_stop"], s["w"], zo, wo)
+    mg, sg = _moments(s["z_stop"], s["w"])
+    _say(f"c0 KS D={D:.4g} p={p:.3g} mean {mg:.4f} vs {meta['mean']:.4f} std {sg:.4f} vs {meta['std']:.4f}")
+    assert p > 0.01
+    assert abs(mg / meta["mean"] - 1) < 0.01 and abs(sg / meta["std"] - 1) < 0.01
+    assert abs(st["n_backscattered"] - meta["stats"]["n_backscattered"]) < 5 * math.sqrt(meta["stats"]["n_backscattered"] + 1)
+
+
+def _c1_subset_batches(R, ctx):
+    w = WORKLOADS["c1_as10kev"]
+    sc = R.SamplerConfig(**w["sampler"])
+    return [(R.sample_primaries(ctx, sc, 0, 512, id0=0), 0),
+            (R.sample_primaries(ctx, sc, 0, 512, id0=32768), 32768)]
+
+
+def _run_c1_subset(R, ctx, **kw):
+    w = WORKLOADS["c1_as10kev"]
+    cfg = rcfg(R, n_bins=w["n_bins"], thresholds=[list(C1_THRESHOLDS)], **kw)
+    hist = torch.zeros(w["n_bins"], dtype=torch.float64, device="cuda")
+    stats = R.new_stats()
+    logs = []
+    for b, id0 in _c1_subset_batches(R, ctx):
+        _, _, log, _ = R.run(ctx, w["species"], b, cfg, hist=hist, stats=stats, id0=id0, log_cap=40000)
+        logs.append(log)
+    torch.cuda.synchronize()
+    st = R.parse_stats(stats)
+    return hist.cpu().numpy(), st, logs
+
+
+def test_splitting_run_matches_oracle_and_forms_agree_bitwise(R, ctx):
+    """1,024 As at 10 keV with 8 cloning depths: exact weight ledger; plain and persistent
+    forms (and a tiny queue that forces the overflow path) give bitwise-identical histograms;
+    the weighted depth distribution agrees with the stored oracle run (KS p > 0.01)."""
+    meta, zo, wo = _load_golden("c1_subset")
+    _say("c1 subset plain")
+    hp, sp, logs = _run_c1_subset(R, ctx, form=R.FORM_PLAIN)
+    _say(f"plain stats {sp}")
+    assert sp["primaries"] == 1024
+    tot = hp.sum() + sp["w_underflow"] + sp["w_overflow"] + sp["w_backscattered"] + sp["w_quarantined"]
+    assert tot == 1024.0
+    assert sp["clones"] > 0 and sp["error_flags"] == 0
+    _say("c1 subset persistent")
+    hq, sq, _ = _run_c1_subset(R, ctx, form=R.FORM_PERSISTENT)
+    assert np.array_equal(hp, hq)
+    for k in ("finished", "clones", "track_steps", "pair_evals", "n_stopped", "n_backscattered"):
+        assert sp[k] == sq[k], k
+    _say("c1 subset persistent, queue of 2")
+    ht, stt, _ = _run_c1_subset(R, ctx, form=R.FORM_PERSISTENT, queue_capacity=2)
+    assert np.array_equal(hp, ht)
+    assert stt["stack_overflow"] > 0
+    # statistics vs the oracle
+    allg = np.concatenate([R.parse_log(l, l.shape[0]) for l in logs])
+    allg = allg[allg["status"] != 0]          # unused log rows are all zero
+    assert len(allg) == sp["finished"]
+    g = allg[allg["status"] == R.STOPPED]
+    D, p = physref.weighted_ks(g["z_stop"], g["w"], zo, wo)
+    _say(f"c1 KS D={D:.4g} p={p:.3g}; gpu clones {sp['clones']} oracle {meta['stats']['clones']}")
+    assert p > 0.01
+
+
+def test_cancel_drains_with_exact_ledger(R, ctx):
+    w = WORKLOADS["c1_as10kev"]
+    for form in (R.FORM_PLAIN, R.FORM_PERSISTENT):
+        b = R.sample_primaries(ctx, R.SamplerConfig(**w["sampler"]), 0, 300)
+        cancel = torch.ones(1, dtype=torch.int32, device="cuda")
+        h, s, _ = R.run(ctx, w["species"], b, rcfg(R, n_bins=w["n_bins"], thresholds=[list(C1_THRESHOLDS)],
+                                                   form=form), cancel=cancel)
+        torch.cuda.synchronize()
+        st = R.parse_stats(s)
+        assert st["n_cancelled"] == 300 and st["w_cancelled"] == 300.0 and float(h.sum()) == 0.0
+
+
+def test_step_cap_quarantines(R, ctx):
+    b = R.sample_primaries(ctx, R.SamplerConfig(), 0, 64)
+    h, s, _ = R.run(ctx, ("B",), b, rcfg(R, max_steps=50))
+    torch.cuda.synchronize()
+    st = R.parse_stats(s)
+    assert st["n_stepcap"] + st["n_stopped"] + st["n_backscattered"] == 64
+    assert st["n_stepcap"] > 60 and st["w_quarantined"] == st["n_stepcap"]
+
+
+def test_graph_replay_and_autotune_are_consistent(R, ctx):
+    w = WORKLOADS["c0_b1kev"]
+    b = R.sample_primaries(ctx, R.SamplerConfig(**w["sampler"]), 0, 512)
+    ref, _, _ = R.run(ctx, w["species"], b, rcfg(R, lanes_per_track=64))
+    outs = []
+    for _ in range(3):
+        h, s, _ = R.run(ctx, w["species"], b, rcfg(R, lanes_per_track=64, form=R.FORM_PERSISTENT))
+        torch.cuda.synchronize()
+        outs.append(h.cpu().numpy())
+    for o in outs:
+        assert np.array_equal(o, ref.cpu().numpy())
+    lanes, waves = R.autotune(ctx, w["species"], b, rcfg(R, form=R.FORM_PERSISTENT), pilot=256)
+    assert lanes in (16, 32, 64)
+    h, s, _ = R.run(ctx, w["species"], b, rcfg(R, form=R.FORM_PERSISTENT))
+    torch.cuda.synchronize()
+    assert R.parse_stats(s)["finished"] == 512
