@@ -32,7 +32,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--form", choices=["auto", "plain", "persistent"], default="auto")
+    ap.add_argument("--form", choices=["auto", "plain", "persistent"], default="persistent")
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--n", type=int, default=65536)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")

@@ -16,7 +16,8 @@ FORM_PLAIN, FORM_PERSISTENT = 0, 1
 DIR_TILT, DIR_CONE, DIR_MIXED = 0, 1, 2
 ACTIVE, STOPPED, BACKSCATTERED, NONFINITE, STEPCAP, CANCELLED, LOST = range(7)
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libreedmd.so")
+LIB_PATH = os.environ.get("REEDMD_LIBRARY") or \
+    os.path.join(os.path.dirname(os.path.abspath(__file__)), "libreedmd.so")
 
 
 class Lattice(C.Structure):

@@ -113,6 +113,25 @@ __device__ __forceinline__ void basis_site(int b, double& fx, double& fy, double
     fz = ((q == 1 || q == 2) ? 0.5 : 0.0) + sh;
 }
 
+// Position of a newly created atom: ideal site of basis atom b in cell
+// (nx,ny,nz) plus its thermal displacement.  Kept out of line so that the
+// rarely taken domain update does not raise the register budget of the step.
+#ifdef REEDMD_NOINLINE_CREATE
+__device__ __attribute__((noinline)) double3 create_atom(uint64_t key, uint64_t seed, int nx, int ny, int nz, int b,
+                                                          double a, double sigma)
+#else
+__device__ __forceinline__ double3 create_atom(uint64_t key, uint64_t seed, int nx, int ny, int nz, int b,
+                                                double a, double sigma)
+#endif
+{
+    double fx, fy, fz, gx, gy, gz;
+    basis_site(b, fx, fy, fz);
+    thermal_gauss(key, seed, nx, ny, nz, b, gx, gy, gz);
+    return make_double3(a * (static_cast<double>(nx) + fx) + sigma * gx,
+                        a * (static_cast<double>(ny) + fy) + sigma * gy,
+                        a * (static_cast<double>(nz) + fz) + sigma * gz);
+}
+
 // ---------------------------------------------------------------------------
 // ZBL universal screening function phi(x) = sum c_i exp(-d_i x).
 constexpr double kZc0 = 0.18175, kZc1 = 0.50986, kZc2 = 0.28022, kZc3 = 0.02817;
@@ -121,14 +140,14 @@ constexpr double kZd0 = 3.19980, kZd1 = 0.94229, kZd2 = 0.40290, kZd3 = 0.20162;
 // Pair term for an ion at separation (dx,dy,dz) = x_ion - x_atom:
 //   coef: force on the ion is coef * (dx,dy,dz) (the atom feels the opposite),
 //         coef = -V'(r) / r with V = zz phi(r/a) / r;
-//   wr:   density weight exp(-r/lambda) / (8 pi lambda^3).
-__device__ __forceinline__ void zbl_pair(const SpeciesConst& c, double dx, double dy, double dz,
-                                         double& coef, double& wr)
+//   wr:   density weight wnorm * exp(-r/lambda).
+__device__ __forceinline__ void zbl_pair(double inv_a, double zz, double inv_lambda, double wnorm, double dx,
+                                         double dy, double dz, double& coef, double& wr)
 {
     const double r2 = dx * dx + dy * dy + dz * dz;
-    const double r = sqrt(r2);
-    const double inv_r = 1.0 / r;
-    const double xs = r * c.inv_a;
+    const double inv_r = rsqrt(r2);
+    const double r = r2 * inv_r;
+    const double xs = r * inv_a;
     const double e0 = exp(-kZd0 * xs);
     const double e1 = exp(-kZd1 * xs);
     const double e2 = exp(-kZd2 * xs);
@@ -136,9 +155,9 @@ __device__ __forceinline__ void zbl_pair(const SpeciesConst& c, double dx, doubl
     const double phi = kZc0 * e0 + kZc1 * e1 + kZc2 * e2 + kZc3 * e3;
     const double dphi = -(kZc0 * kZd0 * e0 + kZc1 * kZd1 * e1 + kZc2 * kZd2 * e2 + kZc3 * kZd3 * e3);
     // V'(r) = zz (phi'(x) / (a r) - phi(x) / r^2)
-    const double dVdr = c.zz * (dphi * c.inv_a * inv_r - phi * inv_r * inv_r);
+    const double dVdr = zz * inv_r * (dphi * inv_a - phi * inv_r);
     coef = -dVdr * inv_r;
-    wr = c.wnorm * exp(-r * c.inv_lambda);
+    wr = wnorm * exp(-r * inv_lambda);
 }
 
 // The unique cell coordinate in {c-1, c, c+1} whose residue mod 3 is `res`.
@@ -147,6 +166,14 @@ __device__ __forceinline__ int cell_of_residue(int res, int c)
     int off = (res - c) % 3;
     if (off < 0) off += 3;
     return c + (off == 2 ? -1 : off);
+}
+
+// True when floor(x / a) == c for certain, decided from x * (1/a) away from the
+// cell faces; near a face the caller evaluates floor(x / a) exactly.
+__device__ __forceinline__ bool inside_cell(double x, int c, double a, double inv_a)
+{
+    const double q = x * inv_a - static_cast<double>(c);
+    return q > 1e-9 && q < 1.0 - 1e-9;
 }
 
 __device__ __forceinline__ int floor_cell(double x, double a)

@@ -149,6 +149,7 @@ void fill_common(const reedmd_ctx* ctx, const reedmd_species* sp, const reedmd_r
     prepare_species(ctx, sp, A);
     A.n_species = sp->n_species;
     A.a = ctx->lat.a;
+    A.inv_a = 1.0 / ctx->lat.a;
     A.M2 = ctx->lat.M2;
     A.sigma = ctx->lat.sigma;
     A.inv_M2sq = 1.0 / (ctx->lat.M2 * ctx->lat.M2);

@@ -17,6 +17,17 @@ namespace reedmd {
 
 enum : int { kModePlain = 0, kModePersistent = 1 };
 
+// Minimum resident wavefronts per SIMD asked of the register allocator for the
+// track kernels (the unified VGPR/AGPR file holds 512 registers per lane).
+#ifndef REEDMD_PAIR_BARRIER
+#define REEDMD_PAIR_BARRIER 0
+#endif
+#ifndef REEDMD_WAVES_PER_SIMD
+#define REEDMD_WAVES_PER_SIMD(L) ((L) == 64 ? 2 : 1)
+#endif
+
+
+
 // Clone queue (persistent form): bounded multi-producer multi-consumer ring
 // with one sequence word per slot (slot free for ticket t when seq == t, full
 // when seq == t + 1).
@@ -33,7 +44,7 @@ struct QueueState {
 struct KernelArgs {
     SpeciesConst sp[kMaxSpecies];
     // crystal
-    double a, M2, sigma, inv_M2sq, half_inv_M2;
+    double a, inv_a, M2, sigma, inv_M2sq, half_inv_M2;
     // integration and events
     double dx_max, dt_max, E_stop, z_start;
     long long max_steps;
@@ -70,25 +81,78 @@ struct KernelArgs {
     int nsteps;
 };
 
+// Species constants are staged in LDS once per workgroup (indexed per lane).
+__device__ __forceinline__ const SpeciesConst* stage_species(const KernelArgs& A, SpeciesConst* s_sp)
+{
+    static_assert(sizeof(SpeciesConst) * kMaxSpecies == 64 * sizeof(double), "species table layout");
+    if (threadIdx.x < 64)
+        reinterpret_cast<double*>(s_sp)[threadIdx.x] = reinterpret_cast<const double*>(A.sp)[threadIdx.x];
+    __syncthreads();
+    return s_sp;
+}
+
 // ---------------------------------------------------------------------------
+// Segment reductions.  Within a 16-lane row: DPP butterflies (quad permutes,
+// half-row and row mirrors); across the two rows of a 32-lane half: a
+// ds_swizzle xor 16; across the two halves of the wavefront: readlane of
+// lanes 0 and 32.  Every stage combines a value with its partner's using a
+// commutative operation, so every lane of a segment ends with bitwise the
+// same result.
+template <int CTRL>
+__device__ __forceinline__ int dpp_i32(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v)
+{
+    return __hiloint2double(dpp_i32<CTRL>(__double2hiint(v)), dpp_i32<CTRL>(__double2loint(v)));
+}
+__device__ __forceinline__ double swz16_f64(double v)
+{
+    return __hiloint2double(__builtin_amdgcn_ds_swizzle(__double2hiint(v), 0x401F),
+                            __builtin_amdgcn_ds_swizzle(__double2loint(v), 0x401F));
+}
+__device__ __forceinline__ double lane_f64(double v, int lane)
+{
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), lane),
+                            __builtin_amdgcn_readlane(__double2loint(v), lane));
+}
+constexpr int kQuadXor1 = 0xB1;      // quad_perm [1,0,3,2]
+constexpr int kQuadXor2 = 0x4E;      // quad_perm [2,3,0,1]
+constexpr int kRowHalfMirror = 0x141;
+constexpr int kRowMirror = 0x140;
+
 template <int L>
 struct SegReduce {
     __device__ __forceinline__ static double sum(double v)
     {
-#pragma unroll
-        for (int m = L / 2; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+        v += dpp_f64<kQuadXor1>(v);
+        v += dpp_f64<kQuadXor2>(v);
+        v += dpp_f64<kRowHalfMirror>(v);
+        v += dpp_f64<kRowMirror>(v);
+        if (L >= 32) v += swz16_f64(v);
+        if (L == 64) v = lane_f64(v, 0) + lane_f64(v, 32);
         return v;
     }
     __device__ __forceinline__ static double max(double v)
     {
-#pragma unroll
-        for (int m = L / 2; m >= 1; m >>= 1) v = fmax(v, __shfl_xor(v, m, 64));
+        v = fmax(v, dpp_f64<kQuadXor1>(v));
+        v = fmax(v, dpp_f64<kQuadXor2>(v));
+        v = fmax(v, dpp_f64<kRowHalfMirror>(v));
+        v = fmax(v, dpp_f64<kRowMirror>(v));
+        if (L >= 32) v = fmax(v, swz16_f64(v));
+        if (L == 64) v = fmax(lane_f64(v, 0), lane_f64(v, 32));
         return v;
     }
     __device__ __forceinline__ static int isum(int v)
     {
-#pragma unroll
-        for (int m = L / 2; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+        v += dpp_i32<kQuadXor1>(v);
+        v += dpp_i32<kQuadXor2>(v);
+        v += dpp_i32<kRowHalfMirror>(v);
+        v += dpp_i32<kRowMirror>(v);
+        if (L >= 32) v += __builtin_amdgcn_ds_swizzle(v, 0x401F);
+        if (L == 64) v = __builtin_amdgcn_readlane(v, 0) + __builtin_amdgcn_readlane(v, 32);
         return v;
     }
 };
@@ -102,12 +166,20 @@ struct TrackRegs {
     // ion (segment-uniform)
     double x, y, z, vx, vy, vz, Fx, Fy, Fz, rho, w, zstop;
     double vmax2a, amax2a;   // largest atom |v|^2 and |f/M2|^2 after the last pass
+    double thr_next;         // next cloning depth (+inf when none is left)
     int cx, cy, cz;
     unsigned long long key;
     long long steps, lineage;
     int species, next_k, table, status;
     int n_exist;             // atoms in the domain (segment-uniform)
 };
+
+template <int L>
+__device__ __forceinline__ void refresh_threshold(TrackRegs<L>& t, const KernelArgs& A)
+{
+    t.thr_next = (t.next_k < A.n_thresh) ? A.thr[static_cast<size_t>(t.table) * A.n_thresh + t.next_k]
+                                         : __builtin_huge_val();
+}
 
 template <int L>
 __device__ __forceinline__ void regenerate(TrackRegs<L>& t, const KernelArgs& A, int sl, int ncx,
@@ -125,12 +197,10 @@ __device__ __forceinline__ void regenerate(TrackRegs<L>& t, const KernelArgs& A,
                              nz != cell_of_residue(rz, t.cz);
         if (changed) {
             if (nz >= 0) {
-                double fx, fy, fz, gx, gy, gz;
-                basis_site(b, fx, fy, fz);
-                thermal_gauss(t.key, A.seed, nx, ny, nz, b, gx, gy, gz);
-                t.ax[i] = A.a * (static_cast<double>(nx) + fx) + A.sigma * gx;
-                t.ay[i] = A.a * (static_cast<double>(ny) + fy) + A.sigma * gy;
-                t.az[i] = A.a * (static_cast<double>(nz) + fz) + A.sigma * gz;
+                const double3 p = create_atom(t.key, A.seed, nx, ny, nz, b, A.a, A.sigma);
+                t.ax[i] = p.x;
+                t.ay[i] = p.y;
+                t.az[i] = p.z;
             } else {
                 t.ax[i] = 0.0; t.ay[i] = 0.0; t.az[i] = 0.0;
             }
@@ -138,6 +208,7 @@ __device__ __forceinline__ void regenerate(TrackRegs<L>& t, const KernelArgs& A,
             t.afx[i] = 0.0; t.afy[i] = 0.0; t.afz[i] = 0.0;
         }
         if (nz >= 0) ex |= (1u << i);
+        __builtin_amdgcn_sched_barrier(0);   // one slot at a time: keeps register pressure low
     }
     t.exist = ex;
     t.cx = ncx; t.cy = ncy; t.cz = ncz;
@@ -148,19 +219,20 @@ __device__ __forceinline__ void regenerate(TrackRegs<L>& t, const KernelArgs& A,
 // step with fresh == true has dt = 0 and builds the whole domain (start of a
 // primary).  Returns the kinetic energy before the step via ke0.
 template <int L>
-__device__ __forceinline__ void track_step(TrackRegs<L>& t, const KernelArgs& A, int sl, bool fresh,
-                                           double& ke0, double& z0)
+__device__ __forceinline__ void track_step(TrackRegs<L>& t, const KernelArgs& A, const SpeciesConst* sp, int sl,
+                                           bool fresh, double& ke0, double& z0)
 {
-    const SpeciesConst& c = A.sp[t.species];
+    const SpeciesConst& c = sp[t.species];
+    const double M1 = c.M1;
     const double v2 = t.vx * t.vx + t.vy * t.vy + t.vz * t.vz;
     const double f2 = t.Fx * t.Fx + t.Fy * t.Fy + t.Fz * t.Fz;
     const double vmax2 = fmax(v2, t.vmax2a);
-    const double amax2 = fmax(f2 / (c.M1 * c.M1), t.amax2a);
+    const double amax2 = fmax(f2 / (M1 * M1), t.amax2a);
     double dt = A.dt_max;
-    if (vmax2 > 0.0) dt = fmin(dt, A.dx_max / sqrt(vmax2));
-    if (amax2 > 0.0) dt = fmin(dt, sqrt(2.0 * A.dx_max / sqrt(amax2)));
+    if (vmax2 > 0.0) dt = fmin(dt, A.dx_max * rsqrt(vmax2));
+    if (amax2 > 0.0) dt = fmin(dt, sqrt(2.0 * A.dx_max * rsqrt(amax2)));
     if (fresh) dt = 0.0;
-    ke0 = 0.5 * c.M1 * v2;
+    ke0 = 0.5 * M1 * v2;
     z0 = t.z;
 
     const double h1 = dt * c.half_inv_M1;
@@ -172,9 +244,13 @@ __device__ __forceinline__ void track_step(TrackRegs<L>& t, const KernelArgs& A,
     t.y += t.vy * dt;
     t.z += t.vz * dt;
 
-    const int ncx = floor_cell(t.x, A.a), ncy = floor_cell(t.y, A.a), ncz = floor_cell(t.z, A.a);
-    if (fresh || ncx != t.cx || ncy != t.cy || ncz != t.cz) regenerate<L>(t, A, sl, ncx, ncy, ncz, fresh);
+    if (fresh || !inside_cell(t.x, t.cx, A.a, A.inv_a) || !inside_cell(t.y, t.cy, A.a, A.inv_a) ||
+        !inside_cell(t.z, t.cz, A.a, A.inv_a)) {
+        const int ncx = floor_cell(t.x, A.a), ncy = floor_cell(t.y, A.a), ncz = floor_cell(t.z, A.a);
+        if (fresh || ncx != t.cx || ncy != t.cy || ncz != t.cz) regenerate<L>(t, A, sl, ncx, ncy, ncz, fresh);
+    }
 
+    const double inv_a = c.inv_a, zz = c.zz, inv_lambda = c.inv_lambda, wnorm = c.wnorm;
     const double h2 = dt * A.half_inv_M2;
     double Fx = 0.0, Fy = 0.0, Fz = 0.0, rho = 0.0, vm = 0.0, fm = 0.0;
 #pragma unroll
@@ -188,7 +264,7 @@ __device__ __forceinline__ void track_step(TrackRegs<L>& t, const KernelArgs& A,
         const double pz = t.az[i] + vz * dt;
         const double dx = t.x - px, dy = t.y - py, dz = t.z - pz;
         double coef, wr;
-        zbl_pair(c, dx, dy, dz, coef, wr);
+        zbl_pair(inv_a, zz, inv_lambda, wnorm, dx, dy, dz, coef, wr);
         const double fx = -coef * dx, fy = -coef * dy, fz = -coef * dz;   // force on the atom
         Fx -= fx; Fy -= fy; Fz -= fz;
         rho += wr;
@@ -198,6 +274,9 @@ __device__ __forceinline__ void track_step(TrackRegs<L>& t, const KernelArgs& A,
         t.afx[i] = fx; t.afy[i] = fy; t.afz[i] = fz;
         vm = fmax(vm, vx * vx + vy * vy + vz * vz);
         fm = fmax(fm, fx * fx + fy * fy + fz * fz);
+#if REEDMD_PAIR_BARRIER
+        __builtin_amdgcn_sched_barrier(0);
+#endif
     }
     t.Fx = SegReduce<L>::sum(Fx);
     t.Fy = SegReduce<L>::sum(Fy);
@@ -294,7 +373,8 @@ __device__ __forceinline__ void load_record(TrackRegs<L>& t, const double* rec, 
 // Starting state of batch entry q (the fresh step that builds the domain and
 // evaluates the first forces is done by the caller).
 template <int L>
-__device__ __forceinline__ void start_primary(TrackRegs<L>& t, const KernelArgs& A, long long q)
+__device__ __forceinline__ void start_primary(TrackRegs<L>& t, const KernelArgs& A, const SpeciesConst* sp,
+                                              long long q)
 {
     t.species = A.species[q];
     t.table = A.table[q];
@@ -305,7 +385,7 @@ __device__ __forceinline__ void start_primary(TrackRegs<L>& t, const KernelArgs&
         t.species = 0;
         t.table = 0;
     }
-    const SpeciesConst& c = A.sp[t.species];
+    const SpeciesConst& c = sp[t.species];
     const double dx = A.dir[q], dy = A.dir[A.n + q], dz = A.dir[2 * A.n + q];
     const double dn = sqrt(dx * dx + dy * dy + dz * dz);
     const double speed = sqrt(2.0 * A.energy[q] / c.M1);
@@ -324,12 +404,13 @@ __device__ __forceinline__ void start_primary(TrackRegs<L>& t, const KernelArgs&
 // Termination events after a step: non-finite state, stop (depth linearly
 // interpolated in kinetic energy within the step), backscatter, step cap.
 template <int L>
-__device__ __forceinline__ int track_events(TrackRegs<L>& t, const KernelArgs& A, double ke0, double z0)
+__device__ __forceinline__ int track_events(TrackRegs<L>& t, const KernelArgs& A, const SpeciesConst* sp,
+                                            double ke0, double z0)
 {
     const bool finite = isfinite(t.x) && isfinite(t.y) && isfinite(t.z) && isfinite(t.vx) &&
                         isfinite(t.vy) && isfinite(t.vz);
     if (!finite) return REEDMD_NONFINITE;
-    const double ke = 0.5 * A.sp[t.species].M1 * (t.vx * t.vx + t.vy * t.vy + t.vz * t.vz);
+    const double ke = 0.5 * sp[t.species].M1 * (t.vx * t.vx + t.vy * t.vy + t.vz * t.vz);
     if (ke < A.E_stop) {
         t.zstop = (ke0 > A.E_stop) ? z0 + (t.z - z0) * (ke0 - A.E_stop) / (ke0 - ke) : z0;
         return REEDMD_STOPPED;
@@ -449,8 +530,10 @@ __device__ __forceinline__ long long queue_reserve_pop(const KernelArgs& A)
 enum : int { kSegNeed = 0, kSegRun = 1, kSegDone = 2 };
 
 template <int L, int MODE>
-__global__ void __launch_bounds__(256) track_kernel(const KernelArgs A)
+__global__ void __launch_bounds__(256, REEDMD_WAVES_PER_SIMD(L)) track_kernel(const KernelArgs A)
 {
+    __shared__ SpeciesConst s_sp[kMaxSpecies];
+    const SpeciesConst* sp = stage_species(A, s_sp);
     const int lane = threadIdx.x & 63;
     const int sl = lane % L;
     const int seg_in_wave = lane / L;
@@ -483,6 +566,7 @@ __global__ void __launch_bounds__(256) track_kernel(const KernelArgs A)
             if (top > 0) {
                 --top;
                 load_record<L>(t, my_stack + static_cast<size_t>(top) * kRecWords, sl, A);
+                refresh_threshold<L>(t, A);
                 got = true;
             } else if (MODE == kModePersistent && A.qcap > 0) {
                 long long slot = -1;
@@ -491,6 +575,7 @@ __global__ void __launch_bounds__(256) track_kernel(const KernelArgs A)
                 if (slot >= 0) {
                     const double* rec = A.qrec + static_cast<size_t>(slot % A.qcap) * kRecWords;
                     load_record<L>(t, rec, sl, A);
+                    refresh_threshold<L>(t, A);
                     __threadfence();
                     if (sl == 0)
                         __hip_atomic_store(&A.qseq[slot % A.qcap], static_cast<unsigned long long>(slot) + A.qcap,
@@ -515,7 +600,8 @@ __global__ void __launch_bounds__(256) track_kernel(const KernelArgs A)
                     if (qi >= A.n) qi = -1;
                 }
                 if (qi >= 0) {
-                    start_primary<L>(t, A, qi);
+                    start_primary<L>(t, A, sp, qi);
+                    if (t.status != REEDMD_LOST) refresh_threshold<L>(t, A);
                     if (sl == 0) add_i64(&A.stats->primaries, 1);
                     fresh = true;
                     got = true;
@@ -560,14 +646,14 @@ __global__ void __launch_bounds__(256) track_kernel(const KernelArgs A)
 
         // ---- one step of a running track ----
         double ke0, z0;
-        track_step<L>(t, A, sl, fresh, ke0, z0);
+        track_step<L>(t, A, sp, sl, fresh, ke0, z0);
         pairs += t.n_exist;
         if (fresh) {
             fresh = false;
             continue;
         }
         exec_steps += 1;
-        int st = track_events<L>(t, A, ke0, z0);
+        int st = track_events<L>(t, A, sp, ke0, z0);
         if (st == REEDMD_ACTIVE && A.cancel != nullptr && ++since_poll >= 256) {
             since_poll = 0;
             int cv = 0;
@@ -583,9 +669,8 @@ __global__ void __launch_bounds__(256) track_kernel(const KernelArgs A)
             continue;
         }
         // cloning at depth thresholds (Sec. 2): weight / n_clones, new keys
-        if (A.n_thresh > 0) {
-            const double* thr = A.thr + static_cast<size_t>(t.table) * A.n_thresh;
-            while (t.next_k < A.n_thresh && t.z >= thr[t.next_k]) {
+        if (t.z >= t.thr_next) {
+            while (t.next_k < A.n_thresh && t.z >= t.thr_next) {
                 const int k = t.next_k;
                 const unsigned long long parent = t.key;
                 t.w = t.w / static_cast<double>(A.n_clones);
@@ -627,6 +712,7 @@ __global__ void __launch_bounds__(256) track_kernel(const KernelArgs A)
                     if (sl == 0) add_i64(&A.stats->clones, 1);
                 }
                 t.key = child_key(parent, A.seed, k, 0);
+                refresh_threshold<L>(t, A);
             }
         }
     }
@@ -636,22 +722,26 @@ __global__ void __launch_bounds__(256) track_kernel(const KernelArgs A)
 template <int L>
 __global__ void __launch_bounds__(256) init_kernel(const KernelArgs A)
 {
+    __shared__ SpeciesConst s_sp[kMaxSpecies];
+    const SpeciesConst* sp = stage_species(A, s_sp);
     const int lane = threadIdx.x & 63;
     const int sl = lane % L;
     const long long seg = (static_cast<long long>(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6)) * (64 / L) + lane / L;
     if (seg >= A.n) return;
     TrackRegs<L> t;
     t.exist = 0;
-    start_primary<L>(t, A, seg);
+    start_primary<L>(t, A, sp, seg);
     double ke0, z0;
-    if (t.status != REEDMD_LOST) track_step<L>(t, A, sl, true, ke0, z0);
+    if (t.status != REEDMD_LOST) track_step<L>(t, A, sp, sl, true, ke0, z0);
     store_record<L>(t, A.records + static_cast<size_t>(seg) * kRecWords, sl);
 }
 
 // Advances caller records by nsteps steps without events (debug / parity).
 template <int L>
-__global__ void __launch_bounds__(256) step_kernel(const KernelArgs A)
+__global__ void __launch_bounds__(256, 2) step_kernel(const KernelArgs A)
 {
+    __shared__ SpeciesConst s_sp[kMaxSpecies];
+    const SpeciesConst* sp = stage_species(A, s_sp);
     const int lane = threadIdx.x & 63;
     const int sl = lane % L;
     const long long seg = (static_cast<long long>(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6)) * (64 / L) + lane / L;
@@ -662,7 +752,7 @@ __global__ void __launch_bounds__(256) step_kernel(const KernelArgs A)
     if (t.status == REEDMD_LOST) return;   // invalid species index: record left as it was
     for (int s = 0; s < A.nsteps; ++s) {
         double ke0, z0;
-        track_step<L>(t, A, sl, false, ke0, z0);
+        track_step<L>(t, A, sp, sl, false, ke0, z0);
     }
     store_record<L>(t, rec, sl);
 }
