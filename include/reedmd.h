@@ -214,7 +214,9 @@ reedmd_status reedmd_run(reedmd_ctx* ctx, const reedmd_species* species, const r
  * REEDMD_RECORD_WORDS 64-bit words).  Record layout: words 0-2 ion position,
  * 3-5 velocity, 6-8 ZBL force, 9 local density, 10 weight, 11 stopping depth,
  * 12-14 centre cell (int64), 15 key (uint64), 16 steps, 17 lineage, 18
- * species, 19 crossed thresholds, 20 table, 21 status, 22-31 zero; then nine
+ * species, 19 crossed thresholds, 20 table, 21 status, 22-23 largest atom |v|^2 and
+ * |f/M2|^2 (valid when word 24 == 1; records made elsewhere may leave 22-31 zero and the
+ * library then recomputes them), 25-31 zero; then nine
  * 216-word fields x, y, z, vx, vy, vz, fx, fy, fz of the domain atoms, slot of
  * basis atom b of cell c = ((c_x mod 3)*9 + (c_y mod 3)*3 + (c_z mod 3))*8 + b.
  * Slots of cells with c_z < 0 do not exist and hold zeros. */
@@ -228,6 +230,25 @@ reedmd_status reedmd_track_init(reedmd_ctx* ctx, const reedmd_species* species,
 reedmd_status reedmd_debug_step(reedmd_ctx* ctx, const reedmd_species* species,
                                 const reedmd_run_params* params, double* d_records, int64_t n,
                                 int32_t nsteps, hipStream_t stream);
+
+/* Derivative of the mean projected range (mean stopping depth over the tracks
+ * of the batch that stop; backscattered and capped tracks are excluded) with
+ * respect to the electronic-stopping scale k and the ZBL screening-length
+ * scale s, evaluated at (k, s) (they replace the context's values for this
+ * call).  Reverse mode: every track runs forward with a checkpoint of its full
+ * state every 64 steps, then each 64-step segment is recomputed from its
+ * checkpoint and the adjoint of its steps applied from last to first.  The
+ * derivative is pathwise: branches (active step-size term, domain updates,
+ * which step stops the ion) are held fixed, created atoms are constants.
+ * Requires params->n_thresh == 0 (EUNSUPPORTED otherwise); params->max_steps
+ * bounds the track length and the checkpoint memory (<= 0: 16,384 steps).
+ * d_track_out (device, optional, n x 5 doubles) receives per track: stopping
+ * depth, d/dk, d/ds, status, steps.  h_result (host, 4 doubles) receives the
+ * mean range, its two derivatives and the number of stopped tracks.
+ * Synchronises the stream. */
+reedmd_status reedmd_grad(reedmd_ctx* ctx, const reedmd_species* species, const reedmd_batch* batch,
+                          const reedmd_run_params* params, double k, double s, double* d_track_out,
+                          double* h_result, hipStream_t stream);
 
 /* Tries each lanes-per-track variant (and, for the persistent form, resident
  * waves per CU) on the first `pilot` primaries of the batch and records the

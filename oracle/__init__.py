@@ -19,7 +19,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = ["or_rng.c", "or_physics.c", "or_track.c", "or_run.c"]
+_SRC = ["or_rng.c", "or_physics.c", "or_track.c", "or_run.c", "or_grad.c"]
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 MAX_SPECIES = 8
@@ -130,6 +130,9 @@ def lib():
                              C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
                              C.c_void_p, P(Stats), C.c_void_p, C.c_int64, P(C.c_int64)]
         L.or_run.restype = C.c_int32
+        L.or_grad_track.argtypes = [P(Params), C.c_int32, C.c_double, P(C.c_double), P(C.c_double),
+                                    C.c_uint64, C.c_int64, P(C.c_double), P(C.c_int64)]
+        L.or_grad_track.restype = C.c_int32
         assert L.or_record_words() == RECORD_WORDS
         _lib = L
     return _lib
@@ -304,6 +307,17 @@ class Track:
     # convenient views of the exchange record
     def state(self):
         return unpack_record(self.record())
+
+
+def grad_track(cfg: Config, species, E0, pos, dir, key, max_steps=0):
+    """Forward-mode (dual number) derivative of one primary's stopping depth.
+    Returns (status, z_stop, dz/dk, dz/ds, steps)."""
+    p, keep = cfg.params()
+    out = (C.c_double * 3)()
+    st = C.c_int64(0)
+    rc = lib().or_grad_track(C.byref(p), int(species), float(E0), (C.c_double * 3)(*pos),
+                             (C.c_double * 3)(*dir), int(key), int(max_steps), out, C.byref(st))
+    return int(rc), out[0], out[1], out[2], int(st.value)
 
 
 def unpack_record(rec):

@@ -179,6 +179,11 @@ int32_t or_run(const or_params* p, int64_t n, const int32_t* species, const doub
                double* hist, or_stats* stats, or_result* log, int64_t log_cap,
                int64_t* log_count);
 
+/* forward-mode derivative of one primary's stopping depth w.r.t. (k, s); no cloning */
+int32_t or_grad_track(const or_params* p, int32_t species, double E0, const double pos[3],
+                      const double dir[3], uint64_t key, int64_t max_steps, double out[3],
+                      int64_t* steps_out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -267,3 +267,40 @@ def autotune(ctx: Context, species, batch, cfg: RunConfig, pilot: int, stream=No
     ctx.check(ctx._lib.reedmd_autotune(ctx.handle, C.byref(sp), C.byref(b), C.byref(p), int(pilot),
                                        _stream(stream), C.byref(bl), C.byref(bw)))
     return bl.value, bw.value
+
+
+def grad(ctx: Context, species, batch, cfg: RunConfig, k: float, s: float, per_track=False, stream=None):
+    """Mean projected range and its derivatives w.r.t. the stopping scale k and the screening
+    scale s (reverse mode, 64-step checkpoints).  Returns dict(mean, dk, ds, count[, tracks])."""
+    keep = []
+    p = cfg.struct(batch["energy"].device, keep)
+    sp = species_table(species) if not isinstance(species, _abi.Species) else species
+    b = _batch_struct(batch)
+    res = (C.c_double * 4)()
+    out = None
+    if per_track:
+        out = torch.zeros((int(batch["energy"].shape[0]), 5), dtype=torch.float64,
+                          device=batch["energy"].device)
+    ctx.check(ctx._lib.reedmd_grad(ctx.handle, C.byref(sp), C.byref(b), C.byref(p), float(k), float(s),
+                                   _ptr(out), res, _stream(stream)))
+    d = dict(mean=res[0], dk=res[1], ds=res[2], count=int(res[3]))
+    if per_track:
+        d["tracks"] = out
+    return d
+
+
+class ReedMDRange(torch.autograd.Function):
+    """R(k, s): mean projected range of a batch as a differentiable function of the
+    electronic-stopping scale k and the ZBL screening-length scale s (0-d float64 tensors).
+    forward runs the adjoint once and keeps both partial derivatives; backward scales them."""
+
+    @staticmethod
+    def forward(fctx, k, s, engine, species, batch, cfg):
+        r = grad(engine, species, batch, cfg, float(k.detach().cpu()), float(s.detach().cpu()))
+        fctx.save_for_backward(torch.tensor([r["dk"], r["ds"]], dtype=torch.float64, device=k.device))
+        return torch.tensor(r["mean"], dtype=torch.float64, device=k.device)
+
+    @staticmethod
+    def backward(fctx, g):
+        (d,) = fctx.saved_tensors
+        return g * d[0], g * d[1], None, None, None, None

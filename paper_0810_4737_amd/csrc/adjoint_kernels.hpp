@@ -1,0 +1,444 @@
+// Reverse-mode (adjoint) derivative of the stopping depth of each track with
+// respect to the electronic-stopping scale k and the screening-length scale s.
+//
+// One wavefront (64 lanes, the same slot layout as the track kernel) per
+// track.  Forward: the track runs to termination with the ordinary step and a
+// checkpoint of its full state every 64 steps.  Reverse: segment by segment
+// from the last, the segment is recomputed from its checkpoint (bitwise the
+// same trajectory: the stored records carry the step-size maxima) with every
+// state kept, then the adjoint of each step is applied from the last step of
+// the segment to the first.  Adjoint state per domain atom (position,
+// velocity, force) lives in VGPRs; the ion's adjoints are wavefront-uniform.
+//
+// Per step, forward (see track_step):
+//   dt = min(dt_max, dx vmax^-1, sqrt(2 dx) amax^-1/2); h1 = dt/2M1; h2 = dt/2M2
+//   v1 = v e^{-g(rho) h1} + F h1;  x1 = x + v1 dt
+//   U_j = V_j + f_j h2;  Y_j = X_j + U_j dt          (kept atoms; created atoms are constants)
+//   c_j = -V'(r_j; s)/r_j, d_j = x1 - Y_j: F' = sum c_j d_j, f'_j = -c_j d_j, rho' = sum w(r_j)
+//   V'_j = U_j + f'_j h2;  v' = (v1 + F' h1) e^{-g(rho') h1}
+// with g(rho) = g_const + g_rho rho (both proportional to k), and
+//   dc/dr = zz (3 phi'/(a r^3) - 3 phi/r^4 - phi''/(a^2 r^2)),  dc/ds = zz phi''/(s a^2 r).
+// The stopping depth z + (z1 - z)(ke0 - E)/(ke0 - ke1) of the last step seeds
+// the adjoint.  The active term of the step-size minimum and the particle that
+// attains the maximum carry the derivative of dt.
+#pragma once
+#include "track_kernels.hpp"
+
+namespace reedmd {
+
+// Adjoint of one step n (S_n -> S_{n+1}).  rn, rn1: records of S_n and S_{n+1}.
+// On entry the adjoint arrays hold the adjoint of S_{n+1}; on exit of S_n.
+struct AdjIon {
+    double xb[3], vb[3], Fb[3], rhob;
+    double kb;            // d z_stop / d k (wavefront-uniform)
+};
+
+template <int L>
+struct AdjAtoms {
+    static constexpr int SL = TrackRegs<L>::SL;
+    double Xb[3][SL], Vb[3][SL], fb[3][SL];
+};
+
+__device__ __forceinline__ void zbl_pair_adjoint(double inv_a, double zz, double inv_s, double inv_lambda,
+                                                 double wnorm, double r2, double& r, double& inv_r, double& c,
+                                                 double& c_r, double& c_s, double& w)
+{
+    inv_r = rsqrt(r2);
+    r = r2 * inv_r;
+    const double xs = r * inv_a;
+    const double e0 = exp(-kZd0 * xs);
+    const double e1 = exp(-kZd1 * xs);
+    const double e2 = exp(-kZd2 * xs);
+    const double e3 = exp(-kZd3 * xs);
+    const double phi = kZc0 * e0 + kZc1 * e1 + kZc2 * e2 + kZc3 * e3;
+    const double dphi = -(kZc0 * kZd0 * e0 + kZc1 * kZd1 * e1 + kZc2 * kZd2 * e2 + kZc3 * kZd3 * e3);
+    const double d2phi = kZc0 * kZd0 * kZd0 * e0 + kZc1 * kZd1 * kZd1 * e1 + kZc2 * kZd2 * kZd2 * e2 +
+                         kZc3 * kZd3 * kZd3 * e3;
+    const double ir2 = inv_r * inv_r;
+    // c = zz (phi/r^3 - phi'/(a r^2)), the same value the step computes as -V'(r)/r
+    const double dVdr = zz * inv_r * (dphi * inv_a - phi * inv_r);
+    c = -dVdr * inv_r;
+    c_r = zz * ir2 * (3.0 * dphi * inv_a * inv_r - 3.0 * phi * ir2 - d2phi * inv_a * inv_a);
+    c_s = zz * d2phi * inv_a * inv_a * inv_s * inv_r;
+    w = wnorm * exp(-r * inv_lambda);
+}
+
+template <int L>
+__device__ __forceinline__ void reverse_step(AdjIon& ai, AdjAtoms<L>& aa, const KernelArgs& A,
+                                             const SpeciesConst& c, const double* rn, const double* rn1,
+                                             int sl, double& sb_lane)
+{
+    constexpr int SL = TrackRegs<L>::SL;
+    const long long* irn = reinterpret_cast<const long long*>(rn);
+    const long long* irn1 = reinterpret_cast<const long long*>(rn1);
+    const double M1 = c.M1;
+    // ---- primal values of the step
+    const double v[3] = {rn[3], rn[4], rn[5]};
+    const double F[3] = {rn[6], rn[7], rn[8]};
+    const double rho = rn[9];
+    const double x1[3] = {rn1[0], rn1[1], rn1[2]};
+    const double vp[3] = {rn1[3], rn1[4], rn1[5]};
+    const double Fp[3] = {rn1[6], rn1[7], rn1[8]};
+    const double rhop = rn1[9];
+    (void)vp;
+    const int cx = static_cast<int>(irn[12]), cy = static_cast<int>(irn[13]), cz = static_cast<int>(irn[14]);
+    const int dx1 = static_cast<int>(irn1[12]), dy1 = static_cast<int>(irn1[13]), dz1 = static_cast<int>(irn1[14]);
+    const double vmax2a = rn[22], amax2a = rn[23];
+
+    const double v2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+    const double f2 = F[0] * F[0] + F[1] * F[1] + F[2] * F[2];
+    const double vmax2 = fmax(v2, vmax2a);
+    const double amax2 = fmax(f2 / (M1 * M1), amax2a);
+    double dt = A.dt_max, dtv = 0.0, dta = 0.0;
+    if (vmax2 > 0.0) { dtv = A.dx_max * rsqrt(vmax2); dt = fmin(dt, dtv); }
+    if (amax2 > 0.0) { dta = sqrt(2.0 * A.dx_max * rsqrt(amax2)); dt = fmin(dt, dta); }
+    const int branch = (amax2 > 0.0 && dt == dta) ? 2 : ((vmax2 > 0.0 && dt == dtv) ? 1 : 0);
+
+    const double h1 = dt * c.half_inv_M1;
+    const double h2 = dt * A.half_inv_M2;
+    const double g1 = c.g_const + c.g_rho * rho;
+    const double fr1 = exp(-g1 * h1);
+    double v1[3];
+    for (int k = 0; k < 3; ++k) v1[k] = v[k] * fr1 + F[k] * h1;
+    const double g2 = c.g_const + c.g_rho * rhop;
+    const double fr2 = exp(-g2 * h1);
+    double q[3];
+    for (int k = 0; k < 3; ++k) q[k] = v1[k] + Fp[k] * h1;
+
+    // ---- R9: v' = q fr2
+    double qb[3], v1b[3], Fpb[3];
+    double fr2b = 0.0, h1b = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        qb[k] = ai.vb[k] * fr2;
+        fr2b += ai.vb[k] * q[k];
+        v1b[k] = qb[k];
+        Fpb[k] = ai.Fb[k] + qb[k] * h1;
+        h1b += qb[k] * Fp[k];
+    }
+    const double g2b = -fr2b * fr2 * h1;
+    h1b += -fr2b * fr2 * g2;
+    ai.kb += g2b * (c.dg_const + c.dg_rho * rhop);
+    const double rhopb = ai.rhob + g2b * c.g_rho;
+
+    // ---- per slot: R8 (atom kick), R7 (pair term), R6 (atom drift and first kick)
+    const double inv_a = c.inv_a, zz = c.zz, inv_lambda = c.inv_lambda, wnorm = c.wnorm;
+    const double* an = rn + kHdr;
+    const double* an1 = rn1 + kHdr;
+    double x1b_l[3] = {0.0, 0.0, 0.0};
+    double dtb_l = 0.0, h2b_l = 0.0;
+    double vm_l = 0.0, fm_l = 0.0;   // slot maxima of S_n (argmax of the step-size terms)
+#pragma unroll
+    for (int i = 0; i < SL; ++i) {
+        const int s = sl + L * i;
+        double nXb[3] = {0.0, 0.0, 0.0}, nVb[3] = {0.0, 0.0, 0.0}, nfb[3] = {0.0, 0.0, 0.0};
+        if (s < kSlots) {
+            const int cell = s >> 3;
+            const int rx = cell / 9, ry = (cell / 3) % 3, rz = cell % 3;
+            const int ox = cell_of_residue(rx, cx), oy = cell_of_residue(ry, cy), oz = cell_of_residue(rz, cz);
+            const int nx = cell_of_residue(rx, dx1), ny = cell_of_residue(ry, dy1), nz = cell_of_residue(rz, dz1);
+            const bool exist_new = nz >= 0;
+            const bool kept = exist_new && nx == ox && ny == oy && nz == oz;
+            if (oz >= 0) {
+                const double Vx = an[3 * kSlots + s], Vy = an[4 * kSlots + s], Vz = an[5 * kSlots + s];
+                const double fx = an[6 * kSlots + s], fy = an[7 * kSlots + s], fz = an[8 * kSlots + s];
+                vm_l = fmax(vm_l, Vx * Vx + Vy * Vy + Vz * Vz);
+                fm_l = fmax(fm_l, fx * fx + fy * fy + fz * fz);
+            }
+            if (exist_new) {
+                const double Y[3] = {an1[0 * kSlots + s], an1[1 * kSlots + s], an1[2 * kSlots + s]};
+                const double fpj[3] = {an1[6 * kSlots + s], an1[7 * kSlots + s], an1[8 * kSlots + s]};
+                double Ub[3], fpb[3], d[3];
+                for (int k = 0; k < 3; ++k) {
+                    Ub[k] = aa.Vb[k][i];
+                    fpb[k] = aa.fb[k][i] + aa.Vb[k][i] * h2;
+                    h2b_l += aa.Vb[k][i] * fpj[k];
+                    d[k] = x1[k] - Y[k];
+                }
+                const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+                double r, inv_r, cc, c_r, c_s, w;
+                zbl_pair_adjoint(inv_a, zz, A.inv_s, inv_lambda, wnorm, r2, r, inv_r, cc, c_r, c_s, w);
+                double G[3], cb = 0.0;
+                for (int k = 0; k < 3; ++k) {
+                    G[k] = Fpb[k] - fpb[k];
+                    cb += G[k] * d[k];
+                }
+                const double rb = cb * c_r - rhopb * w * inv_lambda;
+                sb_lane += cb * c_s;
+                double Yb[3];
+                for (int k = 0; k < 3; ++k) {
+                    const double db = cc * G[k] + rb * d[k] * inv_r;
+                    x1b_l[k] += db;
+                    Yb[k] = aa.Xb[k][i] - db;
+                }
+                if (kept) {
+                    const double Xn[3] = {an[0 * kSlots + s], an[1 * kSlots + s], an[2 * kSlots + s]};
+                    const double Vn[3] = {an[3 * kSlots + s], an[4 * kSlots + s], an[5 * kSlots + s]};
+                    const double fn[3] = {an[6 * kSlots + s], an[7 * kSlots + s], an[8 * kSlots + s]};
+                    (void)Xn;
+                    for (int k = 0; k < 3; ++k) {
+                        const double U = Vn[k] + fn[k] * h2;
+                        nXb[k] = Yb[k];
+                        Ub[k] += Yb[k] * dt;
+                        dtb_l += Yb[k] * U;
+                        nVb[k] = Ub[k];
+                        nfb[k] = Ub[k] * h2;
+                        h2b_l += Ub[k] * fn[k];
+                    }
+                }
+            }
+        }
+        for (int k = 0; k < 3; ++k) {
+            aa.Xb[k][i] = nXb[k];
+            aa.Vb[k][i] = nVb[k];
+            aa.fb[k][i] = nfb[k];
+        }
+    }
+    double x1b[3];
+    for (int k = 0; k < 3; ++k) x1b[k] = ai.xb[k] + SegReduce<L>::sum(x1b_l[k]);
+    double dtb = SegReduce<L>::sum(dtb_l);
+    const double h2b = SegReduce<L>::sum(h2b_l);
+
+    // ---- R5: x1 = x + v1 dt;  R4: v1 = v fr1 + F h1;  R3: fr1 = exp(-g1 h1)
+    double fr1b = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        v1b[k] += x1b[k] * dt;
+        dtb += x1b[k] * v1[k];
+        ai.xb[k] = x1b[k];
+        ai.vb[k] = v1b[k] * fr1;
+        fr1b += v1b[k] * v[k];
+        ai.Fb[k] = v1b[k] * h1;
+        h1b += v1b[k] * F[k];
+    }
+    const double g1b = -fr1b * fr1 * h1;
+    h1b += -fr1b * fr1 * g1;
+    ai.kb += g1b * (c.dg_const + c.dg_rho * rho);
+    ai.rhob = g1b * c.g_rho;
+    dtb += h1b * c.half_inv_M1 + h2b * A.half_inv_M2;
+
+    // ---- R2/R1: the active term of the step-size minimum and its maximising particle
+    if (branch == 1) {
+        const double vmax2b = -0.5 * dtb * dt / vmax2;
+        if (v2 >= vmax2a) {
+            for (int k = 0; k < 3; ++k) ai.vb[k] += 2.0 * vmax2b * v[k];
+        } else {
+            const double vm = SegReduce<L>::max(vm_l);
+#pragma unroll
+            for (int i = 0; i < SL; ++i) {
+                const int s = sl + L * i;
+                if (s >= kSlots) continue;
+                const int oz = cell_of_residue((s >> 3) % 3, cz);
+                if (oz < 0) continue;
+                const double Vx = an[3 * kSlots + s], Vy = an[4 * kSlots + s], Vz = an[5 * kSlots + s];
+                if (Vx * Vx + Vy * Vy + Vz * Vz == vm) {
+                    aa.Vb[0][i] += 2.0 * vmax2b * Vx;
+                    aa.Vb[1][i] += 2.0 * vmax2b * Vy;
+                    aa.Vb[2][i] += 2.0 * vmax2b * Vz;
+                }
+            }
+        }
+    } else if (branch == 2) {
+        const double amax2b = -0.25 * dtb * dt / amax2;
+        if (f2 / (M1 * M1) >= amax2a) {
+            for (int k = 0; k < 3; ++k) ai.Fb[k] += 2.0 * amax2b * F[k] / (M1 * M1);
+        } else {
+            const double fm = SegReduce<L>::max(fm_l);
+#pragma unroll
+            for (int i = 0; i < SL; ++i) {
+                const int s = sl + L * i;
+                if (s >= kSlots) continue;
+                const int oz = cell_of_residue((s >> 3) % 3, cz);
+                if (oz < 0) continue;
+                const double fx = an[6 * kSlots + s], fy = an[7 * kSlots + s], fz = an[8 * kSlots + s];
+                if (fx * fx + fy * fy + fz * fz == fm) {
+                    aa.fb[0][i] += 2.0 * amax2b * fx * A.inv_M2sq;
+                    aa.fb[1][i] += 2.0 * amax2b * fy * A.inv_M2sq;
+                    aa.fb[2][i] += 2.0 * amax2b * fz * A.inv_M2sq;
+                }
+            }
+        }
+    }
+}
+
+template <int L>
+__device__ __forceinline__ void stash_adjoint(const AdjAtoms<L>& aa, double* buf, int sl)
+{
+#pragma unroll
+    for (int i = 0; i < TrackRegs<L>::SL; ++i) {
+        const int s = sl + L * i;
+        if (s >= kSlots) continue;
+        for (int k = 0; k < 3; ++k) {
+            buf[(0 + k) * kSlots + s] = aa.Xb[k][i];
+            buf[(3 + k) * kSlots + s] = aa.Vb[k][i];
+            buf[(6 + k) * kSlots + s] = aa.fb[k][i];
+        }
+    }
+}
+
+template <int L>
+__device__ __forceinline__ void unstash_adjoint(AdjAtoms<L>& aa, const double* buf, int sl)
+{
+#pragma unroll
+    for (int i = 0; i < TrackRegs<L>::SL; ++i) {
+        const int s = sl + L * i;
+        for (int k = 0; k < 3; ++k) {
+            aa.Xb[k][i] = (s < kSlots) ? buf[(0 + k) * kSlots + s] : 0.0;
+            aa.Vb[k][i] = (s < kSlots) ? buf[(3 + k) * kSlots + s] : 0.0;
+            aa.fb[k][i] = (s < kSlots) ? buf[(6 + k) * kSlots + s] : 0.0;
+        }
+    }
+}
+
+// One wavefront per primary (batch entry).  Writes gout[q] = {z_stop, dz/dk,
+// dz/ds, status, steps}; derivatives are zero unless the track stopped.
+__global__ void __launch_bounds__(256, 1) grad_kernel(const KernelArgs A)
+{
+    constexpr int L = 64;
+    __shared__ SpeciesConst s_sp[kMaxSpecies];
+    const SpeciesConst* sp = stage_species(A, s_sp);
+    const int sl = threadIdx.x & 63;
+    const long long local = static_cast<long long>(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const long long q = A.q0 + local;
+    if (q >= A.q_end) return;
+    double* ck = A.ckpt + static_cast<size_t>(local) * A.ckpt_cap * kRecWords;
+    double* sbuf = A.segbuf + static_cast<size_t>(local) * 65 * kRecWords;
+    double* abuf = A.adjbuf + static_cast<size_t>(local) * kRecWords;
+    double* out = A.gout + static_cast<size_t>(q) * 5;
+
+    TrackRegs<L> t;
+    t.exist = 0;
+    start_primary<L>(t, A, sp, q);
+    if (t.status == REEDMD_LOST) {
+        if (sl == 0) { out[0] = 0.0; out[1] = 0.0; out[2] = 0.0; out[3] = REEDMD_LOST; out[4] = 0.0; }
+        return;
+    }
+    double ke0, z0;
+    track_step<L>(t, A, sp, sl, true, ke0, z0);
+    store_record<L>(t, ck, sl);
+
+    // ---- forward with a checkpoint every 64 steps
+    int st = REEDMD_ACTIVE;
+    for (;;) {
+        track_step<L>(t, A, sp, sl, false, ke0, z0);
+        st = track_events<L>(t, A, sp, ke0, z0);
+        if (st != REEDMD_ACTIVE) break;
+        if ((t.steps & 63) == 0) {
+            const long long k = t.steps >> 6;
+            if (k >= A.ckpt_cap) { st = REEDMD_STEPCAP; break; }
+            store_record<L>(t, ck + static_cast<size_t>(k) * kRecWords, sl);
+        }
+    }
+    const long long N = t.steps;
+    if (st != REEDMD_STOPPED) {
+        if (sl == 0) { out[0] = 0.0; out[1] = 0.0; out[2] = 0.0; out[3] = st; out[4] = static_cast<double>(N); }
+        return;
+    }
+    const SpeciesConst& c = sp[t.species];
+    const double M1 = c.M1;
+    const double zstop = t.zstop;
+    // ---- seed: z_stop = z0 + (z1 - z0) theta, theta = (ke0 - E)/(ke0 - ke1)
+    const double ke1 = 0.5 * M1 * (t.vx * t.vx + t.vy * t.vy + t.vz * t.vz);
+    double z1b = 0.0, ke1b = 0.0, z0b = 1.0, ke0b = 0.0;
+    if (ke0 > A.E_stop) {
+        const double den = ke0 - ke1;
+        const double theta = (ke0 - A.E_stop) / den;
+        const double dz = t.z - z0;
+        z1b = theta;
+        z0b = 1.0 - theta;
+        ke1b = dz * (ke0 - A.E_stop) / (den * den);
+        ke0b = dz * (A.E_stop - ke1) / (den * den);
+    }
+    AdjIon ai;
+    for (int k = 0; k < 3; ++k) { ai.xb[k] = 0.0; ai.vb[k] = 0.0; ai.Fb[k] = 0.0; }
+    ai.xb[2] = z1b;
+    ai.vb[0] = ke1b * M1 * t.vx;
+    ai.vb[1] = ke1b * M1 * t.vy;
+    ai.vb[2] = ke1b * M1 * t.vz;
+    ai.rhob = 0.0;
+    ai.kb = 0.0;
+    AdjAtoms<L> aa;
+#pragma unroll
+    for (int i = 0; i < TrackRegs<L>::SL; ++i)
+        for (int k = 0; k < 3; ++k) { aa.Xb[k][i] = 0.0; aa.Vb[k][i] = 0.0; aa.fb[k][i] = 0.0; }
+    double sb_lane = 0.0;
+
+    // ---- reverse, segment by segment
+    for (long long seg = (N - 1) >> 6; seg >= 0; --seg) {
+        const long long start = seg << 6;
+        const long long end = (start + 64 < N) ? start + 64 : N;
+        stash_adjoint<L>(aa, abuf, sl);
+        load_record<L>(t, ck + static_cast<size_t>(seg) * kRecWords, sl, A);
+        store_record<L>(t, sbuf, sl);
+        for (long long n = start; n < end; ++n) {
+            track_step<L>(t, A, sp, sl, false, ke0, z0);
+            store_record<L>(t, sbuf + static_cast<size_t>(n + 1 - start) * kRecWords, sl);
+        }
+        __threadfence();   // the records just written are read back by every lane
+        unstash_adjoint<L>(aa, abuf, sl);
+        for (long long n = end - 1; n >= start; --n) {
+            const double* rn = sbuf + static_cast<size_t>(n - start) * kRecWords;
+            const double* rn1 = rn + kRecWords;
+            reverse_step<L>(ai, aa, A, c, rn, rn1, sl, sb_lane);
+            if (n == N - 1) {
+                // the stopping depth also depends on the state at the start of the last step
+                ai.xb[2] += z0b;
+                for (int k = 0; k < 3; ++k) ai.vb[k] += ke0b * M1 * rn[3 + k];
+            }
+        }
+    }
+    // ---- the starting forces depend on s (positions and velocities are constants)
+    {
+        const double* r0 = ck;
+        const double* a0 = r0 + kHdr;
+        const int cz0 = static_cast<int>(reinterpret_cast<const long long*>(r0)[14]);
+#pragma unroll
+        for (int i = 0; i < TrackRegs<L>::SL; ++i) {
+            const int s = sl + L * i;
+            if (s >= kSlots) continue;
+            if (cell_of_residue((s >> 3) % 3, cz0) < 0) continue;
+            double d[3], G[3], cb = 0.0;
+            for (int k = 0; k < 3; ++k) {
+                d[k] = r0[k] - a0[k * kSlots + s];
+                G[k] = ai.Fb[k] - aa.fb[k][i];
+                cb += G[k] * d[k];
+            }
+            const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+            double r, inv_r, cc, c_r, c_s, w;
+            zbl_pair_adjoint(c.inv_a, c.zz, A.inv_s, c.inv_lambda, c.wnorm, r2, r, inv_r, cc, c_r, c_s, w);
+            sb_lane += cb * c_s;
+        }
+    }
+    const double dzds = SegReduce<L>::sum(sb_lane);
+    if (sl == 0) {
+        out[0] = zstop;
+        out[1] = ai.kb;
+        out[2] = dzds;
+        out[3] = REEDMD_STOPPED;
+        out[4] = static_cast<double>(N);
+    }
+}
+
+// Deterministic mean over stopped tracks: res = {count, sum z, sum dz/dk, sum dz/ds}.
+__global__ void __launch_bounds__(256) grad_reduce_kernel(const double* gout, long long n, double* res)
+{
+    __shared__ double sh[4][256];
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (long long i = threadIdx.x; i < n; i += blockDim.x) {
+        const double* o = gout + static_cast<size_t>(i) * 5;
+        if (o[3] == static_cast<double>(REEDMD_STOPPED)) {
+            acc[0] += 1.0;
+            acc[1] += o[0];
+            acc[2] += o[1];
+            acc[3] += o[2];
+        }
+    }
+    for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if (threadIdx.x < w)
+            for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) res[threadIdx.x] = sh[threadIdx.x][0];
+}
+
+}  // namespace reedmd

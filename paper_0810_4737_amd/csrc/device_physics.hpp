@@ -25,6 +25,8 @@ struct SpeciesConst {
     double wnorm;         // 1 / (8 pi lambda^3)
     double g_const;       // friction: gamma = g_const + g_rho * rho
     double g_rho;
+    double dg_const;      // d g_const / d k
+    double dg_rho;        // d g_rho / d k
 };
 
 // ---------------------------------------------------------------------------

@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "../../include/reedmd.h"
+#include "adjoint_kernels.hpp"
 #include "track_kernels.hpp"
 
 using namespace reedmd;
@@ -23,6 +24,8 @@ constexpr double kCoulomb = 14.3996454784;   // e^2 / (4 pi eps0), eV A (CODATA 
 constexpr double kBohr = 0.529177210903;     // A
 constexpr int kBlock = 256;                  // 4 wavefronts per workgroup
 constexpr long long kDefaultMaxSteps = 2000000;   // step cap when the caller sets none
+constexpr long long kDefaultGradSteps = 16384;    // gradient step cap when the caller sets none
+constexpr size_t kGradScratchBytes = size_t(16) << 30;   // checkpoint memory per launch chunk
 
 thread_local std::string g_create_error;
 
@@ -40,6 +43,8 @@ struct reedmd_ctx {
     size_t scratch_bytes = 0;
     double* stack = nullptr;
     size_t stack_bytes = 0;
+    double* gscratch = nullptr;    // adjoint checkpoints, segment states, outputs
+    size_t gscratch_bytes = 0;
     // autotune cache: config hash -> (lanes, waves per CU)
     std::map<unsigned long long, std::pair<int, int>> tune;
     // captured persistent pipelines
@@ -79,7 +84,7 @@ void prepare_species(const reedmd_ctx* ctx, const reedmd_species* sp, KernelArgs
     for (int i = 0; i < kMaxSpecies; ++i) {
         SpeciesConst& c = A.sp[i];
         if (i >= sp->n_species) {
-            c = SpeciesConst{1.0, 0.5, 1.0, 0.0, 1.0, 0.0, 0.0, 0.0};
+            c = SpeciesConst{1.0, 0.5, 1.0, 0.0, 1.0, 0.0, 0.0, 0.0, 0.0, 0.0};
             continue;
         }
         const double Z1 = sp->Z1[i], M1 = sp->M1[i];
@@ -96,8 +101,16 @@ void prepare_species(const reedmd_ctx* ctx, const reedmd_species* sp, KernelArgs
         c.wnorm = 1.0 / (8.0 * M_PI * lambda * lambda * lambda);
         c.g_const = 0.0;
         c.g_rho = 0.0;
-        if (ctx->stop.mode == REEDMD_STOP_UNIFORM) c.g_const = ctx->stop.k * gamma0;
-        if (ctx->stop.mode == REEDMD_STOP_LOCAL) c.g_rho = ctx->stop.k * gamma0 / N;
+        c.dg_const = 0.0;
+        c.dg_rho = 0.0;
+        if (ctx->stop.mode == REEDMD_STOP_UNIFORM) {
+            c.g_const = ctx->stop.k * gamma0;
+            c.dg_const = gamma0;
+        }
+        if (ctx->stop.mode == REEDMD_STOP_LOCAL) {
+            c.g_rho = ctx->stop.k * gamma0 / N;
+            c.dg_rho = gamma0 / N;
+        }
     }
 }
 
@@ -529,6 +542,7 @@ void reedmd_destroy(reedmd_ctx* ctx)
     }
     if (ctx->scratch) (void)hipFree(ctx->scratch);
     if (ctx->stack) (void)hipFree(ctx->stack);
+    if (ctx->gscratch) (void)hipFree(ctx->gscratch);
     delete ctx;
 }
 
@@ -635,6 +649,78 @@ reedmd_status reedmd_debug_step(reedmd_ctx* ctx, const reedmd_species* species, 
     else if (L == 32) hipLaunchKernelGGL(step_kernel<32>, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, stream, A);
     else hipLaunchKernelGGL(step_kernel<16>, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, stream, A);
     HIP_TRY(ctx, hipGetLastError());
+    return REEDMD_OK;
+}
+
+reedmd_status reedmd_grad(reedmd_ctx* ctx, const reedmd_species* species, const reedmd_batch* batch,
+                          const reedmd_run_params* params, double k, double s, double* d_track_out,
+                          double* h_result, hipStream_t stream)
+{
+    if (!ctx) return fail(nullptr, REEDMD_EINVAL, "ctx is NULL");
+    reedmd_status st;
+    if ((st = check_species(ctx, species)) != REEDMD_OK) return st;
+    if ((st = check_batch(ctx, batch)) != REEDMD_OK) return st;
+    if ((st = check_params(ctx, params, false)) != REEDMD_OK) return st;
+    if (!h_result) return fail(ctx, REEDMD_EINVAL, "h_result is NULL");
+    if (params->n_thresh != 0) return fail(ctx, REEDMD_EUNSUPPORTED, "the gradient is defined without cloning (n_thresh = 0)");
+    if (!(k >= 0.0) || !(s > 0.0)) return fail(ctx, REEDMD_EINVAL, "need k >= 0 and s > 0");
+    for (int i = 0; i < 4; ++i) h_result[i] = 0.0;
+    const long long n = batch->n;
+    if (n == 0) return REEDMD_OK;
+    const long long max_steps = params->max_steps > 0 ? params->max_steps : kDefaultGradSteps;
+    const int ckpt_cap = static_cast<int>(max_steps / 64 + 1);
+    const size_t per_track = (static_cast<size_t>(ckpt_cap) + 65 + 1) * kRecWords * sizeof(double);
+    const long long chunk = std::max<long long>(1, std::min<long long>(n, static_cast<long long>(kGradScratchBytes / per_track)));
+    const size_t out_bytes = static_cast<size_t>(n) * 5 * sizeof(double) + 64;
+    const size_t need = static_cast<size_t>(chunk) * per_track + out_bytes;
+    if (need > ctx->gscratch_bytes) {
+        HIP_TRY(ctx, hipDeviceSynchronize());
+        if (ctx->gscratch) (void)hipFree(ctx->gscratch);
+        ctx->gscratch = nullptr;
+        ctx->gscratch_bytes = 0;
+        if (hipMalloc(reinterpret_cast<void**>(&ctx->gscratch), need) != hipSuccess) {
+            ctx->gscratch = nullptr;
+            return fail(ctx, REEDMD_ENOMEM, "cannot allocate adjoint checkpoints");
+        }
+        ctx->gscratch_bytes = need;
+    }
+    // species constants at the requested (k, s)
+    reedmd_ctx at = *ctx;
+    at.pot.s = s;
+    at.stop.k = k;
+    KernelArgs A;
+    fill_common(&at, species, params, A);
+    fill_batch(batch, A);
+    A.max_steps = max_steps;
+    A.n_thresh = 0;
+    A.inv_s = 1.0 / s;
+    A.ckpt_cap = ckpt_cap;
+    double* base = ctx->gscratch;
+    A.ckpt = base;
+    A.segbuf = base + static_cast<size_t>(chunk) * ckpt_cap * kRecWords;
+    A.adjbuf = A.segbuf + static_cast<size_t>(chunk) * 65 * kRecWords;
+    double* own_out = A.adjbuf + static_cast<size_t>(chunk) * kRecWords;
+    double* res = own_out + static_cast<size_t>(n) * 5;
+    A.gout = d_track_out ? d_track_out : own_out;
+    for (long long q0 = 0; q0 < n; q0 += chunk) {
+        A.q0 = q0;
+        A.q_end = std::min(n, q0 + chunk);
+        const long long waves = A.q_end - q0;
+        const long long blocks = (waves + 3) / 4;
+        hipLaunchKernelGGL(grad_kernel, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, stream, A);
+        HIP_TRY(ctx, hipGetLastError());
+    }
+    hipLaunchKernelGGL(grad_reduce_kernel, dim3(1), dim3(256), 0, stream, A.gout, n, res);
+    HIP_TRY(ctx, hipGetLastError());
+    double h[4];
+    HIP_TRY(ctx, hipMemcpyAsync(h, res, sizeof(h), hipMemcpyDeviceToHost, stream));
+    HIP_TRY(ctx, hipStreamSynchronize(stream));
+    if (h[0] > 0.0) {
+        h_result[0] = h[1] / h[0];
+        h_result[1] = h[2] / h[0];
+        h_result[2] = h[3] / h[0];
+    }
+    h_result[3] = h[0];
     return REEDMD_OK;
 }
 

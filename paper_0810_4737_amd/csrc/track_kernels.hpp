@@ -79,13 +79,22 @@ struct KernelArgs {
     // debug entry points
     double* records;
     int nsteps;
+    // gradient entry point
+    double inv_s;           // 1 / screening-length scale
+    double* ckpt;           // [n][ckpt_cap][kRecWords]  state every 64 steps
+    double* segbuf;         // [n][65][kRecWords]        states of the segment being reversed
+    double* adjbuf;         // [n][kRecWords]            adjoint state while a segment is recomputed
+    int ckpt_cap;
+    double* gout;           // [n][5]: z_stop, dz/dk, dz/ds, status, steps
+    long long q0, q_end;    // batch entries [q0, q_end) handled by this launch
 };
 
 // Species constants are staged in LDS once per workgroup (indexed per lane).
 __device__ __forceinline__ const SpeciesConst* stage_species(const KernelArgs& A, SpeciesConst* s_sp)
 {
-    static_assert(sizeof(SpeciesConst) * kMaxSpecies == 64 * sizeof(double), "species table layout");
-    if (threadIdx.x < 64)
+    constexpr int kWords = sizeof(SpeciesConst) * kMaxSpecies / sizeof(double);
+    static_assert(kWords <= 256, "species table staged by one workgroup");
+    if (threadIdx.x < kWords)
         reinterpret_cast<double*>(s_sp)[threadIdx.x] = reinterpret_cast<const double*>(A.sp)[threadIdx.x];
     __syncthreads();
     return s_sp;
@@ -308,8 +317,10 @@ __device__ __forceinline__ void store_record(const TrackRegs<L>& t, double* rec,
         ir[15] = static_cast<long long>(t.key);
         ir[16] = t.steps; ir[17] = t.lineage;
         ir[18] = t.species; ir[19] = t.next_k; ir[20] = t.table; ir[21] = t.status;
-#pragma unroll
-        for (int k = 22; k < kHdr; ++k) ir[k] = 0;
+        rec[22] = t.vmax2a;
+        rec[23] = t.amax2a;
+        ir[24] = 1;   // words 22-23 hold the atom speed and acceleration maxima
+        for (int k = 25; k < kHdr; ++k) ir[k] = 0;
     }
     double* at = rec + kHdr;
 #pragma unroll
@@ -366,8 +377,15 @@ __device__ __forceinline__ void load_record(TrackRegs<L>& t, const double* rec, 
     }
     t.exist = ex;
     t.n_exist = SegReduce<L>::isum(__popc(ex));
-    t.vmax2a = SegReduce<L>::max(vm);
-    t.amax2a = SegReduce<L>::max(fm) * A.inv_M2sq;
+    if (ir[24] == 1) {
+        // maxima stored by this library: reuse them so that a reloaded record continues
+        // bitwise like the track that wrote it
+        t.vmax2a = rec[22];
+        t.amax2a = rec[23];
+    } else {
+        t.vmax2a = SegReduce<L>::max(vm);
+        t.amax2a = SegReduce<L>::max(fm) * A.inv_M2sq;
+    }
 }
 
 // Starting state of batch entry q (the fresh step that builds the domain and
