@@ -37,6 +37,9 @@ def parse():
     ap.add_argument("--n", type=int, default=65536)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-grad", action="store_true", help="skip the gradient / forward time ratio")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy (HBM counter calibration)")
     return ap.parse_args()
 
 
@@ -72,6 +75,33 @@ def cpu_baseline(target_seconds):
                        f"{total_tracks / t_all:.1f} tracks/s")
 
 
+def grad_forward_ratio(R, ctx, torch):
+    """T(reedmd_grad) / T(reedmd_run) on the adjoint workload: 4,096 P at 5 keV into Si
+    [001] at 7 degree tilt, no cloning, d(mean range)/d(k, s) with a checkpoint every 64 steps."""
+    import math
+    sc = R.SamplerConfig(choice=(0,), E_min=5000.0, E_max=5000.0, tilt=math.radians(7.0))
+    b = R.sample_primaries(ctx, sc, 0, 4096)
+    cfg = R.RunConfig(max_steps=16384, lanes_per_track=64)
+    R.run(ctx, ("P",), b, cfg)
+    R.grad(ctx, ("P",), b, cfg, 1.0, 1.0)
+    torch.cuda.synchronize()
+    tf, tg = [], []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        h, st, _ = R.run(ctx, ("P",), b, cfg)
+        torch.cuda.synchronize()
+        tf.append(time.perf_counter() - t0)
+        t0 = time.perf_counter()
+        g = R.grad(ctx, ("P",), b, cfg, 1.0, 1.0)
+        torch.cuda.synchronize()
+        tg.append(time.perf_counter() - t0)
+    steps = R.parse_stats(st)["track_steps"]
+    return dict(workload="4,096 P at 5 keV, 7 deg tilt, no cloning, checkpoint every 64 steps",
+                forward_ms=1e3 * min(tf), grad_ms=1e3 * min(tg), ratio=min(tg) / min(tf),
+                steps_per_track=steps / 4096, mean_range_A=g["mean"], dR_dk=g["dk"], dR_ds=g["ds"],
+                stopped=g["count"])
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -80,6 +110,16 @@ def main():
         sys.exit(2)
     import numpy as np
     import torch
+
+    if args.copy_calibration:
+        # a plain copy of known size: reads 1 GiB and writes 1 GiB of HBM per launch
+        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": a.numel() * 8, "copy_bytes_written": b.numel() * 8, "launches": 3}))
+        return
 
     import paper_0810_4737_amd as R
     from tests.workloads import C1_THRESHOLDS, WORKLOADS
@@ -224,6 +264,10 @@ def main():
             "pairs_per_launch": pairs_per_launch,
         },
     }
+    if not args.no_grad:
+        gr = grad_forward_ratio(R, ctx, torch)
+        out["grad_fwd_ratio"] = gr["ratio"]
+        out["grad"] = gr
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(out), flush=True)

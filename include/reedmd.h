@@ -250,6 +250,12 @@ reedmd_status reedmd_grad(reedmd_ctx* ctx, const reedmd_species* species, const 
                           const reedmd_run_params* params, double k, double s, double* d_track_out,
                           double* h_result, hipStream_t stream);
 
+/* Evaluates, for y[i] >= 0 (device, n doubles), the exp(-y) that the force
+ * kernels use (Cody-Waite reduction + Taylor series to 12th order) into out
+ * (device).  For accuracy tests of the library's exponential.  Enqueued on
+ * stream; EINVAL for n < 0 or NULL arrays. */
+reedmd_status reedmd_eval_exp_neg(const double* d_y, double* d_out, int64_t n, hipStream_t stream);
+
 /* Tries each lanes-per-track variant (and, for the persistent form, resident
  * waves per CU) on the first `pilot` primaries of the batch and records the
  * fastest in the context's cache under this configuration; *best_lanes and

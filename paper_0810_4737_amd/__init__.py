@@ -304,3 +304,14 @@ class ReedMDRange(torch.autograd.Function):
     def backward(fctx, g):
         (d,) = fctx.saved_tensors
         return g * d[0], g * d[1], None, None, None, None
+
+
+def eval_exp_neg(y: torch.Tensor, stream=None):
+    """The library's exp(-y) (used by the force kernels) on a float64 device tensor."""
+    L = _abi.load()
+    y = y.contiguous()
+    out = torch.empty_like(y)
+    rc = L.reedmd_eval_exp_neg(_ptr(y), _ptr(out), int(y.numel()), _stream(stream))
+    if rc != 0:
+        raise ReedmdError(f"reedmd_eval_exp_neg failed ({rc})")
+    return out

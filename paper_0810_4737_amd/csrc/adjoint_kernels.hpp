@@ -46,10 +46,10 @@ __device__ __forceinline__ void zbl_pair_adjoint(double inv_a, double zz, double
     inv_r = rsqrt(r2);
     r = r2 * inv_r;
     const double xs = r * inv_a;
-    const double e0 = exp(-kZd0 * xs);
-    const double e1 = exp(-kZd1 * xs);
-    const double e2 = exp(-kZd2 * xs);
-    const double e3 = exp(-kZd3 * xs);
+    const double e0 = exp_neg(kZd0 * xs);
+    const double e1 = exp_neg(kZd1 * xs);
+    const double e2 = exp_neg(kZd2 * xs);
+    const double e3 = exp_neg(kZd3 * xs);
     const double phi = kZc0 * e0 + kZc1 * e1 + kZc2 * e2 + kZc3 * e3;
     const double dphi = -(kZc0 * kZd0 * e0 + kZc1 * kZd1 * e1 + kZc2 * kZd2 * e2 + kZc3 * kZd3 * e3);
     const double d2phi = kZc0 * kZd0 * kZd0 * e0 + kZc1 * kZd1 * kZd1 * e1 + kZc2 * kZd2 * kZd2 * e2 +
@@ -60,7 +60,7 @@ __device__ __forceinline__ void zbl_pair_adjoint(double inv_a, double zz, double
     c = -dVdr * inv_r;
     c_r = zz * ir2 * (3.0 * dphi * inv_a * inv_r - 3.0 * phi * ir2 - d2phi * inv_a * inv_a);
     c_s = zz * d2phi * inv_a * inv_a * inv_s * inv_r;
-    w = wnorm * exp(-r * inv_lambda);
+    w = wnorm * exp_neg(r * inv_lambda);
 }
 
 template <int L>
@@ -88,7 +88,7 @@ __device__ __forceinline__ void reverse_step(AdjIon& ai, AdjAtoms<L>& aa, const 
     const double v2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
     const double f2 = F[0] * F[0] + F[1] * F[1] + F[2] * F[2];
     const double vmax2 = fmax(v2, vmax2a);
-    const double amax2 = fmax(f2 / (M1 * M1), amax2a);
+    const double amax2 = fmax(f2 * c.inv_M1sq, amax2a);
     double dt = A.dt_max, dtv = 0.0, dta = 0.0;
     if (vmax2 > 0.0) { dtv = A.dx_max * rsqrt(vmax2); dt = fmin(dt, dtv); }
     if (amax2 > 0.0) { dta = sqrt(2.0 * A.dx_max * rsqrt(amax2)); dt = fmin(dt, dta); }
@@ -238,8 +238,8 @@ __device__ __forceinline__ void reverse_step(AdjIon& ai, AdjAtoms<L>& aa, const 
         }
     } else if (branch == 2) {
         const double amax2b = -0.25 * dtb * dt / amax2;
-        if (f2 / (M1 * M1) >= amax2a) {
-            for (int k = 0; k < 3; ++k) ai.Fb[k] += 2.0 * amax2b * F[k] / (M1 * M1);
+        if (f2 * c.inv_M1sq >= amax2a) {
+            for (int k = 0; k < 3; ++k) ai.Fb[k] += 2.0 * amax2b * F[k] * c.inv_M1sq;
         } else {
             const double fm = SegReduce<L>::max(fm_l);
 #pragma unroll
@@ -294,6 +294,7 @@ __global__ void __launch_bounds__(256, 1) grad_kernel(const KernelArgs A)
 {
     constexpr int L = 64;
     __shared__ SpeciesConst s_sp[kMaxSpecies];
+    __shared__ double s_force[ForceLds<L>::kDoubles];
     const SpeciesConst* sp = stage_species(A, s_sp);
     const int sl = threadIdx.x & 63;
     const long long local = static_cast<long long>(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
@@ -305,6 +306,7 @@ __global__ void __launch_bounds__(256, 1) grad_kernel(const KernelArgs A)
     double* out = A.gout + static_cast<size_t>(q) * 5;
 
     TrackRegs<L> t;
+    t.fl = force_slab<L>(s_force);
     t.exist = 0;
     start_primary<L>(t, A, sp, q);
     if (t.status == REEDMD_LOST) {

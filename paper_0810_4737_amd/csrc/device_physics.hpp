@@ -27,6 +27,7 @@ struct SpeciesConst {
     double g_rho;
     double dg_const;      // d g_const / d k
     double dg_rho;        // d g_rho / d k
+    double inv_M1sq;      // 1 / M1^2
 };
 
 // ---------------------------------------------------------------------------
@@ -135,6 +136,38 @@ __device__ __forceinline__ double3 create_atom(uint64_t key, uint64_t seed, int 
 }
 
 // ---------------------------------------------------------------------------
+// exp(-y) for the force kernels, written from the mathematics: Cody-Waite
+// range reduction y = n ln2 + r with ln 2 split into a double and its
+// remainder (both FMA-exact), |r| <= ln2/2, the Taylor series of e^r to r^12
+// (truncation < 2e-16 relative), and scaling by 2^n (ldexp handles the
+// gradual underflow of very small results).  No overflow or NaN handling is
+// needed: arguments are distances over positive lengths (y >= 0, bounded).
+__device__ __forceinline__ double exp_neg(double y)
+{
+    constexpr double kLog2e = 1.4426950408889634;
+    constexpr double kLn2Hi = 0x1.62e42fefa39efp-1;
+    constexpr double kLn2Lo = 0x1.abc9e3b39803fp-56;
+    const double t = -fmin(y, 1500.0);
+    const double n = rint(t * kLog2e);
+    double r = fma(-n, kLn2Hi, t);
+    r = fma(-n, kLn2Lo, r);
+    double p = 2.08767569878681e-09;            // 1/12!
+    p = fma(p, r, 2.505210838544172e-08);       // 1/11!
+    p = fma(p, r, 2.755731922398589e-07);       // 1/10!
+    p = fma(p, r, 2.7557319223985893e-06);      // 1/9!
+    p = fma(p, r, 2.48015873015873e-05);        // 1/8!
+    p = fma(p, r, 0.0001984126984126984);       // 1/7!
+    p = fma(p, r, 0.001388888888888889);        // 1/6!
+    p = fma(p, r, 0.008333333333333333);        // 1/5!
+    p = fma(p, r, 0.041666666666666664);        // 1/4!
+    p = fma(p, r, 0.16666666666666666);         // 1/3!
+    p = fma(p, r, 0.5);
+    p = fma(p, r, 1.0);
+    p = fma(p, r, 1.0);
+    return ldexp(p, static_cast<int>(n));
+}
+
+// ---------------------------------------------------------------------------
 // ZBL universal screening function phi(x) = sum c_i exp(-d_i x).
 constexpr double kZc0 = 0.18175, kZc1 = 0.50986, kZc2 = 0.28022, kZc3 = 0.02817;
 constexpr double kZd0 = 3.19980, kZd1 = 0.94229, kZd2 = 0.40290, kZd3 = 0.20162;
@@ -150,16 +183,16 @@ __device__ __forceinline__ void zbl_pair(double inv_a, double zz, double inv_lam
     const double inv_r = rsqrt(r2);
     const double r = r2 * inv_r;
     const double xs = r * inv_a;
-    const double e0 = exp(-kZd0 * xs);
-    const double e1 = exp(-kZd1 * xs);
-    const double e2 = exp(-kZd2 * xs);
-    const double e3 = exp(-kZd3 * xs);
+    const double e0 = exp_neg(kZd0 * xs);
+    const double e1 = exp_neg(kZd1 * xs);
+    const double e2 = exp_neg(kZd2 * xs);
+    const double e3 = exp_neg(kZd3 * xs);
     const double phi = kZc0 * e0 + kZc1 * e1 + kZc2 * e2 + kZc3 * e3;
     const double dphi = -(kZc0 * kZd0 * e0 + kZc1 * kZd1 * e1 + kZc2 * kZd2 * e2 + kZc3 * kZd3 * e3);
     // V'(r) = zz (phi'(x) / (a r) - phi(x) / r^2)
     const double dVdr = zz * inv_r * (dphi * inv_a - phi * inv_r);
     coef = -dVdr * inv_r;
-    wr = wnorm * exp(-r * inv_lambda);
+    wr = wnorm * exp_neg(r * inv_lambda);
 }
 
 // The unique cell coordinate in {c-1, c, c+1} whose residue mod 3 is `res`.

@@ -84,7 +84,7 @@ void prepare_species(const reedmd_ctx* ctx, const reedmd_species* sp, KernelArgs
     for (int i = 0; i < kMaxSpecies; ++i) {
         SpeciesConst& c = A.sp[i];
         if (i >= sp->n_species) {
-            c = SpeciesConst{1.0, 0.5, 1.0, 0.0, 1.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            c = SpeciesConst{1.0, 0.5, 1.0, 0.0, 1.0, 0.0, 0.0, 0.0, 0.0, 0.0, 1.0};
             continue;
         }
         const double Z1 = sp->Z1[i], M1 = sp->M1[i];
@@ -95,6 +95,7 @@ void prepare_species(const reedmd_ctx* ctx, const reedmd_species* sp, KernelArgs
         const double gamma0 = N * kL * std::sqrt(M1 / 2.0);
         c.M1 = M1;
         c.half_inv_M1 = 1.0 / (2.0 * M1);
+        c.inv_M1sq = 1.0 / (M1 * M1);
         c.inv_a = 1.0 / (ctx->pot.s * aU);
         c.zz = (ctx->pot.mode == REEDMD_POT_ZBL) ? Z1 * Z2 * kCoulomb : 0.0;
         c.inv_lambda = 1.0 / lambda;
@@ -495,6 +496,12 @@ __global__ void sample_kernel(const SamplerArgs S)
     S.key[q] = primary_key(S.seed, id);
 }
 
+__global__ void exp_neg_kernel(const double* y, double* out, long long n)
+{
+    const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = exp_neg(y[i]);
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -721,6 +728,17 @@ reedmd_status reedmd_grad(reedmd_ctx* ctx, const reedmd_species* species, const 
         h_result[2] = h[3] / h[0];
     }
     h_result[3] = h[0];
+    return REEDMD_OK;
+}
+
+reedmd_status reedmd_eval_exp_neg(const double* d_y, double* d_out, int64_t n, hipStream_t stream)
+{
+    if (n < 0 || (n > 0 && (!d_y || !d_out))) return fail(nullptr, REEDMD_EINVAL, "bad arguments");
+    if (n == 0) return REEDMD_OK;
+    hipLaunchKernelGGL(exp_neg_kernel, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, stream, d_y,
+                       d_out, static_cast<long long>(n));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(nullptr, REEDMD_EHIP, hipGetErrorString(e));
     return REEDMD_OK;
 }
 

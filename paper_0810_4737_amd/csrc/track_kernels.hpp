@@ -23,7 +23,7 @@ enum : int { kModePlain = 0, kModePersistent = 1 };
 #define REEDMD_PAIR_BARRIER 0
 #endif
 #ifndef REEDMD_WAVES_PER_SIMD
-#define REEDMD_WAVES_PER_SIMD(L) ((L) == 64 ? 2 : 1)
+#define REEDMD_WAVES_PER_SIMD(L) ((L) >= 32 ? 2 : 1)
 #endif
 
 
@@ -89,6 +89,19 @@ struct KernelArgs {
     long long q0, q_end;    // batch entries [q0, q_end) handled by this launch
 };
 
+// Per-track force arrays in LDS: [waves per workgroup][tracks per wave][3][216].
+template <int L>
+struct ForceLds {
+    static constexpr int kTracksPerBlock = 4 * (64 / L);
+    static constexpr int kDoubles = kTracksPerBlock * 3 * kSlots;
+};
+template <int L>
+__device__ __forceinline__ double* force_slab(double* s_force)
+{
+    const int track_in_block = (threadIdx.x >> 6) * (64 / L) + (threadIdx.x & 63) / L;
+    return s_force + track_in_block * 3 * kSlots;
+}
+
 // Species constants are staged in LDS once per workgroup (indexed per lane).
 __device__ __forceinline__ const SpeciesConst* stage_species(const KernelArgs& A, SpeciesConst* s_sp)
 {
@@ -110,7 +123,7 @@ __device__ __forceinline__ const SpeciesConst* stage_species(const KernelArgs& A
 template <int CTRL>
 __device__ __forceinline__ int dpp_i32(int v)
 {
-    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+    return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, true);
 }
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double v)
@@ -170,7 +183,8 @@ struct SegReduce {
 template <int L>
 struct TrackRegs {
     static constexpr int SL = (kSlots + L - 1) / L;
-    double ax[SL], ay[SL], az[SL], avx[SL], avy[SL], avz[SL], afx[SL], afy[SL], afz[SL];
+    double ax[SL], ay[SL], az[SL], avx[SL], avy[SL], avz[SL];
+    double* fl;          // LDS: this track's atom forces, [3][216] (fx, fy, fz by slot)
     unsigned exist;      // bit i: register slot i holds an existing atom
     // ion (segment-uniform)
     double x, y, z, vx, vy, vz, Fx, Fy, Fz, rho, w, zstop;
@@ -214,7 +228,7 @@ __device__ __forceinline__ void regenerate(TrackRegs<L>& t, const KernelArgs& A,
                 t.ax[i] = 0.0; t.ay[i] = 0.0; t.az[i] = 0.0;
             }
             t.avx[i] = 0.0; t.avy[i] = 0.0; t.avz[i] = 0.0;
-            t.afx[i] = 0.0; t.afy[i] = 0.0; t.afz[i] = 0.0;
+            t.fl[0 * kSlots + s] = 0.0; t.fl[1 * kSlots + s] = 0.0; t.fl[2 * kSlots + s] = 0.0;
         }
         if (nz >= 0) ex |= (1u << i);
         __builtin_amdgcn_sched_barrier(0);   // one slot at a time: keeps register pressure low
@@ -236,7 +250,7 @@ __device__ __forceinline__ void track_step(TrackRegs<L>& t, const KernelArgs& A,
     const double v2 = t.vx * t.vx + t.vy * t.vy + t.vz * t.vz;
     const double f2 = t.Fx * t.Fx + t.Fy * t.Fy + t.Fz * t.Fz;
     const double vmax2 = fmax(v2, t.vmax2a);
-    const double amax2 = fmax(f2 / (M1 * M1), t.amax2a);
+    const double amax2 = fmax(f2 * c.inv_M1sq, t.amax2a);
     double dt = A.dt_max;
     if (vmax2 > 0.0) dt = fmin(dt, A.dx_max * rsqrt(vmax2));
     if (amax2 > 0.0) dt = fmin(dt, sqrt(2.0 * A.dx_max * rsqrt(amax2)));
@@ -265,9 +279,10 @@ __device__ __forceinline__ void track_step(TrackRegs<L>& t, const KernelArgs& A,
 #pragma unroll
     for (int i = 0; i < TrackRegs<L>::SL; ++i) {
         if (!((t.exist >> i) & 1u)) continue;
-        double vx = t.avx[i] + t.afx[i] * h2;
-        double vy = t.avy[i] + t.afy[i] * h2;
-        double vz = t.avz[i] + t.afz[i] * h2;
+        const int s = sl + L * i;
+        double vx = t.avx[i] + t.fl[0 * kSlots + s] * h2;
+        double vy = t.avy[i] + t.fl[1 * kSlots + s] * h2;
+        double vz = t.avz[i] + t.fl[2 * kSlots + s] * h2;
         const double px = t.ax[i] + vx * dt;
         const double py = t.ay[i] + vy * dt;
         const double pz = t.az[i] + vz * dt;
@@ -280,7 +295,7 @@ __device__ __forceinline__ void track_step(TrackRegs<L>& t, const KernelArgs& A,
         vx += fx * h2; vy += fy * h2; vz += fz * h2;
         t.ax[i] = px; t.ay[i] = py; t.az[i] = pz;
         t.avx[i] = vx; t.avy[i] = vy; t.avz[i] = vz;
-        t.afx[i] = fx; t.afy[i] = fy; t.afz[i] = fz;
+        t.fl[0 * kSlots + s] = fx; t.fl[1 * kSlots + s] = fy; t.fl[2 * kSlots + s] = fz;
         vm = fmax(vm, vx * vx + vy * vy + vz * vz);
         fm = fmax(fm, fx * fx + fy * fy + fz * fz);
 #if REEDMD_PAIR_BARRIER
@@ -334,9 +349,9 @@ __device__ __forceinline__ void store_record(const TrackRegs<L>& t, double* rec,
         at[3 * kSlots + s] = e ? t.avx[i] : 0.0;
         at[4 * kSlots + s] = e ? t.avy[i] : 0.0;
         at[5 * kSlots + s] = e ? t.avz[i] : 0.0;
-        at[6 * kSlots + s] = e ? t.afx[i] : 0.0;
-        at[7 * kSlots + s] = e ? t.afy[i] : 0.0;
-        at[8 * kSlots + s] = e ? t.afz[i] : 0.0;
+        at[6 * kSlots + s] = e ? t.fl[0 * kSlots + s] : 0.0;
+        at[7 * kSlots + s] = e ? t.fl[1 * kSlots + s] : 0.0;
+        at[8 * kSlots + s] = e ? t.fl[2 * kSlots + s] : 0.0;
     }
 }
 
@@ -368,11 +383,12 @@ __device__ __forceinline__ void load_record(TrackRegs<L>& t, const double* rec, 
         const int nz = cell_of_residue(cell % 3, t.cz);
         t.ax[i] = at[0 * kSlots + s]; t.ay[i] = at[1 * kSlots + s]; t.az[i] = at[2 * kSlots + s];
         t.avx[i] = at[3 * kSlots + s]; t.avy[i] = at[4 * kSlots + s]; t.avz[i] = at[5 * kSlots + s];
-        t.afx[i] = at[6 * kSlots + s]; t.afy[i] = at[7 * kSlots + s]; t.afz[i] = at[8 * kSlots + s];
+        const double fx = at[6 * kSlots + s], fy = at[7 * kSlots + s], fz = at[8 * kSlots + s];
+        t.fl[0 * kSlots + s] = fx; t.fl[1 * kSlots + s] = fy; t.fl[2 * kSlots + s] = fz;
         if (nz >= 0) {
             ex |= (1u << i);
             vm = fmax(vm, t.avx[i] * t.avx[i] + t.avy[i] * t.avy[i] + t.avz[i] * t.avz[i]);
-            fm = fmax(fm, t.afx[i] * t.afx[i] + t.afy[i] * t.afy[i] + t.afz[i] * t.afz[i]);
+            fm = fmax(fm, fx * fx + fy * fy + fz * fz);
         }
     }
     t.exist = ex;
@@ -551,6 +567,7 @@ template <int L, int MODE>
 __global__ void __launch_bounds__(256, REEDMD_WAVES_PER_SIMD(L)) track_kernel(const KernelArgs A)
 {
     __shared__ SpeciesConst s_sp[kMaxSpecies];
+    __shared__ double s_force[ForceLds<L>::kDoubles];
     const SpeciesConst* sp = stage_species(A, s_sp);
     const int lane = threadIdx.x & 63;
     const int sl = lane % L;
@@ -560,6 +577,7 @@ __global__ void __launch_bounds__(256, REEDMD_WAVES_PER_SIMD(L)) track_kernel(co
     const long long seg = wave * (64 / L) + seg_in_wave;
 
     TrackRegs<L> t;
+    t.fl = force_slab<L>(s_force);
     t.cx = t.cy = t.cz = kSentinel;
     t.exist = 0;
     t.n_exist = 0;
@@ -741,12 +759,14 @@ template <int L>
 __global__ void __launch_bounds__(256) init_kernel(const KernelArgs A)
 {
     __shared__ SpeciesConst s_sp[kMaxSpecies];
+    __shared__ double s_force[ForceLds<L>::kDoubles];
     const SpeciesConst* sp = stage_species(A, s_sp);
     const int lane = threadIdx.x & 63;
     const int sl = lane % L;
     const long long seg = (static_cast<long long>(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6)) * (64 / L) + lane / L;
     if (seg >= A.n) return;
     TrackRegs<L> t;
+    t.fl = force_slab<L>(s_force);
     t.exist = 0;
     start_primary<L>(t, A, sp, seg);
     double ke0, z0;
@@ -759,12 +779,14 @@ template <int L>
 __global__ void __launch_bounds__(256, 2) step_kernel(const KernelArgs A)
 {
     __shared__ SpeciesConst s_sp[kMaxSpecies];
+    __shared__ double s_force[ForceLds<L>::kDoubles];
     const SpeciesConst* sp = stage_species(A, s_sp);
     const int lane = threadIdx.x & 63;
     const int sl = lane % L;
     const long long seg = (static_cast<long long>(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6)) * (64 / L) + lane / L;
     if (seg >= A.n) return;
     TrackRegs<L> t;
+    t.fl = force_slab<L>(s_force);
     double* rec = A.records + static_cast<size_t>(seg) * kRecWords;
     load_record<L>(t, rec, sl, A);
     if (t.status == REEDMD_LOST) return;   // invalid species index: record left as it was

@@ -98,6 +98,20 @@ def assert_records_close(got, ref, rtol=1e-10, what=""):
         cmp(A[f].ravel(), B[f].ravel(), name)
 
 
+# ----------------------------------------------------------------------------- exp
+def test_library_exponential_is_accurate(R):
+    """The kernels' exp(-y) (Cody-Waite + Taylor) against numpy's exp: <= 4 ulp relative over
+    the argument range of the force terms, and the gradual-underflow tail."""
+    y = np.concatenate([np.linspace(0.0, 50.0, 200001), np.geomspace(1e-12, 700.0, 100001),
+                        np.linspace(700.0, 745.0, 1001)])
+    got = R.eval_exp_neg(torch.as_tensor(y, device="cuda")).cpu().numpy()
+    ref = np.exp(-y)
+    normal = ref > 2.3e-308
+    rel = np.abs(got[normal] - ref[normal]) / ref[normal]
+    assert rel.max() <= 4 * 2.0**-52, rel.max()
+    assert np.all(np.abs(got[~normal] - ref[~normal]) <= 4 * 5e-324)
+
+
 # ----------------------------------------------------------------------------- sampler
 def test_sampler_matches_oracle(R, ctx):
     sc = dict(choice=(0, 1, 2), E_min=1000.0, E_max=100000.0, n_energy_tables=2, dir_mode=2,
