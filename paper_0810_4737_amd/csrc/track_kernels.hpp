@@ -89,6 +89,25 @@ struct KernelArgs {
     long long q0, q_end;    // batch entries [q0, q_end) handled by this launch
 };
 
+// Rarely used kernel arguments are re-read from the kernel-argument segment
+// where they are needed (every kernel of this file takes one KernelArgs by
+// value, which sits at offset 0 of that segment).  The empty asm makes the
+// pointer opaque, so the compiler cannot hoist those scalar loads out of the
+// step loop into scalar registers, which otherwise spill into vector-register
+// lanes inside the hot loop.
+typedef const __attribute__((address_space(4))) unsigned long long KernargWord;
+__device__ __forceinline__ KernelArgs cold_args()
+{
+    static_assert(sizeof(KernelArgs) % 8 == 0, "argument block is copied in 64-bit words");
+    KernargWord* p = (KernargWord*)(__builtin_amdgcn_kernarg_segment_ptr());
+    asm volatile("" : "+s"(p));
+    KernelArgs a;
+    unsigned long long* d = reinterpret_cast<unsigned long long*>(&a);
+#pragma unroll
+    for (int i = 0; i < static_cast<int>(sizeof(KernelArgs) / 8); ++i) d[i] = p[i];
+    return a;
+}
+
 // Per-track force arrays in LDS: [waves per workgroup][tracks per wave][3][216].
 template <int L>
 struct ForceLds {
@@ -220,7 +239,8 @@ __device__ __forceinline__ void regenerate(TrackRegs<L>& t, const KernelArgs& A,
                              nz != cell_of_residue(rz, t.cz);
         if (changed) {
             if (nz >= 0) {
-                const double3 p = create_atom(t.key, A.seed, nx, ny, nz, b, A.a, A.sigma);
+                const KernelArgs C = cold_args();
+                const double3 p = create_atom(t.key, C.seed, nx, ny, nz, b, C.a, C.sigma);
                 t.ax[i] = p.x;
                 t.ay[i] = p.y;
                 t.az[i] = p.z;
@@ -564,8 +584,9 @@ __device__ __forceinline__ long long queue_reserve_pop(const KernelArgs& A)
 enum : int { kSegNeed = 0, kSegRun = 1, kSegDone = 2 };
 
 template <int L, int MODE>
-__global__ void __launch_bounds__(256, REEDMD_WAVES_PER_SIMD(L)) track_kernel(const KernelArgs A)
+__global__ void __launch_bounds__(256, REEDMD_WAVES_PER_SIMD(L)) track_kernel(const KernelArgs A0)
 {
+    const KernelArgs& A = A0;
     __shared__ SpeciesConst s_sp[kMaxSpecies];
     __shared__ double s_force[ForceLds<L>::kDoubles];
     const SpeciesConst* sp = stage_species(A, s_sp);
@@ -593,6 +614,7 @@ __global__ void __launch_bounds__(256, REEDMD_WAVES_PER_SIMD(L)) track_kernel(co
 
     for (;;) {
         if (mode == kSegNeed) {
+            const KernelArgs A = cold_args();
             if (A.cancel != nullptr) {
                 int cv = 0;
                 if (sl == 0) cv = __hip_atomic_load(A.cancel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
@@ -690,13 +712,17 @@ __global__ void __launch_bounds__(256, REEDMD_WAVES_PER_SIMD(L)) track_kernel(co
         }
         exec_steps += 1;
         int st = track_events<L>(t, A, sp, ke0, z0);
-        if (st == REEDMD_ACTIVE && A.cancel != nullptr && ++since_poll >= 256) {
+        if (st == REEDMD_ACTIVE && ++since_poll >= 256) {
             since_poll = 0;
-            int cv = 0;
-            if (sl == 0) cv = __hip_atomic_load(A.cancel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-            if (__shfl(cv, leader, 64) != 0) st = REEDMD_CANCELLED;
+            const KernelArgs C = cold_args();
+            if (C.cancel != nullptr) {
+                int cv = 0;
+                if (sl == 0) cv = __hip_atomic_load(C.cancel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                if (__shfl(cv, leader, 64) != 0) st = REEDMD_CANCELLED;
+            }
         }
         if (st != REEDMD_ACTIVE) {
+            const KernelArgs A = cold_args();
             if (sl == 0) {
                 book_finished(A, st, t.w, t.zstop, t.lineage, t.next_k, t.steps, exec_steps, pairs);
                 if (MODE == kModePersistent) add_i64(&A.q->live, -1);
@@ -706,6 +732,7 @@ __global__ void __launch_bounds__(256, REEDMD_WAVES_PER_SIMD(L)) track_kernel(co
         }
         // cloning at depth thresholds (Sec. 2): weight / n_clones, new keys
         if (t.z >= t.thr_next) {
+            const KernelArgs A = cold_args();
             while (t.next_k < A.n_thresh && t.z >= t.thr_next) {
                 const int k = t.next_k;
                 const unsigned long long parent = t.key;
