@@ -34,7 +34,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--form", choices=["auto", "plain", "persistent"], default="persistent")
     ap.add_argument("--lanes", type=int, default=0)
-    ap.add_argument("--n", type=int, default=65536)
+    ap.add_argument("--n", type=int, default=0, help="primaries (default: the workload's full size)")
+    ap.add_argument("--workload", choices=["c1", "c2", "c4"], default="c1",
+                    help="c1: 10 keV As (default, the benchmark line); c2: mixed B/P/As 1-100 keV, "
+                         "1,048,576 tracks; c4: 100 keV As [001] channeling, 262,144 tracks")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-grad", action="store_true", help="skip the gradient / forward time ratio")
@@ -122,16 +125,28 @@ def main():
         return
 
     import paper_0810_4737_amd as R
-    from tests.workloads import C1_THRESHOLDS, WORKLOADS
+    from tests.workloads import C1_THRESHOLDS, C2_THRESHOLDS, C4_THRESHOLDS, WORKLOADS
 
     assert torch.cuda.is_available(), "bench needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    w = WORKLOADS["c1_as10kev"]
-    n = args.n
+    wname = {"c1": "c1_as10kev", "c2": "c2_mixed", "c4": "c4_as100kev"}[args.workload]
+    w = WORKLOADS[wname]
+    n = args.n if args.n > 0 else w["n"]
     ctx = R.Context()
-    sampler = R.SamplerConfig(**dict(w["sampler"], n_cone=n // 2))
-    base = dict(n_bins=w["n_bins"], bin_width=w["bin_width"], thresholds=[list(C1_THRESHOLDS)])
+    if args.workload == "c1":
+        sampler = R.SamplerConfig(**dict(w["sampler"], n_cone=n // 2))
+        thr = [list(C1_THRESHOLDS)]
+        tail_depth = C1_THRESHOLDS[6]
+    elif args.workload == "c2":
+        sampler = R.SamplerConfig(**w["sampler"])
+        thr = [list(t) for t in C2_THRESHOLDS]
+        tail_depth = 2000.0
+    else:
+        sampler = R.SamplerConfig(**w["sampler"])
+        thr = [list(C4_THRESHOLDS)]
+        tail_depth = 4000.0
+    base = dict(n_bins=w["n_bins"], bin_width=w["bin_width"], thresholds=thr)
     stream = torch.cuda.current_stream()
 
     # launch shape: explicit, or the autotuner on a pilot of the same workload
@@ -186,14 +201,14 @@ def main():
             t_w = time.perf_counter() - t0
             st = R.parse_stats(stats)
             lg = R.parse_log(log, min(st["log_count"], 40 * n))
-            # relative standard error of the weighted probability beyond the 7th cloning depth,
+            # relative standard error of the weighted probability beyond a deep-tail depth,
             # from per-primary sums (unbiased REED estimator), and the figure of merit 1/(T s^2)
-            deep = (lg["status"] == R.STOPPED) & (lg["z_stop"] >= C1_THRESHOLDS[6])
+            deep = (lg["status"] == R.STOPPED) & (lg["z_stop"] >= tail_depth)
             per = np.zeros(n)
             np.add.at(per, lg["lineage"][deep], lg["w"][deep])
             p = per.mean()
             rel = per.std(ddof=1) / math.sqrt(n) / p if p > 0 else float("nan")
-            acc = dict(tail_depth_A=C1_THRESHOLDS[6], tail_probability=p, tail_rel_err=rel,
+            acc = dict(tail_depth_A=tail_depth, tail_probability=p, tail_rel_err=rel,
                        fom_per_s=1.0 / (t_w * rel * rel) if rel > 0 else None)
         else:
             step()
@@ -224,6 +239,15 @@ def main():
     kms = sum(kernel_ms) / len(kernel_ms)
     pairs_per_launch = pairs / args.steps
     achieved = FLOP_PER_PAIR * pairs_per_launch / (kms * 1e-3) / 1e12
+    descr = {
+        "c1": "c1_as10kev: 65,536 As at 10 keV into diamond Si (a=5.431 A, sigma=0.076 A), "
+              "half within 0.5 deg of [110], half at 7 deg tilt; ZBL + local LSS k=1; "
+              "dx_max 0.05 A; 8 cloning depths x 2 clones; 1 A bins 0-8192 A",
+        "c2": "c2_mixed: 1,048,576 tracks, species uniform over B/P/As, energy log-uniform 1-100 keV, "
+              "7 deg tilt; 12 cloning depths per (species, energy decade) table; 1 A bins 0-8192 A",
+        "c4": "c4_as100kev: 262,144 As at 100 keV along [001] (0 deg); 16 cloning depths to 1e-6; "
+              "0-500 nm in 0.5 nm bins",
+    }[args.workload]
     out = {
         "metric": "ion-atom force evaluations per second (REED-MD track throughput)",
         "value": value,
@@ -238,9 +262,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": "c1_as10kev: 65,536 As at 10 keV into diamond Si (a=5.431 A, sigma=0.076 A), "
-                        "half within 0.5 deg of [110], half at 7 deg tilt; ZBL + local LSS k=1; "
-                        "dx_max 0.05 A; 8 cloning depths x 2 clones; 1 A bins 0-8192 A",
+            "workload": descr,
             "primaries": n,
             "form": "persistent" if cfg.form == R.FORM_PERSISTENT else "plain",
             "lanes_per_track": cfg.lanes_per_track,

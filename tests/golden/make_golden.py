@@ -1,7 +1,10 @@
 """Writes the stored oracle results used by the GPU statistical parity tests.
 
-Calls only the oracle (``oracle/``).  Usage:  python tests/golden/make_golden.py [pilot|c0|c1]
+Calls only the oracle (``oracle/``).
+Usage:  python tests/golden/make_golden.py [pilot|pilot2|pilot4|c0|c1|c2|c4]
   pilot: unsplit survival quantiles of the 10 keV As workload (source of C1_THRESHOLDS)
+  pilot2: cloning-depth tables of the mixed B/P/As 1-100 keV workload (C2_THRESHOLDS)
+  pilot4: cloning depths of the 100 keV As [001] channeling workload (C4_THRESHOLDS)
   c0:    65,536 B at 1 keV, 7 degree tilt, no splitting (the c0 sampler, ids 0..65535)
   c1:    1,024 As at 10 keV with the 8 cloning depths: ids 0..511 (channel) and 32768..33279 (tilt)
 Outputs go next to this file as JSON (histogram, totals, moments) plus gzipped text of every
@@ -20,7 +23,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 import oracle  # noqa: E402
-from tests.workloads import C1_THRESHOLDS, WORKLOADS  # noqa: E402
+from tests.workloads import C1_THRESHOLDS, C2_THRESHOLDS, C4_THRESHOLDS, WORKLOADS  # noqa: E402
 
 
 def sampler(w):
@@ -61,6 +64,59 @@ def pilot():
     print("stored:", C1_THRESHOLDS)
 
 
+def survival_depths(z, probs, min_tail=4, min_gap=2.0):
+    """Depths at which the empirical unsplit survival S(z) = P(z_stop > z) equals each target
+    probability.  Where fewer than min_tail pilot ions lie beyond, the tail is extrapolated
+    with an exponential fitted (least squares on ln S) to the pilot's last decade of
+    survival; the result is made strictly increasing with at least min_gap between depths."""
+    z = np.sort(np.asarray(z, float))
+    n = len(z)
+    S = 1.0 - (np.arange(1, n + 1) / n)          # survival just above each sorted depth
+    sel = (S >= min_tail / n) & (S <= 0.1)
+    if sel.sum() < 3:
+        sel = S >= min_tail / n
+    slope, icept = np.polyfit(z[sel], np.log(S[sel]), 1)
+    out = []
+    for p in probs:
+        if p * n >= min_tail:
+            d = float(np.quantile(z, 1.0 - p))
+        else:
+            d = float((math.log(p) - icept) / slope)
+        if out and d < out[-1] + min_gap:
+            d = out[-1] + min_gap
+        out.append(round(d, 1))
+    return out
+
+
+def pilot2():
+    """12 depths per (species, energy decade) table at survival 10^(-5k/12), k = 1..12."""
+    w = WORKLOADS["c2_mixed"]
+    probs = [10.0 ** (-5.0 * k / 12.0) for k in range(1, 13)]
+    tables = []
+    for si in range(3):
+        for band, (e0, e1) in enumerate(((1000.0, 10000.0), (10000.0, 100000.0))):
+            sc = oracle.SamplerCfg(choice=(si,), E_min=e0, E_max=e1, tilt=w["sampler"]["tilt"])
+            prim = oracle.sample_primaries(sc, 1, 256)
+            r = oracle.run(oracle.Config(species=w["species"], n_bins=w["n_bins"]), prim, log=True)
+            lg = r["log"]
+            tables.append(survival_depths(lg["z_stop"][lg["status"] == oracle.STOPPED], probs))
+    print("C2_THRESHOLDS =", tables)
+    print("stored:", C2_THRESHOLDS)
+
+
+def pilot4():
+    """16 depths at survival 10^(-6k/16), k = 1..16."""
+    w = WORKLOADS["c4_as100kev"]
+    probs = [10.0 ** (-6.0 * k / 16.0) for k in range(1, 17)]
+    sc = oracle.SamplerCfg(**w["sampler"])
+    prim = oracle.sample_primaries(sc, 2, 128)
+    r = oracle.run(oracle.Config(species=w["species"], n_bins=w["n_bins"], bin_width=w["bin_width"]),
+                   prim, log=True)
+    lg = r["log"]
+    print("C4_THRESHOLDS =", survival_depths(lg["z_stop"][lg["status"] == oracle.STOPPED], probs))
+    print("stored:", C4_THRESHOLDS)
+
+
 def c0():
     w = WORKLOADS["c0_b1kev"]
     n = 65536
@@ -88,7 +144,31 @@ def c1():
                            thresholds=list(C1_THRESHOLDS)), r)
 
 
+def c2():
+    """256 primaries of the mixed workload (ids 0..255), all 12-depth tables."""
+    w = WORKLOADS["c2_mixed"]
+    prim = oracle.sample_primaries(sampler(w), 0, 256)
+    cfg = oracle.Config(species=w["species"], n_bins=w["n_bins"], bin_width=w["bin_width"],
+                        thresholds=C2_THRESHOLDS)
+    t = time.time()
+    r = oracle.run(cfg, prim, log=True)
+    print("c2 oracle seconds", time.time() - t, r["stats"])
+    save("c2_subset", dict(name="c2_mixed", ids=[[0, 256]], seed=0), r)
+
+
+def c4():
+    """32 primaries of the 100 keV As channeling workload (ids 0..31), 16 depths."""
+    w = WORKLOADS["c4_as100kev"]
+    prim = oracle.sample_primaries(sampler(w), 0, 32)
+    cfg = oracle.Config(species=w["species"], n_bins=w["n_bins"], bin_width=w["bin_width"],
+                        thresholds=[list(C4_THRESHOLDS)])
+    t = time.time()
+    r = oracle.run(cfg, prim, log=True)
+    print("c4 oracle seconds", time.time() - t, r["stats"])
+    save("c4_subset", dict(name="c4_as100kev", ids=[[0, 32]], seed=0), r)
+
+
 if __name__ == "__main__":
     what = sys.argv[1:] or ["c0", "c1"]
     for w in what:
-        {"pilot": pilot, "c0": c0, "c1": c1}[w]()
+        {"pilot": pilot, "pilot2": pilot2, "pilot4": pilot4, "c0": c0, "c1": c1, "c2": c2, "c4": c4}[w]()
