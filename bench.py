@@ -34,6 +34,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--form", choices=["auto", "plain", "persistent"], default="persistent")
     ap.add_argument("--lanes", type=int, default=0)
+    ap.add_argument("--waves", type=int, default=0, help="resident waves per CU with --lanes (0: by occupancy)")
+    ap.add_argument("--queue", type=int, default=0, help="clone-queue capacity in records (0: library default)")
     ap.add_argument("--n", type=int, default=0, help="primaries (default: the workload's full size)")
     ap.add_argument("--workload", choices=["c1", "c2", "c4"], default="c1",
                     help="c1: 10 keV As (default, the benchmark line); c2: mixed B/P/As 1-100 keV, "
@@ -146,7 +148,7 @@ def main():
         sampler = R.SamplerConfig(**w["sampler"])
         thr = [list(C4_THRESHOLDS)]
         tail_depth = 4000.0
-    base = dict(n_bins=w["n_bins"], bin_width=w["bin_width"], thresholds=thr)
+    base = dict(n_bins=w["n_bins"], bin_width=w["bin_width"], thresholds=thr, queue_capacity=args.queue)
     stream = torch.cuda.current_stream()
 
     # launch shape: explicit, or the autotuner on a pilot of the same workload
@@ -156,15 +158,17 @@ def main():
             [R.FORM_PLAIN if args.form == "plain" else R.FORM_PERSISTENT]
         best = None
         for f in forms:
-            pilot = torch.randperm(n, device=dev)[:2048]
-            pb = {k: (v[:, pilot].contiguous() if v.dim() == 2 else v[pilot].contiguous()) for k, v in batch.items()}
-            t0 = time.perf_counter()
-            lanes, waves = R.autotune(ctx, w["species"], pb, R.RunConfig(form=f, lanes_per_track=args.lanes, **base),
-                                      pilot=2048)
+            # the autotuner measures steady-state throughput on the batch itself
+            # (time-boxed candidate launches), then the choice is run once to compare forms
+            lanes, waves = R.autotune(ctx, w["species"], batch, R.RunConfig(form=f, lanes_per_track=args.lanes, **base),
+                                      pilot=n)
             cfg_try = R.RunConfig(form=f, lanes_per_track=lanes, waves_per_cu=waves, **base)
+            if len(forms) == 1:
+                best = (0.0, cfg_try)
+                break
             torch.cuda.synchronize()
             t1 = time.perf_counter()
-            R.run(ctx, w["species"], pb, cfg_try)
+            R.run(ctx, w["species"], batch, cfg_try)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t1
             if best is None or dt < best[0]:
@@ -172,8 +176,9 @@ def main():
         cfg = best[1]
     else:
         cfg = R.RunConfig(form=R.FORM_PLAIN if args.form == "plain" else R.FORM_PERSISTENT,
-                          lanes_per_track=args.lanes, **base)
+                          lanes_per_track=args.lanes, waves_per_cu=args.waves, **base)
 
+    shape = R.launch_shape(ctx, batch, cfg)
     hist = torch.zeros(w["n_bins"], dtype=torch.float64, device=dev)
     stats = R.new_stats(dev)
 
@@ -217,6 +222,7 @@ def main():
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     pairs = tracks = prims = 0
     kernel_ms = []
+    queue_use = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
@@ -227,6 +233,7 @@ def main():
         tracks += st["finished"]
         prims += st["primaries"]
         kernel_ms.append(ev[k][0].elapsed_time(ev[k][1]))
+        queue_use.append([st["max_queue"], st["stack_overflow"]])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     st_last = st
@@ -267,10 +274,13 @@ def main():
             "form": "persistent" if cfg.form == R.FORM_PERSISTENT else "plain",
             "lanes_per_track": cfg.lanes_per_track,
             "waves_per_cu": cfg.waves_per_cu,
+            "launch": shape,
         },
         "tracks_per_s": tracks / wall,
         "primaries_per_s": prims / wall,
         "track_steps_per_s": st_last["track_steps"] * args.steps / wall,
+        "kernel_ms_per_step": [round(x, 1) for x in kernel_ms],
+        "queue_max_and_overflow_per_step": queue_use,
         "profile_accuracy": acc,
         "grad_fwd_ratio": None,
         "roofline": {

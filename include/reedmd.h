@@ -75,7 +75,7 @@ typedef struct {
 typedef struct {
     int32_t mode;        /* REEDMD_POT_ZBL, or REEDMD_POT_NONE (no nuclear force; tests) */
     int32_t reserved;
-    double s;            /* screening-length scale, > 0 (1 = ZBL) */
+    double s;            /* screening-length scale in [0.01, 100] (1 = ZBL); REEDMD_EINVAL outside */
 } reedmd_potential;
 
 /* Electronic stopping (Sec. 2, "Third"), read as a local Lindhard-Scharff
@@ -235,7 +235,7 @@ reedmd_status reedmd_debug_step(reedmd_ctx* ctx, const reedmd_species* species,
  * of the batch that stop; backscattered and capped tracks are excluded) with
  * respect to the electronic-stopping scale k and the ZBL screening-length
  * scale s, evaluated at (k, s) (they replace the context's values for this
- * call).  Reverse mode: every track runs forward with a checkpoint of its full
+ * call; k >= 0 and s in [0.01, 100], EINVAL otherwise).  Reverse mode: every track runs forward with a checkpoint of its full
  * state every 64 steps, then each 64-step segment is recomputed from its
  * checkpoint and the adjoint of its steps applied from last to first.  The
  * derivative is pathwise: branches (active step-size term, domain updates,
@@ -250,20 +250,35 @@ reedmd_status reedmd_grad(reedmd_ctx* ctx, const reedmd_species* species, const 
                           const reedmd_run_params* params, double k, double s, double* d_track_out,
                           double* h_result, hipStream_t stream);
 
-/* Evaluates, for y[i] >= 0 (device, n doubles), the exp(-y) that the force
- * kernels use (Cody-Waite reduction + Taylor series to 12th order) into out
- * (device).  For accuracy tests of the library's exponential.  Enqueued on
- * stream; EINVAL for n < 0 or NULL arrays. */
+/* Evaluates, for finite 0 <= y[i] < 1e9 (device, n doubles), the exp(-y) that
+ * the force kernels use (Cody-Waite reduction to |r| <= ln2/2, degree-10
+ * minimax polynomial, ldexp) into out (device); outside that range the value
+ * is unspecified.  For accuracy tests of the library's exponential.  Enqueued
+ * on stream; EINVAL for n < 0 or NULL arrays. */
 reedmd_status reedmd_eval_exp_neg(const double* d_y, double* d_out, int64_t n, hipStream_t stream);
 
-/* Tries each lanes-per-track variant (and, for the persistent form, resident
- * waves per CU) on the first `pilot` primaries of the batch and records the
- * fastest in the context's cache under this configuration; *best_lanes and
- * *best_waves (host) receive the choice.  Synchronises the stream. */
+/* Chooses the launch shape for runs like this one.  Each candidate (lanes per
+ * track 64, 32, 16; for the persistent form also one workgroup per CU fewer
+ * than the occupancy allows) runs on the first `pilot` primaries of the batch
+ * and is cancelled through a pinned host word 400 ms after it starts (unless
+ * it ends earlier); the candidate with the most pair evaluations per second
+ * (steady-state throughput, not the tail of a small pilot) is recorded in the
+ * context's cache under this configuration and batch size class, and
+ * *best_lanes and *best_waves (host) receive the choice.  The caller's
+ * histogram and statistics are not touched.  Synchronises the stream. */
 reedmd_status reedmd_autotune(reedmd_ctx* ctx, const reedmd_species* species,
                               const reedmd_batch* batch, const reedmd_run_params* params,
                               int64_t pilot, hipStream_t stream, int32_t* best_lanes,
                               int32_t* best_waves);
+
+/* The launch shape reedmd_run would use for this batch size and these
+ * parameters (after the autotune cache), written to out (host, 5 values):
+ * lanes per track, workgroups (256 threads each), track segments, workgroups
+ * of the track kernel that fit on one CU, clone-queue capacity (0 for the
+ * plain form).  Host call; nothing is enqueued.  EINVAL for NULL arguments or
+ * invalid parameters. */
+reedmd_status reedmd_launch_shape(reedmd_ctx* ctx, const reedmd_batch* batch,
+                                  const reedmd_run_params* params, int64_t* out);
 
 #ifdef __cplusplus
 }

@@ -269,6 +269,16 @@ def autotune(ctx: Context, species, batch, cfg: RunConfig, pilot: int, stream=No
     return bl.value, bw.value
 
 
+def launch_shape(ctx: Context, batch, cfg: RunConfig):
+    """The launch shape run() would use: dict(lanes, blocks, segments, blocks_per_cu, queue)."""
+    keep = []
+    p = cfg.struct(batch["energy"].device, keep)
+    b = _batch_struct(batch)
+    out = (C.c_int64 * 5)()
+    ctx.check(ctx._lib.reedmd_launch_shape(ctx.handle, C.byref(b), C.byref(p), out))
+    return dict(lanes=out[0], blocks=out[1], segments=out[2], blocks_per_cu=out[3], queue=out[4])
+
+
 def grad(ctx: Context, species, batch, cfg: RunConfig, k: float, s: float, per_track=False, stream=None):
     """Mean projected range and its derivatives w.r.t. the stopping scale k and the screening
     scale s (reverse mode, 64-step checkpoints).  Returns dict(mean, dk, ds, count[, tracks])."""

@@ -97,11 +97,11 @@ __device__ __forceinline__ void reverse_step(AdjIon& ai, AdjAtoms<L>& aa, const 
     const double h1 = dt * c.half_inv_M1;
     const double h2 = dt * A.half_inv_M2;
     const double g1 = c.g_const + c.g_rho * rho;
-    const double fr1 = exp(-g1 * h1);
+    const double fr1 = exp_neg(g1 * h1);
     double v1[3];
     for (int k = 0; k < 3; ++k) v1[k] = v[k] * fr1 + F[k] * h1;
     const double g2 = c.g_const + c.g_rho * rhop;
-    const double fr2 = exp(-g2 * h1);
+    const double fr2 = exp_neg(g2 * h1);
     double q[3];
     for (int k = 0; k < 3; ++k) q[k] = v1[k] + Fp[k] * h1;
 

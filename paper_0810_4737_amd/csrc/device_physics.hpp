@@ -28,6 +28,9 @@ struct SpeciesConst {
     double dg_const;      // d g_const / d k
     double dg_rho;        // d g_rho / d k
     double inv_M1sq;      // 1 / M1^2
+    // The screened-Coulomb sum with its constants folded per species:
+    //   rate_i = d_i / a,  amp_i = zz c_i,  damp_i = zz c_i d_i / a
+    double rate[4], amp[4], damp[4];
 };
 
 // ---------------------------------------------------------------------------
@@ -117,9 +120,11 @@ __device__ __forceinline__ void basis_site(int b, double& fx, double& fy, double
 }
 
 // Position of a newly created atom: ideal site of basis atom b in cell
-// (nx,ny,nz) plus its thermal displacement.  Kept out of line so that the
-// rarely taken domain update does not raise the register budget of the step.
-#ifdef REEDMD_NOINLINE_CREATE
+// (nx,ny,nz) plus its thermal displacement.  Kept out of line (one copy instead
+// of one per register slot), so that the rarely taken domain update does not
+// raise the register budget of the step: it removes the scalar-register spills
+// of the step loop and the stack arrays of the 16-lane layout.
+#ifndef REEDMD_INLINE_CREATE
 __device__ __attribute__((noinline)) double3 create_atom(uint64_t key, uint64_t seed, int nx, int ny, int nz, int b,
                                                           double a, double sigma)
 #else
@@ -136,35 +141,47 @@ __device__ __forceinline__ double3 create_atom(uint64_t key, uint64_t seed, int 
 }
 
 // ---------------------------------------------------------------------------
-// exp(-y) for the force kernels, written from the mathematics: Cody-Waite
-// range reduction y = n ln2 + r with ln 2 split into a double and its
-// remainder (both FMA-exact), |r| <= ln2/2, the Taylor series of e^r to r^12
-// (truncation < 2e-16 relative), and scaling by 2^n (ldexp handles the
-// gradual underflow of very small results).  No overflow or NaN handling is
-// needed: arguments are distances over positive lengths (y >= 0, bounded).
+// exp(-y) for the force kernels, written from the mathematics: y = n ln2 - r
+// with n the nearest integer to y / ln2 (the rounding is done by adding
+// 1.5 * 2^52, whose sum holds n in its low mantissa bits, so no conversion is
+// needed), r reduced with ln 2 split into a double and its remainder (both
+// FMA-exact), |r| <= ln2/2; e^r from the degree-10 polynomial that minimises
+// the largest relative error on that interval (Remez exchange; 3.0e-16, with
+// the constant term held at 1), and the scaling by 2^-n done by ldexp, which
+// rounds gradual underflow correctly.  Valid for finite 0 <= y < 1e9: the
+// force kernels' arguments are distances over positive lengths, bounded by the
+// parking distance of empty slots (see the library's argument checks).
 __device__ __forceinline__ double exp_neg(double y)
 {
     constexpr double kLog2e = 1.4426950408889634;
     constexpr double kLn2Hi = 0x1.62e42fefa39efp-1;
     constexpr double kLn2Lo = 0x1.abc9e3b39803fp-56;
-    const double t = -fmin(y, 1500.0);
-    const double n = rint(t * kLog2e);
-    double r = fma(-n, kLn2Hi, t);
+    constexpr double kRound = 0x1.8p52;
+    const double nr = fma(-y, kLog2e, kRound);   // kRound + nearest integer to -y / ln2
+    const double n = nr - kRound;
+    double r = fma(-n, kLn2Hi, -y);
     r = fma(-n, kLn2Lo, r);
-    double p = 2.08767569878681e-09;            // 1/12!
-    p = fma(p, r, 2.505210838544172e-08);       // 1/11!
-    p = fma(p, r, 2.755731922398589e-07);       // 1/10!
-    p = fma(p, r, 2.7557319223985893e-06);      // 1/9!
-    p = fma(p, r, 2.48015873015873e-05);        // 1/8!
-    p = fma(p, r, 0.0001984126984126984);       // 1/7!
-    p = fma(p, r, 0.001388888888888889);        // 1/6!
-    p = fma(p, r, 0.008333333333333333);        // 1/5!
-    p = fma(p, r, 0.041666666666666664);        // 1/4!
-    p = fma(p, r, 0.16666666666666666);         // 1/3!
-    p = fma(p, r, 0.5);
+    double p = 0x1.2a475a7d4ddb2p-22;
+    p = fma(p, r, 0x1.730bd57070546p-19);
+    p = fma(p, r, 0x1.a017fb6001714p-16);
+    p = fma(p, r, 0x1.a01967c4ef7f8p-13);
+    p = fma(p, r, 0x1.6c16c20da969ep-10);
+    p = fma(p, r, 0x1.11111133719d9p-7);
+    p = fma(p, r, 0x1.555555552f919p-5);
+    p = fma(p, r, 0x1.5555555548c99p-3);
+    p = fma(p, r, 0x1.000000000004bp-1);
+    p = fma(p, r, 0x1.0000000000029p+0);
     p = fma(p, r, 1.0);
-    p = fma(p, r, 1.0);
-    return ldexp(p, static_cast<int>(n));
+    return ldexp(p, static_cast<int>(__double2loint(nr)));
+}
+
+// 1/sqrt(x) for finite x > 0: the hardware estimate refined by one
+// third-order Newton step on e = 1 - x y^2 (y <- y (1 + e/2 + 3e^2/8)).
+__device__ __forceinline__ double rsqrt_pos(double x)
+{
+    const double y = __builtin_amdgcn_rsq(x);
+    const double e = fma(-x * y, y, 1.0);
+    return fma(y * e, fma(0.375, e, 0.5), y);
 }
 
 // ---------------------------------------------------------------------------
@@ -174,25 +191,25 @@ constexpr double kZd0 = 3.19980, kZd1 = 0.94229, kZd2 = 0.40290, kZd3 = 0.20162;
 
 // Pair term for an ion at separation (dx,dy,dz) = x_ion - x_atom:
 //   coef: force on the ion is coef * (dx,dy,dz) (the atom feels the opposite),
-//         coef = -V'(r) / r with V = zz phi(r/a) / r;
-//   wr:   density weight wnorm * exp(-r/lambda).
-__device__ __forceinline__ void zbl_pair(double inv_a, double zz, double inv_lambda, double wnorm, double dx,
-                                         double dy, double dz, double& coef, double& wr)
+//         coef = -V'(r) / r = zz (phi(r/a) / r + (-phi'(r/a)) / a) / r^2
+//         with V = zz phi(r/a) / r;
+//   ew:   exp(-r/lambda), the density weight without its normalisation.
+// An empty slot sits at the parking distance, where every exponential is 0 and
+// so are coef and ew.
+__device__ __forceinline__ void zbl_pair(const SpeciesConst& c, double dx, double dy, double dz, double& coef,
+                                         double& ew)
 {
     const double r2 = dx * dx + dy * dy + dz * dz;
-    const double inv_r = rsqrt(r2);
+    const double inv_r = rsqrt_pos(r2);
     const double r = r2 * inv_r;
-    const double xs = r * inv_a;
-    const double e0 = exp_neg(kZd0 * xs);
-    const double e1 = exp_neg(kZd1 * xs);
-    const double e2 = exp_neg(kZd2 * xs);
-    const double e3 = exp_neg(kZd3 * xs);
-    const double phi = kZc0 * e0 + kZc1 * e1 + kZc2 * e2 + kZc3 * e3;
-    const double dphi = -(kZc0 * kZd0 * e0 + kZc1 * kZd1 * e1 + kZc2 * kZd2 * e2 + kZc3 * kZd3 * e3);
-    // V'(r) = zz (phi'(x) / (a r) - phi(x) / r^2)
-    const double dVdr = zz * inv_r * (dphi * inv_a - phi * inv_r);
-    coef = -dVdr * inv_r;
-    wr = wnorm * exp_neg(r * inv_lambda);
+    const double e0 = exp_neg(r * c.rate[0]);
+    const double e1 = exp_neg(r * c.rate[1]);
+    const double e2 = exp_neg(r * c.rate[2]);
+    const double e3 = exp_neg(r * c.rate[3]);
+    const double phi = c.amp[0] * e0 + c.amp[1] * e1 + c.amp[2] * e2 + c.amp[3] * e3;
+    const double dphi = c.damp[0] * e0 + c.damp[1] * e1 + c.damp[2] * e2 + c.damp[3] * e3;
+    coef = fma(phi, inv_r, dphi) * (inv_r * inv_r);
+    ew = exp_neg(r * c.inv_lambda);
 }
 
 // The unique cell coordinate in {c-1, c, c+1} whose residue mod 3 is `res`.

@@ -24,7 +24,10 @@ constexpr double kCoulomb = 14.3996454784;   // e^2 / (4 pi eps0), eV A (CODATA 
 constexpr double kBohr = 0.529177210903;     // A
 constexpr int kBlock = 256;                  // 4 wavefronts per workgroup
 constexpr long long kDefaultMaxSteps = 2000000;   // step cap when the caller sets none
+constexpr double kMinScreening = 0.01;         // accepted range of the screening-length scale s:
+constexpr double kMaxScreening = 100.0;        // keeps every exponent argument below 1e9
 constexpr long long kDefaultGradSteps = 16384;    // gradient step cap when the caller sets none
+constexpr int kTuneBoxMs = 400;                   // autotuner: time box of each candidate launch
 constexpr size_t kGradScratchBytes = size_t(16) << 30;   // checkpoint memory per launch chunk
 
 thread_local std::string g_create_error;
@@ -80,6 +83,7 @@ reedmd_status hip_fail(reedmd_ctx* ctx, hipError_t e, const char* what)
 void prepare_species(const reedmd_ctx* ctx, const reedmd_species* sp, KernelArgs& A)
 {
     const double Z2 = ctx->lat.Z2;
+    double min_rate = HUGE_VAL;
     const double N = 8.0 / (ctx->lat.a * ctx->lat.a * ctx->lat.a);
     for (int i = 0; i < kMaxSpecies; ++i) {
         SpeciesConst& c = A.sp[i];
@@ -100,6 +104,13 @@ void prepare_species(const reedmd_ctx* ctx, const reedmd_species* sp, KernelArgs
         c.zz = (ctx->pot.mode == REEDMD_POT_ZBL) ? Z1 * Z2 * kCoulomb : 0.0;
         c.inv_lambda = 1.0 / lambda;
         c.wnorm = 1.0 / (8.0 * M_PI * lambda * lambda * lambda);
+        const double zc[4] = {kZc0, kZc1, kZc2, kZc3}, zd[4] = {kZd0, kZd1, kZd2, kZd3};
+        for (int j = 0; j < 4; ++j) {
+            c.rate[j] = zd[j] * c.inv_a;
+            c.amp[j] = c.zz * zc[j];
+            c.damp[j] = c.zz * zc[j] * zd[j] * c.inv_a;
+        }
+        min_rate = std::min(min_rate, std::min(c.rate[3], c.inv_lambda));
         c.g_const = 0.0;
         c.g_rho = 0.0;
         c.dg_const = 0.0;
@@ -113,6 +124,9 @@ void prepare_species(const reedmd_ctx* ctx, const reedmd_species* sp, KernelArgs
             c.dg_rho = gamma0 / N;
         }
     }
+    // Empty slots are parked where the slowest exponential of every species in use
+    // is below e^-1000, so their pair terms are exactly zero (at least 1 um away).
+    A.park = std::max(1.0e4, 1.0e3 / min_rate);
 }
 
 reedmd_status check_species(reedmd_ctx* ctx, const reedmd_species* sp)
@@ -520,7 +534,8 @@ reedmd_status reedmd_create(const reedmd_lattice* lattice, const reedmd_potentia
     if (lattice->structure != REEDMD_DIAMOND) return fail(nullptr, REEDMD_EUNSUPPORTED, "only the diamond structure");
     if (potential->mode != REEDMD_POT_ZBL && potential->mode != REEDMD_POT_NONE)
         return fail(nullptr, REEDMD_EINVAL, "unknown potential mode");
-    if (!(potential->s > 0.0)) return fail(nullptr, REEDMD_EINVAL, "screening scale s must be positive");
+    if (!(potential->s >= kMinScreening && potential->s <= kMaxScreening))
+        return fail(nullptr, REEDMD_EINVAL, "screening scale s must be in [0.01, 100]");
     if (stopping->mode < REEDMD_STOP_OFF || stopping->mode > REEDMD_STOP_LOCAL || !(stopping->k >= 0.0))
         return fail(nullptr, REEDMD_EINVAL, "unknown stopping mode or negative k");
     int dev = 0;
@@ -670,7 +685,8 @@ reedmd_status reedmd_grad(reedmd_ctx* ctx, const reedmd_species* species, const 
     if ((st = check_params(ctx, params, false)) != REEDMD_OK) return st;
     if (!h_result) return fail(ctx, REEDMD_EINVAL, "h_result is NULL");
     if (params->n_thresh != 0) return fail(ctx, REEDMD_EUNSUPPORTED, "the gradient is defined without cloning (n_thresh = 0)");
-    if (!(k >= 0.0) || !(s > 0.0)) return fail(ctx, REEDMD_EINVAL, "need k >= 0 and s > 0");
+    if (!(k >= 0.0) || !(s >= kMinScreening && s <= kMaxScreening))
+        return fail(ctx, REEDMD_EINVAL, "need k >= 0 and s in [0.01, 100]");
     for (int i = 0; i < 4; ++i) h_result[i] = 0.0;
     const long long n = batch->n;
     if (n == 0) return REEDMD_OK;
@@ -756,48 +772,85 @@ reedmd_status reedmd_autotune(reedmd_ctx* ctx, const reedmd_species* species, co
     pb.n = std::min<int64_t>(pilot, batch->n);
     double* hist = nullptr;
     reedmd_stats* stats = nullptr;
+    int* cancel = nullptr;   // pinned, fine-grained host word polled by the kernel
     HIP_TRY(ctx, hipMalloc(reinterpret_cast<void**>(&hist), sizeof(double) * params->n_bins));
     HIP_TRY(ctx, hipMalloc(reinterpret_cast<void**>(&stats), sizeof(reedmd_stats)));
+    HIP_TRY(ctx, hipHostMalloc(reinterpret_cast<void**>(&cancel), sizeof(int), hipHostMallocCoherent));
     reedmd_run_params p = *params;
     p.track_log = nullptr;
     p.track_log_cap = 0;
-    p.cancel = nullptr;
+    p.cancel = cancel;
     hipEvent_t e0, e1;
     HIP_TRY(ctx, hipEventCreate(&e0));
     HIP_TRY(ctx, hipEventCreate(&e1));
-    float best = 1e30f;
+    double best = -1.0;
     int bl = 64, bw = 0;
     const int lanes[3] = {64, 32, 16};
-    const int wave_opts_p[4] = {0, 4, 8, 12};
-    for (int li = 0; li < 3; ++li) {
-        const int nw = params->form == REEDMD_FORM_PERSISTENT ? 4 : 1;
-        for (int wi = 0; wi < nw; ++wi) {
+    const bool persistent = params->form == REEDMD_FORM_PERSISTENT;
+    for (int li = 0; li < 3 && st == REEDMD_OK; ++li) {
+        // persistent form: the occupancy-sized grid and one workgroup per CU fewer
+        const int occ = resident_blocks_per_cu(lanes[li], persistent ? kModePersistent : kModePlain);
+        const int nw = (persistent && occ > 1) ? 2 : 1;
+        for (int wi = 0; wi < nw && st == REEDMD_OK; ++wi) {
             p.lanes_per_track = lanes[li];
-            p.waves_per_cu = params->form == REEDMD_FORM_PERSISTENT ? wave_opts_p[wi] : 0;
+            p.waves_per_cu = wi == 0 ? 0 : (occ - 1) * (kBlock / 64);
             Shape s = choose_shape(ctx, &p, &pb);
+            reedmd_stats h{};
+            HIP_TRY(ctx, hipMemsetAsync(stats, 0, sizeof(reedmd_stats), stream));
+            __atomic_store_n(cancel, 0, __ATOMIC_SEQ_CST);
             HIP_TRY(ctx, hipEventRecord(e0, stream));
             st = run_impl(ctx, species, &pb, &p, hist, stats, stream, &s);
             if (st != REEDMD_OK) break;
             HIP_TRY(ctx, hipEventRecord(e1, stream));
+            // Steady-state throughput: the run is cancelled (drained with its ledger
+            // intact) after a fixed time box from its start, unless it ends earlier.
+            const auto t0 = std::chrono::steady_clock::now();
+            while (hipEventQuery(e0) == hipErrorNotReady &&
+                   std::chrono::steady_clock::now() - t0 < std::chrono::seconds(30)) {
+            }
+            const auto t1 = std::chrono::steady_clock::now();
+            while (hipEventQuery(e1) == hipErrorNotReady &&
+                   std::chrono::steady_clock::now() - t1 < std::chrono::milliseconds(kTuneBoxMs)) {
+            }
+            __atomic_store_n(cancel, 1, __ATOMIC_SEQ_CST);
             HIP_TRY(ctx, hipEventSynchronize(e1));
             float ms = 0.f;
             HIP_TRY(ctx, hipEventElapsedTime(&ms, e0, e1));
-            if (ms < best) {
-                best = ms;
+            HIP_TRY(ctx, hipMemcpy(&h, stats, sizeof(h), hipMemcpyDeviceToHost));
+            const double rate = ms > 0.f ? static_cast<double>(h.pair_evals) / ms : 0.0;
+            if (rate > best) {
+                best = rate;
                 bl = lanes[li];
                 bw = p.waves_per_cu;
             }
         }
-        if (st != REEDMD_OK) break;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     (void)hipFree(hist);
     (void)hipFree(stats);
+    (void)hipHostFree(cancel);
     if (st != REEDMD_OK) return st;
     ctx->tune[tune_key(params, batch)] = std::make_pair(bl, bw);
     if (best_lanes) *best_lanes = bl;
     if (best_waves) *best_waves = bw;
+    return REEDMD_OK;
+}
+
+reedmd_status reedmd_launch_shape(reedmd_ctx* ctx, const reedmd_batch* batch, const reedmd_run_params* params,
+                                  int64_t* out)
+{
+    if (!ctx) return fail(nullptr, REEDMD_EINVAL, "ctx is NULL");
+    reedmd_status st;
+    if ((st = check_batch(ctx, batch)) != REEDMD_OK) return st;
+    if ((st = check_params(ctx, params, true)) != REEDMD_OK) return st;
+    if (!out) return fail(ctx, REEDMD_EINVAL, "out is NULL");
+    const Shape s = choose_shape(ctx, params, batch);
+    out[0] = s.L;
+    out[1] = s.blocks;
+    out[2] = s.seg_total;
+    out[3] = resident_blocks_per_cu(s.L, s.mode);
+    out[4] = s.mode == kModePersistent ? s.qcap : 0;
     return REEDMD_OK;
 }
 

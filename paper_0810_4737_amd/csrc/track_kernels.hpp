@@ -22,6 +22,9 @@ enum : int { kModePlain = 0, kModePersistent = 1 };
 #ifndef REEDMD_PAIR_BARRIER
 #define REEDMD_PAIR_BARRIER 0
 #endif
+#ifndef REEDMD_SP_RELOAD
+#define REEDMD_SP_RELOAD 0
+#endif
 #ifndef REEDMD_WAVES_PER_SIMD
 #define REEDMD_WAVES_PER_SIMD(L) ((L) >= 32 ? 2 : 1)
 #endif
@@ -45,6 +48,7 @@ struct KernelArgs {
     SpeciesConst sp[kMaxSpecies];
     // crystal
     double a, inv_a, M2, sigma, inv_M2sq, half_inv_M2;
+    double park;            // empty slots sit this far above the domain centre
     // integration and events
     double dx_max, dt_max, E_stop, z_start;
     long long max_steps;
@@ -108,17 +112,19 @@ __device__ __forceinline__ KernelArgs cold_args()
     return a;
 }
 
-// Per-track force arrays in LDS: [waves per workgroup][tracks per wave][3][216].
+// Per-track force arrays in LDS: [waves per workgroup][tracks per wave][3][SL*L]
+// (the slots padded to whole lane rows, so every lane of a row has an entry).
 template <int L>
 struct ForceLds {
+    static constexpr int kStride = ((kSlots + L - 1) / L) * L;
     static constexpr int kTracksPerBlock = 4 * (64 / L);
-    static constexpr int kDoubles = kTracksPerBlock * 3 * kSlots;
+    static constexpr int kDoubles = kTracksPerBlock * 3 * kStride;
 };
 template <int L>
 __device__ __forceinline__ double* force_slab(double* s_force)
 {
     const int track_in_block = (threadIdx.x >> 6) * (64 / L) + (threadIdx.x & 63) / L;
-    return s_force + track_in_block * 3 * kSlots;
+    return s_force + track_in_block * 3 * ForceLds<L>::kStride;
 }
 
 // Species constants are staged in LDS once per workgroup (indexed per lane).
@@ -202,8 +208,9 @@ struct SegReduce {
 template <int L>
 struct TrackRegs {
     static constexpr int SL = (kSlots + L - 1) / L;
+    static constexpr int FS = ForceLds<L>::kStride;
     double ax[SL], ay[SL], az[SL], avx[SL], avy[SL], avz[SL];
-    double* fl;          // LDS: this track's atom forces, [3][216] (fx, fy, fz by slot)
+    double* fl;          // LDS: this track's atom forces, [3][FS] (fx, fy, fz by slot)
     unsigned exist;      // bit i: register slot i holds an existing atom
     // ion (segment-uniform)
     double x, y, z, vx, vy, vz, Fx, Fy, Fz, rho, w, zstop;
@@ -223,34 +230,54 @@ __device__ __forceinline__ void refresh_threshold(TrackRegs<L>& t, const KernelA
                                          : __builtin_huge_val();
 }
 
+// Empty register slots (cells above the surface, and the lanes past slot 215)
+// are parked at rest above the domain centre at the parking distance, where
+// every pair exponential underflows to exactly 0: their pair terms vanish and
+// the pass over the slots needs no branch.
+template <int L>
+__device__ __forceinline__ void park_slot(TrackRegs<L>& t, int i, int s, double px, double py, double pz)
+{
+    constexpr int FS = TrackRegs<L>::FS;
+    t.ax[i] = px; t.ay[i] = py; t.az[i] = pz;
+    t.avx[i] = 0.0; t.avy[i] = 0.0; t.avz[i] = 0.0;
+    t.fl[0 * FS + s] = 0.0; t.fl[1 * FS + s] = 0.0; t.fl[2 * FS + s] = 0.0;
+}
+
 template <int L>
 __device__ __forceinline__ void regenerate(TrackRegs<L>& t, const KernelArgs& A, int sl, int ncx,
                                            int ncy, int ncz, bool all)
 {
+    constexpr int FS = TrackRegs<L>::FS;
+    const KernelArgs C = cold_args();
+    const double parkx = C.a * (static_cast<double>(ncx) + 0.5);
+    const double parky = C.a * (static_cast<double>(ncy) + 0.5);
+    const double parkz = C.a * (static_cast<double>(ncz) + 0.5) - C.park;
     unsigned ex = 0;
 #pragma unroll
     for (int i = 0; i < TrackRegs<L>::SL; ++i) {
         const int s = sl + L * i;
-        if (s >= kSlots) continue;
+        if (s >= kSlots) {
+            park_slot<L>(t, i, s, parkx, parky, parkz);
+            continue;
+        }
         const int cell = s >> 3, b = s & 7;
         const int rx = cell / 9, ry = (cell / 3) % 3, rz = cell % 3;
         const int nx = cell_of_residue(rx, ncx), ny = cell_of_residue(ry, ncy), nz = cell_of_residue(rz, ncz);
         const bool changed = all || nx != cell_of_residue(rx, t.cx) || ny != cell_of_residue(ry, t.cy) ||
                              nz != cell_of_residue(rz, t.cz);
-        if (changed) {
-            if (nz >= 0) {
-                const KernelArgs C = cold_args();
+        if (nz < 0) {
+            park_slot<L>(t, i, s, parkx, parky, parkz);
+        } else {
+            ex |= (1u << i);
+            if (changed) {
                 const double3 p = create_atom(t.key, C.seed, nx, ny, nz, b, C.a, C.sigma);
                 t.ax[i] = p.x;
                 t.ay[i] = p.y;
                 t.az[i] = p.z;
-            } else {
-                t.ax[i] = 0.0; t.ay[i] = 0.0; t.az[i] = 0.0;
+                t.avx[i] = 0.0; t.avy[i] = 0.0; t.avz[i] = 0.0;
+                t.fl[0 * FS + s] = 0.0; t.fl[1 * FS + s] = 0.0; t.fl[2 * FS + s] = 0.0;
             }
-            t.avx[i] = 0.0; t.avy[i] = 0.0; t.avz[i] = 0.0;
-            t.fl[0 * kSlots + s] = 0.0; t.fl[1 * kSlots + s] = 0.0; t.fl[2 * kSlots + s] = 0.0;
         }
-        if (nz >= 0) ex |= (1u << i);
         __builtin_amdgcn_sched_barrier(0);   // one slot at a time: keeps register pressure low
     }
     t.exist = ex;
@@ -265,6 +292,7 @@ template <int L>
 __device__ __forceinline__ void track_step(TrackRegs<L>& t, const KernelArgs& A, const SpeciesConst* sp, int sl,
                                            bool fresh, double& ke0, double& z0)
 {
+    constexpr int FS = TrackRegs<L>::FS;
     const SpeciesConst& c = sp[t.species];
     const double M1 = c.M1;
     const double v2 = t.vx * t.vx + t.vy * t.vy + t.vz * t.vz;
@@ -272,14 +300,14 @@ __device__ __forceinline__ void track_step(TrackRegs<L>& t, const KernelArgs& A,
     const double vmax2 = fmax(v2, t.vmax2a);
     const double amax2 = fmax(f2 * c.inv_M1sq, t.amax2a);
     double dt = A.dt_max;
-    if (vmax2 > 0.0) dt = fmin(dt, A.dx_max * rsqrt(vmax2));
-    if (amax2 > 0.0) dt = fmin(dt, sqrt(2.0 * A.dx_max * rsqrt(amax2)));
+    if (vmax2 > 0.0) dt = fmin(dt, A.dx_max * rsqrt_pos(vmax2));
+    if (amax2 > 0.0) dt = fmin(dt, sqrt(2.0 * A.dx_max * rsqrt_pos(amax2)));
     if (fresh) dt = 0.0;
     ke0 = 0.5 * M1 * v2;
     z0 = t.z;
 
     const double h1 = dt * c.half_inv_M1;
-    const double fr1 = exp(-(c.g_const + c.g_rho * t.rho) * h1);
+    const double fr1 = exp_neg((c.g_const + c.g_rho * t.rho) * h1);
     t.vx = t.vx * fr1 + t.Fx * h1;
     t.vy = t.vy * fr1 + t.Fy * h1;
     t.vz = t.vz * fr1 + t.Fz * h1;
@@ -293,29 +321,35 @@ __device__ __forceinline__ void track_step(TrackRegs<L>& t, const KernelArgs& A,
         if (fresh || ncx != t.cx || ncy != t.cy || ncz != t.cz) regenerate<L>(t, A, sl, ncx, ncy, ncz, fresh);
     }
 
-    const double inv_a = c.inv_a, zz = c.zz, inv_lambda = c.inv_lambda, wnorm = c.wnorm;
+    // fused pass over every register slot (parked slots contribute exact zeros):
+    // atom kick and drift, pair term at the new positions, second atom kick
     const double h2 = dt * A.half_inv_M2;
     double Fx = 0.0, Fy = 0.0, Fz = 0.0, rho = 0.0, vm = 0.0, fm = 0.0;
 #pragma unroll
     for (int i = 0; i < TrackRegs<L>::SL; ++i) {
-        if (!((t.exist >> i) & 1u)) continue;
-        const int s = sl + L * i;
-        double vx = t.avx[i] + t.fl[0 * kSlots + s] * h2;
-        double vy = t.avy[i] + t.fl[1 * kSlots + s] * h2;
-        double vz = t.avz[i] + t.fl[2 * kSlots + s] * h2;
+        double* f = t.fl + (sl + L * i);
+        double vx = t.avx[i] + f[0 * FS] * h2;
+        double vy = t.avy[i] + f[1 * FS] * h2;
+        double vz = t.avz[i] + f[2 * FS] * h2;
         const double px = t.ax[i] + vx * dt;
         const double py = t.ay[i] + vy * dt;
         const double pz = t.az[i] + vz * dt;
         const double dx = t.x - px, dy = t.y - py, dz = t.z - pz;
-        double coef, wr;
-        zbl_pair(inv_a, zz, inv_lambda, wnorm, dx, dy, dz, coef, wr);
+        double coef, ew;
+#if REEDMD_SP_RELOAD
+        const SpeciesConst* cp = &c;
+        asm volatile("" : "+v"(cp));   // re-read the species constants for every slot
+        zbl_pair(*cp, dx, dy, dz, coef, ew);
+#else
+        zbl_pair(c, dx, dy, dz, coef, ew);
+#endif
         const double fx = -coef * dx, fy = -coef * dy, fz = -coef * dz;   // force on the atom
         Fx -= fx; Fy -= fy; Fz -= fz;
-        rho += wr;
+        rho += ew;
         vx += fx * h2; vy += fy * h2; vz += fz * h2;
         t.ax[i] = px; t.ay[i] = py; t.az[i] = pz;
         t.avx[i] = vx; t.avy[i] = vy; t.avz[i] = vz;
-        t.fl[0 * kSlots + s] = fx; t.fl[1 * kSlots + s] = fy; t.fl[2 * kSlots + s] = fz;
+        f[0 * FS] = fx; f[1 * FS] = fy; f[2 * FS] = fz;
         vm = fmax(vm, vx * vx + vy * vy + vz * vz);
         fm = fmax(fm, fx * fx + fy * fy + fz * fz);
 #if REEDMD_PAIR_BARRIER
@@ -325,11 +359,11 @@ __device__ __forceinline__ void track_step(TrackRegs<L>& t, const KernelArgs& A,
     t.Fx = SegReduce<L>::sum(Fx);
     t.Fy = SegReduce<L>::sum(Fy);
     t.Fz = SegReduce<L>::sum(Fz);
-    t.rho = SegReduce<L>::sum(rho);
+    t.rho = SegReduce<L>::sum(rho) * c.wnorm;
     t.vmax2a = SegReduce<L>::max(vm);
     t.amax2a = SegReduce<L>::max(fm) * A.inv_M2sq;
 
-    const double fr2 = exp(-(c.g_const + c.g_rho * t.rho) * h1);
+    const double fr2 = exp_neg((c.g_const + c.g_rho * t.rho) * h1);
     t.vx = (t.vx + t.Fx * h1) * fr2;
     t.vy = (t.vy + t.Fy * h1) * fr2;
     t.vz = (t.vz + t.Fz * h1) * fr2;
@@ -369,9 +403,9 @@ __device__ __forceinline__ void store_record(const TrackRegs<L>& t, double* rec,
         at[3 * kSlots + s] = e ? t.avx[i] : 0.0;
         at[4 * kSlots + s] = e ? t.avy[i] : 0.0;
         at[5 * kSlots + s] = e ? t.avz[i] : 0.0;
-        at[6 * kSlots + s] = e ? t.fl[0 * kSlots + s] : 0.0;
-        at[7 * kSlots + s] = e ? t.fl[1 * kSlots + s] : 0.0;
-        at[8 * kSlots + s] = e ? t.fl[2 * kSlots + s] : 0.0;
+        at[6 * kSlots + s] = e ? t.fl[0 * TrackRegs<L>::FS + s] : 0.0;
+        at[7 * kSlots + s] = e ? t.fl[1 * TrackRegs<L>::FS + s] : 0.0;
+        at[8 * kSlots + s] = e ? t.fl[2 * TrackRegs<L>::FS + s] : 0.0;
     }
 }
 
@@ -393,23 +427,28 @@ __device__ __forceinline__ void load_record(TrackRegs<L>& t, const double* rec, 
         t.status = REEDMD_LOST;
     }
     const double* at = rec + kHdr;
+    constexpr int FS = TrackRegs<L>::FS;
+    const KernelArgs C = cold_args();
+    const double parkx = C.a * (static_cast<double>(t.cx) + 0.5);
+    const double parky = C.a * (static_cast<double>(t.cy) + 0.5);
+    const double parkz = C.a * (static_cast<double>(t.cz) + 0.5) - C.park;
     unsigned ex = 0;
     double vm = 0.0, fm = 0.0;
 #pragma unroll
     for (int i = 0; i < TrackRegs<L>::SL; ++i) {
         const int s = sl + L * i;
-        if (s >= kSlots) continue;
         const int cell = s >> 3;
-        const int nz = cell_of_residue(cell % 3, t.cz);
+        if (s >= kSlots || cell_of_residue(cell % 3, t.cz) < 0) {
+            park_slot<L>(t, i, s, parkx, parky, parkz);
+            continue;
+        }
         t.ax[i] = at[0 * kSlots + s]; t.ay[i] = at[1 * kSlots + s]; t.az[i] = at[2 * kSlots + s];
         t.avx[i] = at[3 * kSlots + s]; t.avy[i] = at[4 * kSlots + s]; t.avz[i] = at[5 * kSlots + s];
         const double fx = at[6 * kSlots + s], fy = at[7 * kSlots + s], fz = at[8 * kSlots + s];
-        t.fl[0 * kSlots + s] = fx; t.fl[1 * kSlots + s] = fy; t.fl[2 * kSlots + s] = fz;
-        if (nz >= 0) {
-            ex |= (1u << i);
-            vm = fmax(vm, t.avx[i] * t.avx[i] + t.avy[i] * t.avy[i] + t.avz[i] * t.avz[i]);
-            fm = fmax(fm, fx * fx + fy * fy + fz * fz);
-        }
+        t.fl[0 * FS + s] = fx; t.fl[1 * FS + s] = fy; t.fl[2 * FS + s] = fz;
+        ex |= (1u << i);
+        vm = fmax(vm, t.avx[i] * t.avx[i] + t.avy[i] * t.avy[i] + t.avz[i] * t.avz[i]);
+        fm = fmax(fm, fx * fx + fy * fy + fz * fz);
     }
     t.exist = ex;
     t.n_exist = SegReduce<L>::isum(__popc(ex));

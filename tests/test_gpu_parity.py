@@ -100,7 +100,7 @@ def assert_records_close(got, ref, rtol=1e-10, what=""):
 
 # ----------------------------------------------------------------------------- exp
 def test_library_exponential_is_accurate(R):
-    """The kernels' exp(-y) (Cody-Waite + Taylor) against numpy's exp: <= 4 ulp relative over
+    """The kernels' exp(-y) (Cody-Waite + minimax polynomial) against numpy's exp: <= 4 ulp over
     the argument range of the force terms, and the gradual-underflow tail."""
     y = np.concatenate([np.linspace(0.0, 50.0, 200001), np.geomspace(1e-12, 700.0, 100001),
                         np.linspace(700.0, 745.0, 1001)])
