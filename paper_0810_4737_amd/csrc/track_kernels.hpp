@@ -243,12 +243,71 @@ __device__ __forceinline__ void park_slot(TrackRegs<L>& t, int i, int s, double 
     t.fl[0 * FS + s] = 0.0; t.fl[1 * FS + s] = 0.0; t.fl[2 * FS + s] = 0.0;
 }
 
+// Position of the k-th set bit (from 0) of m, k < popcount(m).
+__device__ __forceinline__ int kth_set_bit(unsigned m, int k)
+{
+    int pos = 0;
+#pragma unroll
+    for (int w = 16; w >= 1; w >>= 1) {
+        const int c = __popc(m & ((1u << w) - 1u));
+        if (k >= c) {
+            k -= c;
+            m >>= w;
+            pos += w;
+        }
+    }
+    return pos;
+}
+
+// Bit c set: ring cell c (residues c / 9, c / 3 % 3, c % 3) holds a different
+// unit cell around the new centre than around the old one (every cell when
+// `all`) and that cell lies in the crystal.  One ballot per 27 cells over the
+// segment's lanes; the result is the same in every lane of the segment.
+template <int L>
+__device__ __forceinline__ unsigned new_cell_mask(int sl, int ncx, int ncy, int ncz, int ocx, int ocy, int ocz,
+                                                  bool all)
+{
+    const int base = (threadIdx.x & 63) - sl;
+    unsigned m = 0;
+#pragma unroll
+    for (int pass = 0; pass * L < 27; ++pass) {
+        const int c = pass * L + sl;
+        const int rx = c / 9, ry = (c / 3) % 3, rz = c % 3;
+        const int nz = cell_of_residue(rz, ncz);
+        const bool changed = all || cell_of_residue(rx, ncx) != cell_of_residue(rx, ocx) ||
+                             cell_of_residue(ry, ncy) != cell_of_residue(ry, ocy) || nz != cell_of_residue(rz, ocz);
+        const unsigned long long b = __ballot(c < 27 && changed && nz >= 0);
+        const unsigned long long seg = (L == 64) ? b : ((b >> base) & ((1ull << (L % 64)) - 1ull));
+        m |= static_cast<unsigned>(seg) << (pass * L);
+    }
+    return m;
+}
+
 template <int L>
 __device__ __forceinline__ void regenerate(TrackRegs<L>& t, const KernelArgs& A, int sl, int ncx,
                                            int ncy, int ncz, bool all)
 {
     constexpr int FS = TrackRegs<L>::FS;
     const KernelArgs C = cold_args();
+    const unsigned newc = new_cell_mask<L>(sl, ncx, ncy, ncz, t.cx, t.cy, t.cz, all);
+    // The 8 atoms of every new cell are created spread evenly over the lanes of
+    // the segment (a face shift creates 72 of the 216), and each position is
+    // staged in the force entries of its slot, which the new atom discards.
+    const int n_new = 8 * __popc(newc);
+    for (int idx = sl; idx < n_new; idx += L) {
+        const int cell = kth_set_bit(newc, idx >> 3), b = idx & 7;
+        const int rx = cell / 9, ry = (cell / 3) % 3, rz = cell % 3;
+        const double3 p = create_atom(t.key, C.seed, cell_of_residue(rx, ncx), cell_of_residue(ry, ncy),
+                                      cell_of_residue(rz, ncz), b, C.a, C.sigma);
+        const int s = cell * 8 + b;
+        t.fl[0 * FS + s] = p.x;
+        t.fl[1 * FS + s] = p.y;
+        t.fl[2 * FS + s] = p.z;
+    }
+    // positions written by other lanes of this wavefront are read below
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     const double parkx = C.a * (static_cast<double>(ncx) + 0.5);
     const double parky = C.a * (static_cast<double>(ncy) + 0.5);
     const double parkz = C.a * (static_cast<double>(ncz) + 0.5) - C.park;
@@ -256,29 +315,19 @@ __device__ __forceinline__ void regenerate(TrackRegs<L>& t, const KernelArgs& A,
 #pragma unroll
     for (int i = 0; i < TrackRegs<L>::SL; ++i) {
         const int s = sl + L * i;
-        if (s >= kSlots) {
+        const int cell = s >> 3;
+        if (s >= kSlots || cell_of_residue(cell % 3, ncz) < 0) {
             park_slot<L>(t, i, s, parkx, parky, parkz);
             continue;
         }
-        const int cell = s >> 3, b = s & 7;
-        const int rx = cell / 9, ry = (cell / 3) % 3, rz = cell % 3;
-        const int nx = cell_of_residue(rx, ncx), ny = cell_of_residue(ry, ncy), nz = cell_of_residue(rz, ncz);
-        const bool changed = all || nx != cell_of_residue(rx, t.cx) || ny != cell_of_residue(ry, t.cy) ||
-                             nz != cell_of_residue(rz, t.cz);
-        if (nz < 0) {
-            park_slot<L>(t, i, s, parkx, parky, parkz);
-        } else {
-            ex |= (1u << i);
-            if (changed) {
-                const double3 p = create_atom(t.key, C.seed, nx, ny, nz, b, C.a, C.sigma);
-                t.ax[i] = p.x;
-                t.ay[i] = p.y;
-                t.az[i] = p.z;
-                t.avx[i] = 0.0; t.avy[i] = 0.0; t.avz[i] = 0.0;
-                t.fl[0 * FS + s] = 0.0; t.fl[1 * FS + s] = 0.0; t.fl[2 * FS + s] = 0.0;
-            }
+        ex |= (1u << i);
+        if ((newc >> cell) & 1u) {
+            t.ax[i] = t.fl[0 * FS + s];
+            t.ay[i] = t.fl[1 * FS + s];
+            t.az[i] = t.fl[2 * FS + s];
+            t.avx[i] = 0.0; t.avy[i] = 0.0; t.avz[i] = 0.0;
+            t.fl[0 * FS + s] = 0.0; t.fl[1 * FS + s] = 0.0; t.fl[2 * FS + s] = 0.0;
         }
-        __builtin_amdgcn_sched_barrier(0);   // one slot at a time: keeps register pressure low
     }
     t.exist = ex;
     t.cx = ncx; t.cy = ncy; t.cz = ncz;
