@@ -26,6 +26,29 @@ sys.path.insert(0, ROOT)
 FLOP_PER_PAIR = 67
 FP64_VECTOR_PEAK_TFLOPS = 78.6   # 256 CU x 2.4 GHz x 128 FP64 FLOP/clk/CU
 
+# HBM bytes per launch of the track kernel measured with rocprofv3 --pmc FETCH_SIZE and
+# WRITE_SIZE (separate runs), scaled by the same counters on a 1 GiB copy (FETCH x 2.000,
+# WRITE x 1.000); reported only while the kernel sources and the launch match the ones the
+# counters were taken on.
+MEASURED_TRAFFIC = {
+    "sources_sha256_prefix": "9171e348c21e5dd3",
+    "workload": "c1", "form": "persistent", "lanes": 16,
+    "fetch_bytes": 2608002.875 * 1024 * 2.000,
+    "write_bytes": 5175175.0625 * 1024 * 1.000,
+}
+
+
+def kernel_sources_hash():
+    import glob
+    import hashlib
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_0810_4737_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(here, "*.hpp")) + glob.glob(os.path.join(here, "*.hip"))):
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -246,6 +269,11 @@ def main():
     kms = sum(kernel_ms) / len(kernel_ms)
     pairs_per_launch = pairs / args.steps
     achieved = FLOP_PER_PAIR * pairs_per_launch / (kms * 1e-3) / 1e12
+    m = MEASURED_TRAFFIC
+    traffic = None
+    if (kernel_sources_hash() == m["sources_sha256_prefix"] and args.workload == m["workload"]
+            and cfg.form == R.FORM_PERSISTENT and shape["lanes"] == m["lanes"] and n == WORKLOADS[wname]["n"]):
+        traffic = m["fetch_bytes"] + m["write_bytes"]
     descr = {
         "c1": "c1_as10kev: 65,536 As at 10 keV into diamond Si (a=5.431 A, sigma=0.076 A), "
               "half within 0.5 deg of [110], half at 7 deg tilt; ZBL + local LSS k=1; "
@@ -289,7 +317,7 @@ def main():
             "peak": FP64_VECTOR_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
-            "traffic": None,
+            "traffic": traffic,
             "kernel": "track_kernel (reedmd_run)",
             "kernel_ms": kms,
             "flop_per_pair": FLOP_PER_PAIR,
