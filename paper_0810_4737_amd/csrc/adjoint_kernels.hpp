@@ -288,14 +288,25 @@ __device__ __forceinline__ void unstash_adjoint(AdjAtoms<L>& aa, const double* b
     }
 }
 
-// One wavefront per primary (batch entry).  Writes gout[q] = {z_stop, dz/dk,
-// dz/ds, status, steps}; derivatives are zero unless the track stopped.
-__global__ void __launch_bounds__(256, 1) grad_kernel(const KernelArgs A)
+#ifndef REEDMD_GRAD_WAVES_PER_SIMD
+#define REEDMD_GRAD_WAVES_PER_SIMD 1
+#endif
+
+// One wavefront per primary (batch entry), launched as one-wavefront
+// workgroups: tracks differ in length by orders of magnitude, and a finished
+// wavefront frees its SIMD for the next track at once.  Writes gout[q] =
+// {z_stop, dz/dk, dz/ds, status, steps}; derivatives are zero unless the track
+// stopped.
+__global__ void __launch_bounds__(64, REEDMD_GRAD_WAVES_PER_SIMD) grad_kernel(const KernelArgs A)
 {
     constexpr int L = 64;
     __shared__ SpeciesConst s_sp[kMaxSpecies];
-    __shared__ double s_force[ForceLds<L>::kDoubles];
-    const SpeciesConst* sp = stage_species(A, s_sp);
+    __shared__ double s_force[3 * ForceLds<L>::kStride];
+    constexpr int kWords = sizeof(SpeciesConst) * kMaxSpecies / sizeof(double);
+    for (int i = threadIdx.x; i < kWords; i += blockDim.x)
+        reinterpret_cast<double*>(s_sp)[i] = reinterpret_cast<const double*>(A.sp)[i];
+    __syncthreads();
+    const SpeciesConst* sp = s_sp;
     const int sl = threadIdx.x & 63;
     const long long local = static_cast<long long>(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const long long q = A.q0 + local;

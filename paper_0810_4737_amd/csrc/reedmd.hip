@@ -28,7 +28,7 @@ constexpr double kMinScreening = 0.01;         // accepted range of the screenin
 constexpr double kMaxScreening = 100.0;        // keeps every exponent argument below 1e9
 constexpr long long kDefaultGradSteps = 16384;    // gradient step cap when the caller sets none
 constexpr int kTuneBoxMs = 400;                   // autotuner: time box of each candidate launch
-constexpr size_t kGradScratchBytes = size_t(16) << 30;   // checkpoint memory per launch chunk
+constexpr size_t kGradScratchBytes = size_t(48) << 30;   // checkpoint memory per launch chunk
 
 thread_local std::string g_create_error;
 
@@ -729,8 +729,7 @@ reedmd_status reedmd_grad(reedmd_ctx* ctx, const reedmd_species* species, const 
         A.q0 = q0;
         A.q_end = std::min(n, q0 + chunk);
         const long long waves = A.q_end - q0;
-        const long long blocks = (waves + 3) / 4;
-        hipLaunchKernelGGL(grad_kernel, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, stream, A);
+        hipLaunchKernelGGL(grad_kernel, dim3(static_cast<unsigned>(waves)), dim3(64), 0, stream, A);
         HIP_TRY(ctx, hipGetLastError());
     }
     hipLaunchKernelGGL(grad_reduce_kernel, dim3(1), dim3(256), 0, stream, A.gout, n, res);
