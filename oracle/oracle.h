@@ -30,6 +30,18 @@
  *
  * Units: length in Angstrom, energy in eV, mass in amu; time in
  * tau = sqrt(amu * A^2 / eV) = 10.18 fs (the unit quoted with Fig. 2).
+ *
+ * Pins (tests/test_oracle_pins.py, each against something other than this
+ * code): Philox against numpy's generator; the ZBL potential, its derivative,
+ * screening length and nuclear stopping against closed forms and published
+ * fits; the stopping constant against Lindhard's reduced form; pure friction
+ * and the collision-free stopping depth and its k-derivative against closed
+ * forms; head-on turning points and scattering angles against root finding and
+ * quadrature; energy, momentum and weight ledgers; splitting against brute
+ * force; the forward-mode derivative against finite differences of the
+ * oracle's own stopping depth.  The absolute range profile of a full run is
+ * parity unpinned against the paper (it prints no profile values and its
+ * figures are not available); it is only compared with the GPU library.
  */
 #ifndef REEDMD_ORACLE_H
 #define REEDMD_ORACLE_H

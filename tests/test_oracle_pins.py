@@ -437,3 +437,61 @@ def test_sampler_distributions():
     # distinct primaries get distinct keys; the same id always gets the same key
     assert len(set(pr["key"].tolist())) == n
     assert oracle.sample_primaries(sc, 0, 5, id0=10)["key"].tolist() == pr["key"][10:15].tolist()
+
+
+# --------------------------------------------------------------------------- derivative
+def test_forward_mode_derivative_matches_closed_form_without_collisions():
+    """Nuclear force off, uniform stopping: the stopping depth is z0 + L with
+    L = 2 (sqrt(E0) - sqrt(E_stop)) / (k N kL), so dz/dk = -L / k and dz/ds = 0.  The
+    forward-mode derivative of the discrete map approaches the closed form as the step
+    shrinks (O(dx_max): 2-3e-4 at 0.05 A, 3-5e-5 at 0.01 A, 1e-5 at 0.002 A); at
+    dx_max = 0.05 A, where no step count changes within +-h, it equals central differences
+    of the same map to 1e-7."""
+    for sp, E0, k in ((B, 1000.0, 1.0), (P, 5000.0, 1.3)):
+        errs = []
+        for dx in (0.05, 0.01):
+            c = cfg(pot_mode=oracle.POT_NONE, stop_mode=oracle.STOP_UNIFORM, k=k, dx_max=dx)
+            st, z, dk, ds, n = oracle.grad_track(c, sp, E0, [0.0, 0.0, -3.0], [0.0, 0.0, 1.0], 1)
+            assert st == oracle.STOPPED and ds == 0.0
+            errs.append(abs(dk / (-(z + 3.0) / k) - 1.0))
+        assert errs[1] < 1e-4 and errs[1] < errs[0] / 3, (sp, errs)
+    for sp, E0, k in ((B, 1000.0, 1.0), (P, 5000.0, 1.3)):
+        def z_of(kk):
+            c = cfg(pot_mode=oracle.POT_NONE, stop_mode=oracle.STOP_UNIFORM, k=kk)
+            return oracle.grad_track(c, sp, E0, [0.0, 0.0, -3.0], [0.0, 0.0, 1.0], 1)
+        dk = z_of(k)[2]
+        fd = (z_of(k + 1e-6)[1] - z_of(k - 1e-6)[1]) / 2e-6
+        assert abs(dk / fd - 1.0) < 1e-7, (sp, dk, fd)
+
+
+def test_forward_mode_derivative_matches_finite_differences_on_short_tracks():
+    """ZBL collisions and local stopping on: on short 300 eV B tracks the forward-mode
+    derivatives equal central differences of the oracle's own stopping depth to 2e-5,
+    on the tracks where differences at two step sizes agree to 1e-5 (the linear regime of
+    the discrete map: the paths are chaotic, so d/ds needs h <= 1e-7)."""
+    c = cfg(species=("B",))
+    sc = oracle.SamplerCfg(choice=(0,), E_min=300.0, E_max=300.0, tilt=math.radians(7.0))
+    pr = oracle.sample_primaries(sc, 3, 16)
+    steps = {"k": (1e-6, 1e-7), "s": (1e-7, 1e-8)}
+    checked = {"k": 0, "s": 0}
+    for i in range(16):
+        args = (0, pr["E0"][i], pr["pos"][:, i], pr["dir"][:, i], int(pr["key"][i]))
+        st, z, dk, ds, n = oracle.grad_track(c, *args)
+        if st != oracle.STOPPED:
+            continue
+        for name, d in (("k", dk), ("s", ds)):
+            fd = []
+            for h in steps[name]:
+                zz = []
+                for sign in (1, -1):
+                    kw = {"k": c.k, "s": c.s}
+                    kw[name] += sign * h
+                    r = oracle.grad_track(cfg(species=("B",), **kw), *args)
+                    zz.append(r[1] if r[0] == oracle.STOPPED else float("nan"))
+                fd.append((zz[0] - zz[1]) / (2 * h))
+            scale = max(abs(fd[0]), 1e-3)
+            if not np.all(np.isfinite(fd)) or abs(fd[0] - fd[1]) > 1e-5 * scale:
+                continue
+            checked[name] += 1
+            assert abs(d - fd[0]) <= 2e-5 * scale, (i, name, d, fd)
+    assert checked["k"] >= 4 and checked["s"] >= 4, checked
