@@ -98,12 +98,13 @@ __device__ __forceinline__ void thermal_gauss(uint64_t key, uint64_t seed, int c
                                   static_cast<uint64_t>(static_cast<int64_t>(cx)),
                                   static_cast<uint64_t>(static_cast<int64_t>(cy)),
                                   static_cast<uint64_t>(static_cast<int64_t>(cz)), key, seed);
-    constexpr double kTwoPi = 6.283185307179586476925286766559;
     const double rad0 = sqrt(-2.0 * log(open_unit(r.w[0])));
     const double rad1 = sqrt(-2.0 * log(open_unit(r.w[2])));
+    // the angle is 2 pi u with u in (0, 1): sin and cos of pi (2u), where 2u is
+    // exact, need no reduction of a large argument
     double s0, c0, s1, c1;
-    sincos(kTwoPi * open_unit(r.w[1]), &s0, &c0);
-    sincos(kTwoPi * open_unit(r.w[3]), &s1, &c1);
+    sincospi(2.0 * open_unit(r.w[1]), &s0, &c0);
+    sincospi(2.0 * open_unit(r.w[3]), &s1, &c1);
     gx = rad0 * c0;
     gy = rad0 * s0;
     gz = rad1 * c1;
