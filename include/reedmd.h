@@ -209,6 +209,34 @@ reedmd_status reedmd_run(reedmd_ctx* ctx, const reedmd_species* species, const r
                          const reedmd_run_params* params, double* d_hist, reedmd_stats* d_stats,
                          hipStream_t stream);
 
+/* Adaptive cloning depths (Sec. 2: the depths are placed from the statistics
+ * gathered so far; Sec. 3: criteria are updated between complete tracks). */
+typedef struct {
+    int32_t n_epochs;       /* the batch runs in n_epochs consecutive id ranges, 1..4096 */
+    int32_t reserved;
+    const double* probs;    /* host, n_thresh target survival probabilities, strictly decreasing in (0,1) */
+    double min_gap;         /* minimum spacing of successive depths (A), >= 0 */
+} reedmd_refine;
+
+/* Like reedmd_run, with the cloning depths refined between epochs.  Epoch e
+ * runs batch entries [n e / E, n (e+1) / E) with the depth tables in force;
+ * params->thresholds (device, n_tables x n_thresh) are those of epoch 0.
+ * Before epoch e > 0 every table is re-placed from all tracks of that table
+ * booked so far: with S(z) = (weight stopped at z_stop >= z) / (all weight
+ * booked for the table) on the histogram's bin edges, depth k is where S falls
+ * to probs[k] (linear in S within the bin); a target that S does not reach
+ * within the histogram keeps its previous depth; the depths are then made
+ * increasing by at least min_gap.  New depths apply only to primaries started
+ * later, so every primary family keeps one depth table and the estimator stays
+ * unbiased.  d_hist, d_stats and the optional track log accumulate over all
+ * epochs as in reedmd_run; d_depths (device, optional, n_epochs x n_tables x
+ * n_thresh doubles) receives the tables each epoch ran with; params->thresholds
+ * is not modified.  Allocates its work buffers, synchronises the stream.
+ * EINVAL for invalid settings (n_thresh >= 1 is required). */
+reedmd_status reedmd_run_refined(reedmd_ctx* ctx, const reedmd_species* species, const reedmd_batch* batch,
+                                 const reedmd_run_params* params, const reedmd_refine* rf, double* d_hist,
+                                 reedmd_stats* d_stats, double* d_depths, hipStream_t stream);
+
 /* Builds the starting record (ion, its full domain and the forces at the
  * start point) of each batch entry into d_records (device, n *
  * REEDMD_RECORD_WORDS 64-bit words).  Record layout: words 0-2 ion position,

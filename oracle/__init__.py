@@ -378,3 +378,76 @@ def run(cfg: Config, prim: dict, nthreads: int | None = None, log: bool = False,
         arr = np.ctypeslib.as_array(logbuf)[:m]
         out["log"] = np.array(arr)
     return out
+
+
+# --------------------------------------------------------------------------- adaptive depths
+def refine_depths(tstat, n_bins: int, bin_width: float, probs, old, min_gap: float):
+    """Cloning depths re-placed from the statistics gathered so far (Sec. 2: depths from the
+    ongoing statistics; Sec. 3: criteria updated between complete tracks).
+
+    tstat[t] = (stopped weight in each of the n_bins depth bins, stopped weight beyond the
+    last bin, all weight booked for table t).  The survival S(z) = (stopped weight with
+    z_stop >= z) / (all booked weight) is taken at the bin edges; depth k of table t is where
+    S falls to probs[k], linear in S inside the bin; a target that S does not reach within
+    the histogram keeps the old depth; finally each depth is raised to at least the previous
+    one plus min_gap."""
+    tstat = np.asarray(tstat, dtype=np.float64)
+    new = np.array(np.atleast_2d(old), dtype=np.float64, copy=True)
+    for t in range(new.shape[0]):
+        h = tstat[t, :n_bins]
+        over, total = tstat[t, n_bins], tstat[t, n_bins + 1]
+        if total > 0.0:
+            beyond = np.append(np.cumsum(h[::-1])[::-1], 0.0) + over   # at edges 0 .. n_bins
+            S = beyond / total
+            for k, pk in enumerate(probs):
+                below = np.nonzero(S[1:] <= pk)[0]      # bins whose upper edge is at or below pk
+                if below.size == 0:
+                    continue
+                b = int(below[0])
+                lo, hi = S[b], S[b + 1]
+                new[t, k] = (b + (lo - pk) / (lo - hi)) * bin_width if pk < lo else b * bin_width
+        for k in range(1, new.shape[1]):
+            new[t, k] = max(new[t, k], new[t, k - 1] + min_gap)
+    return new
+
+
+def table_stats(log, tables, n_tables: int, n_bins: int, bin_width: float):
+    """Per-table statistics of finished tracks (see refine_depths) from a track log;
+    tables[i] is the depth table of the track with lineage i."""
+    ts = np.zeros((n_tables, n_bins + 2))
+    for lin, st, z, w in zip(log["lineage"], log["status"], log["z_stop"], log["w"]):
+        t = int(tables[int(lin)])
+        ts[t, n_bins + 1] += w
+        if st == STOPPED and z >= 0.0:
+            b = int(np.floor(z / bin_width))
+            ts[t, b if b < n_bins else n_bins] += w
+    return ts
+
+
+def run_refined(cfg: Config, prim: dict, n_epochs: int, probs, min_gap: float = 1.0,
+                nthreads: int | None = None):
+    """The batch in n_epochs consecutive id ranges (epoch e: ids [n e / E, n (e+1) / E)), the
+    depth tables re-placed before every epoch after the first from all tracks finished so far
+    (refine_depths); cfg.thresholds are the tables of epoch 0.  Returns dict(hist, stats,
+    depths [E, n_tables, n_thresh], log)."""
+    n = int(prim["E0"].shape[0])
+    E = max(1, min(int(n_epochs), n))
+    thr = np.array(np.atleast_2d(cfg.thresholds), dtype=np.float64)
+    ts = np.zeros((thr.shape[0], cfg.n_bins + 2))
+    hist = np.zeros(cfg.n_bins)
+    stats, logs, depths = {}, [], []
+    for e in range(E):
+        lo, hi = n * e // E, n * (e + 1) // E
+        if e > 0:
+            thr = refine_depths(ts, cfg.n_bins, cfg.bin_width, probs, thr, min_gap)
+        depths.append(thr.copy())
+        sub = {k: v[..., lo:hi] for k, v in prim.items()}
+        c = Config(**{**cfg.__dict__, "thresholds": thr})
+        r = run(c, sub, nthreads=nthreads, log=True, lineage=np.arange(lo, hi, dtype=np.int64))
+        hist += r["hist"]
+        for k, v in r["stats"].items():
+            stats[k] = stats.get(k, 0) + v
+        ts += table_stats(r["log"], prim["table"], thr.shape[0], cfg.n_bins, cfg.bin_width)
+        logs.append(r["log"])
+    return dict(hist=hist, stats=stats, depths=np.array(depths), log=np.concatenate(logs),
+                nthreads=r["nthreads"])

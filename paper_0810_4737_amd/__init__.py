@@ -228,6 +228,39 @@ def run(ctx: Context, species, batch, cfg: RunConfig, hist=None, stats=None, id0
     return hist, stats, keep
 
 
+def run_refined(ctx: Context, species, batch, cfg: RunConfig, n_epochs: int, probs, min_gap: float = 1.0,
+                hist=None, stats=None, id0=0, log_cap=0, stream=None):
+    """Runs the batch in n_epochs epochs with the cloning depths re-placed between epochs from
+    the survival of the tracks booked so far (cfg.thresholds: the tables of epoch 0).
+    Returns (hist, stats, depths[n_epochs, n_tables, n_thresh][, log])."""
+    dev = batch["energy"].device
+    keep = []
+    p = cfg.struct(dev, keep)
+    if hist is None:
+        hist = torch.zeros(cfg.n_bins, dtype=torch.float64, device=dev)
+    if stats is None:
+        stats = new_stats(dev)
+    log = None
+    if log_cap > 0:
+        log = torch.zeros((log_cap, 5), dtype=torch.int64, device=dev)
+        p.track_log = log.data_ptr()
+        p.track_log_cap = log_cap
+    pr = np.ascontiguousarray(np.asarray(probs, dtype=np.float64))
+    rf = _abi.Refine()
+    rf.n_epochs = int(n_epochs)
+    rf.probs = pr.ctypes.data_as(C.POINTER(C.c_double))
+    rf.min_gap = float(min_gap)
+    depths = torch.zeros((max(1, min(int(n_epochs), int(batch["energy"].shape[0]))), p.n_tables, p.n_thresh),
+                         dtype=torch.float64, device=dev)
+    sp = species_table(species) if not isinstance(species, _abi.Species) else species
+    b = _batch_struct(batch, id0)
+    ctx.check(ctx._lib.reedmd_run_refined(ctx.handle, C.byref(sp), C.byref(b), C.byref(p), C.byref(rf),
+                                          _ptr(hist), _ptr(stats), _ptr(depths), _stream(stream)))
+    if log is not None:
+        return hist, stats, depths, log
+    return hist, stats, depths
+
+
 def parse_log(log: torch.Tensor, count: int):
     raw = log[:count].detach().cpu().numpy()
     dt = np.dtype([("lineage", np.int64), ("status", np.int32), ("next_k", np.int32),

@@ -62,6 +62,11 @@ class RunParams(C.Structure):
                 ("track_log_cap", C.c_int64)]
 
 
+class Refine(C.Structure):
+    _fields_ = [("n_epochs", C.c_int32), ("reserved", C.c_int32), ("probs", C.POINTER(C.c_double)),
+                ("min_gap", C.c_double)]
+
+
 class Result(C.Structure):
     _fields_ = [("lineage", C.c_int64), ("status", C.c_int32), ("next_k", C.c_int32),
                 ("z_stop", C.c_double), ("w", C.c_double), ("steps", C.c_int64)]
@@ -77,7 +82,8 @@ STATS_WORDS = len(STATS_INT_A) + len(STATS_DBL) + len(STATS_INT_B)
 # every entry point declared in include/reedmd.h
 EXPORTS = ("reedmd_version", "reedmd_create", "reedmd_destroy", "reedmd_last_error",
            "reedmd_sample_primaries", "reedmd_run", "reedmd_track_init", "reedmd_debug_step",
-           "reedmd_autotune", "reedmd_grad", "reedmd_eval_exp_neg", "reedmd_launch_shape")
+           "reedmd_autotune", "reedmd_grad", "reedmd_eval_exp_neg", "reedmd_launch_shape",
+           "reedmd_run_refined")
 
 _lib = None
 
@@ -117,5 +123,7 @@ def load():
     L.reedmd_eval_exp_neg.restype = C.c_int
     L.reedmd_launch_shape.argtypes = [V, P(Batch), P(RunParams), P(C.c_int64)]
     L.reedmd_launch_shape.restype = C.c_int
+    L.reedmd_run_refined.argtypes = [V, P(Species), P(Batch), P(RunParams), P(Refine), V, V, V, V]
+    L.reedmd_run_refined.restype = C.c_int
     _lib = L
     return L

@@ -368,7 +368,7 @@ Shape choose_shape(reedmd_ctx* ctx, const reedmd_run_params* p, const reedmd_bat
 
 reedmd_status run_impl(reedmd_ctx* ctx, const reedmd_species* sp, const reedmd_batch* b,
                        const reedmd_run_params* p, double* d_hist, reedmd_stats* d_stats, hipStream_t stream,
-                       const Shape* forced)
+                       const Shape* forced, double* d_tstat = nullptr)
 {
     Shape s = forced ? *forced : choose_shape(ctx, p, b);
     const int qcap = s.qcap > 0 ? s.qcap : 1;
@@ -381,6 +381,7 @@ reedmd_status run_impl(reedmd_ctx* ctx, const reedmd_species* sp, const reedmd_b
     fill_batch(b, A);
     A.hist = d_hist;
     A.stats = d_stats;
+    A.tstat = d_tstat;
     A.log = static_cast<reedmd_result*>(p->track_log);
     A.log_cap = p->track_log ? p->track_log_cap : 0;
     A.stack = ctx->stack;
@@ -438,6 +439,41 @@ reedmd_status run_impl(reedmd_ctx* ctx, const reedmd_species* sp, const reedmd_b
     }
     HIP_TRY(ctx, enqueue(stream));
     return REEDMD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Adaptive cloning depths (Sec. 2: depths placed from the statistics gathered
+// so far; Sec. 3: criteria updated between complete tracks).  For every depth
+// table t, from its booked tracks: S(z) = (stopped weight with z_stop >= z) /
+// (all weight booked for the table), evaluated at bin edges; depth k is where
+// S falls to probs[k], linear in S within the bin; a target the histogram does
+// not resolve (S at its end still above it) keeps the previous depth; the
+// depths are then made increasing by at least min_gap.  One thread per table.
+__global__ void refine_kernel(const double* tstat, int n_bins, double bin_width, int n_tables, int n_thresh,
+                              const double* probs, double min_gap, double* thr)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_tables) return;
+    const double* h = tstat + static_cast<size_t>(t) * (n_bins + 2);
+    double* d = thr + static_cast<size_t>(t) * n_thresh;
+    const double total = h[n_bins + 1];
+    if (total > 0.0) {
+        double beyond = h[n_bins];                 // stopped weight at or beyond the lower edge of bin b
+        for (int b = n_bins - 1; b >= 0; --b) beyond += h[b];
+        double s_lo = beyond / total;
+        int k = 0;
+        for (int b = 0; b < n_bins && k < n_thresh; ++b) {
+            beyond -= h[b];
+            const double s_hi = beyond / total;
+            while (k < n_thresh && probs[k] >= s_hi) {
+                d[k] = (probs[k] < s_lo) ? (static_cast<double>(b) + (s_lo - probs[k]) / (s_lo - s_hi)) * bin_width
+                                         : static_cast<double>(b) * bin_width;
+                ++k;
+            }
+            s_lo = s_hi;
+        }
+    }
+    for (int k = 1; k < n_thresh; ++k) d[k] = fmax(d[k], d[k - 1] + min_gap);
 }
 
 // ---------------------------------------------------------------------------
@@ -834,6 +870,108 @@ reedmd_status reedmd_autotune(reedmd_ctx* ctx, const reedmd_species* species, co
     if (best_lanes) *best_lanes = bl;
     if (best_waves) *best_waves = bw;
     return REEDMD_OK;
+}
+
+reedmd_status reedmd_run_refined(reedmd_ctx* ctx, const reedmd_species* species, const reedmd_batch* batch,
+                                 const reedmd_run_params* params, const reedmd_refine* rf, double* d_hist,
+                                 reedmd_stats* d_stats, double* d_depths, hipStream_t stream)
+{
+    if (!ctx) return fail(nullptr, REEDMD_EINVAL, "ctx is NULL");
+    reedmd_status st;
+    if ((st = check_species(ctx, species)) != REEDMD_OK) return st;
+    if ((st = check_batch(ctx, batch)) != REEDMD_OK) return st;
+    if ((st = check_params(ctx, params, true)) != REEDMD_OK) return st;
+    if (!d_hist || !d_stats) return fail(ctx, REEDMD_EINVAL, "d_hist and d_stats must be non-NULL");
+    if (!rf || !rf->probs) return fail(ctx, REEDMD_EINVAL, "refine settings and probs must be non-NULL");
+    if (params->n_thresh < 1) return fail(ctx, REEDMD_EINVAL, "adaptive depths need n_thresh >= 1");
+    if (rf->n_epochs < 1 || rf->n_epochs > 4096) return fail(ctx, REEDMD_EINVAL, "n_epochs must be in 1..4096");
+    if (!(rf->min_gap >= 0.0) || !std::isfinite(rf->min_gap)) return fail(ctx, REEDMD_EINVAL, "min_gap must be >= 0");
+    for (int k = 0; k < params->n_thresh; ++k) {
+        const double pk = rf->probs[k];
+        if (!(pk > 0.0 && pk < 1.0) || (k > 0 && !(pk < rf->probs[k - 1])))
+            return fail(ctx, REEDMD_EINVAL, "probs must decrease strictly inside (0, 1)");
+    }
+    const long long n = batch->n;
+    if (n == 0) return REEDMD_OK;
+    const int E = static_cast<int>(std::min<long long>(rf->n_epochs, n));
+    const int nt = params->n_tables, nk = params->n_thresh, nb = params->n_bins;
+    const long long m = (n + E - 1) / E;   // largest epoch
+    // work buffers: depth tables, per-table statistics, targets, one epoch of primaries
+    const size_t thr_b = sizeof(double) * nt * nk, ts_b = sizeof(double) * nt * (nb + 2), pr_b = sizeof(double) * nk;
+    const size_t sub_b = static_cast<size_t>(m) * (sizeof(int) * 2 + sizeof(double) * 7 + sizeof(unsigned long long));
+    char* work = nullptr;
+    HIP_TRY(ctx, hipMalloc(reinterpret_cast<void**>(&work), thr_b + ts_b + pr_b + sub_b + 256));
+    double* thr = reinterpret_cast<double*>(work);
+    double* tstat = thr + nt * nk;
+    double* probs = tstat + static_cast<size_t>(nt) * (nb + 2);
+    double* sub_energy = probs + nk;
+    double* sub_pos = sub_energy + m;
+    double* sub_dir = sub_pos + 3 * m;
+    unsigned long long* sub_key = reinterpret_cast<unsigned long long*>(sub_dir + 3 * m);
+    int* sub_species = reinterpret_cast<int*>(sub_key + m);
+    int* sub_table = sub_species + m;
+    auto body = [&]() -> reedmd_status {
+        HIP_TRY(ctx, hipMemcpyAsync(thr, params->thresholds, thr_b, hipMemcpyDeviceToDevice, stream));
+        HIP_TRY(ctx, hipMemsetAsync(tstat, 0, ts_b, stream));
+        HIP_TRY(ctx, hipMemcpyAsync(probs, rf->probs, pr_b, hipMemcpyHostToDevice, stream));
+        reedmd_run_params p = *params;
+        p.thresholds = thr;
+        reedmd_result* log0 = static_cast<reedmd_result*>(params->track_log);
+        int64_t log_done = 0;
+        reedmd_stats h0{};
+        if (log0) {
+            HIP_TRY(ctx, hipMemcpyAsync(&h0, d_stats, sizeof(h0), hipMemcpyDeviceToHost, stream));
+            HIP_TRY(ctx, hipStreamSynchronize(stream));
+        }
+        for (int e = 0; e < E; ++e) {
+            const long long lo = n * e / E, hi = n * (e + 1) / E, ne = hi - lo;
+            if (e > 0)
+                hipLaunchKernelGGL(refine_kernel, dim3((nt + 63) / 64), dim3(64), 0, stream, tstat, nb,
+                                   params->bin_width, nt, nk, probs, rf->min_gap, thr);
+            HIP_TRY(ctx, hipGetLastError());
+            if (d_depths)
+                HIP_TRY(ctx, hipMemcpyAsync(d_depths + static_cast<size_t>(e) * nt * nk, thr, thr_b,
+                                            hipMemcpyDeviceToDevice, stream));
+            HIP_TRY(ctx, hipMemcpyAsync(sub_species, batch->species + lo, sizeof(int) * ne, hipMemcpyDeviceToDevice, stream));
+            HIP_TRY(ctx, hipMemcpyAsync(sub_table, batch->table + lo, sizeof(int) * ne, hipMemcpyDeviceToDevice, stream));
+            HIP_TRY(ctx, hipMemcpyAsync(sub_energy, batch->energy + lo, sizeof(double) * ne, hipMemcpyDeviceToDevice, stream));
+            HIP_TRY(ctx, hipMemcpyAsync(sub_key, batch->key + lo, sizeof(uint64_t) * ne, hipMemcpyDeviceToDevice, stream));
+            for (int c = 0; c < 3; ++c) {
+                HIP_TRY(ctx, hipMemcpyAsync(sub_pos + c * ne, batch->pos + c * n + lo, sizeof(double) * ne,
+                                            hipMemcpyDeviceToDevice, stream));
+                HIP_TRY(ctx, hipMemcpyAsync(sub_dir + c * ne, batch->dir + c * n + lo, sizeof(double) * ne,
+                                            hipMemcpyDeviceToDevice, stream));
+            }
+            reedmd_batch sb{};
+            sb.n = ne;
+            sb.id0 = batch->id0 + lo;
+            sb.species = sub_species;
+            sb.energy = sub_energy;
+            sb.pos = sub_pos;
+            sb.dir = sub_dir;
+            sb.key = reinterpret_cast<uint64_t*>(sub_key);
+            sb.table = sub_table;
+            if (log0) {
+                p.track_log = log0 + log_done;
+                p.track_log_cap = std::max<int64_t>(0, params->track_log_cap - log_done);
+            }
+            const Shape shape = choose_shape(ctx, &p, &sb);
+            const reedmd_status rs = run_impl(ctx, species, &sb, &p, d_hist, d_stats, stream, &shape, tstat);
+            if (rs != REEDMD_OK) return rs;
+            if (log0) {
+                reedmd_stats h{};
+                HIP_TRY(ctx, hipMemcpyAsync(&h, d_stats, sizeof(h), hipMemcpyDeviceToHost, stream));
+                HIP_TRY(ctx, hipStreamSynchronize(stream));
+                log_done = std::min<int64_t>(params->track_log_cap, h.log_count - h0.log_count);
+            }
+        }
+        HIP_TRY(ctx, hipStreamSynchronize(stream));
+        return REEDMD_OK;
+    };
+    const reedmd_status rs = body();
+    (void)hipStreamSynchronize(stream);
+    (void)hipFree(work);
+    return rs;
 }
 
 reedmd_status reedmd_launch_shape(reedmd_ctx* ctx, const reedmd_batch* batch, const reedmd_run_params* params,

@@ -68,6 +68,7 @@ struct KernelArgs {
     const int* table;
     // outputs
     double* hist;
+    double* tstat;          // optional, per depth table: [n_bins] stopped weight by bin, overflow, total
     reedmd_stats* stats;
     reedmd_result* log;
     long long log_cap;
@@ -575,9 +576,19 @@ __device__ __forceinline__ void add_i64(int64_t* p, long long v)
 // Books a finished track (segment leader only).
 __device__ __forceinline__ void book_finished(const KernelArgs& A, int status, double w, double zstop,
                                               long long lineage, int next_k, long long steps,
-                                              long long exec_steps, long long pairs)
+                                              long long exec_steps, long long pairs, int table)
 {
     reedmd_stats* S = A.stats;
+    if (A.tstat != nullptr && table >= 0 && table < A.n_tables) {
+        // per-table survival statistics for adaptive cloning depths
+        double* ts = A.tstat + static_cast<size_t>(table) * (A.n_bins + 2);
+        add_f64(&ts[A.n_bins + 1], w);
+        if (status == REEDMD_STOPPED && zstop >= 0.0) {
+            const double fb = floor(zstop / A.bin_width);
+            if (!(fb < static_cast<double>(A.n_bins))) add_f64(&ts[A.n_bins], w);
+            else add_f64(&ts[static_cast<int>(fb)], w);
+        }
+    }
     add_i64(&S->finished, 1);
     add_i64(&S->track_steps, exec_steps);
     add_i64(&S->pair_evals, pairs);
@@ -760,7 +771,7 @@ __global__ void __launch_bounds__(256, REEDMD_WAVES_PER_SIMD(L)) track_kernel(co
                 if (t.status == REEDMD_LOST) {
                     // invalid species or table index: weight quarantined, error flagged
                     if (sl == 0) {
-                        book_finished(A, REEDMD_LOST, t.w, 0.0, t.lineage, t.next_k, t.steps, 0, 0);
+                        book_finished(A, REEDMD_LOST, t.w, 0.0, t.lineage, t.next_k, t.steps, 0, 0, -1);
                         add_i64(&A.stats->error_flags, 1);
                         if (MODE == kModePersistent) add_i64(&A.q->live, -1);
                     }
@@ -769,7 +780,7 @@ __global__ void __launch_bounds__(256, REEDMD_WAVES_PER_SIMD(L)) track_kernel(co
                 } else if (cancelled) {
                     // drain: the track ends where it is, its weight is booked as cancelled
                     if (sl == 0) {
-                        book_finished(A, REEDMD_CANCELLED, t.w, 0.0, t.lineage, t.next_k, t.steps, 0, 0);
+                        book_finished(A, REEDMD_CANCELLED, t.w, 0.0, t.lineage, t.next_k, t.steps, 0, 0, t.table);
                         if (MODE == kModePersistent) add_i64(&A.q->live, -1);
                     }
                     mode = kSegNeed;
@@ -812,7 +823,7 @@ __global__ void __launch_bounds__(256, REEDMD_WAVES_PER_SIMD(L)) track_kernel(co
         if (st != REEDMD_ACTIVE) {
             const KernelArgs A = cold_args();
             if (sl == 0) {
-                book_finished(A, st, t.w, t.zstop, t.lineage, t.next_k, t.steps, exec_steps, pairs);
+                book_finished(A, st, t.w, t.zstop, t.lineage, t.next_k, t.steps, exec_steps, pairs, t.table);
                 if (MODE == kModePersistent) add_i64(&A.q->live, -1);
             }
             mode = kSegNeed;

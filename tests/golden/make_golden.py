@@ -1,12 +1,14 @@
 """Writes the stored oracle results used by the GPU statistical parity tests.
 
 Calls only the oracle (``oracle/``).
-Usage:  python tests/golden/make_golden.py [pilot|pilot2|pilot4|c0|c1|c2|c4]
+Usage:  python tests/golden/make_golden.py [pilot|pilot2|pilot4|c0|c1|c2|c4|refine]
   pilot: unsplit survival quantiles of the 10 keV As workload (source of C1_THRESHOLDS)
   pilot2: cloning-depth tables of the mixed B/P/As 1-100 keV workload (C2_THRESHOLDS)
   pilot4: cloning depths of the 100 keV As [001] channeling workload (C4_THRESHOLDS)
   c0:    65,536 B at 1 keV, 7 degree tilt, no splitting (the c0 sampler, ids 0..65535)
   c1:    1,024 As at 10 keV with the 8 cloning depths: ids 0..511 (channel) and 32768..33279 (tilt)
+  refine: 2,048 B at 1 keV (the c0 sampler, ids 0..2047) with 6 adaptive cloning depths at
+         survival 2^-k, re-placed between 4 epochs from a deliberately shallow first table
 Outputs go next to this file as JSON (histogram, totals, moments) plus gzipped text of every
 stopped track's depth and weight.
 """
@@ -144,6 +146,24 @@ def c1():
                            thresholds=list(C1_THRESHOLDS)), r)
 
 
+REFINE = dict(n=2048, n_epochs=4, probs=[2.0 ** -k for k in range(1, 7)],
+              first=[10.0, 20.0, 30.0, 40.0, 50.0, 60.0], min_gap=1.0)
+
+
+def refine():
+    """Adaptive cloning depths: the oracle's epoch runner on 2,048 B at 1 keV."""
+    w = WORKLOADS["c0_b1kev"]
+    prim = oracle.sample_primaries(sampler(w), 0, REFINE["n"])
+    cfg = oracle.Config(species=w["species"], n_bins=w["n_bins"], bin_width=w["bin_width"],
+                        thresholds=[REFINE["first"]])
+    t = time.time()
+    r = oracle.run_refined(cfg, prim, REFINE["n_epochs"], REFINE["probs"], REFINE["min_gap"])
+    print("refine oracle seconds", time.time() - t, r["stats"])
+    print("depths", np.round(r["depths"], 2).tolist())
+    save("c0_refined", dict(name="c0_b1kev", ids=[[0, REFINE["n"]]], seed=0, **REFINE), r,
+         extra=dict(depths=r["depths"].tolist()))
+
+
 def c2():
     """256 primaries of the mixed workload (ids 0..255), all 12-depth tables."""
     w = WORKLOADS["c2_mixed"]
@@ -171,4 +191,5 @@ def c4():
 if __name__ == "__main__":
     what = sys.argv[1:] or ["c0", "c1"]
     for w in what:
-        {"pilot": pilot, "pilot2": pilot2, "pilot4": pilot4, "c0": c0, "c1": c1, "c2": c2, "c4": c4}[w]()
+        {"pilot": pilot, "pilot2": pilot2, "pilot4": pilot4, "c0": c0, "c1": c1, "c2": c2, "c4": c4,
+         "refine": refine}[w]()

@@ -262,6 +262,41 @@ def test_c0_acceptance_set_matches_oracle_statistics(R, ctx):
     assert abs(st["n_backscattered"] - meta["stats"]["n_backscattered"]) < 5 * math.sqrt(meta["stats"]["n_backscattered"] + 1)
 
 
+def test_adaptive_depths_follow_the_oracle_rule_and_statistics(R, ctx):
+    """Cloning depths re-placed between epochs (2,048 B at 1 keV, 6 depths at survival 2^-k,
+    4 epochs from a shallow first table): every table the GPU ran with equals the oracle's
+    rule (oracle.refine_depths) applied to the GPU's own tracks of the earlier epochs, to
+    1e-6 A; the ledger is exact; the weighted stopping depths match the stored oracle run of
+    the same procedure (KS p > 0.01)."""
+    meta, zo, wo = _load_golden("c0_refined")
+    w = WORKLOADS["c0_b1kev"]
+    m = meta["workload"]
+    n, E, probs, first, gap = m["n"], m["n_epochs"], m["probs"], m["first"], m["min_gap"]
+    batch = R.sample_primaries(ctx, R.SamplerConfig(**w["sampler"]), 0, n)
+    cfg = rcfg(R, n_bins=w["n_bins"], thresholds=[first], form=R.FORM_PERSISTENT)
+    hist, stats, depths, log = R.run_refined(ctx, w["species"], batch, cfg, E, probs, gap, log_cap=200000)
+    torch.cuda.synchronize()
+    st = R.parse_stats(stats)
+    assert st["primaries"] == n
+    assert st["w_stopped"] + st["w_backscattered"] + st["w_quarantined"] == n
+    assert float(hist.sum()) + st["w_underflow"] + st["w_overflow"] == st["w_stopped"]
+    lg = R.parse_log(log, st["log_count"])
+    assert len(lg) == st["finished"]
+    d = depths.cpu().numpy()
+    assert np.array_equal(d[0], [first])
+    tables = batch["table"].cpu().numpy()
+    bounds = [n * e // E for e in range(E + 1)]
+    for e in range(1, E):
+        ts = oracle.table_stats(lg[lg["lineage"] < bounds[e]], tables, 1, w["n_bins"], w["bin_width"])
+        ref = oracle.refine_depths(ts, w["n_bins"], w["bin_width"], probs, d[e - 1], gap)
+        assert np.allclose(d[e], ref, rtol=0, atol=1e-6), (e, d[e], ref)
+    s = lg[lg["status"] == R.STOPPED]
+    D, p = physref.weighted_ks(s["z_stop"], s["w"], zo, wo)
+    _say(f"refined depths {np.round(d[:, 0], 1).tolist()} vs oracle "
+         f"{np.round(np.array(meta['depths'])[:, 0], 1).tolist()}; KS D={D:.4g} p={p:.3g}")
+    assert p > 0.01
+
+
 def _c1_subset_batches(R, ctx):
     w = WORKLOADS["c1_as10kev"]
     sc = R.SamplerConfig(**w["sampler"])

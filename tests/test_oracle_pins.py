@@ -495,3 +495,36 @@ def test_forward_mode_derivative_matches_finite_differences_on_short_tracks():
             checked[name] += 1
             assert abs(d - fd[0]) <= 2e-5 * scale, (i, name, d, fd)
     assert checked["k"] >= 4 and checked["s"] >= 4, checked
+
+
+# --------------------------------------------------------------------------- adaptive depths
+def test_refined_depths_match_exponential_quantiles():
+    """Survival exp(-z/mu) booked into 1 A bins: the re-placed depths are the quantiles
+    -mu ln p up to the linear-in-S interpolation inside a bin (error <= dz^2 / (8 mu))."""
+    mu, nb, dz = 200.0, 4096, 1.0
+    S = np.exp(-np.arange(nb + 1) * dz / mu)
+    ts = np.array([np.concatenate([S[:-1] - S[1:], [S[-1]], [1.0]])])
+    probs = [2.0 ** -k for k in range(1, 9)]
+    d = oracle.refine_depths(ts, nb, dz, probs, np.zeros((1, 8)), 1.0)
+    assert np.allclose(d[0], [-mu * math.log(p) for p in probs], atol=dz * dz / (8 * mu) + 1e-9)
+
+
+def test_refined_depths_keep_unresolved_targets_and_spacing():
+    """A target the histogram does not resolve keeps its old depth, an empty table keeps its
+    depths, and the depths are raised to the previous one plus min_gap."""
+    nb = 10
+    ts = np.zeros((2, nb + 2))
+    ts[0, :nb] = 1.0            # 10 units stopped uniformly in [0, 10) A
+    ts[0, nb + 1] = 10.0        # everything booked for table 0; table 1 has no data
+    old = np.array([[1.0, 2.0, 50.0], [7.0, 8.0, 9.0]])
+    d = oracle.refine_depths(ts, nb, 1.0, [0.5, 0.25, 1e-4], old, 0.0)
+    # S(z) = (10 - z) / 10: 0.5 at 5 A, 0.25 at 7.5 A, 1e-4 at 9.999 A
+    assert np.allclose(d[0], [5.0, 7.5, 9.999], rtol=0, atol=1e-12)
+    assert np.array_equal(d[1], old[1])
+    ts[0, nb] = 5.0             # 5 more units stopped beyond the histogram
+    ts[0, nb + 1] = 15.0
+    d = oracle.refine_depths(ts, nb, 1.0, [0.5, 0.25, 1e-4], old, 3.0)
+    # S(z) = (15 - z) / 15 on [0, 10]: 0.5 at 7.5 A; S never falls below 1/3, so the deeper
+    # targets keep 2.0 and 50.0, raised by the 3 A spacing where needed
+    assert np.allclose(d[0], [7.5, 10.5, 50.0], rtol=0, atol=1e-12)
+    assert np.array_equal(d[1], [7.0, 10.0, 13.0])
