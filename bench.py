@@ -31,10 +31,10 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6   # 256 CU x 2.4 GHz x 128 FP64 FLOP/clk/CU
 # WRITE x 1.000); reported only while the track kernel's device sources (track_kernels.hpp,
 # device_physics.hpp) and the launch match the ones the counters were taken on.
 MEASURED_TRAFFIC = {
-    "sources_sha256_prefix": "adbaec66d7600e4d",
+    "sources_sha256_prefix": "3006258748d6a65b",
     "workload": "c1", "form": "persistent", "lanes": 16,
-    "fetch_bytes": 2608002.875 * 1024 * 2.000,
-    "write_bytes": 5175175.0625 * 1024 * 1.000,
+    "fetch_bytes": 2609209.0625 * 1024 * 2.000,
+    "write_bytes": 5174116.15625 * 1024 * 1.000,
 }
 
 
@@ -58,6 +58,9 @@ def parse():
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--waves", type=int, default=0, help="resident waves per CU with --lanes (0: by occupancy)")
     ap.add_argument("--queue", type=int, default=0, help="clone-queue capacity in records (0: library default)")
+    ap.add_argument("--refine-epochs", type=int, default=0,
+                    help="also time one run with the cloning depths re-placed between this many epochs "
+                         "(10 keV As workload: targets 2^-k, first table the stored depths); reported apart")
     ap.add_argument("--n", type=int, default=0, help="primaries (default: the workload's full size)")
     ap.add_argument("--workload", choices=["c1", "c2", "c4"], default="c1",
                     help="c1: 10 keV As (default, the benchmark line); c2: mixed B/P/As 1-100 keV, "
@@ -323,6 +326,20 @@ def main():
             "pairs_per_launch": pairs_per_launch,
         },
     }
+    if args.refine_epochs > 0 and args.workload == "c1":
+        b = R.sample_primaries(ctx, sampler, 0, n, stream=stream)
+        hist.zero_()
+        stats.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, depths = R.run_refined(ctx, w["species"], b, cfg, args.refine_epochs,
+                                     [2.0 ** -k for k in range(1, len(C1_THRESHOLDS) + 1)], 1.0,
+                                     hist=hist, stats=stats, stream=stream)
+        torch.cuda.synchronize()
+        tr = time.perf_counter() - t0
+        sr = R.parse_stats(stats)
+        out["refined"] = dict(epochs=args.refine_epochs, ms=1e3 * tr, force_evals_per_s=sr["pair_evals"] / tr,
+                              tracks=sr["finished"], last_depths=[round(x, 1) for x in depths[-1, 0].tolist()])
     if not args.no_grad:
         gr = grad_forward_ratio(R, ctx, torch)
         out["grad_fwd_ratio"] = gr["ratio"]
