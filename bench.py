@@ -4,8 +4,8 @@ One step = sample the 65,536 primaries of the 10 keV As workload on the device a
 every primary with all of its clones to termination (domain following, ZBL forces, local
 stopping, adaptive velocity Verlet, cloning at 8 depths, weighted histogram).  Prints one
 JSON line: ion-atom force evaluations per second (value), tracks per second, the FP64
-VALU roofline fraction of the track kernel, and the FP64 CPU oracle timed on a bounded
-sample of the same workload on the host cores.
+VALU roofline fraction of the track kernel, the FP32 pair-term variant beside it, and the
+FP64 CPU oracle timed on a bounded sample of the same workload on the host cores.
 """
 from __future__ import annotations
 
@@ -25,6 +25,11 @@ sys.path.insert(0, ROOT)
 # density weight 3 and sum 1, atom half kicks 12, atom drift 6.
 FLOP_PER_PAIR = 67
 FP64_VECTOR_PEAK_TFLOPS = 78.6   # 256 CU x 2.4 GHz x 128 FP64 FLOP/clk/CU
+FP32_VECTOR_PEAK_TFLOPS = 157.3  # 256 CU x 2.4 GHz x 256 FP32 FLOP/clk/CU
+# With the FP32 pair term, 38 of the 67 move to FP32 (r^2 5, sqrt 1, 1/r 1, r/a 1, the
+# exponents 8, phi 7, phi' 7, V'(r) 5, coefficient 1, density-weight exponent 2); the
+# separation, force components and sums, density sum, kicks and drifts (29) stay FP64.
+FLOP_PER_PAIR_F32_PART = 38
 
 # HBM bytes per launch of the track kernel measured with rocprofv3 --pmc FETCH_SIZE and
 # WRITE_SIZE (separate runs), scaled by the same counters on a 1 GiB copy (FETCH x 2.000,
@@ -68,6 +73,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-grad", action="store_true", help="skip the gradient / forward time ratio")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 pair-term variant leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (HBM counter calibration)")
     return ap.parse_args()
@@ -103,6 +109,50 @@ def cpu_baseline(target_seconds):
                 sample=f"{total_prim} primaries of the same workload (ids 0..{offset - 1} and "
                        f"32768..{32768 + offset - 1}, all clones), {t_all:.1f} s wall, "
                        f"{total_tracks / t_all:.1f} tracks/s")
+
+
+def fp32_leg(R, ctx, torch, w, sampler, n, base, stream, hist, stats, form, lanes=0, waves=0):
+    """The same workload with the FP32 pair term (FP64 integration and step control): its
+    own autotuned shape (or the one given), one warm launch, two timed launches.  Reported
+    beside the FP64 headline, never as it."""
+    f = R.FORM_PLAIN if form == "plain" else R.FORM_PERSISTENT
+    batch = R.sample_primaries(ctx, sampler, 0, n)
+    if lanes == 0:
+        lanes, waves = R.autotune(ctx, w["species"], batch,
+                                  R.RunConfig(form=f, force_precision=R.FORCE_FP32, **base), pilot=n)
+    cfg = R.RunConfig(form=f, lanes_per_track=lanes, waves_per_cu=waves, force_precision=R.FORCE_FP32, **base)
+    R.run(ctx, w["species"], batch, cfg)
+    torch.cuda.synchronize()
+    kms, pairs, tracks = [], 0, 0
+    t_all = 0.0
+    for _ in range(2):
+        b = R.sample_primaries(ctx, sampler, 0, n, stream=stream)
+        hist.zero_()
+        stats.zero_()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0.record(stream)
+        R.run(ctx, w["species"], b, cfg, hist=hist, stats=stats, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t_all += time.perf_counter() - t0
+        st = R.parse_stats(stats)
+        pairs += st["pair_evals"]
+        tracks += st["finished"]
+        kms.append(e0.elapsed_time(e1))
+    k = sum(kms) / len(kms)
+    ppl = pairs / 2
+    # ideal time at the two vector peaks over the measured kernel time
+    t_ideal = ppl * ((FLOP_PER_PAIR - FLOP_PER_PAIR_F32_PART) / FP64_VECTOR_PEAK_TFLOPS +
+                     FLOP_PER_PAIR_F32_PART / FP32_VECTOR_PEAK_TFLOPS) * 1e-12
+    return dict(force_evals_per_s=pairs / t_all, tracks_per_s=tracks / t_all,
+                kernel_ms_per_step=[round(x, 1) for x in kms], lanes_per_track=lanes, waves_per_cu=waves,
+                roofline={"bound": "alu", "peak": f"FP64 {FP64_VECTOR_PEAK_TFLOPS} + FP32 {FP32_VECTOR_PEAK_TFLOPS} TFLOP/s",
+                          "fp64_flop_per_pair": FLOP_PER_PAIR - FLOP_PER_PAIR_F32_PART,
+                          "fp32_flop_per_pair": FLOP_PER_PAIR_F32_PART,
+                          "frac": t_ideal / (k * 1e-3)},
+                tolerance="1e-5 relative per step against the FP64 oracle")
 
 
 def grad_forward_ratio(R, ctx, torch):
@@ -340,6 +390,9 @@ def main():
         sr = R.parse_stats(stats)
         out["refined"] = dict(epochs=args.refine_epochs, ms=1e3 * tr, force_evals_per_s=sr["pair_evals"] / tr,
                               tracks=sr["finished"], last_depths=[round(x, 1) for x in depths[-1, 0].tolist()])
+    if not args.no_fp32:
+        out["fp32_pair_variant"] = fp32_leg(R, ctx, torch, w, sampler, n, base, stream, hist, stats, args.form,
+                                            args.lanes, args.waves)
     if not args.no_grad:
         gr = grad_forward_ratio(R, ctx, torch)
         out["grad_fwd_ratio"] = gr["ratio"]

@@ -52,6 +52,10 @@ enum { REEDMD_DIAMOND = 0 };
 enum { REEDMD_POT_ZBL = 0, REEDMD_POT_NONE = 1 };
 enum { REEDMD_STOP_OFF = 0, REEDMD_STOP_UNIFORM = 1, REEDMD_STOP_LOCAL = 2 };
 enum { REEDMD_FORM_PLAIN = 0, REEDMD_FORM_PERSISTENT = 1 };
+/* Precision of the ion-atom pair term (distance, screening exponentials, force
+ * coefficient, density weight).  Positions, velocities, force components and
+ * sums, kicks, drifts and the step size are FP64 in both. */
+enum { REEDMD_FORCE_FP64 = 0, REEDMD_FORCE_FP32 = 1 };
 enum { REEDMD_DIR_TILT = 0, REEDMD_DIR_CONE = 1, REEDMD_DIR_MIXED = 2 };
 /* track status (record word 21, result log) */
 enum { REEDMD_ACTIVE = 0, REEDMD_STOPPED = 1, REEDMD_BACKSCATTERED = 2, REEDMD_NONFINITE = 3,
@@ -151,6 +155,9 @@ typedef struct {
     const int32_t* cancel;     /* device word polled by the kernel, non-zero = cancel; may be NULL */
     void* track_log;           /* optional device array of reedmd_result, may be NULL */
     int64_t track_log_cap;
+    int32_t force_precision;   /* REEDMD_FORCE_FP64 (0) or REEDMD_FORCE_FP32 (1; run, track_init,
+                                  debug_step, autotune; reedmd_grad is FP64 only) */
+    int32_t reserved;
 } reedmd_run_params;
 
 /* Finished-track entry of the optional log (40 bytes). */

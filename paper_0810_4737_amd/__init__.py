@@ -16,7 +16,7 @@ import torch
 
 from . import _abi
 from ._abi import (ACTIVE, BACKSCATTERED, CANCELLED, DIR_CONE, DIR_MIXED, DIR_TILT,  # noqa: F401
-                   FORM_PERSISTENT, FORM_PLAIN, NONFINITE, NSLOT, POT_NONE, POT_ZBL, RECORD_WORDS,
+                   FORCE_FP32, FORCE_FP64, FORM_PERSISTENT, FORM_PLAIN, NONFINITE, NSLOT, POT_NONE, POT_ZBL, RECORD_WORDS,
                    STEPCAP, STOP_LOCAL, STOP_OFF, STOP_UNIFORM, STOPPED)
 
 SPECIES = {"B": (5, 10.81), "P": (15, 30.97), "As": (33, 74.92)}
@@ -101,6 +101,7 @@ class RunConfig:
     lanes_per_track: int = 0
     waves_per_cu: int = 0
     queue_capacity: int = 0
+    force_precision: int = FORCE_FP64
 
     def struct(self, device, keep):
         p = _abi.RunParams()
@@ -114,6 +115,7 @@ class RunConfig:
         p.n_clones, p.n_bins, p.bin_width = self.n_clones, self.n_bins, self.bin_width
         p.form, p.lanes_per_track = self.form, self.lanes_per_track
         p.waves_per_cu, p.queue_capacity = self.waves_per_cu, self.queue_capacity
+        p.force_precision = self.force_precision
         return p
 
 

@@ -13,6 +13,7 @@ DIAMOND = 0
 POT_ZBL, POT_NONE = 0, 1
 STOP_OFF, STOP_UNIFORM, STOP_LOCAL = 0, 1, 2
 FORM_PLAIN, FORM_PERSISTENT = 0, 1
+FORCE_FP64, FORCE_FP32 = 0, 1
 DIR_TILT, DIR_CONE, DIR_MIXED = 0, 1, 2
 ACTIVE, STOPPED, BACKSCATTERED, NONFINITE, STEPCAP, CANCELLED, LOST = range(7)
 
@@ -59,7 +60,7 @@ class RunParams(C.Structure):
                 ("n_clones", C.c_int32), ("n_bins", C.c_int32), ("bin_width", C.c_double),
                 ("form", C.c_int32), ("lanes_per_track", C.c_int32), ("waves_per_cu", C.c_int32),
                 ("queue_capacity", C.c_int32), ("cancel", C.c_void_p), ("track_log", C.c_void_p),
-                ("track_log_cap", C.c_int64)]
+                ("track_log_cap", C.c_int64), ("force_precision", C.c_int32), ("reserved2", C.c_int32)]
 
 
 class Refine(C.Structure):

@@ -31,6 +31,10 @@ struct SpeciesConst {
     // The screened-Coulomb sum with its constants folded per species:
     //   rate_i = d_i / a,  amp_i = zz c_i,  damp_i = zz c_i d_i / a
     double rate[4], amp[4], damp[4];
+    // The same in FP32 for the FP32 pair term, the rates (and 1/lambda) times
+    // log2(e) for the hardware 2^x
+    float rate2f[4], amp_f[4], damp_f[4];
+    float lam2f, pad_f;
 };
 
 // ---------------------------------------------------------------------------
@@ -211,6 +215,30 @@ __device__ __forceinline__ void zbl_pair(const SpeciesConst& c, double dx, doubl
     const double dphi = c.damp[0] * e0 + c.damp[1] * e1 + c.damp[2] * e2 + c.damp[3] * e3;
     coef = fma(phi, inv_r, dphi) * (inv_r * inv_r);
     ew = exp_neg(r * c.inv_lambda);
+}
+
+// FP32 variant of the pair term (force precision option; tolerance 1e-5
+// relative per step instead of 1e-10): the separation comes in FP64 and is
+// rounded once; the distance (hardware 1/sqrt), the four screening terms and
+// the density weight (hardware 2^x of an FP32 argument: relative error about
+// |argument| x 6e-8, below 2e-6 for every term that is not negligible) and the
+// coefficient are FP32.  The caller keeps FP64 for the force components, the
+// sums, kicks, drifts and the step size.
+__device__ __forceinline__ void zbl_pair_f32(const SpeciesConst& c, double dx, double dy, double dz,
+                                             double& coef, double& ew)
+{
+    const float x = static_cast<float>(dx), y = static_cast<float>(dy), z = static_cast<float>(dz);
+    const float r2 = fmaf(x, x, fmaf(y, y, z * z));
+    const float inv_r = __builtin_amdgcn_rsqf(r2);
+    const float r = r2 * inv_r;
+    const float e0 = __builtin_amdgcn_exp2f(-r * c.rate2f[0]);
+    const float e1 = __builtin_amdgcn_exp2f(-r * c.rate2f[1]);
+    const float e2 = __builtin_amdgcn_exp2f(-r * c.rate2f[2]);
+    const float e3 = __builtin_amdgcn_exp2f(-r * c.rate2f[3]);
+    const float phi = c.amp_f[0] * e0 + c.amp_f[1] * e1 + c.amp_f[2] * e2 + c.amp_f[3] * e3;
+    const float dphi = c.damp_f[0] * e0 + c.damp_f[1] * e1 + c.damp_f[2] * e2 + c.damp_f[3] * e3;
+    coef = static_cast<double>(fmaf(phi, inv_r, dphi) * (inv_r * inv_r));
+    ew = static_cast<double>(__builtin_amdgcn_exp2f(-r * c.lam2f));
 }
 
 // The unique cell coordinate in {c-1, c, c+1} whose residue mod 3 is `res`.

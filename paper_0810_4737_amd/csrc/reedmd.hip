@@ -109,7 +109,11 @@ void prepare_species(const reedmd_ctx* ctx, const reedmd_species* sp, KernelArgs
             c.rate[j] = zd[j] * c.inv_a;
             c.amp[j] = c.zz * zc[j];
             c.damp[j] = c.zz * zc[j] * zd[j] * c.inv_a;
+            c.rate2f[j] = static_cast<float>(c.rate[j] * M_LOG2E);
+            c.amp_f[j] = static_cast<float>(c.amp[j]);
+            c.damp_f[j] = static_cast<float>(c.damp[j]);
         }
+        c.lam2f = static_cast<float>(c.inv_lambda * M_LOG2E);
         min_rate = std::min(min_rate, std::min(c.rate[3], c.inv_lambda));
         c.g_const = 0.0;
         c.g_rho = 0.0;
@@ -159,6 +163,8 @@ reedmd_status check_params(reedmd_ctx* ctx, const reedmd_run_params* p, bool nee
     if (p->waves_per_cu < 0 || p->waves_per_cu > 32) return fail(ctx, REEDMD_EINVAL, "waves_per_cu must be in 0..32");
     if (p->queue_capacity < 0) return fail(ctx, REEDMD_EINVAL, "queue_capacity must be >= 0");
     if (p->track_log && p->track_log_cap < 0) return fail(ctx, REEDMD_EINVAL, "track_log_cap must be >= 0");
+    if (p->force_precision != REEDMD_FORCE_FP64 && p->force_precision != REEDMD_FORCE_FP32)
+        return fail(ctx, REEDMD_EINVAL, "force_precision must be REEDMD_FORCE_FP64 or REEDMD_FORCE_FP32");
     return REEDMD_OK;
 }
 
@@ -208,40 +214,61 @@ void fill_batch(const reedmd_batch* b, KernelArgs& A)
     A.table = b->table;
 }
 
-template <int L, int MODE>
+// Kernel variants: lanes per track (64, 32, 16) x form x pair-term precision.
+template <int L, int MODE, bool F32>
 hipError_t launch_track(const KernelArgs& A, long long blocks, hipStream_t s)
 {
-    hipLaunchKernelGGL((track_kernel<L, MODE>), dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s, A);
+    hipLaunchKernelGGL((track_kernel<L, MODE, F32>), dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s, A);
     return hipGetLastError();
 }
 
-hipError_t launch_track_any(int L, int mode, const KernelArgs& A, long long blocks, hipStream_t s)
+template <int MODE, bool F32>
+hipError_t launch_track_l(int L, const KernelArgs& A, long long blocks, hipStream_t s)
 {
-    if (mode == kModePlain) {
-        if (L == 64) return launch_track<64, kModePlain>(A, blocks, s);
-        if (L == 32) return launch_track<32, kModePlain>(A, blocks, s);
-        return launch_track<16, kModePlain>(A, blocks, s);
-    }
-    if (L == 64) return launch_track<64, kModePersistent>(A, blocks, s);
-    if (L == 32) return launch_track<32, kModePersistent>(A, blocks, s);
-    return launch_track<16, kModePersistent>(A, blocks, s);
+    if (L == 64) return launch_track<64, MODE, F32>(A, blocks, s);
+    if (L == 32) return launch_track<32, MODE, F32>(A, blocks, s);
+    return launch_track<16, MODE, F32>(A, blocks, s);
 }
 
-int resident_blocks_per_cu(int L, int mode)
+hipError_t launch_track_any(int L, int mode, bool f32, const KernelArgs& A, long long blocks, hipStream_t s)
+{
+    if (mode == kModePlain)
+        return f32 ? launch_track_l<kModePlain, true>(L, A, blocks, s) : launch_track_l<kModePlain, false>(L, A, blocks, s);
+    return f32 ? launch_track_l<kModePersistent, true>(L, A, blocks, s)
+               : launch_track_l<kModePersistent, false>(L, A, blocks, s);
+}
+
+template <int MODE, bool F32>
+int occupancy_l(int L)
 {
     int nb = 0;
     hipError_t e = hipSuccess;
-    if (mode == kModePlain) {
-        if (L == 64) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, track_kernel<64, kModePlain>, kBlock, 0);
-        else if (L == 32) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, track_kernel<32, kModePlain>, kBlock, 0);
-        else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, track_kernel<16, kModePlain>, kBlock, 0);
-    } else {
-        if (L == 64) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, track_kernel<64, kModePersistent>, kBlock, 0);
-        else if (L == 32) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, track_kernel<32, kModePersistent>, kBlock, 0);
-        else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, track_kernel<16, kModePersistent>, kBlock, 0);
-    }
-    if (e != hipSuccess || nb < 1) nb = 1;
-    return nb;
+    if (L == 64) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, track_kernel<64, MODE, F32>, kBlock, 0);
+    else if (L == 32) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, track_kernel<32, MODE, F32>, kBlock, 0);
+    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, track_kernel<16, MODE, F32>, kBlock, 0);
+    return (e != hipSuccess || nb < 1) ? 1 : nb;
+}
+
+int resident_blocks_per_cu(int L, int mode, bool f32)
+{
+    if (mode == kModePlain) return f32 ? occupancy_l<kModePlain, true>(L) : occupancy_l<kModePlain, false>(L);
+    return f32 ? occupancy_l<kModePersistent, true>(L) : occupancy_l<kModePersistent, false>(L);
+}
+
+template <bool F32>
+void launch_init_l(int L, const KernelArgs& A, long long blocks, hipStream_t s)
+{
+    if (L == 64) hipLaunchKernelGGL((init_kernel<64, F32>), dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s, A);
+    else if (L == 32) hipLaunchKernelGGL((init_kernel<32, F32>), dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s, A);
+    else hipLaunchKernelGGL((init_kernel<16, F32>), dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s, A);
+}
+
+template <bool F32>
+void launch_step_l(int L, const KernelArgs& A, long long blocks, hipStream_t s)
+{
+    if (L == 64) hipLaunchKernelGGL((step_kernel<64, F32>), dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s, A);
+    else if (L == 32) hipLaunchKernelGGL((step_kernel<32, F32>), dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s, A);
+    else hipLaunchKernelGGL((step_kernel<16, F32>), dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s, A);
 }
 
 // Queue state reset (a kernel, not a memset, so the pipeline can be captured).
@@ -317,6 +344,7 @@ unsigned long long tune_key(const reedmd_run_params* p, const reedmd_batch* b)
     unsigned long long h = 1469598103934665603ULL;
     h = hash_mix(h, static_cast<unsigned long long>(p->form));
     h = hash_mix(h, static_cast<unsigned long long>(p->n_thresh));
+    h = hash_mix(h, static_cast<unsigned long long>(p->force_precision));
     h = hash_mix(h, static_cast<unsigned long long>(b->n > 0 ? 63 - __builtin_clzll(static_cast<unsigned long long>(b->n)) : 0));
     return h;
 }
@@ -325,6 +353,7 @@ unsigned long long tune_key(const reedmd_run_params* p, const reedmd_batch* b)
 struct Shape {
     int L;
     int mode;
+    bool f32;
     long long seg_total;
     long long blocks;
     int stack_cap;
@@ -335,6 +364,7 @@ Shape choose_shape(reedmd_ctx* ctx, const reedmd_run_params* p, const reedmd_bat
 {
     Shape s{};
     s.mode = p->form == REEDMD_FORM_PERSISTENT ? kModePersistent : kModePlain;
+    s.f32 = p->force_precision == REEDMD_FORCE_FP32;
     int L = p->lanes_per_track;
     int waves = p->waves_per_cu;
     if (L == 0 || (s.mode == kModePersistent && waves == 0)) {
@@ -356,7 +386,7 @@ Shape choose_shape(reedmd_ctx* ctx, const reedmd_run_params* p, const reedmd_bat
         s.blocks = (waves_needed + per_wave_block - 1) / per_wave_block;
         s.qcap = 0;
     } else {
-        int bpc = resident_blocks_per_cu(L, s.mode);
+        int bpc = resident_blocks_per_cu(L, s.mode, s.f32);
         if (waves > 0) bpc = std::max(1, std::min(bpc, (waves + per_wave_block - 1) / per_wave_block));
         s.blocks = static_cast<long long>(bpc) * ctx->cu_count;
         s.seg_total = s.blocks * per_wave_block * T;
@@ -400,7 +430,7 @@ reedmd_status run_impl(reedmd_ctx* ctx, const reedmd_species* sp, const reedmd_b
         hipLaunchKernelGGL(queue_reset_kernel, dim3(rb), dim3(256), 0, sm, A.q, A.qseq, qcap, b->n);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        e = launch_track_any(s.L, s.mode, A, s.blocks, sm);
+        e = launch_track_any(s.L, s.mode, s.f32, A, s.blocks, sm);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(stats_finalize_kernel, dim3(1), dim3(64), 0, sm, A.q, d_stats);
         return hipGetLastError();
@@ -416,6 +446,7 @@ reedmd_status run_impl(reedmd_ctx* ctx, const reedmd_species* sp, const reedmd_b
             const unsigned long long* raw = reinterpret_cast<const unsigned long long*>(&A);
             key.assign(raw, raw + sizeof(A) / 8);
             key.push_back(static_cast<unsigned long long>(s.L));
+            key.push_back(static_cast<unsigned long long>(s.f32));
             key.push_back(static_cast<unsigned long long>(s.blocks));
             auto it = ctx->graphs.find(key);
             if (it == ctx->graphs.end()) {
@@ -678,9 +709,8 @@ reedmd_status reedmd_track_init(reedmd_ctx* ctx, const reedmd_species* species, 
     const int L = params->lanes_per_track ? params->lanes_per_track : 64;
     const long long waves = (batch->n + (64 / L) - 1) / (64 / L);
     const long long blocks = (waves + 3) / 4;
-    if (L == 64) hipLaunchKernelGGL(init_kernel<64>, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, stream, A);
-    else if (L == 32) hipLaunchKernelGGL(init_kernel<32>, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, stream, A);
-    else hipLaunchKernelGGL(init_kernel<16>, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, stream, A);
+    if (params->force_precision == REEDMD_FORCE_FP32) launch_init_l<true>(L, A, blocks, stream);
+    else launch_init_l<false>(L, A, blocks, stream);
     HIP_TRY(ctx, hipGetLastError());
     return REEDMD_OK;
 }
@@ -703,9 +733,8 @@ reedmd_status reedmd_debug_step(reedmd_ctx* ctx, const reedmd_species* species, 
     const int L = params->lanes_per_track ? params->lanes_per_track : 64;
     const long long waves = (n + (64 / L) - 1) / (64 / L);
     const long long blocks = (waves + 3) / 4;
-    if (L == 64) hipLaunchKernelGGL(step_kernel<64>, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, stream, A);
-    else if (L == 32) hipLaunchKernelGGL(step_kernel<32>, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, stream, A);
-    else hipLaunchKernelGGL(step_kernel<16>, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, stream, A);
+    if (params->force_precision == REEDMD_FORCE_FP32) launch_step_l<true>(L, A, blocks, stream);
+    else launch_step_l<false>(L, A, blocks, stream);
     HIP_TRY(ctx, hipGetLastError());
     return REEDMD_OK;
 }
@@ -721,6 +750,8 @@ reedmd_status reedmd_grad(reedmd_ctx* ctx, const reedmd_species* species, const 
     if ((st = check_params(ctx, params, false)) != REEDMD_OK) return st;
     if (!h_result) return fail(ctx, REEDMD_EINVAL, "h_result is NULL");
     if (params->n_thresh != 0) return fail(ctx, REEDMD_EUNSUPPORTED, "the gradient is defined without cloning (n_thresh = 0)");
+    if (params->force_precision != REEDMD_FORCE_FP64)
+        return fail(ctx, REEDMD_EUNSUPPORTED, "the adjoint is FP64 only (force_precision = REEDMD_FORCE_FP64)");
     if (!(k >= 0.0) || !(s >= kMinScreening && s <= kMaxScreening))
         return fail(ctx, REEDMD_EINVAL, "need k >= 0 and s in [0.01, 100]");
     for (int i = 0; i < 4; ++i) h_result[i] = 0.0;
@@ -824,7 +855,8 @@ reedmd_status reedmd_autotune(reedmd_ctx* ctx, const reedmd_species* species, co
     const bool persistent = params->form == REEDMD_FORM_PERSISTENT;
     for (int li = 0; li < 3 && st == REEDMD_OK; ++li) {
         // persistent form: the occupancy-sized grid and one workgroup per CU fewer
-        const int occ = resident_blocks_per_cu(lanes[li], persistent ? kModePersistent : kModePlain);
+        const int occ = resident_blocks_per_cu(lanes[li], persistent ? kModePersistent : kModePlain,
+                                               params->force_precision == REEDMD_FORCE_FP32);
         const int nw = (persistent && occ > 1) ? 2 : 1;
         for (int wi = 0; wi < nw && st == REEDMD_OK; ++wi) {
             p.lanes_per_track = lanes[li];
@@ -986,7 +1018,7 @@ reedmd_status reedmd_launch_shape(reedmd_ctx* ctx, const reedmd_batch* batch, co
     out[0] = s.L;
     out[1] = s.blocks;
     out[2] = s.seg_total;
-    out[3] = resident_blocks_per_cu(s.L, s.mode);
+    out[3] = resident_blocks_per_cu(s.L, s.mode, s.f32);
     out[4] = s.mode == kModePersistent ? s.qcap : 0;
     return REEDMD_OK;
 }

@@ -22,9 +22,6 @@ enum : int { kModePlain = 0, kModePersistent = 1 };
 #ifndef REEDMD_PAIR_BARRIER
 #define REEDMD_PAIR_BARRIER 0
 #endif
-#ifndef REEDMD_SP_RELOAD
-#define REEDMD_SP_RELOAD 0
-#endif
 #ifndef REEDMD_WAVES_PER_SIMD
 #define REEDMD_WAVES_PER_SIMD(L) ((L) >= 32 ? 2 : 1)
 #endif
@@ -338,7 +335,7 @@ __device__ __forceinline__ void regenerate(TrackRegs<L>& t, const KernelArgs& A,
 // One integration step (velocity Verlet with symmetric friction halves); a
 // step with fresh == true has dt = 0 and builds the whole domain (start of a
 // primary).  Returns the kinetic energy before the step via ke0.
-template <int L>
+template <int L, bool F32 = false>
 __device__ __forceinline__ void track_step(TrackRegs<L>& t, const KernelArgs& A, const SpeciesConst* sp, int sl,
                                            bool fresh, double& ke0, double& z0)
 {
@@ -386,13 +383,8 @@ __device__ __forceinline__ void track_step(TrackRegs<L>& t, const KernelArgs& A,
         const double pz = t.az[i] + vz * dt;
         const double dx = t.x - px, dy = t.y - py, dz = t.z - pz;
         double coef, ew;
-#if REEDMD_SP_RELOAD
-        const SpeciesConst* cp = &c;
-        asm volatile("" : "+v"(cp));   // re-read the species constants for every slot
-        zbl_pair(*cp, dx, dy, dz, coef, ew);
-#else
-        zbl_pair(c, dx, dy, dz, coef, ew);
-#endif
+        if constexpr (F32) zbl_pair_f32(c, dx, dy, dz, coef, ew);
+        else zbl_pair(c, dx, dy, dz, coef, ew);
         const double fx = -coef * dx, fy = -coef * dy, fz = -coef * dz;   // force on the atom
         Fx -= fx; Fy -= fy; Fz -= fz;
         rho += ew;
@@ -682,7 +674,7 @@ __device__ __forceinline__ long long queue_reserve_pop(const KernelArgs& A)
 // from device counters and the clone queue until no track is live).
 enum : int { kSegNeed = 0, kSegRun = 1, kSegDone = 2 };
 
-template <int L, int MODE>
+template <int L, int MODE, bool F32 = false>
 __global__ void __launch_bounds__(256, REEDMD_WAVES_PER_SIMD(L)) track_kernel(const KernelArgs A0)
 {
     const KernelArgs& A = A0;
@@ -803,7 +795,7 @@ __global__ void __launch_bounds__(256, REEDMD_WAVES_PER_SIMD(L)) track_kernel(co
 
         // ---- one step of a running track ----
         double ke0, z0;
-        track_step<L>(t, A, sp, sl, fresh, ke0, z0);
+        track_step<L, F32>(t, A, sp, sl, fresh, ke0, z0);
         pairs += t.n_exist;
         if (fresh) {
             fresh = false;
@@ -881,7 +873,7 @@ __global__ void __launch_bounds__(256, REEDMD_WAVES_PER_SIMD(L)) track_kernel(co
 }
 
 // Builds the starting record of every batch entry (debug / parity entry point).
-template <int L>
+template <int L, bool F32 = false>
 __global__ void __launch_bounds__(256) init_kernel(const KernelArgs A)
 {
     __shared__ SpeciesConst s_sp[kMaxSpecies];
@@ -896,12 +888,12 @@ __global__ void __launch_bounds__(256) init_kernel(const KernelArgs A)
     t.exist = 0;
     start_primary<L>(t, A, sp, seg);
     double ke0, z0;
-    if (t.status != REEDMD_LOST) track_step<L>(t, A, sp, sl, true, ke0, z0);
+    if (t.status != REEDMD_LOST) track_step<L, F32>(t, A, sp, sl, true, ke0, z0);
     store_record<L>(t, A.records + static_cast<size_t>(seg) * kRecWords, sl);
 }
 
 // Advances caller records by nsteps steps without events (debug / parity).
-template <int L>
+template <int L, bool F32 = false>
 __global__ void __launch_bounds__(256, 2) step_kernel(const KernelArgs A)
 {
     __shared__ SpeciesConst s_sp[kMaxSpecies];
@@ -918,7 +910,7 @@ __global__ void __launch_bounds__(256, 2) step_kernel(const KernelArgs A)
     if (t.status == REEDMD_LOST) return;   // invalid species index: record left as it was
     for (int s = 0; s < A.nsteps; ++s) {
         double ke0, z0;
-        track_step<L>(t, A, sp, sl, false, ke0, z0);
+        track_step<L, F32>(t, A, sp, sl, false, ke0, z0);
     }
     store_record<L>(t, rec, sl);
 }

@@ -44,6 +44,9 @@ def test_struct_sizes_match_header_layout():
     assert C.sizeof(_abi.Species) == 8 + 4 * 8 + 8 * 8
     assert _abi.STATS_WORDS * 8 == 10 * 8 + 8 * 8 + 4 * 8
     assert _abi.RECORD_WORDS == 32 + 9 * 216
+    # reedmd_run_params: 4 doubles, max_steps, seed, 2 ints, thresholds, 2 ints, bin_width,
+    # 4 ints, cancel and track_log, track_log_cap, force_precision + reserved
+    assert C.sizeof(_abi.RunParams) == 4 * 8 + 8 + 8 + 8 + 8 + 8 + 8 + 16 + 16 + 8 + 8
 
 
 def test_version_and_create_argument_errors_without_gpu():
@@ -72,3 +75,30 @@ def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(_abi, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError, match="not built"):
         _abi.load()
+
+
+def test_binding_structs_match_the_c_header(tmp_path):
+    """sizeof of every struct the binding mirrors, as the C compiler lays it out from the header."""
+    import shutil
+    import subprocess
+    from paper_0810_4737_amd import _abi
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    names = {"reedmd_lattice": _abi.Lattice, "reedmd_potential": _abi.Potential,
+             "reedmd_stopping": _abi.Stopping, "reedmd_species": _abi.Species, "reedmd_batch": _abi.Batch,
+             "reedmd_sampler": _abi.Sampler, "reedmd_run_params": _abi.RunParams,
+             "reedmd_result": _abi.Result, "reedmd_refine": _abi.Refine}
+    src = tmp_path / "sizes.c"
+    src.write_text('#include <stdio.h>\n#include "reedmd.h"\nint main(void){\n' +
+                   "".join(f'printf("{n} %zu\\n", sizeof({n}));\n' for n in names) + "return 0;}\n")
+    exe = tmp_path / "sizes"
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    if not os.path.exists(os.path.join(rocm, "include", "hip", "hip_runtime_api.h")):
+        pytest.skip("HIP headers not found")
+    subprocess.run([cc, "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(rocm, "include"), "-I",
+                    os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
+    got = dict(zip(out[0::2], map(int, out[1::2])))
+    for n, cls in names.items():
+        assert got[n] == C.sizeof(cls), (n, got[n], C.sizeof(cls))

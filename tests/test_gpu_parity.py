@@ -225,6 +225,52 @@ def test_lane_layouts_agree(R, ctx, lanes):
         assert_records_close(gb[i], ga[i], rtol=1e-11, what=f"lanes {lanes} {i}")
 
 
+# ------------------------------------------------------------------ FP32 pair-term variant
+# Force precision option: the pair term (distance, screening exponentials, density weight)
+# in FP32, integration and step control in FP64; per-step tolerance 1e-5 relative.
+@pytest.mark.parametrize("lanes", [64, 16])
+def test_fp32_initial_forces_match_oracle(R, ctx, lanes):
+    n = 48
+    pr = _prims(n, seed=13)
+    pr["pos"][2, ::3] = 37.3 + 11.0 * np.arange(len(pr["pos"][2, ::3]))
+    cfg = rcfg(R, lanes_per_track=lanes, force_precision=R.FORCE_FP32)
+    got = R.track_init(ctx, SPECIES3, R.batch_from_numpy(pr), cfg).cpu().numpy()
+    c = ocfg()
+    worst = 0.0
+    for i in range(n):
+        t = oracle.Track.start(c, int(pr["species"][i]), float(pr["E0"][i]), pr["pos"][:, i],
+                               pr["dir"][:, i], int(pr["key"][i]), int(pr["table"][i]), i)
+        ref = t.record()
+        assert_records_close(got[i], ref, rtol=1e-5, what=f"fp32 init {i} lanes {lanes}")
+        ex = _exists(ref)
+        # the domain itself does not depend on the force precision: FP64 tolerance
+        xa = got[i][32:32 + 3 * 216].reshape(3, 216)[:, ex]
+        xb = ref[32:32 + 3 * 216].reshape(3, 216)[:, ex]
+        assert np.abs(xa - xb).max() <= 1e-10 * np.abs(xb).max(), ("fp32 init domain", i)
+        fa = got[i][32 + 6 * 216:].reshape(3, 216)[:, ex]
+        fb = ref[32 + 6 * 216:].reshape(3, 216)[:, ex]
+        worst = max(worst, float((np.abs(fa - fb) / np.maximum(np.abs(fb), 1e-300)).max()))
+    _say(f"fp32 init lanes {lanes}: worst atom-force relative error {worst:.3g}")
+    assert worst > 0.0     # the FP32 path really ran
+
+
+def test_fp32_one_step_matches_oracle(R, ctx):
+    c, recs = _oracle_states(40, seed=21)
+    dev = torch.as_tensor(recs.copy(), device="cuda")
+    R.debug_step(ctx, SPECIES3, dev, rcfg(R, lanes_per_track=64, force_precision=R.FORCE_FP32), nsteps=1)
+    got = dev.cpu().numpy()
+    for i in range(len(recs)):
+        t = oracle.Track.from_record(c, recs[i])
+        t.step()
+        assert_records_close(got[i], t.record(), rtol=1e-5, what=f"fp32 step {i}")
+
+
+def test_fp32_rejected_by_the_adjoint(R, ctx):
+    b = R.sample_primaries(ctx, R.SamplerConfig(), 0, 8)
+    with pytest.raises(R.ReedmdError, match="FP64"):
+        R.grad(ctx, ("B",), b, rcfg(R, force_precision=R.FORCE_FP32), k=1.0, s=1.0)
+
+
 # ----------------------------------------------------------------------------- whole runs
 def _load_golden(name):
     meta = json.load(open(os.path.join(GOLDEN, name + ".json")))
@@ -238,17 +284,21 @@ def _moments(z, w):
     return m, math.sqrt((w * (z - m) ** 2).sum() / W)
 
 
-def test_c0_acceptance_set_matches_oracle_statistics(R, ctx):
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_c0_acceptance_set_matches_oracle_statistics(R, ctx, precision):
     """65,536 B at 1 keV (the 256-ion workload's sampler, extended): exact ledger, weighted
-    KS p > 0.01 and mean/std of the stopping depth within 1 % of the stored oracle run."""
+    KS p > 0.01 and mean/std of the stopping depth within 1 % of the stored FP64 oracle run,
+    for the FP64 path and for the FP32 pair-term variant."""
     meta, zo, wo = _load_golden("c0_accept")
     w = WORKLOADS["c0_b1kev"]
     n = meta["workload"]["n"]
     batch = R.sample_primaries(ctx, R.SamplerConfig(**w["sampler"]), 0, n)
-    hist, stats, log, _ = R.run(ctx, w["species"], batch, rcfg(R, n_bins=w["n_bins"]), log_cap=n + 16)
+    fp = R.FORCE_FP32 if precision == "fp32" else R.FORCE_FP64
+    hist, stats, log, _ = R.run(ctx, w["species"], batch, rcfg(R, n_bins=w["n_bins"], force_precision=fp),
+                                log_cap=n + 16)
     torch.cuda.synchronize()
     st = R.parse_stats(stats)
-    _say(f"c0 gpu stats {st}")
+    _say(f"c0 {precision} gpu stats {st}")
     assert st["primaries"] == n and st["finished"] == n
     assert st["w_stopped"] + st["w_backscattered"] + st["w_quarantined"] == n
     assert float(hist.sum()) + st["w_underflow"] + st["w_overflow"] == st["w_stopped"]
