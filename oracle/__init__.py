@@ -25,12 +25,16 @@ LIB_PATH = os.path.join(_HERE, "liboracle.so")
 MAX_SPECIES = 8
 NSLOT = 216
 RECORD_WORDS = 32 + 9 * NSLOT
+NSLOT_FLUORITE = 344             # 108 cation slots padded to 128, then 216 anion slots
+RECORD_WORDS_FLUORITE = 32 + 9 * NSLOT_FLUORITE
 
-DIAMOND, ISOLATED = 0, 1
+DIAMOND, ISOLATED, FLUORITE = 0, 1, 2
+RANGE_DEPTH, RANGE_RADIAL = 0, 1
+START_SURFACE, START_SITE = 0, 1
 POT_ZBL, POT_NONE = 0, 1
 STOP_OFF, STOP_UNIFORM, STOP_LOCAL = 0, 1, 2
 ACTIVE, STOPPED, BACKSCATTERED, NONFINITE, STEPCAP = 0, 1, 2, 3, 4
-DIR_TILT, DIR_CONE, DIR_MIXED = 0, 1, 2
+DIR_TILT, DIR_CONE, DIR_MIXED, DIR_ISOTROPIC = 0, 1, 2, 3
 
 
 def build(force: bool = True) -> str:
@@ -59,6 +63,8 @@ class Params(C.Structure):
         ("n_clones", C.c_int32), ("n_bins", C.c_int32), ("bin_width", C.c_double),
         ("n_species", C.c_int32), ("Z1", C.c_int32 * MAX_SPECIES),
         ("M1", C.c_double * MAX_SPECIES),
+        ("M2b", C.c_double), ("sigma_b", C.c_double), ("Z2b", C.c_int32),
+        ("range_mode", C.c_int32), ("vacancy", C.c_int32), ("pad_", C.c_int32),
     ]
 
 
@@ -86,6 +92,7 @@ class Sampler(C.Structure):
         ("E_min", C.c_double), ("E_max", C.c_double), ("tilt", C.c_double),
         ("axis", C.c_double * 3), ("half_angle", C.c_double), ("n_cone", C.c_int64),
         ("a", C.c_double), ("z_start", C.c_double),
+        ("start_mode", C.c_int32), ("pad_", C.c_int32),
     ]
 
 
@@ -102,20 +109,24 @@ def lib():
         L.or_philox4x64.argtypes = [P(C.c_uint64), P(C.c_uint64), P(C.c_uint64)]
         L.or_u01.argtypes = [C.c_uint64]
         L.or_u01.restype = C.c_double
-        L.or_screening_length.argtypes = [P(Params), C.c_int]
+        L.or_screening_length.argtypes = [P(Params), C.c_int, C.c_int]
         L.or_screening_length.restype = C.c_double
-        L.or_unscaled_screening_length.argtypes = [P(Params), C.c_int]
+        L.or_unscaled_screening_length.argtypes = [P(Params), C.c_int, C.c_int]
         L.or_unscaled_screening_length.restype = C.c_double
-        L.or_zbl.argtypes = [P(Params), C.c_int, C.c_double, P(C.c_double), P(C.c_double)]
-        L.or_lss_kL.argtypes = [P(Params), C.c_int]
+        L.or_zbl.argtypes = [P(Params), C.c_int, C.c_int, C.c_double, P(C.c_double), P(C.c_double)]
+        L.or_lss_kL.argtypes = [P(Params), C.c_int, C.c_int]
         L.or_lss_kL.restype = C.c_double
-        L.or_density_weight.argtypes = [P(Params), C.c_int, C.c_double]
+        L.or_density_weight.argtypes = [P(Params), C.c_int, C.c_int, C.c_double]
         L.or_density_weight.restype = C.c_double
+        L.or_gamma.argtypes = [P(Params), C.c_int, C.c_double]
+        L.or_gamma.restype = C.c_double
+        L.or_site.argtypes = [P(Params), C.c_int, P(C.c_double), P(C.c_int)]
         L.or_sample_primaries.argtypes = [P(Sampler), C.c_uint64, C.c_int64, C.c_int64,
                                           C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                           C.c_void_p, C.c_void_p]
         L.or_track_size.restype = C.c_int64
         L.or_record_words.restype = C.c_int64
+        L.or_record_words.argtypes = [P(Params)]
         L.or_track_init.argtypes = [P(Params), C.c_int32, C.c_double, P(C.c_double),
                                     P(C.c_double), C.c_uint64, C.c_int32, C.c_int64, C.c_void_p]
         L.or_track_step.argtypes = [P(Params), C.c_void_p]
@@ -133,8 +144,9 @@ def lib():
         L.or_grad_track.argtypes = [P(Params), C.c_int32, C.c_double, P(C.c_double), P(C.c_double),
                                     C.c_uint64, C.c_int64, P(C.c_double), P(C.c_int64)]
         L.or_grad_track.restype = C.c_int32
-        assert L.or_record_words() == RECORD_WORDS
         _lib = L
+        assert record_words(Config()) == RECORD_WORDS
+        assert record_words(Config(structure=FLUORITE)) == RECORD_WORDS_FLUORITE
     return _lib
 
 
@@ -145,6 +157,12 @@ SPECIES = {  # symbol: (Z, mass in amu)
     "B": (5, 10.81), "P": (15, 30.97), "As": (33, 74.92),
 }
 SI = dict(a=5.431, Z2=14, M2=28.0855, sigma=0.076)
+SPECIES["U"] = (92, 238.03)
+# Fluorite UO2 (Sec. 4): cubic constant and masses from the literature; the rms thermal
+# displacements at 300 K are representative Debye-Waller amplitudes (the paper takes its
+# values from MD runs it does not print).
+UO2 = dict(a=5.470, Z2=92, M2=238.03, sigma=0.050, Z2b=8, M2b=15.999, sigma_b=0.067,
+           structure=FLUORITE)
 
 
 @dataclass
@@ -169,6 +187,11 @@ class Config:
     n_bins: int = 1024
     bin_width: float = 1.0
     species: tuple = (("B",),)
+    Z2b: int = 0
+    M2b: float = 0.0
+    sigma_b: float = 0.0
+    range_mode: int = RANGE_DEPTH
+    vacancy: int = 0
 
     def params(self):
         """Returns (Params, keepalive) where keepalive holds referenced arrays."""
@@ -182,6 +205,8 @@ class Config:
         p.n_tables, p.n_thresh = thr.shape[0], thr.shape[1]
         p.thresholds = thr.ctypes.data_as(C.POINTER(C.c_double)) if thr.size else None
         p.n_clones, p.n_bins, p.bin_width = self.n_clones, self.n_bins, self.bin_width
+        p.Z2b, p.M2b, p.sigma_b = self.Z2b, self.M2b, self.sigma_b
+        p.range_mode, p.vacancy = self.range_mode, self.vacancy
         sp = [s[0] if isinstance(s, tuple) else s for s in self.species]
         p.n_species = len(sp)
         for i, name in enumerate(sp):
@@ -202,27 +227,51 @@ def philox4x64(ctr, key):
     return [int(x) for x in o]
 
 
-def zbl(cfg: Config, species: int, r: float):
+def zbl(cfg: Config, species: int, r: float, type: int = 0):
     p, keep = cfg.params()
     V, dV = C.c_double(), C.c_double()
-    lib().or_zbl(C.byref(p), species, float(r), C.byref(V), C.byref(dV))
+    lib().or_zbl(C.byref(p), species, type, float(r), C.byref(V), C.byref(dV))
     return V.value, dV.value
 
 
-def screening_length(cfg: Config, species: int = 0, scaled: bool = True) -> float:
+def screening_length(cfg: Config, species: int = 0, scaled: bool = True, type: int = 0) -> float:
     p, keep = cfg.params()
     f = lib().or_screening_length if scaled else lib().or_unscaled_screening_length
-    return f(C.byref(p), species)
+    return f(C.byref(p), species, type)
 
 
-def lss_kL(cfg: Config, species: int = 0) -> float:
+def lss_kL(cfg: Config, species: int = 0, type: int = 0) -> float:
     p, keep = cfg.params()
-    return lib().or_lss_kL(C.byref(p), species)
+    return lib().or_lss_kL(C.byref(p), species, type)
 
 
-def density_weight(cfg: Config, species: int, r: float) -> float:
+def density_weight(cfg: Config, species: int, r: float, type: int = 0) -> float:
     p, keep = cfg.params()
-    return lib().or_density_weight(C.byref(p), species, float(r))
+    return lib().or_density_weight(C.byref(p), species, type, float(r))
+
+
+def gamma(cfg: Config, species: int, rho: float) -> float:
+    """Friction coefficient (force = -gamma v) at the stopping-weighted density rho."""
+    p, keep = cfg.params()
+    return lib().or_gamma(C.byref(p), species, float(rho))
+
+
+def site(cfg: Config, b: int):
+    """(fractional position in the cubic cell, target species) of basis site b."""
+    p, keep = cfg.params()
+    f = (C.c_double * 3)()
+    t = C.c_int()
+    lib().or_site(C.byref(p), b, f, C.byref(t))
+    return np.array(list(f)), t.value
+
+
+def record_words(cfg: Config) -> int:
+    p, keep = cfg.params()
+    return int(lib().or_record_words(C.byref(p)))
+
+
+def nslot(cfg: Config) -> int:
+    return NSLOT_FLUORITE if cfg.structure == FLUORITE else NSLOT
 
 
 @dataclass
@@ -238,6 +287,7 @@ class SamplerCfg:
     n_cone: int = 0
     a: float = SI["a"]
     z_start: float = -3.0
+    start_mode: int = START_SURFACE
 
     def struct(self):
         s = Sampler()
@@ -249,6 +299,7 @@ class SamplerCfg:
         for i in range(3):
             s.axis[i] = self.axis[i]
         s.half_angle, s.n_cone, s.a, s.z_start = self.half_angle, self.n_cone, self.a, self.z_start
+        s.start_mode = self.start_mode
         return s
 
 
@@ -294,7 +345,7 @@ class Track:
         lib().or_track_advance(C.byref(self._p), self.buf.ctypes.data, int(nsteps), int(events))
 
     def record(self):
-        rec = np.zeros(RECORD_WORDS, np.float64)
+        rec = np.zeros(record_words(self.cfg), np.float64)
         lib().or_track_export(C.byref(self._p), self.buf.ctypes.data, rec.ctypes.data)
         return rec
 
@@ -323,23 +374,30 @@ def grad_track(cfg: Config, species, E0, pos, dir, key, max_steps=0):
 def unpack_record(rec):
     rec = np.asarray(rec, dtype=np.float64)
     ir = rec.view(np.int64)
-    atoms = rec[32:].reshape(9, NSLOT)
+    ns = (rec.shape[0] - 32) // 9
+    atoms = rec[32:].reshape(9, ns)
     return dict(x=rec[0:3].copy(), v=rec[3:6].copy(), F=rec[6:9].copy(), rho=rec[9], w=rec[10],
                 z_stop=rec[11], center=ir[12:15].copy(), key=int(ir[15]) & (2**64 - 1),
                 steps=int(ir[16]), lineage=int(ir[17]), species=int(ir[18]), next_k=int(ir[19]),
-                table=int(ir[20]), status=int(ir[21]), ax=atoms[0:3].copy(), av=atoms[3:6].copy(),
-                af=atoms[6:9].copy())
+                table=int(ir[20]), status=int(ir[21]), vac_cell=ir[25:28].copy(), vac_basis=int(ir[28]),
+                x0=rec[29:32].copy(), ax=atoms[0:3].copy(), av=atoms[3:6].copy(), af=atoms[6:9].copy())
 
 
-def slot_exists(center):
-    """Boolean mask over the 216 record slots: True where the slot's cell exists (c_z >= 0)."""
-    ex = np.zeros(NSLOT, bool)
+def slot_exists(center, structure=DIAMOND, vac_cell=None, vac_basis=-1):
+    """Boolean mask over the record slots: True where the slot holds an atom (its cell has
+    c_z >= 0, it is not padding and not the vacant site)."""
+    fl = structure == FLUORITE
+    ex = np.zeros(NSLOT_FLUORITE if fl else NSLOT, bool)
     for i in (-1, 0, 1):
         for j in (-1, 0, 1):
             for k in (-1, 0, 1):
                 c = (center[0] + i, center[1] + j, center[2] + k)
-                base = ((c[0] % 3) * 9 + (c[1] % 3) * 3 + (c[2] % 3)) * 8
-                ex[base:base + 8] = c[2] >= 0
+                r = (c[0] % 3) * 9 + (c[1] % 3) * 3 + (c[2] % 3)
+                slots = ([r * 4 + b for b in range(4)] + [128 + r * 8 + b for b in range(8)]) if fl \
+                    else [r * 8 + b for b in range(8)]
+                for b, sl in enumerate(slots):
+                    vac = vac_basis >= 0 and b == vac_basis and tuple(c) == tuple(vac_cell)
+                    ex[sl] = c[2] >= 0 and not vac
     return ex
 
 

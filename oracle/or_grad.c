@@ -66,7 +66,7 @@ static const double gd[4] = {3.19980, 0.94229, 0.40290, 0.20162};
 /* ZBL pair term on duals: the screening length a = s a_U carries d/ds = a_U. */
 static void gpair(const or_params* p, int species, const dn d[3], dn* coef, dn* wr)
 {
-    double aU = or_unscaled_screening_length(p, species);
+    double aU = or_unscaled_screening_length(p, species, 0);
     dn a = {p->s * aU, 0.0, aU};
     double zz = (p->pot_mode == OR_POT_NONE) ? 0.0 : (double)p->Z1[species] * (double)p->Z2 * OR_COULOMB;
     dn r2 = dadd(dadd(dmul(d[0], d[0]), dmul(d[1], d[1])), dmul(d[2], d[2]));
@@ -110,7 +110,8 @@ static void gforces(const or_params* p, gtrack* t)
 static void gcreate(const or_params* p, const gtrack* t, const int64_t c[3], int b, gatom* at)
 {
     double f[3], g[3];
-    or_basis(b, f);
+    int type;
+    or_site(p, b, f, &type);
     or_gauss3(t->key, p->seed, c[0], c[1], c[2], b, g);
     for (int d = 0; d < 3; ++d) {
         at->x[d] = D(p->a * ((double)c[d] + f[d]) + p->sigma * g[d]);
@@ -188,7 +189,7 @@ static void gstep(const or_params* p, gtrack* t)
     }
     /* friction coefficient: gamma = k * gamma0 * rho / N (local) or k * gamma0 (uniform) */
     double N = (double)OR_NBASIS / (p->a * p->a * p->a);
-    double gamma0 = N * or_lss_kL(p, t->species) * sqrt(M1 / 2.0);
+    double gamma0 = N * or_lss_kL(p, t->species, 0) * sqrt(M1 / 2.0);
     dn kk = {p->k, 1.0, 0.0};
     dn g1;
     if (p->stop_mode == OR_STOP_OFF) g1 = D(0.0);
@@ -233,6 +234,8 @@ int32_t or_grad_track(const or_params* p, int32_t species, double E0, const doub
                       const double dir[3], uint64_t key, int64_t max_steps, double out[3],
                       int64_t* steps_out)
 {
+    /* diamond, depth range and no vacancy only (the adjoint's domain) */
+    if (p->structure != OR_DIAMOND || p->range_mode != OR_RANGE_DEPTH || p->vacancy) return -3;
     gtrack* t = (gtrack*)calloc(1, sizeof(gtrack));
     if (!t) return -1;
     double M1 = p->M1[species];

@@ -18,17 +18,17 @@ uint64_t or_primary_key(uint64_t seed, int64_t id);
 
 typedef struct {
     int on;
-    double a, zz, lambda;
+    double a, zz, lambda, wscale;
 } or_pair_consts;
-void or_pair_constants(const or_params* p, int species, or_pair_consts* c);
+void or_pair_constants(const or_params* p, int species, int type, or_pair_consts* c);
 void or_zbl_c(const or_pair_consts* c, double r, double* V, double* dVdr);
 double or_density_weight_c(const or_pair_consts* c, double r);
 
-double or_gamma(const or_params* p, int species, double rho);
-double or_number_density(const or_params* p);
-double or_pair_potential(const or_params* p, int species, double r);
+double or_number_density(const or_params* p, int type);
+double or_pair_potential(const or_params* p, int species, int type, double r);
 
 void or_compute_forces(const or_params* p, or_track* t);
-void or_basis(int b, double f[3]);
+int or_nbasis(const or_params* p);
+double or_type_mass(const or_params* p, int type);
 
 #endif

@@ -14,8 +14,11 @@
  * species drawn uniformly from the list, energy log-uniform in
  * [E_min, E_max] (fixed when equal), direction either a fixed polar tilt
  * with uniform azimuth, or uniform on a cone of half-angle alpha about an
- * axis, or the cone for ids below n_cone and the tilt for the rest.  The
- * threshold table is chosen by species and by equal log-energy band. */
+ * axis, or the cone for ids below n_cone and the tilt for the rest, or
+ * uniform over the sphere (a recoil, Sec. 4: random direction).  With
+ * start_mode OR_START_SITE the start point is the lattice point (0, 0,
+ * z_start) instead (an on-lattice recoil, Sec. 4).  The threshold table is
+ * chosen by species and by equal log-energy band. */
 void or_sample_primaries(const or_sampler* s, uint64_t seed, int64_t id0, int64_t n,
                          int32_t* species, double* E0, double* pos, double* dir,
                          uint64_t* key, int32_t* table)
@@ -33,8 +36,13 @@ void or_sample_primaries(const or_sampler* s, uint64_t seed, int64_t id0, int64_
             u[i] = or_u01(r0[i]);
             u[4 + i] = or_u01(r1[i]);
         }
-        pos[q] = s->a * u[0];
-        pos[n + q] = s->a * u[1];
+        if (s->start_mode == OR_START_SITE) {
+            pos[q] = 0.0;
+            pos[n + q] = 0.0;
+        } else {
+            pos[q] = s->a * u[0];
+            pos[n + q] = s->a * u[1];
+        }
         pos[2 * n + q] = s->z_start;
 
         int ci = (int)floor((double)s->n_choice * u[2]);
@@ -54,7 +62,14 @@ void or_sample_primaries(const or_sampler* s, uint64_t seed, int64_t id0, int64_
 
         int cone = s->dir_mode == OR_DIR_CONE || (s->dir_mode == OR_DIR_MIXED && id < s->n_cone);
         double phi = 2.0 * OR_PI * u[4];
-        if (!cone) {
+        if (s->dir_mode == OR_DIR_ISOTROPIC) {
+            /* uniform on the sphere: cos(theta) uniform in [-1, 1] */
+            double ct = 1.0 - 2.0 * u[5];
+            double st = sqrt(fmax(0.0, 1.0 - ct * ct));
+            dir[q] = st * cos(phi);
+            dir[n + q] = st * sin(phi);
+            dir[2 * n + q] = ct;
+        } else if (!cone) {
             dir[q] = sin(s->tilt) * cos(phi);
             dir[n + q] = sin(s->tilt) * sin(phi);
             dir[2 * n + q] = cos(s->tilt);
@@ -178,14 +193,15 @@ static void run_primary(run_local* L, int64_t q)
         while (t->status == OR_ACTIVE) {
             double M1 = p->M1[t->species];
             double ke = 0.5 * M1 * (t->v[0] * t->v[0] + t->v[1] * t->v[1] + t->v[2] * t->v[2]);
-            double z = t->x[2];
+            double z = or_range_coord(p, t);
             or_track_step(p, t);
             L->st.track_steps += 1;
             L->st.pair_evals += domain_atoms(t);
             int32_t st = or_track_events(p, t, ke, z);
             if (st != OR_ACTIVE) break;
             const double* thr = p->thresholds + (int64_t)t->table * p->n_thresh;
-            while (t->next_k < p->n_thresh && t->x[2] >= thr[t->next_k]) {
+            const double zr = or_range_coord(p, t);
+            while (t->next_k < p->n_thresh && zr >= thr[t->next_k]) {
                 int32_t k = t->next_k;
                 uint64_t parent = t->key;
                 t->w = t->w / (double)p->n_clones;

@@ -39,7 +39,13 @@
  * forms; head-on turning points and scattering angles against root finding and
  * quadrature; energy, momentum and weight ledgers; splitting against brute
  * force; the forward-mode derivative against finite differences of the
- * oracle's own stopping depth.  The absolute range profile of a full run is
+ * oracle's own stopping depth.  Fluorite (tests/test_oracle_fluorite.py):
+ * textbook geometry and coordination, the anion pair and stopping constants
+ * against the Coulomb limit, the printed reduced energy and Lindhard's form,
+ * compound friction paths in closed form, the stopping-weighted mean density,
+ * the recoil vacancy, the isotropic on-site sampler, the radial range of a
+ * free ion, energy and momentum ledgers with two masses, exact record round
+ * trips.  The absolute range profile of a full run is
  * parity unpinned against the paper (it prints no profile values and its
  * figures are not available); it is only compared with the GPU library.
  */
@@ -52,9 +58,15 @@ extern "C" {
 #endif
 
 enum { OR_MAX_SPECIES = 8, OR_NCELL = 27, OR_NBASIS = 8, OR_NSLOT = 216 };
+/* Fluorite (UO2, Sec. 2 and Sec. 4: 27 cells of the 12-atom fluorite cell):
+ * 4 cation and 8 anion sites per cell, 324 domain atoms; the record keeps the
+ * 108 cation slots first, padded to 128, then the 216 anion slots. */
+enum { OR_MAX_BASIS = 12, OR_MAX_ATOMS = 324, OR_NSLOT_FLUORITE = 344, OR_ANION_SLOT0 = 128 };
 
 /* structures */
-enum { OR_DIAMOND = 0, OR_ISOLATED = 1 };
+enum { OR_DIAMOND = 0, OR_ISOLATED = 1, OR_FLUORITE = 2 };
+/* range coordinate (cloning distances and the histogram) */
+enum { OR_RANGE_DEPTH = 0, OR_RANGE_RADIAL = 1 };
 /* potential modes */
 enum { OR_POT_ZBL = 0, OR_POT_NONE = 1 };
 /* stopping modes */
@@ -93,6 +105,14 @@ typedef struct {
     int32_t n_species;
     int32_t Z1[OR_MAX_SPECIES];
     double M1[OR_MAX_SPECIES];
+    /* second target species: the anion sites of fluorite (the fields above
+     * describe target species 0, the only one of diamond) */
+    double M2b, sigma_b;
+    int32_t Z2b;
+    int32_t range_mode;  /* OR_RANGE_DEPTH: z; OR_RANGE_RADIAL: distance from the start point */
+    int32_t vacancy;     /* 1: the primary is the recoil of the basis-0 atom of the cell whose
+                            origin is nearest its start point; that site stays empty */
+    int32_t pad_;
 } or_params;
 
 /* One domain atom. */
@@ -100,7 +120,9 @@ typedef struct {
     double x[3], v[3], f[3];
     int64_t cell[3];
     int32_t basis;
+    int32_t type;        /* target species */
     int32_t exists;
+    int32_t pad_;
 } or_atom;
 
 /* One ion track with its 27-cell domain (atoms in canonical offset order:
@@ -115,9 +137,11 @@ typedef struct {
     int64_t lineage;            /* primary id */
     int32_t species, next_k, table, status;
     double z_stop;
-    int32_t n_atoms;            /* 216 for the lattice, 1 for OR_ISOLATED */
-    int32_t pad;
-    or_atom atom[OR_NSLOT];
+    int32_t n_atoms;            /* 216 (diamond) or 324 (fluorite), 1 for OR_ISOLATED */
+    int32_t vac_basis;          /* basis index of the vacant site, -1: none */
+    int64_t vac_cell[3];        /* cell of the vacant site */
+    double x0[3];               /* start point of the primary (radial range) */
+    or_atom atom[OR_MAX_ATOMS];
     /* conservation ledger (stopping off): energy and momentum carried out of
      * the domain by dropped atoms, and potential energy brought in by created atoms */
     double e_out, e_in, p_out[3];
@@ -140,7 +164,8 @@ typedef struct {
 } or_result;
 
 /* Primary sampler description. */
-enum { OR_DIR_TILT = 0, OR_DIR_CONE = 1, OR_DIR_MIXED = 2 };
+enum { OR_DIR_TILT = 0, OR_DIR_CONE = 1, OR_DIR_MIXED = 2, OR_DIR_ISOTROPIC = 3 };
+enum { OR_START_SURFACE = 0, OR_START_SITE = 1 };
 typedef struct {
     int32_t n_choice;         /* species drawn uniformly from choice[0..n_choice) */
     int32_t choice[OR_MAX_SPECIES];
@@ -153,6 +178,9 @@ typedef struct {
     int64_t n_cone;           /* DIR_MIXED: ids below this use the cone */
     double a;                 /* entry area is [0,a)^2 */
     double z_start;
+    int32_t start_mode;       /* OR_START_SURFACE: uniform over [0,a)^2 at z_start;
+                                 OR_START_SITE: the lattice point (0, 0, z_start) */
+    int32_t pad_;
 } or_sampler;
 
 /* RNG (counter-based Philox4x64-10) */
@@ -160,11 +188,14 @@ void or_philox4x64(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]
 double or_u01(uint64_t w);
 
 /* physics primitives */
-double or_screening_length(const or_params* p, int species);
-double or_unscaled_screening_length(const or_params* p, int species);
-void or_zbl(const or_params* p, int species, double r, double* V, double* dVdr);
-double or_lss_kL(const or_params* p, int species);
-double or_density_weight(const or_params* p, int species, double r);
+/* `type` is the target species (0, or 1 for the fluorite anions) */
+double or_screening_length(const or_params* p, int species, int type);
+double or_unscaled_screening_length(const or_params* p, int species, int type);
+void or_zbl(const or_params* p, int species, int type, double r, double* V, double* dVdr);
+double or_lss_kL(const or_params* p, int species, int type);
+double or_density_weight(const or_params* p, int species, int type, double r);
+double or_gamma(const or_params* p, int species, double rho);
+void or_site(const or_params* p, int b, double f[3], int* type);
 
 /* sampler */
 void or_sample_primaries(const or_sampler* s, uint64_t seed, int64_t id0, int64_t n,
@@ -178,11 +209,12 @@ void or_track_init(const or_params* p, int32_t species, double E0, const double 
                    or_track* t);
 double or_track_step(const or_params* p, or_track* t);      /* returns dt */
 int32_t or_track_events(const or_params* p, or_track* t, double ke_before, double z_before);
+double or_range_coord(const or_params* p, const or_track* t);
 void or_track_advance(const or_params* p, or_track* t, int64_t nsteps, int32_t with_events);
 void or_track_ledger(const or_params* p, const or_track* t, double* energy, double momentum[3]);
 void or_track_export(const or_params* p, const or_track* t, double* record);
 void or_track_import(const or_params* p, const double* record, or_track* t);
-int64_t or_record_words(void);
+int64_t or_record_words(const or_params* p);
 
 /* whole run: every primary with all of its clones, weighted histogram out */
 int32_t or_run(const or_params* p, int64_t n, const int32_t* species, const double* E0,
