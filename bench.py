@@ -4,8 +4,9 @@ One step = sample the 65,536 primaries of the 10 keV As workload on the device a
 every primary with all of its clones to termination (domain following, ZBL forces, local
 stopping, adaptive velocity Verlet, cloning at 8 depths, weighted histogram).  Prints one
 JSON line: ion-atom force evaluations per second (value), tracks per second, the FP64
-VALU roofline fraction of the track kernel, the FP32 pair-term variant beside it, and the
-FP64 CPU oracle timed on a bounded sample of the same workload on the host cores.
+VALU roofline fraction of the track kernel, the FP32 pair-term variant and the 85 keV U
+recoil in fluorite UO2 beside it, and the FP64 CPU oracle timed on a bounded sample of the
+same workload on the host cores.
 """
 from __future__ import annotations
 
@@ -74,6 +75,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-grad", action="store_true", help="skip the gradient / forward time ratio")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 pair-term variant leg")
+    ap.add_argument("--no-uo2", action="store_true", help="skip the 85 keV U recoil in UO2 leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (HBM counter calibration)")
     return ap.parse_args()
@@ -153,6 +155,57 @@ def fp32_leg(R, ctx, torch, w, sampler, n, base, stream, hist, stats, form, lane
                           "fp32_flop_per_pair": FLOP_PER_PAIR_F32_PART,
                           "frac": t_ideal / (k * 1e-3)},
                 tolerance="1e-5 relative per step against the FP64 oracle")
+
+
+def uo2_leg(R, torch):
+    """The 85 keV U recoil workload in fluorite UO2 (5,120 primaries, on-site start with the
+    site left vacant, random directions, 8 cloning distances from the start point): autotuned
+    shape (64 or 32 lanes), one warm launch, two timed launches."""
+    from tests.workloads import C5_THRESHOLDS, UO2, WORKLOADS
+    w = WORKLOADS["c5_u85kev_uo2"]
+    ctx = R.Context(structure=R.FLUORITE, **UO2)
+    sc = R.SamplerConfig(**w["sampler"])
+    base = dict(n_bins=w["n_bins"], bin_width=w["bin_width"], thresholds=[list(C5_THRESHOLDS)],
+                range_mode=w["range_mode"], vacancy=w["vacancy"], form=R.FORM_PERSISTENT)
+    batch = R.sample_primaries(ctx, sc, 0, w["n"])
+    lanes, waves = R.autotune(ctx, w["species"], batch, R.RunConfig(**base), pilot=w["n"])
+    cfg = R.RunConfig(lanes_per_track=lanes, waves_per_cu=waves, **base)
+    R.run(ctx, w["species"], batch, cfg)
+    torch.cuda.synchronize()
+    hist = torch.zeros(w["n_bins"], dtype=torch.float64, device="cuda")
+    stats = R.new_stats()
+    pairs = tracks = 0
+    t_all = 0.0
+    kms = []
+    stream = torch.cuda.current_stream()
+    for _ in range(2):
+        b = R.sample_primaries(ctx, sc, 0, w["n"], stream=stream)
+        hist.zero_()
+        stats.zero_()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0.record(stream)
+        R.run(ctx, w["species"], b, cfg, hist=hist, stats=stats, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t_all += time.perf_counter() - t0
+        st = R.parse_stats(stats)
+        pairs += st["pair_evals"]
+        tracks += st["finished"]
+        kms.append(e0.elapsed_time(e1))
+    mean_range = st["sum_wz"] / max(st["w_stopped"], 1e-300)
+    shape = R.launch_shape(ctx, batch, cfg)
+    ctx.close()
+    k = sum(kms) / len(kms)
+    return dict(workload="5,120 U at 85 keV in UO2 (a=5.47 A, sigma U 0.050 / O 0.067 A), on-site recoils "
+                         "at 1,094 A depth, random direction, vacant start site, radial range, 8 cloning "
+                         "distances, 0.5 A bins",
+                force_evals_per_s=pairs / t_all, tracks_per_s=tracks / t_all, kernel_ms_per_step=[round(x, 1) for x in kms],
+                launch=shape, mean_range_A=mean_range,
+                roofline={"bound": "alu", "achieved": FLOP_PER_PAIR * pairs / 2 / (k * 1e-3) / 1e12,
+                          "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                          "frac": FLOP_PER_PAIR * pairs / 2 / (k * 1e-3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS})
 
 
 def grad_forward_ratio(R, ctx, torch):
@@ -393,6 +446,8 @@ def main():
     if not args.no_fp32:
         out["fp32_pair_variant"] = fp32_leg(R, ctx, torch, w, sampler, n, base, stream, hist, stats, args.form,
                                             args.lanes, args.waves)
+    if not args.no_uo2:
+        out["uo2_recoil"] = uo2_leg(R, torch)
     if not args.no_grad:
         gr = grad_forward_ratio(R, ctx, torch)
         out["grad_fwd_ratio"] = gr["ratio"]

@@ -36,6 +36,8 @@ extern "C" {
 
 #define REEDMD_NSLOT 216                 /* 27 cells x 8 diamond basis atoms */
 #define REEDMD_RECORD_WORDS (32 + 9 * 216)
+#define REEDMD_NSLOT_FLUORITE 344        /* 27 x 4 cation slots padded to 128, then 27 x 8 anion slots */
+#define REEDMD_RECORD_WORDS_FLUORITE (32 + 9 * 344)
 #define REEDMD_MAX_SPECIES 8
 
 typedef struct reedmd_ctx reedmd_ctx;
@@ -48,7 +50,9 @@ typedef enum {
     REEDMD_EUNSUPPORTED = -5   /* valid but not implemented combination */
 } reedmd_status;
 
-enum { REEDMD_DIAMOND = 0 };
+enum { REEDMD_DIAMOND = 0, REEDMD_FLUORITE = 1 };
+/* range coordinate used for the cloning depths and the histogram */
+enum { REEDMD_RANGE_DEPTH = 0, REEDMD_RANGE_RADIAL = 1 };
 enum { REEDMD_POT_ZBL = 0, REEDMD_POT_NONE = 1 };
 enum { REEDMD_STOP_OFF = 0, REEDMD_STOP_UNIFORM = 1, REEDMD_STOP_LOCAL = 2 };
 enum { REEDMD_FORM_PLAIN = 0, REEDMD_FORM_PERSISTENT = 1 };
@@ -56,22 +60,32 @@ enum { REEDMD_FORM_PLAIN = 0, REEDMD_FORM_PERSISTENT = 1 };
  * coefficient, density weight).  Positions, velocities, force components and
  * sums, kicks, drifts and the step size are FP64 in both. */
 enum { REEDMD_FORCE_FP64 = 0, REEDMD_FORCE_FP32 = 1 };
-enum { REEDMD_DIR_TILT = 0, REEDMD_DIR_CONE = 1, REEDMD_DIR_MIXED = 2 };
+enum { REEDMD_DIR_TILT = 0, REEDMD_DIR_CONE = 1, REEDMD_DIR_MIXED = 2, REEDMD_DIR_ISOTROPIC = 3 };
+enum { REEDMD_START_SURFACE = 0, REEDMD_START_SITE = 1 };
 /* track status (record word 21, result log) */
 enum { REEDMD_ACTIVE = 0, REEDMD_STOPPED = 1, REEDMD_BACKSCATTERED = 2, REEDMD_NONFINITE = 3,
        REEDMD_STEPCAP = 4, REEDMD_CANCELLED = 5, REEDMD_LOST = 6 };
 
 /* Target crystal (Sec. 2: the domain is made of unit cells of the target
  * structure; Sec. 4: temperature as Gaussian displacements of lattice atoms).
- * Diamond cubic with cubic constant a; every created atom sits at its ideal
- * site plus an independent N(0, sigma^2) displacement per axis, at rest.  The
- * crystal occupies z >= 0 (cells with c_z >= 0). */
+ * Cubic cell of constant a; every created atom sits at its ideal site plus an
+ * independent N(0, sigma^2) displacement per axis (sigma of its species), at
+ * rest.  The crystal occupies z >= 0 (cells with c_z >= 0).
+ *   REEDMD_DIAMOND: 8 atoms per cell of one species (Z2, M2, sigma).
+ *   REEDMD_FLUORITE (UO2, Sec. 4: 27 cells of the 12-atom cell): cations
+ *   (Z2, M2, sigma) on the 4 fcc sites, anions (Z2b, M2b, sigma_b) on the 8
+ *   sites with every coordinate 1/4 or 3/4.  Local stopping adds over the two
+ *   species (Bragg's rule). */
 typedef struct {
     double a;            /* cubic lattice constant (A), > 0 */
-    double M2;           /* target mass (amu), > 0 */
+    double M2;           /* target (cation) mass (amu), > 0 */
     double sigma;        /* thermal rms displacement per axis (A), >= 0 */
-    int32_t Z2;          /* target atomic number, > 0 */
-    int32_t structure;   /* REEDMD_DIAMOND */
+    int32_t Z2;          /* target (cation) atomic number, > 0 */
+    int32_t structure;   /* REEDMD_DIAMOND or REEDMD_FLUORITE */
+    double M2b;          /* fluorite anion mass (amu), > 0 for fluorite */
+    double sigma_b;      /* fluorite anion rms displacement (A), >= 0 */
+    int32_t Z2b;         /* fluorite anion atomic number, > 0 for fluorite */
+    int32_t reserved;
 } reedmd_lattice;
 
 /* Ion-atom interaction (Sec. 2, "First"): ZBL universal screened Coulomb,
@@ -115,16 +129,18 @@ typedef struct {
 } reedmd_batch;
 
 /* Primary sampler (counter-based, seed + lineage id): entry point uniform in
- * [0,a)^2 at z = z_start; species uniform over choice[]; energy log-uniform in
- * [E_min, E_max] (fixed if equal); direction a polar tilt with uniform azimuth,
- * or uniform in a cone of half angle about axis, or the cone for ids < n_cone
- * and the tilt otherwise.  table = choice index * n_energy_tables + energy band. */
+ * [0,a)^2 at z = z_start, or the lattice point (0, 0, z_start) (START_SITE: an
+ * on-lattice recoil, Sec. 4); species uniform over choice[]; energy log-uniform
+ * in [E_min, E_max] (fixed if equal); direction a polar tilt with uniform
+ * azimuth, or uniform in a cone of half angle about axis, or the cone for
+ * ids < n_cone and the tilt otherwise, or uniform over the sphere (ISOTROPIC).
+ * table = choice index * n_energy_tables + energy band. */
 typedef struct {
     int32_t n_choice;
     int32_t choice[REEDMD_MAX_SPECIES];
     int32_t dir_mode;                 /* REEDMD_DIR_* */
     int32_t n_energy_tables;          /* >= 1 */
-    int32_t reserved;
+    int32_t start_mode;               /* REEDMD_START_SURFACE or REEDMD_START_SITE */
     double E_min, E_max;
     double tilt;                      /* rad */
     double axis[3];                   /* unit vector */
@@ -157,6 +173,14 @@ typedef struct {
     int64_t track_log_cap;
     int32_t force_precision;   /* REEDMD_FORCE_FP64 (0) or REEDMD_FORCE_FP32 (1; run, track_init,
                                   debug_step, autotune; reedmd_grad is FP64 only) */
+    int32_t range_mode;        /* REEDMD_RANGE_DEPTH: cloning depths and histogram in z;
+                                  REEDMD_RANGE_RADIAL: in the distance from the primary's start
+                                  point (recoils inside the crystal, Sec. 4); fluorite only
+                                  (diamond: REEDMD_EUNSUPPORTED) */
+    int32_t vacancy;           /* 1: each primary is the recoil of the basis-0 atom of the cell
+                                  whose origin is nearest its start point (floor(x/a + 1/4) per
+                                  axis); that site stays empty for the whole track and its clones;
+                                  fluorite only (diamond: REEDMD_EUNSUPPORTED) */
     int32_t reserved;
 } reedmd_run_params;
 
@@ -246,15 +270,21 @@ reedmd_status reedmd_run_refined(reedmd_ctx* ctx, const reedmd_species* species,
 
 /* Builds the starting record (ion, its full domain and the forces at the
  * start point) of each batch entry into d_records (device, n *
- * REEDMD_RECORD_WORDS 64-bit words).  Record layout: words 0-2 ion position,
- * 3-5 velocity, 6-8 ZBL force, 9 local density, 10 weight, 11 stopping depth,
- * 12-14 centre cell (int64), 15 key (uint64), 16 steps, 17 lineage, 18
- * species, 19 crossed thresholds, 20 table, 21 status, 22-23 largest atom |v|^2 and
- * |f/M2|^2 (valid when word 24 == 1; records made elsewhere may leave 22-31 zero and the
- * library then recomputes them), 25-31 zero; then nine
- * 216-word fields x, y, z, vx, vy, vz, fx, fy, fz of the domain atoms, slot of
- * basis atom b of cell c = ((c_x mod 3)*9 + (c_y mod 3)*3 + (c_z mod 3))*8 + b.
- * Slots of cells with c_z < 0 do not exist and hold zeros. */
+ * REEDMD_RECORD_WORDS 64-bit words; REEDMD_RECORD_WORDS_FLUORITE for a
+ * fluorite context).  Record layout: words 0-2 ion position,
+ * 3-5 velocity, 6-8 ZBL force, 9 local (stopping-weighted) density, 10 weight,
+ * 11 stopping depth (range coordinate), 12-14 centre cell (int64), 15 key
+ * (uint64), 16 steps, 17 lineage, 18 species, 19 crossed thresholds, 20 table,
+ * 21 status, 22-23 largest atom |v|^2 and |f/M|^2 (valid when word 24 == 1;
+ * records made elsewhere may leave 22-24 zero and the library then recomputes
+ * them), 25-27 cell of the vacant site (int64), 28 its basis index (-1: none),
+ * 29-31 start point of the primary; then nine fields x, y, z, vx, vy, vz, fx,
+ * fy, fz of the domain atoms with NS = 216 (diamond) or 344 (fluorite) entries
+ * each.  With r = (c_x mod 3)*9 + (c_y mod 3)*3 + (c_z mod 3), the slot of
+ * basis atom b of cell c is r*8 + b (diamond); r*4 + b for the fluorite
+ * cations (b < 4) and 128 + r*8 + b - 4 for its anions.  Slots of cells with
+ * c_z < 0, the vacant site and fluorite slots 108..127 hold no atom (zeros).
+ * Fluorite runs on 64 or 32 lanes per track (16: REEDMD_EUNSUPPORTED). */
 reedmd_status reedmd_track_init(reedmd_ctx* ctx, const reedmd_species* species,
                                 const reedmd_batch* batch, const reedmd_run_params* params,
                                 double* d_records, hipStream_t stream);

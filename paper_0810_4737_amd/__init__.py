@@ -15,12 +15,17 @@ import numpy as np
 import torch
 
 from . import _abi
-from ._abi import (ACTIVE, BACKSCATTERED, CANCELLED, DIR_CONE, DIR_MIXED, DIR_TILT,  # noqa: F401
-                   FORCE_FP32, FORCE_FP64, FORM_PERSISTENT, FORM_PLAIN, NONFINITE, NSLOT, POT_NONE, POT_ZBL, RECORD_WORDS,
-                   STEPCAP, STOP_LOCAL, STOP_OFF, STOP_UNIFORM, STOPPED)
+from ._abi import (ACTIVE, BACKSCATTERED, CANCELLED, DIAMOND, DIR_CONE, DIR_ISOTROPIC, DIR_MIXED,  # noqa: F401
+                   DIR_TILT, FLUORITE, FORCE_FP32, FORCE_FP64, FORM_PERSISTENT, FORM_PLAIN, NONFINITE, NSLOT,
+                   NSLOT_FLUORITE, POT_NONE, POT_ZBL, RANGE_DEPTH, RANGE_RADIAL, RECORD_WORDS,
+                   RECORD_WORDS_FLUORITE, START_SITE, START_SURFACE, STEPCAP, STOP_LOCAL, STOP_OFF,
+                   STOP_UNIFORM, STOPPED)
 
-SPECIES = {"B": (5, 10.81), "P": (15, 30.97), "As": (33, 74.92)}
+SPECIES = {"B": (5, 10.81), "P": (15, 30.97), "As": (33, 74.92), "U": (92, 238.03)}
 SILICON = dict(a=5.431, Z2=14, M2=28.0855, sigma=0.076)
+# Fluorite UO2 (cations U, anions O); rms thermal displacements are representative
+# 300 K Debye-Waller amplitudes
+UO2 = dict(a=5.470, Z2=92, M2=238.03, sigma=0.050, Z2b=8, M2b=15.999, sigma_b=0.067, structure=FLUORITE)
 
 
 class ReedmdError(RuntimeError):
@@ -47,10 +52,12 @@ class Context:
     """One target crystal + interaction model on the current device."""
 
     def __init__(self, a=SILICON["a"], Z2=SILICON["Z2"], M2=SILICON["M2"], sigma=SILICON["sigma"],
-                 pot_mode=POT_ZBL, s=1.0, stop_mode=STOP_LOCAL, k=1.0):
+                 pot_mode=POT_ZBL, s=1.0, stop_mode=STOP_LOCAL, k=1.0, structure=DIAMOND,
+                 Z2b=0, M2b=0.0, sigma_b=0.0):
         L = _abi.load()
         self._lib = L
-        lat = _abi.Lattice(a=a, M2=M2, sigma=sigma, Z2=Z2, structure=_abi.DIAMOND)
+        lat = _abi.Lattice(a=a, M2=M2, sigma=sigma, Z2=Z2, structure=structure, M2b=M2b,
+                           sigma_b=sigma_b, Z2b=Z2b)
         pot = _abi.Potential(mode=pot_mode, s=s)
         stp = _abi.Stopping(mode=stop_mode, k=k)
         h = C.c_void_p()
@@ -59,6 +66,8 @@ class Context:
             raise ReedmdError(f"reedmd_create failed ({rc}): {L.reedmd_last_error(None).decode()}")
         self.handle = h
         self.a = a
+        self.structure = structure
+        self.record_words = RECORD_WORDS_FLUORITE if structure == FLUORITE else RECORD_WORDS
 
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:
@@ -102,6 +111,8 @@ class RunConfig:
     waves_per_cu: int = 0
     queue_capacity: int = 0
     force_precision: int = FORCE_FP64
+    range_mode: int = RANGE_DEPTH
+    vacancy: int = 0
 
     def struct(self, device, keep):
         p = _abi.RunParams()
@@ -116,6 +127,7 @@ class RunConfig:
         p.form, p.lanes_per_track = self.form, self.lanes_per_track
         p.waves_per_cu, p.queue_capacity = self.waves_per_cu, self.queue_capacity
         p.force_precision = self.force_precision
+        p.range_mode, p.vacancy = self.range_mode, self.vacancy
         return p
 
 
@@ -132,6 +144,7 @@ class SamplerConfig:
     n_cone: int = 0
     a: float = SILICON["a"]
     z_start: float = -3.0
+    start_mode: int = START_SURFACE
 
     def struct(self):
         s = _abi.Sampler()
@@ -143,6 +156,7 @@ class SamplerConfig:
         for i in range(3):
             s.axis[i] = self.axis[i]
         s.half_angle, s.n_cone, s.a, s.z_start = self.half_angle, self.n_cone, self.a, self.z_start
+        s.start_mode = self.start_mode
         return s
 
 
@@ -275,7 +289,7 @@ def track_init(ctx: Context, species, batch, cfg: RunConfig, id0=0, stream=None)
     keep = []
     p = cfg.struct(dev, keep)
     n = int(batch["energy"].shape[0])
-    rec = torch.zeros((n, RECORD_WORDS), dtype=torch.float64, device=dev)
+    rec = torch.zeros((n, ctx.record_words), dtype=torch.float64, device=dev)
     sp = species_table(species) if not isinstance(species, _abi.Species) else species
     b = _batch_struct(batch, id0)
     ctx.check(ctx._lib.reedmd_track_init(ctx.handle, C.byref(sp), C.byref(b), C.byref(p), _ptr(rec),
@@ -288,6 +302,8 @@ def debug_step(ctx: Context, species, records: torch.Tensor, cfg: RunConfig, nst
     p = cfg.struct(records.device, keep)
     sp = species_table(species) if not isinstance(species, _abi.Species) else species
     assert records.is_contiguous() and records.dtype == torch.float64
+    if records.dim() != 2 or records.shape[1] != ctx.record_words:
+        raise ReedmdError(f"records must be [n, {ctx.record_words}] for this target")
     ctx.check(ctx._lib.reedmd_debug_step(ctx.handle, C.byref(sp), C.byref(p), _ptr(records),
                                          int(records.shape[0]), int(nsteps), _stream(stream)))
     return records

@@ -7,14 +7,18 @@ import os
 MAX_SPECIES = 8
 NSLOT = 216
 RECORD_WORDS = 32 + 9 * NSLOT
+NSLOT_FLUORITE = 344
+RECORD_WORDS_FLUORITE = 32 + 9 * NSLOT_FLUORITE
 
 OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED = 0, -1, -2, -3, -5
-DIAMOND = 0
+DIAMOND, FLUORITE = 0, 1
+RANGE_DEPTH, RANGE_RADIAL = 0, 1
+START_SURFACE, START_SITE = 0, 1
 POT_ZBL, POT_NONE = 0, 1
 STOP_OFF, STOP_UNIFORM, STOP_LOCAL = 0, 1, 2
 FORM_PLAIN, FORM_PERSISTENT = 0, 1
 FORCE_FP64, FORCE_FP32 = 0, 1
-DIR_TILT, DIR_CONE, DIR_MIXED = 0, 1, 2
+DIR_TILT, DIR_CONE, DIR_MIXED, DIR_ISOTROPIC = 0, 1, 2, 3
 ACTIVE, STOPPED, BACKSCATTERED, NONFINITE, STEPCAP, CANCELLED, LOST = range(7)
 
 LIB_PATH = os.environ.get("REEDMD_LIBRARY") or \
@@ -23,7 +27,8 @@ LIB_PATH = os.environ.get("REEDMD_LIBRARY") or \
 
 class Lattice(C.Structure):
     _fields_ = [("a", C.c_double), ("M2", C.c_double), ("sigma", C.c_double),
-                ("Z2", C.c_int32), ("structure", C.c_int32)]
+                ("Z2", C.c_int32), ("structure", C.c_int32),
+                ("M2b", C.c_double), ("sigma_b", C.c_double), ("Z2b", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Potential(C.Structure):
@@ -47,7 +52,7 @@ class Batch(C.Structure):
 
 class Sampler(C.Structure):
     _fields_ = [("n_choice", C.c_int32), ("choice", C.c_int32 * MAX_SPECIES),
-                ("dir_mode", C.c_int32), ("n_energy_tables", C.c_int32), ("reserved", C.c_int32),
+                ("dir_mode", C.c_int32), ("n_energy_tables", C.c_int32), ("start_mode", C.c_int32),
                 ("E_min", C.c_double), ("E_max", C.c_double), ("tilt", C.c_double),
                 ("axis", C.c_double * 3), ("half_angle", C.c_double), ("n_cone", C.c_int64),
                 ("a", C.c_double), ("z_start", C.c_double)]
@@ -60,7 +65,8 @@ class RunParams(C.Structure):
                 ("n_clones", C.c_int32), ("n_bins", C.c_int32), ("bin_width", C.c_double),
                 ("form", C.c_int32), ("lanes_per_track", C.c_int32), ("waves_per_cu", C.c_int32),
                 ("queue_capacity", C.c_int32), ("cancel", C.c_void_p), ("track_log", C.c_void_p),
-                ("track_log_cap", C.c_int64), ("force_precision", C.c_int32), ("reserved2", C.c_int32)]
+                ("track_log_cap", C.c_int64), ("force_precision", C.c_int32), ("range_mode", C.c_int32),
+                ("vacancy", C.c_int32), ("reserved2", C.c_int32)]
 
 
 class Refine(C.Structure):

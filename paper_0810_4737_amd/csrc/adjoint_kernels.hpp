@@ -301,7 +301,7 @@ __global__ void __launch_bounds__(64, REEDMD_GRAD_WAVES_PER_SIMD) grad_kernel(co
 {
     constexpr int L = 64;
     __shared__ SpeciesConst s_sp[kMaxSpecies];
-    __shared__ double s_force[3 * ForceLds<L>::kStride];
+    __shared__ double s_force[ForceLds<L>::kTrackDoubles];
     constexpr int kWords = sizeof(SpeciesConst) * kMaxSpecies / sizeof(double);
     for (int i = threadIdx.x; i < kWords; i += blockDim.x)
         reinterpret_cast<double*>(s_sp)[i] = reinterpret_cast<const double*>(A.sp)[i];

@@ -11,6 +11,32 @@ namespace reedmd {
 constexpr int kSlots = 216;       // 27 cells x 8 diamond basis atoms
 constexpr int kHdr = 32;          // record header words
 constexpr int kRecWords = kHdr + 9 * kSlots;
+
+// Target structures.  Slots are indexed by the ring cell r of a unit cell
+// (r = (c_x mod 3)*9 + (c_y mod 3)*3 + (c_z mod 3)) and its basis atom b.
+// Diamond: slot r*8 + b, one target species.  Fluorite (UO2, 27 cells of the
+// 12-atom cell): the cations (species 0, b = 0..3) in slots r*4 + b, slots
+// 108..127 empty, the anions (species 1, b = 4..11) in slots 128 + r*8 + b - 4,
+// so that every lane row of 16, 32 or 64 slots holds one target species.
+enum : int { kDiamond = 0, kFluorite = 1 };
+template <int LAT>
+struct Lattice;
+template <>
+struct Lattice<kDiamond> {
+    static constexpr int kSlots = 216, kCellAtoms = 8, kAnion0 = 1 << 20;
+    static constexpr int kRecWords = kHdr + 9 * kSlots;
+    __device__ static int slot(int r, int b) { return r * 8 + b; }
+    __device__ static int cell_of_slot(int s) { return s >> 3; }
+    __device__ static int basis_of_slot(int s) { return s & 7; }
+};
+template <>
+struct Lattice<kFluorite> {
+    static constexpr int kSlots = 344, kCellAtoms = 12, kAnion0 = 128;
+    static constexpr int kRecWords = kHdr + 9 * kSlots;
+    __device__ static int slot(int r, int b) { return b < 4 ? r * 4 + b : kAnion0 + r * 8 + (b - 4); }
+    __device__ static int cell_of_slot(int s) { return s < 108 ? (s >> 2) : (s < kAnion0 ? -1 : (s - kAnion0) >> 3); }
+    __device__ static int basis_of_slot(int s) { return s < kAnion0 ? (s & 3) : 4 + ((s - kAnion0) & 7); }
+};
 constexpr int kMaxSpecies = 8;
 constexpr int kSentinel = -(1 << 29);  // "no domain yet": every slot is regenerated
 
@@ -33,6 +59,17 @@ struct SpeciesConst {
     double rate[4], amp[4], damp[4];
     // The same in FP32 for the FP32 pair term, the rates (and 1/lambda) times
     // log2(e) for the hardware 2^x
+    float rate2f[4], amp_f[4], damp_f[4];
+    float lam2f, pad_f;
+};
+
+// Pair-term constants of an ion species against the second target species
+// (fluorite anions), folded like those above; wnorm includes the ratio of the
+// Lindhard-Scharff constants of the two target species (stopping-weighted
+// density, Bragg additivity).
+struct PairConst {
+    double rate[4], amp[4], damp[4];
+    double inv_lambda, wnorm;
     float rate2f[4], amp_f[4], damp_f[4];
     float lam2f, pad_f;
 };
@@ -114,9 +151,18 @@ __device__ __forceinline__ void thermal_gauss(uint64_t key, uint64_t seed, int c
     gz = rad1 * c1;
 }
 
-// Fractional diamond-cubic basis: fcc sites, then the same plus (1/4,1/4,1/4).
-__device__ __forceinline__ void basis_site(int b, double& fx, double& fy, double& fz)
+// Fractional basis sites.  Diamond: fcc sites, then the same plus
+// (1/4,1/4,1/4).  Fluorite: the fcc sites (cations), then the eight sites with
+// every coordinate 1/4 or 3/4 (anions; bit 2 of b - 4 selects x, bit 1 y, bit 0 z).
+__device__ __forceinline__ void basis_site(int b, bool fluorite, double& fx, double& fy, double& fz)
 {
+    if (fluorite && b >= 4) {
+        const int j = b - 4;
+        fx = ((j >> 2) & 1) ? 0.75 : 0.25;
+        fy = ((j >> 1) & 1) ? 0.75 : 0.25;
+        fz = (j & 1) ? 0.75 : 0.25;
+        return;
+    }
     const int q = b & 3;
     const double sh = (b >= 4) ? 0.25 : 0.0;
     fx = ((q == 2 || q == 3) ? 0.5 : 0.0) + sh;
@@ -131,14 +177,15 @@ __device__ __forceinline__ void basis_site(int b, double& fx, double& fy, double
 // of the step loop and the stack arrays of the 16-lane layout.
 #ifndef REEDMD_INLINE_CREATE
 __device__ __attribute__((noinline)) double3 create_atom(uint64_t key, uint64_t seed, int nx, int ny, int nz, int b,
-                                                          double a, double sigma)
+                                                          double a, double sigma, double sigma_b, int fluorite)
 #else
 __device__ __forceinline__ double3 create_atom(uint64_t key, uint64_t seed, int nx, int ny, int nz, int b,
-                                                double a, double sigma)
+                                                double a, double sigma, double sigma_b, int fluorite)
 #endif
 {
     double fx, fy, fz, gx, gy, gz;
-    basis_site(b, fx, fy, fz);
+    basis_site(b, fluorite != 0, fx, fy, fz);
+    if (fluorite && b >= 4) sigma = sigma_b;
     thermal_gauss(key, seed, nx, ny, nz, b, gx, gy, gz);
     return make_double3(a * (static_cast<double>(nx) + fx) + sigma * gx,
                         a * (static_cast<double>(ny) + fy) + sigma * gy,
@@ -201,8 +248,8 @@ constexpr double kZd0 = 3.19980, kZd1 = 0.94229, kZd2 = 0.40290, kZd3 = 0.20162;
 //   ew:   exp(-r/lambda), the density weight without its normalisation.
 // An empty slot sits at the parking distance, where every exponential is 0 and
 // so are coef and ew.
-__device__ __forceinline__ void zbl_pair(const SpeciesConst& c, double dx, double dy, double dz, double& coef,
-                                         double& ew)
+template <class PC>
+__device__ __forceinline__ void zbl_pair(const PC& c, double dx, double dy, double dz, double& coef, double& ew)
 {
     const double r2 = dx * dx + dy * dy + dz * dz;
     const double inv_r = rsqrt_pos(r2);
@@ -224,8 +271,8 @@ __device__ __forceinline__ void zbl_pair(const SpeciesConst& c, double dx, doubl
 // |argument| x 6e-8, below 2e-6 for every term that is not negligible) and the
 // coefficient are FP32.  The caller keeps FP64 for the force components, the
 // sums, kicks, drifts and the step size.
-__device__ __forceinline__ void zbl_pair_f32(const SpeciesConst& c, double dx, double dy, double dz,
-                                             double& coef, double& ew)
+template <class PC>
+__device__ __forceinline__ void zbl_pair_f32(const PC& c, double dx, double dy, double dz, double& coef, double& ew)
 {
     const float x = static_cast<float>(dx), y = static_cast<float>(dy), z = static_cast<float>(dz);
     const float r2 = fmaf(x, x, fmaf(y, y, z * z));

@@ -79,32 +79,52 @@ reedmd_status hip_fail(reedmd_ctx* ctx, hipError_t e, const char* what)
     } while (0)
 
 // Per-species constants for the kernels (ZBL screening length and Coulomb
-// prefactor, density kernel, Lindhard-Scharff friction coefficient).
+// prefactor, density kernel, Lindhard-Scharff friction coefficient).  With two
+// target species (fluorite) the second gets its own pair constants, its density
+// weight carries k_L(species 1) / k_L(species 0) (Bragg additivity), and the
+// friction uses the stopping-weighted uniform density N_0 + N_1 k_L1 / k_L0.
 void prepare_species(const reedmd_ctx* ctx, const reedmd_species* sp, KernelArgs& A)
 {
-    const double Z2 = ctx->lat.Z2;
+    const bool fl = ctx->lat.structure == REEDMD_FLUORITE;
+    const double a3 = ctx->lat.a * ctx->lat.a * ctx->lat.a;
+    const double N0 = (fl ? 4.0 : 8.0) / a3, N1 = fl ? 8.0 / a3 : 0.0;
     double min_rate = HUGE_VAL;
-    const double N = 8.0 / (ctx->lat.a * ctx->lat.a * ctx->lat.a);
-    for (int i = 0; i < kMaxSpecies; ++i) {
-        SpeciesConst& c = A.sp[i];
-        if (i >= sp->n_species) {
-            c = SpeciesConst{1.0, 0.5, 1.0, 0.0, 1.0, 0.0, 0.0, 0.0, 0.0, 0.0, 1.0};
-            continue;
-        }
-        const double Z1 = sp->Z1[i], M1 = sp->M1[i];
+    const double zc[4] = {kZc0, kZc1, kZc2, kZc3}, zd[4] = {kZd0, kZd1, kZd2, kZd3};
+    struct Target {
+        double inv_a, zz, inv_lambda, wnorm, kL;
+    };
+    auto target = [&](double Z1, double M1, double Z2) {
+        Target t;
         const double aU = 0.8854 * kBohr / (std::pow(Z1, 0.23) + std::pow(Z2, 0.23));
         const double lambda = aU / 0.3;
         const double z23 = std::pow(Z1, 2.0 / 3.0) + std::pow(Z2, 2.0 / 3.0);
-        const double kL = 1.212 * std::pow(Z1, 7.0 / 6.0) * Z2 / (std::pow(z23, 1.5) * std::sqrt(M1));
-        const double gamma0 = N * kL * std::sqrt(M1 / 2.0);
+        t.kL = 1.212 * std::pow(Z1, 7.0 / 6.0) * Z2 / (std::pow(z23, 1.5) * std::sqrt(M1));
+        t.inv_a = 1.0 / (ctx->pot.s * aU);
+        t.zz = (ctx->pot.mode == REEDMD_POT_ZBL) ? Z1 * Z2 * kCoulomb : 0.0;
+        t.inv_lambda = 1.0 / lambda;
+        t.wnorm = 1.0 / (8.0 * M_PI * lambda * lambda * lambda);
+        return t;
+    };
+    for (int i = 0; i < kMaxSpecies; ++i) {
+        SpeciesConst& c = A.sp[i];
+        PairConst& c2 = A.pc2[i];
+        if (i >= sp->n_species) {
+            c = SpeciesConst{1.0, 0.5, 1.0, 0.0, 1.0, 0.0, 0.0, 0.0, 0.0, 0.0, 1.0};
+            c2 = PairConst{};
+            c2.inv_lambda = 1.0;
+            continue;
+        }
+        const double Z1 = sp->Z1[i], M1 = sp->M1[i];
+        const Target t0 = target(Z1, M1, ctx->lat.Z2);
+        const double N = fl ? N0 + N1 * target(Z1, M1, ctx->lat.Z2b).kL / t0.kL : N0;
+        const double gamma0 = N * t0.kL * std::sqrt(M1 / 2.0);
         c.M1 = M1;
         c.half_inv_M1 = 1.0 / (2.0 * M1);
         c.inv_M1sq = 1.0 / (M1 * M1);
-        c.inv_a = 1.0 / (ctx->pot.s * aU);
-        c.zz = (ctx->pot.mode == REEDMD_POT_ZBL) ? Z1 * Z2 * kCoulomb : 0.0;
-        c.inv_lambda = 1.0 / lambda;
-        c.wnorm = 1.0 / (8.0 * M_PI * lambda * lambda * lambda);
-        const double zc[4] = {kZc0, kZc1, kZc2, kZc3}, zd[4] = {kZd0, kZd1, kZd2, kZd3};
+        c.inv_a = t0.inv_a;
+        c.zz = t0.zz;
+        c.inv_lambda = t0.inv_lambda;
+        c.wnorm = t0.wnorm;
         for (int j = 0; j < 4; ++j) {
             c.rate[j] = zd[j] * c.inv_a;
             c.amp[j] = c.zz * zc[j];
@@ -115,6 +135,23 @@ void prepare_species(const reedmd_ctx* ctx, const reedmd_species* sp, KernelArgs
         }
         c.lam2f = static_cast<float>(c.inv_lambda * M_LOG2E);
         min_rate = std::min(min_rate, std::min(c.rate[3], c.inv_lambda));
+        c2 = PairConst{};
+        c2.inv_lambda = 1.0;
+        if (fl) {
+            const Target t1 = target(Z1, M1, ctx->lat.Z2b);
+            c2.inv_lambda = t1.inv_lambda;
+            c2.wnorm = t1.wnorm * (t1.kL / t0.kL);
+            for (int j = 0; j < 4; ++j) {
+                c2.rate[j] = zd[j] * t1.inv_a;
+                c2.amp[j] = t1.zz * zc[j];
+                c2.damp[j] = t1.zz * zc[j] * zd[j] * t1.inv_a;
+                c2.rate2f[j] = static_cast<float>(c2.rate[j] * M_LOG2E);
+                c2.amp_f[j] = static_cast<float>(c2.amp[j]);
+                c2.damp_f[j] = static_cast<float>(c2.damp[j]);
+            }
+            c2.lam2f = static_cast<float>(c2.inv_lambda * M_LOG2E);
+            min_rate = std::min(min_rate, std::min(c2.rate[3], c2.inv_lambda));
+        }
         c.g_const = 0.0;
         c.g_rho = 0.0;
         c.dg_const = 0.0;
@@ -133,6 +170,12 @@ void prepare_species(const reedmd_ctx* ctx, const reedmd_species* sp, KernelArgs
     A.park = std::max(1.0e4, 1.0e3 / min_rate);
 }
 
+int lattice_of(const reedmd_ctx* ctx) { return ctx->lat.structure == REEDMD_FLUORITE ? kFluorite : kDiamond; }
+size_t record_words(const reedmd_ctx* ctx)
+{
+    return lattice_of(ctx) == kFluorite ? Lattice<kFluorite>::kRecWords : Lattice<kDiamond>::kRecWords;
+}
+
 reedmd_status check_species(reedmd_ctx* ctx, const reedmd_species* sp)
 {
     if (!sp) return fail(ctx, REEDMD_EINVAL, "species table is NULL");
@@ -146,6 +189,13 @@ reedmd_status check_species(reedmd_ctx* ctx, const reedmd_species* sp)
 reedmd_status check_params(reedmd_ctx* ctx, const reedmd_run_params* p, bool need_hist)
 {
     if (!p) return fail(ctx, REEDMD_EINVAL, "params is NULL");
+    if (p->range_mode != REEDMD_RANGE_DEPTH && p->range_mode != REEDMD_RANGE_RADIAL)
+        return fail(ctx, REEDMD_EINVAL, "range_mode must be REEDMD_RANGE_DEPTH or REEDMD_RANGE_RADIAL");
+    if (p->vacancy != 0 && p->vacancy != 1) return fail(ctx, REEDMD_EINVAL, "vacancy must be 0 or 1");
+    if (lattice_of(ctx) != kFluorite && (p->range_mode != REEDMD_RANGE_DEPTH || p->vacancy != 0))
+        return fail(ctx, REEDMD_EUNSUPPORTED, "the radial range and the recoil vacancy are built for the fluorite target");
+    if (lattice_of(ctx) == kFluorite && p->lanes_per_track == 16)
+        return fail(ctx, REEDMD_EUNSUPPORTED, "the fluorite domain (344 slots) runs on 32 or 64 lanes per track");
     if (!(p->dx_max > 0.0) || !(p->dt_max > 0.0) || !(p->E_stop > 0.0) || !std::isfinite(p->z_start))
         return fail(ctx, REEDMD_EINVAL, "dx_max, dt_max and E_stop must be positive, z_start finite");
     if (p->n_thresh < 0 || p->n_thresh > 64) return fail(ctx, REEDMD_EINVAL, "n_thresh must be in 0..64");
@@ -188,6 +238,14 @@ void fill_common(const reedmd_ctx* ctx, const reedmd_species* sp, const reedmd_r
     A.sigma = ctx->lat.sigma;
     A.inv_M2sq = 1.0 / (ctx->lat.M2 * ctx->lat.M2);
     A.half_inv_M2 = 1.0 / (2.0 * ctx->lat.M2);
+    const bool fl = lattice_of(ctx) == kFluorite;
+    A.M2b = fl ? ctx->lat.M2b : ctx->lat.M2;
+    A.sigma_b = fl ? ctx->lat.sigma_b : ctx->lat.sigma;
+    A.inv_M2bsq = 1.0 / (A.M2b * A.M2b);
+    A.half_inv_M2b = 1.0 / (2.0 * A.M2b);
+    A.structure = lattice_of(ctx);
+    A.range_mode = p->range_mode;
+    A.vacancy = p->vacancy;
     A.dx_max = p->dx_max;
     A.dt_max = p->dt_max;
     A.E_stop = p->E_stop;
@@ -214,61 +272,119 @@ void fill_batch(const reedmd_batch* b, KernelArgs& A)
     A.table = b->table;
 }
 
-// Kernel variants: lanes per track (64, 32, 16) x form x pair-term precision.
-template <int L, int MODE, bool F32>
+// Kernel variants: lanes per track (64, 32, 16; fluorite 64, 32) x form x
+// pair-term precision x target structure.
+template <int L, int MODE, bool F32, int LAT>
 hipError_t launch_track(const KernelArgs& A, long long blocks, hipStream_t s)
 {
-    hipLaunchKernelGGL((track_kernel<L, MODE, F32>), dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s, A);
+    hipLaunchKernelGGL((track_kernel<L, MODE, F32, LAT>), dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s, A);
     return hipGetLastError();
 }
 
-template <int MODE, bool F32>
+template <int MODE, bool F32, int LAT>
 hipError_t launch_track_l(int L, const KernelArgs& A, long long blocks, hipStream_t s)
 {
-    if (L == 64) return launch_track<64, MODE, F32>(A, blocks, s);
-    if (L == 32) return launch_track<32, MODE, F32>(A, blocks, s);
-    return launch_track<16, MODE, F32>(A, blocks, s);
+    if (L == 64) return launch_track<64, MODE, F32, LAT>(A, blocks, s);
+    if constexpr (LAT == kFluorite) {
+        return launch_track<32, MODE, F32, LAT>(A, blocks, s);
+    } else {
+        if (L == 32) return launch_track<32, MODE, F32, LAT>(A, blocks, s);
+        return launch_track<16, MODE, F32, LAT>(A, blocks, s);
+    }
 }
 
-hipError_t launch_track_any(int L, int mode, bool f32, const KernelArgs& A, long long blocks, hipStream_t s)
+template <int LAT>
+hipError_t launch_track_lat(int L, int mode, bool f32, const KernelArgs& A, long long blocks, hipStream_t s)
 {
     if (mode == kModePlain)
-        return f32 ? launch_track_l<kModePlain, true>(L, A, blocks, s) : launch_track_l<kModePlain, false>(L, A, blocks, s);
-    return f32 ? launch_track_l<kModePersistent, true>(L, A, blocks, s)
-               : launch_track_l<kModePersistent, false>(L, A, blocks, s);
+        return f32 ? launch_track_l<kModePlain, true, LAT>(L, A, blocks, s)
+                   : launch_track_l<kModePlain, false, LAT>(L, A, blocks, s);
+    return f32 ? launch_track_l<kModePersistent, true, LAT>(L, A, blocks, s)
+               : launch_track_l<kModePersistent, false, LAT>(L, A, blocks, s);
 }
 
-template <int MODE, bool F32>
+hipError_t launch_track_any(int L, int mode, bool f32, int lat, const KernelArgs& A, long long blocks, hipStream_t s)
+{
+    return lat == kFluorite ? launch_track_lat<kFluorite>(L, mode, f32, A, blocks, s)
+                            : launch_track_lat<kDiamond>(L, mode, f32, A, blocks, s);
+}
+
+template <int MODE, bool F32, int LAT>
 int occupancy_l(int L)
 {
     int nb = 0;
     hipError_t e = hipSuccess;
-    if (L == 64) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, track_kernel<64, MODE, F32>, kBlock, 0);
-    else if (L == 32) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, track_kernel<32, MODE, F32>, kBlock, 0);
-    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, track_kernel<16, MODE, F32>, kBlock, 0);
+    if (L == 64) {
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, track_kernel<64, MODE, F32, LAT>, kBlock, 0);
+    } else if constexpr (LAT == kFluorite) {
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, track_kernel<32, MODE, F32, LAT>, kBlock, 0);
+    } else {
+        if (L == 32) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, track_kernel<32, MODE, F32, LAT>, kBlock, 0);
+        else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, track_kernel<16, MODE, F32, LAT>, kBlock, 0);
+    }
     return (e != hipSuccess || nb < 1) ? 1 : nb;
 }
 
-int resident_blocks_per_cu(int L, int mode, bool f32)
+template <int LAT>
+int resident_blocks_lat(int L, int mode, bool f32)
 {
-    if (mode == kModePlain) return f32 ? occupancy_l<kModePlain, true>(L) : occupancy_l<kModePlain, false>(L);
-    return f32 ? occupancy_l<kModePersistent, true>(L) : occupancy_l<kModePersistent, false>(L);
+    if (mode == kModePlain) return f32 ? occupancy_l<kModePlain, true, LAT>(L) : occupancy_l<kModePlain, false, LAT>(L);
+    return f32 ? occupancy_l<kModePersistent, true, LAT>(L) : occupancy_l<kModePersistent, false, LAT>(L);
 }
 
-template <bool F32>
+int resident_blocks_per_cu(int L, int mode, bool f32, int lat)
+{
+    return lat == kFluorite ? resident_blocks_lat<kFluorite>(L, mode, f32) : resident_blocks_lat<kDiamond>(L, mode, f32);
+}
+
+template <bool F32, int LAT>
 void launch_init_l(int L, const KernelArgs& A, long long blocks, hipStream_t s)
 {
-    if (L == 64) hipLaunchKernelGGL((init_kernel<64, F32>), dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s, A);
-    else if (L == 32) hipLaunchKernelGGL((init_kernel<32, F32>), dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s, A);
-    else hipLaunchKernelGGL((init_kernel<16, F32>), dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s, A);
+    const dim3 g(static_cast<unsigned>(blocks)), b(kBlock);
+    if (L == 64) {
+        hipLaunchKernelGGL((init_kernel<64, F32, LAT>), g, b, 0, s, A);
+    } else if constexpr (LAT == kFluorite) {
+        hipLaunchKernelGGL((init_kernel<32, F32, LAT>), g, b, 0, s, A);
+    } else {
+        if (L == 32) hipLaunchKernelGGL((init_kernel<32, F32, LAT>), g, b, 0, s, A);
+        else hipLaunchKernelGGL((init_kernel<16, F32, LAT>), g, b, 0, s, A);
+    }
 }
 
-template <bool F32>
+template <bool F32, int LAT>
 void launch_step_l(int L, const KernelArgs& A, long long blocks, hipStream_t s)
 {
-    if (L == 64) hipLaunchKernelGGL((step_kernel<64, F32>), dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s, A);
-    else if (L == 32) hipLaunchKernelGGL((step_kernel<32, F32>), dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s, A);
-    else hipLaunchKernelGGL((step_kernel<16, F32>), dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s, A);
+    const dim3 g(static_cast<unsigned>(blocks)), b(kBlock);
+    if (L == 64) {
+        hipLaunchKernelGGL((step_kernel<64, F32, LAT>), g, b, 0, s, A);
+    } else if constexpr (LAT == kFluorite) {
+        hipLaunchKernelGGL((step_kernel<32, F32, LAT>), g, b, 0, s, A);
+    } else {
+        if (L == 32) hipLaunchKernelGGL((step_kernel<32, F32, LAT>), g, b, 0, s, A);
+        else hipLaunchKernelGGL((step_kernel<16, F32, LAT>), g, b, 0, s, A);
+    }
+}
+
+void launch_init_any(int L, bool f32, int lat, const KernelArgs& A, long long blocks, hipStream_t s)
+{
+    if (lat == kFluorite) {
+        if (f32) launch_init_l<true, kFluorite>(L, A, blocks, s);
+        else launch_init_l<false, kFluorite>(L, A, blocks, s);
+    } else {
+        if (f32) launch_init_l<true, kDiamond>(L, A, blocks, s);
+        else launch_init_l<false, kDiamond>(L, A, blocks, s);
+    }
+}
+
+void launch_step_any(int L, bool f32, int lat, const KernelArgs& A, long long blocks, hipStream_t s)
+{
+    if (lat == kFluorite) {
+        if (f32) launch_step_l<true, kFluorite>(L, A, blocks, s);
+        else launch_step_l<false, kFluorite>(L, A, blocks, s);
+    } else {
+        if (f32) launch_step_l<true, kDiamond>(L, A, blocks, s);
+        else launch_step_l<false, kDiamond>(L, A, blocks, s);
+    }
 }
 
 // Queue state reset (a kernel, not a memset, so the pipeline can be captured).
@@ -295,7 +411,7 @@ __global__ void stats_finalize_kernel(const QueueState* q, reedmd_stats* st)
 
 reedmd_status ensure_scratch(reedmd_ctx* ctx, int qcap, size_t stack_records)
 {
-    const size_t qbytes = 256 + static_cast<size_t>(qcap) * 8 + static_cast<size_t>(qcap) * kRecWords * 8;
+    const size_t qbytes = 256 + static_cast<size_t>(qcap) * 8 + static_cast<size_t>(qcap) * record_words(ctx) * 8;
     const size_t need_q = ((qbytes + 4095) / 4096) * 4096;
     if (need_q > ctx->scratch_bytes) {
         HIP_TRY(ctx, hipDeviceSynchronize());
@@ -313,7 +429,7 @@ reedmd_status ensure_scratch(reedmd_ctx* ctx, int qcap, size_t stack_records)
         }
         ctx->scratch_bytes = need_q;
     }
-    const size_t need_s = std::max<size_t>(stack_records, 1) * kRecWords * 8;
+    const size_t need_s = std::max<size_t>(stack_records, 1) * record_words(ctx) * 8;
     if (need_s > ctx->stack_bytes) {
         HIP_TRY(ctx, hipDeviceSynchronize());
         if (ctx->stack) (void)hipFree(ctx->stack);
@@ -375,6 +491,7 @@ Shape choose_shape(reedmd_ctx* ctx, const reedmd_run_params* p, const reedmd_bat
         }
     }
     if (L == 0) L = 64;
+    if (lattice_of(ctx) == kFluorite && L == 16) L = 32;
     s.L = L;
     const int T = 64 / L;
     const int per_wave_block = kBlock / 64;
@@ -386,7 +503,7 @@ Shape choose_shape(reedmd_ctx* ctx, const reedmd_run_params* p, const reedmd_bat
         s.blocks = (waves_needed + per_wave_block - 1) / per_wave_block;
         s.qcap = 0;
     } else {
-        int bpc = resident_blocks_per_cu(L, s.mode, s.f32);
+        int bpc = resident_blocks_per_cu(L, s.mode, s.f32, lattice_of(ctx));
         if (waves > 0) bpc = std::max(1, std::min(bpc, (waves + per_wave_block - 1) / per_wave_block));
         s.blocks = static_cast<long long>(bpc) * ctx->cu_count;
         s.seg_total = s.blocks * per_wave_block * T;
@@ -430,7 +547,7 @@ reedmd_status run_impl(reedmd_ctx* ctx, const reedmd_species* sp, const reedmd_b
         hipLaunchKernelGGL(queue_reset_kernel, dim3(rb), dim3(256), 0, sm, A.q, A.qseq, qcap, b->n);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        e = launch_track_any(s.L, s.mode, s.f32, A, s.blocks, sm);
+        e = launch_track_any(s.L, s.mode, s.f32, lattice_of(ctx), A, s.blocks, sm);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(stats_finalize_kernel, dim3(1), dim3(64), 0, sm, A.q, d_stats);
         return hipGetLastError();
@@ -534,8 +651,9 @@ __global__ void sample_kernel(const SamplerArgs S)
         u[4 + i] = open_unit(r1.w[i]);
     }
     const reedmd_sampler& s = S.s;
-    S.pos[q] = s.a * u[0];
-    S.pos[S.n + q] = s.a * u[1];
+    const bool site = s.start_mode == REEDMD_START_SITE;
+    S.pos[q] = site ? 0.0 : s.a * u[0];
+    S.pos[S.n + q] = site ? 0.0 : s.a * u[1];
     S.pos[2 * S.n + q] = s.z_start;
     int ci = static_cast<int>(floor(static_cast<double>(s.n_choice) * u[2]));
     if (ci > s.n_choice - 1) ci = s.n_choice - 1;
@@ -553,7 +671,14 @@ __global__ void sample_kernel(const SamplerArgs S)
     const double phi = kTwoPi * u[4];
     double sp, cp;
     sincos(phi, &sp, &cp);
-    if (!cone) {
+    if (s.dir_mode == REEDMD_DIR_ISOTROPIC) {
+        // uniform on the sphere: cos(theta) uniform in [-1, 1]
+        const double ct = 1.0 - 2.0 * u[5];
+        const double st = sqrt(fmax(0.0, 1.0 - ct * ct));
+        S.dir[q] = st * cp;
+        S.dir[S.n + q] = st * sp;
+        S.dir[2 * S.n + q] = ct;
+    } else if (!cone) {
         double st, ct;
         sincos(s.tilt, &st, &ct);
         S.dir[q] = st * cp;
@@ -598,7 +723,11 @@ reedmd_status reedmd_create(const reedmd_lattice* lattice, const reedmd_potentia
     if (!lattice || !potential || !stopping) return fail(nullptr, REEDMD_EINVAL, "NULL model description");
     if (!(lattice->a > 0.0) || !(lattice->M2 > 0.0) || !(lattice->sigma >= 0.0) || lattice->Z2 <= 0)
         return fail(nullptr, REEDMD_EINVAL, "lattice a, M2, Z2 must be positive and sigma >= 0");
-    if (lattice->structure != REEDMD_DIAMOND) return fail(nullptr, REEDMD_EUNSUPPORTED, "only the diamond structure");
+    if (lattice->structure != REEDMD_DIAMOND && lattice->structure != REEDMD_FLUORITE)
+        return fail(nullptr, REEDMD_EUNSUPPORTED, "structure must be REEDMD_DIAMOND or REEDMD_FLUORITE");
+    if (lattice->structure == REEDMD_FLUORITE &&
+        (!(lattice->M2b > 0.0) || !(lattice->sigma_b >= 0.0) || lattice->Z2b <= 0))
+        return fail(nullptr, REEDMD_EINVAL, "fluorite needs M2b, Z2b > 0 and sigma_b >= 0");
     if (potential->mode != REEDMD_POT_ZBL && potential->mode != REEDMD_POT_NONE)
         return fail(nullptr, REEDMD_EINVAL, "unknown potential mode");
     if (!(potential->s >= kMinScreening && potential->s <= kMaxScreening))
@@ -653,9 +782,11 @@ reedmd_status reedmd_sample_primaries(reedmd_ctx* ctx, const reedmd_sampler* sam
     if (sampler->n_energy_tables < 1) return fail(ctx, REEDMD_EINVAL, "n_energy_tables must be >= 1");
     if (!(sampler->E_min > 0.0) || !(sampler->E_max >= sampler->E_min))
         return fail(ctx, REEDMD_EINVAL, "need 0 < E_min <= E_max");
-    if (sampler->dir_mode < REEDMD_DIR_TILT || sampler->dir_mode > REEDMD_DIR_MIXED)
+    if (sampler->dir_mode < REEDMD_DIR_TILT || sampler->dir_mode > REEDMD_DIR_ISOTROPIC)
         return fail(ctx, REEDMD_EINVAL, "unknown direction mode");
-    if (sampler->dir_mode != REEDMD_DIR_TILT) {
+    if (sampler->start_mode != REEDMD_START_SURFACE && sampler->start_mode != REEDMD_START_SITE)
+        return fail(ctx, REEDMD_EINVAL, "unknown start mode");
+    if (sampler->dir_mode == REEDMD_DIR_CONE || sampler->dir_mode == REEDMD_DIR_MIXED) {
         const double n2 = sampler->axis[0] * sampler->axis[0] + sampler->axis[1] * sampler->axis[1] +
                           sampler->axis[2] * sampler->axis[2];
         if (std::fabs(n2 - 1.0) > 1e-12) return fail(ctx, REEDMD_EINVAL, "cone axis must be a unit vector");
@@ -709,8 +840,7 @@ reedmd_status reedmd_track_init(reedmd_ctx* ctx, const reedmd_species* species, 
     const int L = params->lanes_per_track ? params->lanes_per_track : 64;
     const long long waves = (batch->n + (64 / L) - 1) / (64 / L);
     const long long blocks = (waves + 3) / 4;
-    if (params->force_precision == REEDMD_FORCE_FP32) launch_init_l<true>(L, A, blocks, stream);
-    else launch_init_l<false>(L, A, blocks, stream);
+    launch_init_any(L, params->force_precision == REEDMD_FORCE_FP32, lattice_of(ctx), A, blocks, stream);
     HIP_TRY(ctx, hipGetLastError());
     return REEDMD_OK;
 }
@@ -733,8 +863,7 @@ reedmd_status reedmd_debug_step(reedmd_ctx* ctx, const reedmd_species* species, 
     const int L = params->lanes_per_track ? params->lanes_per_track : 64;
     const long long waves = (n + (64 / L) - 1) / (64 / L);
     const long long blocks = (waves + 3) / 4;
-    if (params->force_precision == REEDMD_FORCE_FP32) launch_step_l<true>(L, A, blocks, stream);
-    else launch_step_l<false>(L, A, blocks, stream);
+    launch_step_any(L, params->force_precision == REEDMD_FORCE_FP32, lattice_of(ctx), A, blocks, stream);
     HIP_TRY(ctx, hipGetLastError());
     return REEDMD_OK;
 }
@@ -752,6 +881,8 @@ reedmd_status reedmd_grad(reedmd_ctx* ctx, const reedmd_species* species, const 
     if (params->n_thresh != 0) return fail(ctx, REEDMD_EUNSUPPORTED, "the gradient is defined without cloning (n_thresh = 0)");
     if (params->force_precision != REEDMD_FORCE_FP64)
         return fail(ctx, REEDMD_EUNSUPPORTED, "the adjoint is FP64 only (force_precision = REEDMD_FORCE_FP64)");
+    if (lattice_of(ctx) != kDiamond || params->range_mode != REEDMD_RANGE_DEPTH || params->vacancy != 0)
+        return fail(ctx, REEDMD_EUNSUPPORTED, "the adjoint covers the diamond target, depth range, no vacancy");
     if (!(k >= 0.0) || !(s >= kMinScreening && s <= kMaxScreening))
         return fail(ctx, REEDMD_EINVAL, "need k >= 0 and s in [0.01, 100]");
     for (int i = 0; i < 4; ++i) h_result[i] = 0.0;
@@ -855,8 +986,9 @@ reedmd_status reedmd_autotune(reedmd_ctx* ctx, const reedmd_species* species, co
     const bool persistent = params->form == REEDMD_FORM_PERSISTENT;
     for (int li = 0; li < 3 && st == REEDMD_OK; ++li) {
         // persistent form: the occupancy-sized grid and one workgroup per CU fewer
+        if (lattice_of(ctx) == kFluorite && lanes[li] == 16) continue;
         const int occ = resident_blocks_per_cu(lanes[li], persistent ? kModePersistent : kModePlain,
-                                               params->force_precision == REEDMD_FORCE_FP32);
+                                               params->force_precision == REEDMD_FORCE_FP32, lattice_of(ctx));
         const int nw = (persistent && occ > 1) ? 2 : 1;
         for (int wi = 0; wi < nw && st == REEDMD_OK; ++wi) {
             p.lanes_per_track = lanes[li];
@@ -1018,7 +1150,7 @@ reedmd_status reedmd_launch_shape(reedmd_ctx* ctx, const reedmd_batch* batch, co
     out[0] = s.L;
     out[1] = s.blocks;
     out[2] = s.seg_total;
-    out[3] = resident_blocks_per_cu(s.L, s.mode, s.f32);
+    out[3] = resident_blocks_per_cu(s.L, s.mode, s.f32, lattice_of(ctx));
     out[4] = s.mode == kModePersistent ? s.qcap : 0;
     return REEDMD_OK;
 }

@@ -1,8 +1,8 @@
 // REED-MD track kernels for gfx950.
 //
-// Mapping: one wavefront holds T = 64 / L track segments of L lanes.  The 216
-// domain atoms of a track live in the VGPRs of its segment: slot s is held by
-// lane (s mod L) as its register element s / L.  Slots are indexed by cell
+// Mapping: one wavefront holds T = 64 / L track segments of L lanes.  The
+// domain atoms of a track (216 for diamond, 324 for fluorite) live in the VGPRs
+// of its segment: slot s is held by lane (s mod L) as its register element s / L.  Slots are indexed by cell
 // residue (c mod 3 per axis) so that moving the domain never moves data: when
 // the centre cell changes, exactly the slots whose cell left the 3x3x3 block
 // are re-created in place (Sec. 2, Fig. 1).  Per step, one fused pass over a
@@ -23,7 +23,7 @@ enum : int { kModePlain = 0, kModePersistent = 1 };
 #define REEDMD_PAIR_BARRIER 0
 #endif
 #ifndef REEDMD_WAVES_PER_SIMD
-#define REEDMD_WAVES_PER_SIMD(L) ((L) >= 32 ? 2 : 1)
+#define REEDMD_WAVES_PER_SIMD(L, LAT) ((L) >= 32 && (LAT) == kDiamond ? 2 : 1)
 #endif
 
 
@@ -43,9 +43,15 @@ struct QueueState {
 
 struct KernelArgs {
     SpeciesConst sp[kMaxSpecies];
-    // crystal
+    PairConst pc2[kMaxSpecies];   // against the second target species (fluorite anions)
+    // crystal (M2, sigma: target species 0; M2b, sigma_b: species 1)
     double a, inv_a, M2, sigma, inv_M2sq, half_inv_M2;
+    double M2b, sigma_b, inv_M2bsq, half_inv_M2b;
     double park;            // empty slots sit this far above the domain centre
+    int structure;          // kDiamond / kFluorite
+    int range_mode;         // 0: depth z; 1: distance from the start point
+    int vacancy;            // 1: the basis-0 site of the start cell is vacant (recoil)
+    int pad_lat;
     // integration and events
     double dx_max, dt_max, E_stop, z_start;
     long long max_steps;
@@ -110,30 +116,42 @@ __device__ __forceinline__ KernelArgs cold_args()
     return a;
 }
 
-// Per-track force arrays in LDS: [waves per workgroup][tracks per wave][3][SL*L]
-// (the slots padded to whole lane rows, so every lane of a row has an entry).
-template <int L>
+// Per-track LDS area: [waves per workgroup][tracks per wave] of the atom
+// forces [3][SL*L] (the slots padded to whole lane rows, so every lane of a row
+// has an entry) followed by kTrackHdr words: the start point (3), the cell of
+// the vacant site (3) and its basis index (-1: none).
+constexpr int kTrackHdr = 8;
+template <int L, int LAT = kDiamond>
 struct ForceLds {
-    static constexpr int kStride = ((kSlots + L - 1) / L) * L;
+    static constexpr int kStride = ((Lattice<LAT>::kSlots + L - 1) / L) * L;
     static constexpr int kTracksPerBlock = 4 * (64 / L);
-    static constexpr int kDoubles = kTracksPerBlock * 3 * kStride;
+    static constexpr int kTrackDoubles = 3 * kStride + kTrackHdr;
+    static constexpr int kDoubles = kTracksPerBlock * kTrackDoubles;
 };
-template <int L>
+template <int L, int LAT = kDiamond>
 __device__ __forceinline__ double* force_slab(double* s_force)
 {
     const int track_in_block = (threadIdx.x >> 6) * (64 / L) + (threadIdx.x & 63) / L;
-    return s_force + track_in_block * 3 * ForceLds<L>::kStride;
+    return s_force + track_in_block * ForceLds<L, LAT>::kTrackDoubles;
 }
 
-// Species constants are staged in LDS once per workgroup (indexed per lane).
-__device__ __forceinline__ const SpeciesConst* stage_species(const KernelArgs& A, SpeciesConst* s_sp)
+// Species constants are staged in LDS once per workgroup (indexed per lane):
+// the SpeciesConst table, followed by the PairConst table of the second target
+// species.
+constexpr int kSpeciesLdsDoubles = (sizeof(SpeciesConst) + sizeof(PairConst)) * kMaxSpecies / sizeof(double);
+__device__ __forceinline__ const SpeciesConst* stage_species(const KernelArgs& A, double* s_sp)
 {
-    constexpr int kWords = sizeof(SpeciesConst) * kMaxSpecies / sizeof(double);
-    static_assert(kWords <= 256, "species table staged by one workgroup");
-    if (threadIdx.x < kWords)
-        reinterpret_cast<double*>(s_sp)[threadIdx.x] = reinterpret_cast<const double*>(A.sp)[threadIdx.x];
+    constexpr int kW1 = sizeof(SpeciesConst) * kMaxSpecies / sizeof(double);
+    constexpr int kW2 = sizeof(PairConst) * kMaxSpecies / sizeof(double);
+    static_assert(kW1 + kW2 == kSpeciesLdsDoubles, "species tables are whole doubles");
+    for (int i = threadIdx.x; i < kW1 + kW2; i += blockDim.x)
+        s_sp[i] = (i < kW1) ? reinterpret_cast<const double*>(A.sp)[i] : reinterpret_cast<const double*>(A.pc2)[i - kW1];
     __syncthreads();
-    return s_sp;
+    return reinterpret_cast<const SpeciesConst*>(s_sp);
+}
+__device__ __forceinline__ const PairConst* pair_table2(const SpeciesConst* sp)
+{
+    return reinterpret_cast<const PairConst*>(sp + kMaxSpecies);
 }
 
 // ---------------------------------------------------------------------------
@@ -203,12 +221,12 @@ struct SegReduce {
 };
 
 // Register-resident state of one track segment.
-template <int L>
+template <int L, int LAT = kDiamond>
 struct TrackRegs {
-    static constexpr int SL = (kSlots + L - 1) / L;
-    static constexpr int FS = ForceLds<L>::kStride;
+    static constexpr int SL = (Lattice<LAT>::kSlots + L - 1) / L;
+    static constexpr int FS = ForceLds<L, LAT>::kStride;
     double ax[SL], ay[SL], az[SL], avx[SL], avy[SL], avz[SL];
-    double* fl;          // LDS: this track's atom forces, [3][FS] (fx, fy, fz by slot)
+    double* fl;          // LDS: this track's atom forces, [3][FS] (fx, fy, fz by slot), then its header
     unsigned exist;      // bit i: register slot i holds an existing atom
     // ion (segment-uniform)
     double x, y, z, vx, vy, vz, Fx, Fy, Fz, rho, w, zstop;
@@ -221,8 +239,8 @@ struct TrackRegs {
     int n_exist;             // atoms in the domain (segment-uniform)
 };
 
-template <int L>
-__device__ __forceinline__ void refresh_threshold(TrackRegs<L>& t, const KernelArgs& A)
+template <int L, int LAT>
+__device__ __forceinline__ void refresh_threshold(TrackRegs<L, LAT>& t, const KernelArgs& A)
 {
     t.thr_next = (t.next_k < A.n_thresh) ? A.thr[static_cast<size_t>(t.table) * A.n_thresh + t.next_k]
                                          : __builtin_huge_val();
@@ -232,10 +250,10 @@ __device__ __forceinline__ void refresh_threshold(TrackRegs<L>& t, const KernelA
 // are parked at rest above the domain centre at the parking distance, where
 // every pair exponential underflows to exactly 0: their pair terms vanish and
 // the pass over the slots needs no branch.
-template <int L>
-__device__ __forceinline__ void park_slot(TrackRegs<L>& t, int i, int s, double px, double py, double pz)
+template <int L, int LAT>
+__device__ __forceinline__ void park_slot(TrackRegs<L, LAT>& t, int i, int s, double px, double py, double pz)
 {
-    constexpr int FS = TrackRegs<L>::FS;
+    constexpr int FS = TrackRegs<L, LAT>::FS;
     t.ax[i] = px; t.ay[i] = py; t.az[i] = pz;
     t.avx[i] = 0.0; t.avy[i] = 0.0; t.avz[i] = 0.0;
     t.fl[0 * FS + s] = 0.0; t.fl[1 * FS + s] = 0.0; t.fl[2 * FS + s] = 0.0;
@@ -281,23 +299,42 @@ __device__ __forceinline__ unsigned new_cell_mask(int sl, int ncx, int ncy, int 
     return m;
 }
 
-template <int L>
-__device__ __forceinline__ void regenerate(TrackRegs<L>& t, const KernelArgs& A, int sl, int ncx,
+// The track's header words in LDS (after its forces): start point, cell of
+// the vacant site and its basis index (negative: none).  Every lane of the
+// segment writes the same values.
+template <int L, int LAT>
+__device__ __forceinline__ double* track_hdr(const TrackRegs<L, LAT>& t)
+{
+    return t.fl + 3 * TrackRegs<L, LAT>::FS;
+}
+__device__ __forceinline__ bool vacant_site(const double* h, int cx, int cy, int cz, int b)
+{
+    return h[6] >= 0.0 && b == static_cast<int>(h[6]) && cx == static_cast<int>(h[3]) &&
+           cy == static_cast<int>(h[4]) && cz == static_cast<int>(h[5]);
+}
+
+template <int L, int LAT>
+__device__ __forceinline__ void regenerate(TrackRegs<L, LAT>& t, const KernelArgs& A, int sl, int ncx,
                                            int ncy, int ncz, bool all)
 {
-    constexpr int FS = TrackRegs<L>::FS;
+    using Lat = Lattice<LAT>;
+    constexpr int FS = TrackRegs<L, LAT>::FS;
+    constexpr int NB = Lat::kCellAtoms;
     const KernelArgs C = cold_args();
+    const double* h = track_hdr(t);
     const unsigned newc = new_cell_mask<L>(sl, ncx, ncy, ncz, t.cx, t.cy, t.cz, all);
-    // The 8 atoms of every new cell are created spread evenly over the lanes of
-    // the segment (a face shift creates 72 of the 216), and each position is
-    // staged in the force entries of its slot, which the new atom discards.
-    const int n_new = 8 * __popc(newc);
+    // The atoms of every new cell are created spread evenly over the lanes of
+    // the segment (a face shift creates a third of the domain), and each
+    // position is staged in the force entries of its slot, which the new atom
+    // discards.  The vacant site of a recoil is not created.
+    const int n_new = NB * __popc(newc);
     for (int idx = sl; idx < n_new; idx += L) {
-        const int cell = kth_set_bit(newc, idx >> 3), b = idx & 7;
+        const int cell = kth_set_bit(newc, idx / NB), b = idx % NB;
         const int rx = cell / 9, ry = (cell / 3) % 3, rz = cell % 3;
-        const double3 p = create_atom(t.key, C.seed, cell_of_residue(rx, ncx), cell_of_residue(ry, ncy),
-                                      cell_of_residue(rz, ncz), b, C.a, C.sigma);
-        const int s = cell * 8 + b;
+        const int gx = cell_of_residue(rx, ncx), gy = cell_of_residue(ry, ncy), gz = cell_of_residue(rz, ncz);
+        if (LAT == kFluorite && vacant_site(h, gx, gy, gz, b)) continue;
+        const double3 p = create_atom(t.key, C.seed, gx, gy, gz, b, C.a, C.sigma, C.sigma_b, LAT == kFluorite);
+        const int s = Lat::slot(cell, b);
         t.fl[0 * FS + s] = p.x;
         t.fl[1 * FS + s] = p.y;
         t.fl[2 * FS + s] = p.z;
@@ -311,11 +348,14 @@ __device__ __forceinline__ void regenerate(TrackRegs<L>& t, const KernelArgs& A,
     const double parkz = C.a * (static_cast<double>(ncz) + 0.5) - C.park;
     unsigned ex = 0;
 #pragma unroll
-    for (int i = 0; i < TrackRegs<L>::SL; ++i) {
+    for (int i = 0; i < TrackRegs<L, LAT>::SL; ++i) {
         const int s = sl + L * i;
-        const int cell = s >> 3;
-        if (s >= kSlots || cell_of_residue(cell % 3, ncz) < 0) {
-            park_slot<L>(t, i, s, parkx, parky, parkz);
+        const int cell = (s < Lat::kSlots) ? Lat::cell_of_slot(s) : -1;
+        if (cell < 0 || cell_of_residue(cell % 3, ncz) < 0 ||
+            (LAT == kFluorite &&
+             vacant_site(h, cell_of_residue(cell / 9, ncx), cell_of_residue((cell / 3) % 3, ncy),
+                         cell_of_residue(cell % 3, ncz), Lat::basis_of_slot(s)))) {
+            park_slot<L, LAT>(t, i, s, parkx, parky, parkz);
             continue;
         }
         ex |= (1u << i);
@@ -332,15 +372,28 @@ __device__ __forceinline__ void regenerate(TrackRegs<L>& t, const KernelArgs& A,
     t.n_exist = SegReduce<L>::isum(__popc(ex));
 }
 
+// The range coordinate: the depth z, or the distance from the start point
+// (recoils; built into the fluorite kernels only, as is the vacant site).
+template <int L, int LAT>
+__device__ __forceinline__ double range_coord(const TrackRegs<L, LAT>& t, int range_mode)
+{
+    if (LAT != kFluorite || range_mode == 0) return t.z;
+    const double* h = track_hdr(t);
+    const double dx = t.x - h[0], dy = t.y - h[1], dz = t.z - h[2];
+    return sqrt(dx * dx + dy * dy + dz * dz);
+}
+
 // One integration step (velocity Verlet with symmetric friction halves); a
 // step with fresh == true has dt = 0 and builds the whole domain (start of a
 // primary).  Returns the kinetic energy before the step via ke0.
-template <int L, bool F32 = false>
-__device__ __forceinline__ void track_step(TrackRegs<L>& t, const KernelArgs& A, const SpeciesConst* sp, int sl,
+template <int L, bool F32 = false, int LAT = kDiamond>
+__device__ __forceinline__ void track_step(TrackRegs<L, LAT>& t, const KernelArgs& A, const SpeciesConst* sp, int sl,
                                            bool fresh, double& ke0, double& z0)
 {
-    constexpr int FS = TrackRegs<L>::FS;
+    constexpr int FS = TrackRegs<L, LAT>::FS;
+    constexpr bool FL = LAT == kFluorite;
     const SpeciesConst& c = sp[t.species];
+    const PairConst& c1 = pair_table2(sp)[t.species];
     const double M1 = c.M1;
     const double v2 = t.vx * t.vx + t.vy * t.vy + t.vz * t.vz;
     const double f2 = t.Fx * t.Fx + t.Fy * t.Fy + t.Fz * t.Fz;
@@ -351,7 +404,7 @@ __device__ __forceinline__ void track_step(TrackRegs<L>& t, const KernelArgs& A,
     if (amax2 > 0.0) dt = fmin(dt, sqrt(2.0 * A.dx_max * rsqrt_pos(amax2)));
     if (fresh) dt = 0.0;
     ke0 = 0.5 * M1 * v2;
-    z0 = t.z;
+    z0 = range_coord(t, A.range_mode);
 
     const double h1 = dt * c.half_inv_M1;
     const double fr1 = exp_neg((c.g_const + c.g_rho * t.rho) * h1);
@@ -365,15 +418,20 @@ __device__ __forceinline__ void track_step(TrackRegs<L>& t, const KernelArgs& A,
     if (fresh || !inside_cell(t.x, t.cx, A.a, A.inv_a) || !inside_cell(t.y, t.cy, A.a, A.inv_a) ||
         !inside_cell(t.z, t.cz, A.a, A.inv_a)) {
         const int ncx = floor_cell(t.x, A.a), ncy = floor_cell(t.y, A.a), ncz = floor_cell(t.z, A.a);
-        if (fresh || ncx != t.cx || ncy != t.cy || ncz != t.cz) regenerate<L>(t, A, sl, ncx, ncy, ncz, fresh);
+        if (fresh || ncx != t.cx || ncy != t.cy || ncz != t.cz) regenerate<L, LAT>(t, A, sl, ncx, ncy, ncz, fresh);
     }
 
     // fused pass over every register slot (parked slots contribute exact zeros):
     // atom kick and drift, pair term at the new positions, second atom kick
-    const double h2 = dt * A.half_inv_M2;
-    double Fx = 0.0, Fy = 0.0, Fz = 0.0, rho = 0.0, vm = 0.0, fm = 0.0;
+    // (fluorite: register slot i holds anions from slot 128 on, a whole lane row
+    // of one target species, so the choice of constants and mass is static)
+    const double h2a = dt * A.half_inv_M2;
+    const double h2b = FL ? dt * A.half_inv_M2b : h2a;
+    double Fx = 0.0, Fy = 0.0, Fz = 0.0, rho = 0.0, rho1 = 0.0, vm = 0.0, fm = 0.0;
 #pragma unroll
-    for (int i = 0; i < TrackRegs<L>::SL; ++i) {
+    for (int i = 0; i < TrackRegs<L, LAT>::SL; ++i) {
+        const bool anion = FL && L * i >= Lattice<LAT>::kAnion0;
+        const double h2 = anion ? h2b : h2a;
         double* f = t.fl + (sl + L * i);
         double vx = t.avx[i] + f[0 * FS] * h2;
         double vy = t.avy[i] + f[1 * FS] * h2;
@@ -383,17 +441,24 @@ __device__ __forceinline__ void track_step(TrackRegs<L>& t, const KernelArgs& A,
         const double pz = t.az[i] + vz * dt;
         const double dx = t.x - px, dy = t.y - py, dz = t.z - pz;
         double coef, ew;
-        if constexpr (F32) zbl_pair_f32(c, dx, dy, dz, coef, ew);
-        else zbl_pair(c, dx, dy, dz, coef, ew);
+        if (anion) {
+            if constexpr (F32) zbl_pair_f32(c1, dx, dy, dz, coef, ew);
+            else zbl_pair(c1, dx, dy, dz, coef, ew);
+        } else {
+            if constexpr (F32) zbl_pair_f32(c, dx, dy, dz, coef, ew);
+            else zbl_pair(c, dx, dy, dz, coef, ew);
+        }
         const double fx = -coef * dx, fy = -coef * dy, fz = -coef * dz;   // force on the atom
         Fx -= fx; Fy -= fy; Fz -= fz;
-        rho += ew;
+        if (anion) rho1 += ew;
+        else rho += ew;
         vx += fx * h2; vy += fy * h2; vz += fz * h2;
         t.ax[i] = px; t.ay[i] = py; t.az[i] = pz;
         t.avx[i] = vx; t.avy[i] = vy; t.avz[i] = vz;
         f[0 * FS] = fx; f[1 * FS] = fy; f[2 * FS] = fz;
         vm = fmax(vm, vx * vx + vy * vy + vz * vz);
-        fm = fmax(fm, fx * fx + fy * fy + fz * fz);
+        if constexpr (FL) fm = fmax(fm, (fx * fx + fy * fy + fz * fz) * (anion ? A.inv_M2bsq : A.inv_M2sq));
+        else fm = fmax(fm, fx * fx + fy * fy + fz * fz);
 #if REEDMD_PAIR_BARRIER
         __builtin_amdgcn_sched_barrier(0);
 #endif
@@ -401,9 +466,15 @@ __device__ __forceinline__ void track_step(TrackRegs<L>& t, const KernelArgs& A,
     t.Fx = SegReduce<L>::sum(Fx);
     t.Fy = SegReduce<L>::sum(Fy);
     t.Fz = SegReduce<L>::sum(Fz);
-    t.rho = SegReduce<L>::sum(rho) * c.wnorm;
-    t.vmax2a = SegReduce<L>::max(vm);
-    t.amax2a = SegReduce<L>::max(fm) * A.inv_M2sq;
+    if constexpr (FL) {
+        t.rho = SegReduce<L>::sum(rho) * c.wnorm + SegReduce<L>::sum(rho1) * c1.wnorm;
+        t.vmax2a = SegReduce<L>::max(vm);
+        t.amax2a = SegReduce<L>::max(fm);
+    } else {
+        t.rho = SegReduce<L>::sum(rho) * c.wnorm;
+        t.vmax2a = SegReduce<L>::max(vm);
+        t.amax2a = SegReduce<L>::max(fm) * A.inv_M2sq;
+    }
 
     const double fr2 = exp_neg((c.g_const + c.g_rho * t.rho) * h1);
     t.vx = (t.vx + t.Fx * h1) * fr2;
@@ -414,11 +485,13 @@ __device__ __forceinline__ void track_step(TrackRegs<L>& t, const KernelArgs& A,
 
 // ---------------------------------------------------------------------------
 // Record transfer (segment cooperative).  Layout as documented for
-// reedmd_track_init.
-template <int L>
-__device__ __forceinline__ void store_record(const TrackRegs<L>& t, double* rec, int sl)
+// reedmd_track_init; the atom fields have Lattice<LAT>::kSlots entries.
+template <int L, int LAT>
+__device__ __forceinline__ void store_record(const TrackRegs<L, LAT>& t, double* rec, int sl)
 {
+    constexpr int NS = Lattice<LAT>::kSlots;
     if (sl == 0) {
+        const double* h = track_hdr(t);
         long long* ir = reinterpret_cast<long long*>(rec);
         rec[0] = t.x; rec[1] = t.y; rec[2] = t.z;
         rec[3] = t.vx; rec[4] = t.vy; rec[5] = t.vz;
@@ -431,29 +504,36 @@ __device__ __forceinline__ void store_record(const TrackRegs<L>& t, double* rec,
         rec[22] = t.vmax2a;
         rec[23] = t.amax2a;
         ir[24] = 1;   // words 22-23 hold the atom speed and acceleration maxima
-        for (int k = 25; k < kHdr; ++k) ir[k] = 0;
+        const bool vac = h[6] >= 0.0;
+        ir[25] = vac ? static_cast<long long>(h[3]) : 0;
+        ir[26] = vac ? static_cast<long long>(h[4]) : 0;
+        ir[27] = vac ? static_cast<long long>(h[5]) : 0;
+        ir[28] = vac ? static_cast<long long>(h[6]) : -1;
+        rec[29] = h[0]; rec[30] = h[1]; rec[31] = h[2];
     }
     double* at = rec + kHdr;
 #pragma unroll
-    for (int i = 0; i < TrackRegs<L>::SL; ++i) {
+    for (int i = 0; i < TrackRegs<L, LAT>::SL; ++i) {
         const int s = sl + L * i;
-        if (s >= kSlots) continue;
+        if (s >= NS) continue;
         const bool e = (t.exist >> i) & 1u;
-        at[0 * kSlots + s] = e ? t.ax[i] : 0.0;
-        at[1 * kSlots + s] = e ? t.ay[i] : 0.0;
-        at[2 * kSlots + s] = e ? t.az[i] : 0.0;
-        at[3 * kSlots + s] = e ? t.avx[i] : 0.0;
-        at[4 * kSlots + s] = e ? t.avy[i] : 0.0;
-        at[5 * kSlots + s] = e ? t.avz[i] : 0.0;
-        at[6 * kSlots + s] = e ? t.fl[0 * TrackRegs<L>::FS + s] : 0.0;
-        at[7 * kSlots + s] = e ? t.fl[1 * TrackRegs<L>::FS + s] : 0.0;
-        at[8 * kSlots + s] = e ? t.fl[2 * TrackRegs<L>::FS + s] : 0.0;
+        at[0 * NS + s] = e ? t.ax[i] : 0.0;
+        at[1 * NS + s] = e ? t.ay[i] : 0.0;
+        at[2 * NS + s] = e ? t.az[i] : 0.0;
+        at[3 * NS + s] = e ? t.avx[i] : 0.0;
+        at[4 * NS + s] = e ? t.avy[i] : 0.0;
+        at[5 * NS + s] = e ? t.avz[i] : 0.0;
+        at[6 * NS + s] = e ? t.fl[0 * TrackRegs<L, LAT>::FS + s] : 0.0;
+        at[7 * NS + s] = e ? t.fl[1 * TrackRegs<L, LAT>::FS + s] : 0.0;
+        at[8 * NS + s] = e ? t.fl[2 * TrackRegs<L, LAT>::FS + s] : 0.0;
     }
 }
 
-template <int L>
-__device__ __forceinline__ void load_record(TrackRegs<L>& t, const double* rec, int sl, const KernelArgs& A)
+template <int L, int LAT>
+__device__ __forceinline__ void load_record(TrackRegs<L, LAT>& t, const double* rec, int sl, const KernelArgs& A)
 {
+    using Lat = Lattice<LAT>;
+    constexpr int NS = Lat::kSlots;
     const long long* ir = reinterpret_cast<const long long*>(rec);
     t.x = rec[0]; t.y = rec[1]; t.z = rec[2];
     t.vx = rec[3]; t.vy = rec[4]; t.vz = rec[5];
@@ -468,8 +548,12 @@ __device__ __forceinline__ void load_record(TrackRegs<L>& t, const double* rec, 
         t.species = 0;
         t.status = REEDMD_LOST;
     }
+    double* h = track_hdr(t);
+    h[0] = rec[29]; h[1] = rec[30]; h[2] = rec[31];
+    h[3] = static_cast<double>(ir[25]); h[4] = static_cast<double>(ir[26]); h[5] = static_cast<double>(ir[27]);
+    h[6] = (ir[28] >= 0 && ir[28] < Lat::kCellAtoms) ? static_cast<double>(ir[28]) : -1.0;
     const double* at = rec + kHdr;
-    constexpr int FS = TrackRegs<L>::FS;
+    constexpr int FS = TrackRegs<L, LAT>::FS;
     const KernelArgs C = cold_args();
     const double parkx = C.a * (static_cast<double>(t.cx) + 0.5);
     const double parky = C.a * (static_cast<double>(t.cy) + 0.5);
@@ -477,20 +561,24 @@ __device__ __forceinline__ void load_record(TrackRegs<L>& t, const double* rec, 
     unsigned ex = 0;
     double vm = 0.0, fm = 0.0;
 #pragma unroll
-    for (int i = 0; i < TrackRegs<L>::SL; ++i) {
+    for (int i = 0; i < TrackRegs<L, LAT>::SL; ++i) {
         const int s = sl + L * i;
-        const int cell = s >> 3;
-        if (s >= kSlots || cell_of_residue(cell % 3, t.cz) < 0) {
-            park_slot<L>(t, i, s, parkx, parky, parkz);
+        const int cell = (s < NS) ? Lat::cell_of_slot(s) : -1;
+        if (cell < 0 || cell_of_residue(cell % 3, t.cz) < 0 ||
+            (LAT == kFluorite &&
+             vacant_site(h, cell_of_residue(cell / 9, t.cx), cell_of_residue((cell / 3) % 3, t.cy),
+                         cell_of_residue(cell % 3, t.cz), Lat::basis_of_slot(s)))) {
+            park_slot<L, LAT>(t, i, s, parkx, parky, parkz);
             continue;
         }
-        t.ax[i] = at[0 * kSlots + s]; t.ay[i] = at[1 * kSlots + s]; t.az[i] = at[2 * kSlots + s];
-        t.avx[i] = at[3 * kSlots + s]; t.avy[i] = at[4 * kSlots + s]; t.avz[i] = at[5 * kSlots + s];
-        const double fx = at[6 * kSlots + s], fy = at[7 * kSlots + s], fz = at[8 * kSlots + s];
+        t.ax[i] = at[0 * NS + s]; t.ay[i] = at[1 * NS + s]; t.az[i] = at[2 * NS + s];
+        t.avx[i] = at[3 * NS + s]; t.avy[i] = at[4 * NS + s]; t.avz[i] = at[5 * NS + s];
+        const double fx = at[6 * NS + s], fy = at[7 * NS + s], fz = at[8 * NS + s];
         t.fl[0 * FS + s] = fx; t.fl[1 * FS + s] = fy; t.fl[2 * FS + s] = fz;
         ex |= (1u << i);
         vm = fmax(vm, t.avx[i] * t.avx[i] + t.avy[i] * t.avy[i] + t.avz[i] * t.avz[i]);
-        fm = fmax(fm, fx * fx + fy * fy + fz * fz);
+        const bool anion = LAT == kFluorite && L * i >= Lat::kAnion0;
+        fm = fmax(fm, (fx * fx + fy * fy + fz * fz) * (anion ? A.inv_M2bsq : A.inv_M2sq));
     }
     t.exist = ex;
     t.n_exist = SegReduce<L>::isum(__popc(ex));
@@ -501,14 +589,14 @@ __device__ __forceinline__ void load_record(TrackRegs<L>& t, const double* rec, 
         t.amax2a = rec[23];
     } else {
         t.vmax2a = SegReduce<L>::max(vm);
-        t.amax2a = SegReduce<L>::max(fm) * A.inv_M2sq;
+        t.amax2a = SegReduce<L>::max(fm);
     }
 }
 
 // Starting state of batch entry q (the fresh step that builds the domain and
 // evaluates the first forces is done by the caller).
-template <int L>
-__device__ __forceinline__ void start_primary(TrackRegs<L>& t, const KernelArgs& A, const SpeciesConst* sp,
+template <int L, int LAT>
+__device__ __forceinline__ void start_primary(TrackRegs<L, LAT>& t, const KernelArgs& A, const SpeciesConst* sp,
                                               long long q)
 {
     t.species = A.species[q];
@@ -526,6 +614,17 @@ __device__ __forceinline__ void start_primary(TrackRegs<L>& t, const KernelArgs&
     const double speed = sqrt(2.0 * A.energy[q] / c.M1);
     t.x = A.pos[q]; t.y = A.pos[A.n + q]; t.z = A.pos[2 * A.n + q];
     t.vx = speed * dx / dn; t.vy = speed * dy / dn; t.vz = speed * dz / dn;
+    {
+        // start point; a recoil leaves the basis-0 site of the cell whose origin is
+        // nearest its start point empty
+        double* h = track_hdr(t);
+        const KernelArgs C = cold_args();
+        h[0] = t.x; h[1] = t.y; h[2] = t.z;
+        h[3] = floor(t.x * C.inv_a + 0.25);
+        h[4] = floor(t.y * C.inv_a + 0.25);
+        h[5] = floor(t.z * C.inv_a + 0.25);
+        h[6] = C.vacancy ? 0.0 : -1.0;
+    }
     t.Fx = 0.0; t.Fy = 0.0; t.Fz = 0.0;
     t.rho = 0.0; t.w = 1.0; t.zstop = 0.0;
     t.vmax2a = 0.0; t.amax2a = 0.0;
@@ -538,8 +637,8 @@ __device__ __forceinline__ void start_primary(TrackRegs<L>& t, const KernelArgs&
 
 // Termination events after a step: non-finite state, stop (depth linearly
 // interpolated in kinetic energy within the step), backscatter, step cap.
-template <int L>
-__device__ __forceinline__ int track_events(TrackRegs<L>& t, const KernelArgs& A, const SpeciesConst* sp,
+template <int L, int LAT>
+__device__ __forceinline__ int track_events(TrackRegs<L, LAT>& t, const KernelArgs& A, const SpeciesConst* sp,
                                             double ke0, double z0)
 {
     const bool finite = isfinite(t.x) && isfinite(t.y) && isfinite(t.z) && isfinite(t.vx) &&
@@ -547,7 +646,8 @@ __device__ __forceinline__ int track_events(TrackRegs<L>& t, const KernelArgs& A
     if (!finite) return REEDMD_NONFINITE;
     const double ke = 0.5 * sp[t.species].M1 * (t.vx * t.vx + t.vy * t.vy + t.vz * t.vz);
     if (ke < A.E_stop) {
-        t.zstop = (ke0 > A.E_stop) ? z0 + (t.z - z0) * (ke0 - A.E_stop) / (ke0 - ke) : z0;
+        const double zr = range_coord(t, A.range_mode);
+        t.zstop = (ke0 > A.E_stop) ? z0 + (zr - z0) * (ke0 - A.E_stop) / (ke0 - ke) : z0;
         return REEDMD_STOPPED;
     }
     if (t.z < A.z_start && t.vz < 0.0) return REEDMD_BACKSCATTERED;
@@ -674,12 +774,12 @@ __device__ __forceinline__ long long queue_reserve_pop(const KernelArgs& A)
 // from device counters and the clone queue until no track is live).
 enum : int { kSegNeed = 0, kSegRun = 1, kSegDone = 2 };
 
-template <int L, int MODE, bool F32 = false>
-__global__ void __launch_bounds__(256, REEDMD_WAVES_PER_SIMD(L)) track_kernel(const KernelArgs A0)
+template <int L, int MODE, bool F32 = false, int LAT = kDiamond>
+__global__ void __launch_bounds__(256, REEDMD_WAVES_PER_SIMD(L, LAT)) track_kernel(const KernelArgs A0)
 {
     const KernelArgs& A = A0;
-    __shared__ SpeciesConst s_sp[kMaxSpecies];
-    __shared__ double s_force[ForceLds<L>::kDoubles];
+    __shared__ double s_sp[kSpeciesLdsDoubles];
+    __shared__ double s_force[ForceLds<L, LAT>::kDoubles];
     const SpeciesConst* sp = stage_species(A, s_sp);
     const int lane = threadIdx.x & 63;
     const int sl = lane % L;
@@ -688,8 +788,9 @@ __global__ void __launch_bounds__(256, REEDMD_WAVES_PER_SIMD(L)) track_kernel(co
     const long long wave = static_cast<long long>(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const long long seg = wave * (64 / L) + seg_in_wave;
 
-    TrackRegs<L> t;
-    t.fl = force_slab<L>(s_force);
+    constexpr int RW = Lattice<LAT>::kRecWords;
+    TrackRegs<L, LAT> t;
+    t.fl = force_slab<L, LAT>(s_force);
     t.cx = t.cy = t.cz = kSentinel;
     t.exist = 0;
     t.n_exist = 0;
@@ -701,7 +802,7 @@ __global__ void __launch_bounds__(256, REEDMD_WAVES_PER_SIMD(L)) track_kernel(co
     int since_poll = 0;
     bool cancelled = false;
     double* my_stack = A.stack + static_cast<size_t>(seg < A.seg_total ? seg : 0) *
-                                     static_cast<size_t>(A.stack_cap) * kRecWords;
+                                     static_cast<size_t>(A.stack_cap) * RW;
 
     for (;;) {
         if (mode == kSegNeed) {
@@ -714,17 +815,17 @@ __global__ void __launch_bounds__(256, REEDMD_WAVES_PER_SIMD(L)) track_kernel(co
             bool got = false;
             if (top > 0) {
                 --top;
-                load_record<L>(t, my_stack + static_cast<size_t>(top) * kRecWords, sl, A);
-                refresh_threshold<L>(t, A);
+                load_record<L, LAT>(t, my_stack + static_cast<size_t>(top) * RW, sl, A);
+                refresh_threshold(t, A);
                 got = true;
             } else if (MODE == kModePersistent && A.qcap > 0) {
                 long long slot = -1;
                 if (sl == 0) slot = queue_reserve_pop(A);
                 slot = __shfl(slot, leader, 64);
                 if (slot >= 0) {
-                    const double* rec = A.qrec + static_cast<size_t>(slot % A.qcap) * kRecWords;
-                    load_record<L>(t, rec, sl, A);
-                    refresh_threshold<L>(t, A);
+                    const double* rec = A.qrec + static_cast<size_t>(slot % A.qcap) * RW;
+                    load_record<L, LAT>(t, rec, sl, A);
+                    refresh_threshold(t, A);
                     __threadfence();
                     if (sl == 0)
                         __hip_atomic_store(&A.qseq[slot % A.qcap], static_cast<unsigned long long>(slot) + A.qcap,
@@ -749,8 +850,8 @@ __global__ void __launch_bounds__(256, REEDMD_WAVES_PER_SIMD(L)) track_kernel(co
                     if (qi >= A.n) qi = -1;
                 }
                 if (qi >= 0) {
-                    start_primary<L>(t, A, sp, qi);
-                    if (t.status != REEDMD_LOST) refresh_threshold<L>(t, A);
+                    start_primary<L, LAT>(t, A, sp, qi);
+                    if (t.status != REEDMD_LOST) refresh_threshold(t, A);
                     if (sl == 0) add_i64(&A.stats->primaries, 1);
                     fresh = true;
                     got = true;
@@ -795,14 +896,14 @@ __global__ void __launch_bounds__(256, REEDMD_WAVES_PER_SIMD(L)) track_kernel(co
 
         // ---- one step of a running track ----
         double ke0, z0;
-        track_step<L, F32>(t, A, sp, sl, fresh, ke0, z0);
+        track_step<L, F32, LAT>(t, A, sp, sl, fresh, ke0, z0);
         pairs += t.n_exist;
         if (fresh) {
             fresh = false;
             continue;
         }
         exec_steps += 1;
-        int st = track_events<L>(t, A, sp, ke0, z0);
+        int st = track_events<L, LAT>(t, A, sp, ke0, z0);
         if (st == REEDMD_ACTIVE && ++since_poll >= 256) {
             since_poll = 0;
             const KernelArgs C = cold_args();
@@ -822,9 +923,10 @@ __global__ void __launch_bounds__(256, REEDMD_WAVES_PER_SIMD(L)) track_kernel(co
             continue;
         }
         // cloning at depth thresholds (Sec. 2): weight / n_clones, new keys
-        if (t.z >= t.thr_next) {
+        const double zr = range_coord(t, A.range_mode);
+        if (zr >= t.thr_next) {
             const KernelArgs A = cold_args();
-            while (t.next_k < A.n_thresh && t.z >= t.thr_next) {
+            while (t.next_k < A.n_thresh && zr >= t.thr_next) {
                 const int k = t.next_k;
                 const unsigned long long parent = t.key;
                 t.w = t.w / static_cast<double>(A.n_clones);
@@ -838,7 +940,7 @@ __global__ void __launch_bounds__(256, REEDMD_WAVES_PER_SIMD(L)) track_kernel(co
                     }
                     if (slot >= 0) {
                         if (sl == 0) add_i64(&A.q->live, 1);
-                        store_record<L>(t, A.qrec + static_cast<size_t>(slot % A.qcap) * kRecWords, sl);
+                        store_record<L, LAT>(t, A.qrec + static_cast<size_t>(slot % A.qcap) * RW, sl);
                         __threadfence();
                         if (sl == 0) {
                             __hip_atomic_store(&A.qseq[slot % A.qcap], static_cast<unsigned long long>(slot) + 1,
@@ -854,7 +956,7 @@ __global__ void __launch_bounds__(256, REEDMD_WAVES_PER_SIMD(L)) track_kernel(co
                             add_i64(&A.q->live, 1);
                             if (A.qcap > 0) add_i64(&A.stats->stack_overflow, 1);
                         }
-                        store_record<L>(t, my_stack + static_cast<size_t>(top) * kRecWords, sl);
+                        store_record<L, LAT>(t, my_stack + static_cast<size_t>(top) * RW, sl);
                         ++top;
                     } else {
                         // no room anywhere: the clone's weight is quarantined (ledger stays exact)
@@ -866,53 +968,53 @@ __global__ void __launch_bounds__(256, REEDMD_WAVES_PER_SIMD(L)) track_kernel(co
                     if (sl == 0) add_i64(&A.stats->clones, 1);
                 }
                 t.key = child_key(parent, A.seed, k, 0);
-                refresh_threshold<L>(t, A);
+                refresh_threshold(t, A);
             }
         }
     }
 }
 
 // Builds the starting record of every batch entry (debug / parity entry point).
-template <int L, bool F32 = false>
+template <int L, bool F32 = false, int LAT = kDiamond>
 __global__ void __launch_bounds__(256) init_kernel(const KernelArgs A)
 {
-    __shared__ SpeciesConst s_sp[kMaxSpecies];
-    __shared__ double s_force[ForceLds<L>::kDoubles];
+    __shared__ double s_sp[kSpeciesLdsDoubles];
+    __shared__ double s_force[ForceLds<L, LAT>::kDoubles];
     const SpeciesConst* sp = stage_species(A, s_sp);
     const int lane = threadIdx.x & 63;
     const int sl = lane % L;
     const long long seg = (static_cast<long long>(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6)) * (64 / L) + lane / L;
     if (seg >= A.n) return;
-    TrackRegs<L> t;
-    t.fl = force_slab<L>(s_force);
+    TrackRegs<L, LAT> t;
+    t.fl = force_slab<L, LAT>(s_force);
     t.exist = 0;
-    start_primary<L>(t, A, sp, seg);
+    start_primary<L, LAT>(t, A, sp, seg);
     double ke0, z0;
-    if (t.status != REEDMD_LOST) track_step<L, F32>(t, A, sp, sl, true, ke0, z0);
-    store_record<L>(t, A.records + static_cast<size_t>(seg) * kRecWords, sl);
+    if (t.status != REEDMD_LOST) track_step<L, F32, LAT>(t, A, sp, sl, true, ke0, z0);
+    store_record<L, LAT>(t, A.records + static_cast<size_t>(seg) * Lattice<LAT>::kRecWords, sl);
 }
 
 // Advances caller records by nsteps steps without events (debug / parity).
-template <int L, bool F32 = false>
+template <int L, bool F32 = false, int LAT = kDiamond>
 __global__ void __launch_bounds__(256, 2) step_kernel(const KernelArgs A)
 {
-    __shared__ SpeciesConst s_sp[kMaxSpecies];
-    __shared__ double s_force[ForceLds<L>::kDoubles];
+    __shared__ double s_sp[kSpeciesLdsDoubles];
+    __shared__ double s_force[ForceLds<L, LAT>::kDoubles];
     const SpeciesConst* sp = stage_species(A, s_sp);
     const int lane = threadIdx.x & 63;
     const int sl = lane % L;
     const long long seg = (static_cast<long long>(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6)) * (64 / L) + lane / L;
     if (seg >= A.n) return;
-    TrackRegs<L> t;
-    t.fl = force_slab<L>(s_force);
-    double* rec = A.records + static_cast<size_t>(seg) * kRecWords;
-    load_record<L>(t, rec, sl, A);
+    TrackRegs<L, LAT> t;
+    t.fl = force_slab<L, LAT>(s_force);
+    double* rec = A.records + static_cast<size_t>(seg) * Lattice<LAT>::kRecWords;
+    load_record<L, LAT>(t, rec, sl, A);
     if (t.status == REEDMD_LOST) return;   // invalid species index: record left as it was
     for (int s = 0; s < A.nsteps; ++s) {
         double ke0, z0;
-        track_step<L, F32>(t, A, sp, sl, false, ke0, z0);
+        track_step<L, F32, LAT>(t, A, sp, sl, false, ke0, z0);
     }
-    store_record<L>(t, rec, sl);
+    store_record<L, LAT>(t, rec, sl);
 }
 
 }  // namespace reedmd

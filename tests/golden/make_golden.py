@@ -5,6 +5,8 @@ Usage:  python tests/golden/make_golden.py [pilot|pilot2|pilot4|c0|c1|c2|c4|refi
   pilot: unsplit survival quantiles of the 10 keV As workload (source of C1_THRESHOLDS)
   pilot2: cloning-depth tables of the mixed B/P/As 1-100 keV workload (C2_THRESHOLDS)
   pilot4: cloning depths of the 100 keV As [001] channeling workload (C4_THRESHOLDS)
+  pilot5: cloning distances of the 85 keV U recoils in UO2 (C5_THRESHOLDS)
+  c5:    256 U recoils at 85 keV in UO2 (ids 0..255) with the 8 cloning distances
   c0:    65,536 B at 1 keV, 7 degree tilt, no splitting (the c0 sampler, ids 0..65535)
   c1:    1,024 As at 10 keV with the 8 cloning depths: ids 0..511 (channel) and 32768..33279 (tilt)
   refine: 2,048 B at 1 keV (the c0 sampler, ids 0..2047) with 6 adaptive cloning depths at
@@ -25,7 +27,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 import oracle  # noqa: E402
-from tests.workloads import C1_THRESHOLDS, C2_THRESHOLDS, C4_THRESHOLDS, WORKLOADS  # noqa: E402
+from tests.workloads import C1_THRESHOLDS, C2_THRESHOLDS, C4_THRESHOLDS, C5_THRESHOLDS, WORKLOADS  # noqa: E402
 
 
 def sampler(w):
@@ -119,6 +121,37 @@ def pilot4():
     print("stored:", C4_THRESHOLDS)
 
 
+def c5_config(w, thresholds=None):
+    t = w["target"]
+    return oracle.Config(species=w["species"], structure=oracle.FLUORITE, a=t["a"], Z2=t["Z2"], M2=t["M2"],
+                         sigma=t["sigma"], Z2b=t["Z2b"], M2b=t["M2b"], sigma_b=t["sigma_b"],
+                         range_mode=w["range_mode"], vacancy=w["vacancy"], n_bins=w["n_bins"],
+                         bin_width=w["bin_width"], thresholds=thresholds if thresholds is not None else np.zeros((1, 0)))
+
+
+def pilot5():
+    """8 cloning distances of the 85 keV U recoils in UO2 at unsplit survival 2^-k."""
+    w = WORKLOADS["c5_u85kev_uo2"]
+    probs = [2.0 ** -k for k in range(1, 9)]
+    prim = oracle.sample_primaries(sampler(w), 5, 512)
+    t = time.time()
+    r = oracle.run(c5_config(w), prim, log=True)
+    lg = r["log"]
+    print("pilot5 seconds", time.time() - t, r["stats"])
+    print("C5_THRESHOLDS =", survival_depths(lg["z_stop"][lg["status"] == oracle.STOPPED], probs, min_gap=1.0))
+    print("stored:", C5_THRESHOLDS)
+
+
+def c5():
+    """256 primaries of the 85 keV U recoil workload (ids 0..255), 8 cloning distances."""
+    w = WORKLOADS["c5_u85kev_uo2"]
+    prim = oracle.sample_primaries(sampler(w), 0, 256)
+    t = time.time()
+    r = oracle.run(c5_config(w, [list(C5_THRESHOLDS)]), prim, log=True)
+    print("c5 oracle seconds", time.time() - t, r["stats"])
+    save("c5_subset", dict(name="c5_u85kev_uo2", ids=[[0, 256]], seed=0), r)
+
+
 def c0():
     w = WORKLOADS["c0_b1kev"]
     n = 65536
@@ -191,5 +224,5 @@ def c4():
 if __name__ == "__main__":
     what = sys.argv[1:] or ["c0", "c1"]
     for w in what:
-        {"pilot": pilot, "pilot2": pilot2, "pilot4": pilot4, "c0": c0, "c1": c1, "c2": c2, "c4": c4,
-         "refine": refine}[w]()
+        {"pilot": pilot, "pilot2": pilot2, "pilot4": pilot4, "pilot5": pilot5, "c0": c0, "c1": c1, "c2": c2,
+         "c4": c4, "c5": c5, "refine": refine}[w]()

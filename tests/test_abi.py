@@ -44,9 +44,13 @@ def test_struct_sizes_match_header_layout():
     assert C.sizeof(_abi.Species) == 8 + 4 * 8 + 8 * 8
     assert _abi.STATS_WORDS * 8 == 10 * 8 + 8 * 8 + 4 * 8
     assert _abi.RECORD_WORDS == 32 + 9 * 216
+    assert _abi.RECORD_WORDS_FLUORITE == 32 + 9 * 344
     # reedmd_run_params: 4 doubles, max_steps, seed, 2 ints, thresholds, 2 ints, bin_width,
-    # 4 ints, cancel and track_log, track_log_cap, force_precision + reserved
-    assert C.sizeof(_abi.RunParams) == 4 * 8 + 8 + 8 + 8 + 8 + 8 + 8 + 16 + 16 + 8 + 8
+    # 4 ints, cancel and track_log, track_log_cap, force_precision + range_mode,
+    # vacancy + reserved
+    assert C.sizeof(_abi.RunParams) == 4 * 8 + 8 + 8 + 8 + 8 + 8 + 8 + 16 + 16 + 8 + 8 + 8
+    # reedmd_lattice: a, M2, sigma, Z2 + structure, M2b, sigma_b, Z2b + reserved
+    assert C.sizeof(_abi.Lattice) == 3 * 8 + 8 + 2 * 8 + 8
 
 
 def test_version_and_create_argument_errors_without_gpu():
@@ -65,6 +69,10 @@ def test_version_and_create_argument_errors_without_gpu():
     assert L.reedmd_create(C.byref(lat), C.byref(badp), C.byref(stp), C.byref(h)) == _abi.EINVAL
     bads = _abi.Lattice(a=5.431, M2=28.0855, sigma=0.076, Z2=14, structure=3)
     assert L.reedmd_create(C.byref(bads), C.byref(pot), C.byref(stp), C.byref(h)) == _abi.EUNSUPPORTED
+    # fluorite needs the anion species
+    badf = _abi.Lattice(a=5.47, M2=238.03, sigma=0.05, Z2=92, structure=_abi.FLUORITE)
+    assert L.reedmd_create(C.byref(badf), C.byref(pot), C.byref(stp), C.byref(h)) == _abi.EINVAL
+    assert b"fluorite" in L.reedmd_last_error(None)
     assert L.reedmd_run(None, None, None, None, None, None, None) == _abi.EINVAL
     L.reedmd_destroy(None)
 

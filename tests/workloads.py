@@ -36,6 +36,16 @@ C2_THRESHOLDS = (
 C4_THRESHOLDS = (3613.4, 5090.6, 6132.5, 6481.5, 6911.2, 7315.8, 7720.5, 8125.1, 8529.7, 8934.3,
                  9338.9, 9743.6, 10148.2, 10552.8, 10957.4, 11362.0)
 
+# Fluorite UO2 target (cations U, anions O); cubic constant and masses from the literature, the
+# rms thermal displacements representative 300 K Debye-Waller amplitudes (Sec. 4 takes its
+# values from MD runs it does not print).
+UO2 = dict(a=5.470, Z2=92, M2=238.03, sigma=0.050, Z2b=8, M2b=15.999, sigma_b=0.067)
+
+# Cloning distances (A from the start point) of the 85 keV U recoils in UO2: 8 distances at unsplit
+# survival 2^-k, k = 1..8 (the paper uses eight cloning points for this case), from a 512-primary
+# oracle pilot of the same sampler (pilot5).
+C5_THRESHOLDS = (141.8, 203.7, 249.2, 302.1, 368.0, 428.2, 487.3, 546.9)
+
 WORKLOADS = {
     # 256 B at 1 keV, [100] surface, 7 degree tilt, uniform azimuth, no splitting, 1 A bins
     "c0_b1kev": dict(species=("B",), n=256, sampler=dict(choice=(0,), E_min=1000.0, E_max=1000.0,
@@ -58,4 +68,12 @@ WORKLOADS = {
     "c4_as100kev": dict(species=("As",), n=262144,
                         sampler=dict(choice=(0,), E_min=100000.0, E_max=100000.0, dir_mode=0, tilt=0.0),
                         thresholds="c4", n_bins=1000, bin_width=5.0),
+    # 5,120 U recoils at 85 keV in UO2 (a plutonium alpha-decay recoil, Sec. 4): each primary is the
+    # U atom of the cation site at the origin of cell (0, 0, 200), 1,094 A below the surface, moving
+    # in a uniformly random direction, its own site left empty; the range is the distance from the
+    # start point; 8 cloning distances; 0.5 A bins over 0-1024 A
+    "c5_u85kev_uo2": dict(species=("U",), n=5120, target=UO2,
+                          sampler=dict(choice=(0,), E_min=85000.0, E_max=85000.0, dir_mode=3, start_mode=1,
+                                       a=UO2["a"], z_start=200 * UO2["a"]),
+                          thresholds="c5", n_bins=2048, bin_width=0.5, range_mode=1, vacancy=1),
 }
