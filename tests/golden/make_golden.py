@@ -7,6 +7,8 @@ Usage:  python tests/golden/make_golden.py [pilot|pilot2|pilot4|c0|c1|c2|c4|refi
   pilot4: cloning depths of the 100 keV As [001] channeling workload (C4_THRESHOLDS)
   pilot5: cloning distances of the 85 keV U recoils in UO2 (C5_THRESHOLDS)
   c5:    256 U recoils at 85 keV in UO2 (ids 0..255) with the 8 cloning distances
+  c5refine: 512 U recoils at 85 keV in UO2 with 8 distances at survival 2^-k re-placed between
+         4 epochs from a deliberately short first table
   c0:    65,536 B at 1 keV, 7 degree tilt, no splitting (the c0 sampler, ids 0..65535)
   c1:    1,024 As at 10 keV with the 8 cloning depths: ids 0..511 (channel) and 32768..33279 (tilt)
   refine: 2,048 B at 1 keV (the c0 sampler, ids 0..2047) with 6 adaptive cloning depths at
@@ -197,6 +199,24 @@ def refine():
          extra=dict(depths=r["depths"].tolist()))
 
 
+REFINE5 = dict(n=512, n_epochs=4, probs=[2.0 ** -k for k in range(1, 9)],
+               first=[40.0, 60.0, 80.0, 100.0, 120.0, 140.0, 160.0, 180.0], min_gap=1.0)
+
+
+def c5refine():
+    """Eight dynamically placed cloning distances for the 85 keV U recoils in UO2 (the setting
+    of Sec. 4): the oracle's epoch runner on 512 primaries from a deliberately short table."""
+    w = WORKLOADS["c5_u85kev_uo2"]
+    prim = oracle.sample_primaries(sampler(w), 0, REFINE5["n"])
+    cfg = c5_config(w, [REFINE5["first"]])
+    t = time.time()
+    r = oracle.run_refined(cfg, prim, REFINE5["n_epochs"], REFINE5["probs"], REFINE5["min_gap"])
+    print("c5refine oracle seconds", time.time() - t, r["stats"])
+    print("distances", np.round(r["depths"], 2).tolist())
+    save("c5_refined", dict(name="c5_u85kev_uo2", ids=[[0, REFINE5["n"]]], seed=0, **REFINE5), r,
+         extra=dict(depths=r["depths"].tolist()))
+
+
 def c2():
     """256 primaries of the mixed workload (ids 0..255), all 12-depth tables."""
     w = WORKLOADS["c2_mixed"]
@@ -225,4 +245,4 @@ if __name__ == "__main__":
     what = sys.argv[1:] or ["c0", "c1"]
     for w in what:
         {"pilot": pilot, "pilot2": pilot2, "pilot4": pilot4, "pilot5": pilot5, "c0": c0, "c1": c1, "c2": c2,
-         "c4": c4, "c5": c5, "refine": refine}[w]()
+         "c4": c4, "c5": c5, "c5refine": c5refine, "refine": refine}[w]()

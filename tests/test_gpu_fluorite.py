@@ -229,3 +229,37 @@ def test_u_recoil_subset_matches_oracle(R, ctx):
     D, p = physref.weighted_ks(s["z_stop"], s["w"], zo, wo)
     _say(f"c5 KS D={D:.4g} p={p:.3g}; gpu clones {sp['clones']} oracle {meta['stats']['clones']}")
     assert p > 0.01
+
+
+def test_u_recoil_adaptive_distances_follow_the_oracle_rule(R, ctx):
+    """Eight cloning distances re-placed between 4 epochs (512 U recoils at 85 keV, survival
+    2^-k, from a deliberately short first table; the setting of Sec. 4): every table the GPU ran
+    with equals the oracle's rule applied to the GPU's own tracks of the earlier epochs, to 1e-6
+    A; the ledger is exact; the weighted stopping distances match the stored oracle run of the
+    same procedure (KS p > 0.01)."""
+    meta, zo, wo = _load_golden("c5_refined")
+    m = meta["workload"]
+    n, E, probs, first, gap = m["n"], m["n_epochs"], m["probs"], m["first"], m["min_gap"]
+    batch = R.sample_primaries(ctx, R.SamplerConfig(**W5["sampler"]), 0, n)
+    cfg = rcfg(R, n_bins=W5["n_bins"], bin_width=W5["bin_width"], thresholds=[first], form=R.FORM_PERSISTENT)
+    hist, stats, depths, log = R.run_refined(ctx, W5["species"], batch, cfg, E, probs, gap, log_cap=200000)
+    torch.cuda.synchronize()
+    st = R.parse_stats(stats)
+    assert st["primaries"] == n
+    assert st["w_stopped"] + st["w_backscattered"] + st["w_quarantined"] == n
+    assert float(hist.sum()) + st["w_underflow"] + st["w_overflow"] == st["w_stopped"]
+    lg = R.parse_log(log, st["log_count"])
+    assert len(lg) == st["finished"]
+    d = depths.cpu().numpy()
+    assert np.array_equal(d[0], [first])
+    tables = batch["table"].cpu().numpy()
+    bounds = [n * e // E for e in range(E + 1)]
+    for e in range(1, E):
+        ts = oracle.table_stats(lg[lg["lineage"] < bounds[e]], tables, 1, W5["n_bins"], W5["bin_width"])
+        ref = oracle.refine_depths(ts, W5["n_bins"], W5["bin_width"], probs, d[e - 1], gap)
+        assert np.allclose(d[e], ref, rtol=0, atol=1e-6), (e, d[e], ref)
+    s = lg[lg["status"] == R.STOPPED]
+    D, p = physref.weighted_ks(s["z_stop"], s["w"], zo, wo)
+    _say(f"c5 refined distances {np.round(d[:, 0], 1).tolist()} vs oracle "
+         f"{np.round(np.array(meta['depths'])[:, 0], 1).tolist()}; KS D={D:.4g} p={p:.3g}")
+    assert p > 0.01
