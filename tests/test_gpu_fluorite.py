@@ -202,20 +202,23 @@ def _load_golden(name):
     return meta, zw[:, 0], zw[:, 1]
 
 
-def test_u_recoil_subset_matches_oracle(R, ctx):
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_u_recoil_subset_matches_oracle(R, ctx, precision):
     """256 U recoils at 85 keV in UO2 with 8 radial cloning distances: exact weight ledger;
     plain and persistent forms give bitwise-identical histograms; the weighted distribution
-    of the stopping distance agrees with the stored oracle run (KS p > 0.01)."""
+    of the stopping distance agrees with the stored FP64 oracle run (KS p > 0.01), for the
+    FP64 path and for the FP32 pair term."""
     meta, zo, wo = _load_golden("c5_subset")
     batch = R.sample_primaries(ctx, R.SamplerConfig(**W5["sampler"]), 0, 256)
+    fp = R.FORCE_FP32 if precision == "fp32" else R.FORCE_FP64
     out = {}
     for form in (R.FORM_PLAIN, R.FORM_PERSISTENT):
         cfg = rcfg(R, n_bins=W5["n_bins"], bin_width=W5["bin_width"], thresholds=[list(C5_THRESHOLDS)],
-                   form=form)
+                   form=form, force_precision=fp)
         hist, stats, log, _ = R.run(ctx, W5["species"], batch, cfg, log_cap=20000)
         torch.cuda.synchronize()
         st = R.parse_stats(stats)
-        _say(f"c5 form {form} stats {st}")
+        _say(f"c5 {precision} form {form} stats {st}")
         assert st["primaries"] == 256 and st["error_flags"] == 0
         tot = float(hist.sum()) + st["w_underflow"] + st["w_overflow"] + st["w_backscattered"] + st["w_quarantined"]
         assert tot == 256.0
@@ -227,7 +230,7 @@ def test_u_recoil_subset_matches_oracle(R, ctx):
         assert sp[k] == sq[k], k
     s = lg[lg["status"] == R.STOPPED]
     D, p = physref.weighted_ks(s["z_stop"], s["w"], zo, wo)
-    _say(f"c5 KS D={D:.4g} p={p:.3g}; gpu clones {sp['clones']} oracle {meta['stats']['clones']}")
+    _say(f"c5 {precision} KS D={D:.4g} p={p:.3g}; gpu clones {sp['clones']} oracle {meta['stats']['clones']}")
     assert p > 0.01
 
 
