@@ -113,6 +113,52 @@ def cpu_baseline(target_seconds):
                        f"{total_tracks / t_all:.1f} tracks/s")
 
 
+def profile_accuracy(R, torch, np, ctx, w, sampler, n, cfg, reed_log, t_reed, tail_depth):
+    """Accuracy per unit time of the deep tail, REED against no splitting.  The same primaries
+    run once without cloning; the depth D where their survival is 1e-3 (the 0.1 % deepest
+    stop) is the probe.  For both runs the probability of stopping beyond D (and beyond the
+    7th cloning depth) is estimated with its relative standard error from 32 independent
+    sub-batches (primary id mod 32, batch means), and the figure of merit 1 / (T s^2) uses the
+    launch's wall time T.  REED's estimate is the weighted sum over every track of the family."""
+    import dataclasses
+    ns_cfg = dataclasses.replace(cfg, thresholds=None)
+    b = R.sample_primaries(ctx, sampler, 0, n)
+    hist = torch.zeros(w["n_bins"], dtype=torch.float64, device="cuda")
+    stats = R.new_stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, log, _ = R.run(ctx, w["species"], b, ns_cfg, hist=hist, stats=stats, log_cap=n + 16)
+    torch.cuda.synchronize()
+    t_ns = time.perf_counter() - t0
+    st = R.parse_stats(stats)
+    ns_log = R.parse_log(log, st["log_count"])
+    zs = np.sort(ns_log["z_stop"][ns_log["status"] == R.STOPPED])
+    D = float(zs[min(len(zs) - 1, int(round(len(zs) * (1.0 - 1e-3))))]) if len(zs) else tail_depth
+
+    def estimate(lg, depth):
+        deep = (lg["status"] == R.STOPPED) & (lg["z_stop"] >= depth)
+        per = np.zeros(n)
+        np.add.at(per, lg["lineage"][deep], lg["w"][deep])
+        bm = np.array([per[k::32].mean() for k in range(32)])
+        p = per.mean()
+        rel = bm.std(ddof=1) / math.sqrt(32) / p if p > 0 else float("nan")
+        return p, rel
+
+    out = {}
+    for name, depth in (("survival_1e-3", D), ("depth_7", tail_depth)):
+        pr, rr = estimate(reed_log, depth)
+        pn, rn = estimate(ns_log, depth)
+        fr = 1.0 / (t_reed * rr * rr) if rr > 0 else None
+        fn = 1.0 / (t_ns * rn * rn) if rn > 0 else None
+        out[name] = dict(depth_A=depth, reed_probability=pr, reed_rel_err=rr, reed_fom_per_s=fr,
+                         nosplit_probability=pn, nosplit_rel_err=rn, nosplit_fom_per_s=fn,
+                         fom_ratio=(fr / fn) if (fr and fn) else None)
+    out["reed_s"] = t_reed
+    out["nosplit_s"] = t_ns
+    out["method"] = "32 sub-batches (primary id mod 32), batch means; FOM = 1/(T s^2) with the launch wall time"
+    return out
+
+
 def fp32_leg(R, ctx, torch, w, sampler, n, base, stream, hist, stats, form, lanes=0, waves=0):
     """The same workload with the FP32 pair term (FP64 integration and step control): its
     own autotuned shape (or the one given), one warm launch, two timed launches.  Reported
@@ -320,8 +366,8 @@ def main():
         if timed_events is not None:
             timed_events[1].record(stream)
 
-    # warmup (the first one also measures the profile accuracy from the track log)
-    acc = {}
+    # warmup (the first one also keeps the track log for the profile accuracy below)
+    reed_log, t_w = None, None
     for i in range(args.warmup):
         if i == 0:
             b = R.sample_primaries(ctx, sampler, 0, n)
@@ -333,16 +379,7 @@ def main():
             torch.cuda.synchronize()
             t_w = time.perf_counter() - t0
             st = R.parse_stats(stats)
-            lg = R.parse_log(log, min(st["log_count"], 40 * n))
-            # relative standard error of the weighted probability beyond a deep-tail depth,
-            # from per-primary sums (unbiased REED estimator), and the figure of merit 1/(T s^2)
-            deep = (lg["status"] == R.STOPPED) & (lg["z_stop"] >= tail_depth)
-            per = np.zeros(n)
-            np.add.at(per, lg["lineage"][deep], lg["w"][deep])
-            p = per.mean()
-            rel = per.std(ddof=1) / math.sqrt(n) / p if p > 0 else float("nan")
-            acc = dict(tail_depth_A=tail_depth, tail_probability=p, tail_rel_err=rel,
-                       fom_per_s=1.0 / (t_w * rel * rel) if rel > 0 else None)
+            reed_log = R.parse_log(log, min(st["log_count"], 40 * n))
         else:
             step()
     torch.cuda.synchronize()
@@ -414,7 +451,7 @@ def main():
         "track_steps_per_s": st_last["track_steps"] * args.steps / wall,
         "kernel_ms_per_step": [round(x, 1) for x in kernel_ms],
         "queue_max_and_overflow_per_step": queue_use,
-        "profile_accuracy": acc,
+        "profile_accuracy": None,
         "grad_fwd_ratio": None,
         "roofline": {
             "bound": "alu",
@@ -443,6 +480,8 @@ def main():
         sr = R.parse_stats(stats)
         out["refined"] = dict(epochs=args.refine_epochs, ms=1e3 * tr, force_evals_per_s=sr["pair_evals"] / tr,
                               tracks=sr["finished"], last_depths=[round(x, 1) for x in depths[-1, 0].tolist()])
+    if reed_log is not None and cfg.thresholds is not None:
+        out["profile_accuracy"] = profile_accuracy(R, torch, np, ctx, w, sampler, n, cfg, reed_log, t_w, tail_depth)
     if not args.no_fp32:
         out["fp32_pair_variant"] = fp32_leg(R, ctx, torch, w, sampler, n, base, stream, hist, stats, args.form,
                                             args.lanes, args.waves)
