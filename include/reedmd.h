@@ -291,7 +291,9 @@ reedmd_status reedmd_track_init(reedmd_ctx* ctx, const reedmd_species* species,
 
 /* Advances each of the n records in d_records (device, in place) by nsteps
  * integration steps (Sec. 2), without termination events or cloning.  For
- * per-step parity checks.  lanes_per_track in params selects the kernel. */
+ * per-step parity checks.  lanes_per_track in params selects the kernel.
+ * Records are laid out as for reedmd_track_init (REEDMD_RECORD_WORDS, or
+ * REEDMD_RECORD_WORDS_FLUORITE for a fluorite context). */
 reedmd_status reedmd_debug_step(reedmd_ctx* ctx, const reedmd_species* species,
                                 const reedmd_run_params* params, double* d_records, int64_t n,
                                 int32_t nsteps, hipStream_t stream);
@@ -305,7 +307,8 @@ reedmd_status reedmd_debug_step(reedmd_ctx* ctx, const reedmd_species* species,
  * checkpoint and the adjoint of its steps applied from last to first.  The
  * derivative is pathwise: branches (active step-size term, domain updates,
  * which step stops the ion) are held fixed, created atoms are constants.
- * Requires params->n_thresh == 0 (EUNSUPPORTED otherwise); params->max_steps
+ * Requires params->n_thresh == 0, FP64 pair terms, a diamond context, the
+ * depth range and no vacancy (EUNSUPPORTED otherwise); params->max_steps
  * bounds the track length and the checkpoint memory (<= 0: 16,384 steps).
  * d_track_out (device, optional, n x 5 doubles) receives per track: stopping
  * depth, d/dk, d/ds, status, steps.  h_result (host, 4 doubles) receives the
