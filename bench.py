@@ -76,6 +76,7 @@ def parse():
     ap.add_argument("--no-grad", action="store_true", help="skip the gradient / forward time ratio")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 pair-term variant leg")
     ap.add_argument("--no-uo2", action="store_true", help="skip the 85 keV U recoil in UO2 leg")
+    ap.add_argument("--uo2-n", type=int, default=0, help="primaries of the UO2 leg (default: the workload's 5,120)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (HBM counter calibration)")
     return ap.parse_args()
@@ -203,12 +204,14 @@ def fp32_leg(R, ctx, torch, w, sampler, n, base, stream, hist, stats, form, lane
                 tolerance="1e-5 relative per step against the FP64 oracle")
 
 
-def uo2_leg(R, torch):
+def uo2_leg(R, torch, n_override=0):
     """The 85 keV U recoil workload in fluorite UO2 (5,120 primaries, on-site start with the
     site left vacant, random directions, 8 cloning distances from the start point): autotuned
     shape (64 or 32 lanes), one warm launch, two timed launches."""
     from tests.workloads import C5_THRESHOLDS, UO2, WORKLOADS
-    w = WORKLOADS["c5_u85kev_uo2"]
+    w = dict(WORKLOADS["c5_u85kev_uo2"])
+    if n_override > 0:
+        w["n"] = n_override
     ctx = R.Context(structure=R.FLUORITE, **UO2)
     sc = R.SamplerConfig(**w["sampler"])
     base = dict(n_bins=w["n_bins"], bin_width=w["bin_width"], thresholds=[list(C5_THRESHOLDS)],
@@ -244,7 +247,7 @@ def uo2_leg(R, torch):
     shape = R.launch_shape(ctx, batch, cfg)
     ctx.close()
     k = sum(kms) / len(kms)
-    return dict(workload="5,120 U at 85 keV in UO2 (a=5.47 A, sigma U 0.050 / O 0.067 A), on-site recoils "
+    return dict(primaries=w["n"], workload="U at 85 keV in UO2 (a=5.47 A, sigma U 0.050 / O 0.067 A), on-site recoils "
                          "at 1,094 A depth, random direction, vacant start site, radial range, 8 cloning "
                          "distances, 0.5 A bins",
                 force_evals_per_s=pairs / t_all, tracks_per_s=tracks / t_all, kernel_ms_per_step=[round(x, 1) for x in kms],
@@ -486,7 +489,7 @@ def main():
         out["fp32_pair_variant"] = fp32_leg(R, ctx, torch, w, sampler, n, base, stream, hist, stats, args.form,
                                             args.lanes, args.waves)
     if not args.no_uo2:
-        out["uo2_recoil"] = uo2_leg(R, torch)
+        out["uo2_recoil"] = uo2_leg(R, torch, args.uo2_n)
     if not args.no_grad:
         gr = grad_forward_ratio(R, ctx, torch)
         out["grad_fwd_ratio"] = gr["ratio"]
