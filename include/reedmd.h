@@ -318,12 +318,16 @@ reedmd_status reedmd_grad(reedmd_ctx* ctx, const reedmd_species* species, const 
                           const reedmd_run_params* params, double k, double s, double* d_track_out,
                           double* h_result, hipStream_t stream);
 
-/* Evaluates, for finite 0 <= y[i] < 1e9 (device, n doubles), the exp(-y) that
- * the force kernels use (Cody-Waite reduction to |r| <= ln2/2, degree-10
- * minimax polynomial, ldexp) into out (device); outside that range the value
- * is unspecified.  For accuracy tests of the library's exponential.  Enqueued
- * on stream; EINVAL for n < 0 or NULL arrays. */
+/* Evaluates, for finite 0 <= y[i] < 1e9 (device, n doubles), the library's
+ * exp(-y) into out (device); outside that range the value is unspecified.
+ * reedmd_eval_exp_neg: the friction factors' exponential (Cody-Waite reduction
+ * to |r| <= ln2/2, degree-10 minimax polynomial, ldexp; relative error 3e-16).
+ * reedmd_eval_exp_neg_pair: the exponential of the ion-atom pair terms (same
+ * reduction, degree-8 minimax polynomial; relative error 1.08e-12, inside the
+ * per-step tolerance of 1e-10 of the FP64 path).  For accuracy tests.
+ * Enqueued on stream; EINVAL for n < 0 or NULL arrays. */
 reedmd_status reedmd_eval_exp_neg(const double* d_y, double* d_out, int64_t n, hipStream_t stream);
+reedmd_status reedmd_eval_exp_neg_pair(const double* d_y, double* d_out, int64_t n, hipStream_t stream);
 
 /* Chooses the launch shape for runs like this one.  Each candidate (lanes per
  * track 64, 32, 16; for the persistent form also one workgroup per CU fewer

@@ -367,12 +367,14 @@ class ReedMDRange(torch.autograd.Function):
         return g * d[0], g * d[1], None, None, None, None
 
 
-def eval_exp_neg(y: torch.Tensor, stream=None):
-    """The library's exp(-y) (used by the force kernels) on a float64 device tensor."""
+def eval_exp_neg(y: torch.Tensor, stream=None, pair=False):
+    """The library's exp(-y) on a float64 device tensor: the friction factors' exponential, or
+    with pair=True the one of the ion-atom pair terms."""
     L = _abi.load()
     y = y.contiguous()
     out = torch.empty_like(y)
-    rc = L.reedmd_eval_exp_neg(_ptr(y), _ptr(out), int(y.numel()), _stream(stream))
+    fn = L.reedmd_eval_exp_neg_pair if pair else L.reedmd_eval_exp_neg
+    rc = fn(_ptr(y), _ptr(out), int(y.numel()), _stream(stream))
     if rc != 0:
         raise ReedmdError(f"reedmd_eval_exp_neg failed ({rc})")
     return out

@@ -46,10 +46,10 @@ __device__ __forceinline__ void zbl_pair_adjoint(double inv_a, double zz, double
     inv_r = rsqrt(r2);
     r = r2 * inv_r;
     const double xs = r * inv_a;
-    const double e0 = exp_neg(kZd0 * xs);
-    const double e1 = exp_neg(kZd1 * xs);
-    const double e2 = exp_neg(kZd2 * xs);
-    const double e3 = exp_neg(kZd3 * xs);
+    const double e0 = exp_neg_pair(kZd0 * xs);
+    const double e1 = exp_neg_pair(kZd1 * xs);
+    const double e2 = exp_neg_pair(kZd2 * xs);
+    const double e3 = exp_neg_pair(kZd3 * xs);
     const double phi = kZc0 * e0 + kZc1 * e1 + kZc2 * e2 + kZc3 * e3;
     const double dphi = -(kZc0 * kZd0 * e0 + kZc1 * kZd1 * e1 + kZc2 * kZd2 * e2 + kZc3 * kZd3 * e3);
     const double d2phi = kZc0 * kZd0 * kZd0 * e0 + kZc1 * kZd1 * kZd1 * e1 + kZc2 * kZd2 * kZd2 * e2 +
@@ -60,7 +60,7 @@ __device__ __forceinline__ void zbl_pair_adjoint(double inv_a, double zz, double
     c = -dVdr * inv_r;
     c_r = zz * ir2 * (3.0 * dphi * inv_a * inv_r - 3.0 * phi * ir2 - d2phi * inv_a * inv_a);
     c_s = zz * d2phi * inv_a * inv_a * inv_s * inv_r;
-    w = wnorm * exp_neg(r * inv_lambda);
+    w = wnorm * exp_neg_pair(r * inv_lambda);
 }
 
 template <int L>

@@ -193,17 +193,17 @@ __device__ __forceinline__ double3 create_atom(uint64_t key, uint64_t seed, int 
 }
 
 // ---------------------------------------------------------------------------
-// exp(-y) for the force kernels, written from the mathematics: y = n ln2 - r
-// with n the nearest integer to y / ln2 (the rounding is done by adding
-// 1.5 * 2^52, whose sum holds n in its low mantissa bits, so no conversion is
-// needed), r reduced with ln 2 split into a double and its remainder (both
-// FMA-exact), |r| <= ln2/2; e^r from the degree-10 polynomial that minimises
-// the largest relative error on that interval (Remez exchange; 3.0e-16, with
-// the constant term held at 1), and the scaling by 2^-n done by ldexp, which
-// rounds gradual underflow correctly.  Valid for finite 0 <= y < 1e9: the
-// force kernels' arguments are distances over positive lengths, bounded by the
-// parking distance of empty slots (see the library's argument checks).
-__device__ __forceinline__ double exp_neg(double y)
+// exp(-y), written from the mathematics: y = n ln2 - r with n the nearest
+// integer to y / ln2 (the rounding is done by adding 1.5 * 2^52, whose sum
+// holds n in its low mantissa bits, so no conversion is needed), r reduced with
+// ln 2 split into a double and its remainder (both FMA-exact), |r| <= ln2/2;
+// e^r from a polynomial that minimises the largest relative error on that
+// interval (Remez exchange, constant term held at 1), and the scaling by 2^-n
+// done by ldexp, which rounds gradual underflow correctly.  Valid for finite
+// 0 <= y < 1e9: the kernels' arguments are distances over positive lengths,
+// bounded by the parking distance of empty slots (see the library's argument
+// checks).
+__device__ __forceinline__ double exp_reduce(double y, double& r)
 {
     constexpr double kLog2e = 1.4426950408889634;
     constexpr double kLn2Hi = 0x1.62e42fefa39efp-1;
@@ -211,8 +211,16 @@ __device__ __forceinline__ double exp_neg(double y)
     constexpr double kRound = 0x1.8p52;
     const double nr = fma(-y, kLog2e, kRound);   // kRound + nearest integer to -y / ln2
     const double n = nr - kRound;
-    double r = fma(-n, kLn2Hi, -y);
+    r = fma(-n, kLn2Hi, -y);
     r = fma(-n, kLn2Lo, r);
+    return nr;
+}
+
+// Degree 10 (relative error 3.0e-16): the friction factors and other scalars.
+__device__ __forceinline__ double exp_neg(double y)
+{
+    double r;
+    const double nr = exp_reduce(y, r);
     double p = 0x1.2a475a7d4ddb2p-22;
     p = fma(p, r, 0x1.730bd57070546p-19);
     p = fma(p, r, 0x1.a017fb6001714p-16);
@@ -223,6 +231,26 @@ __device__ __forceinline__ double exp_neg(double y)
     p = fma(p, r, 0x1.5555555548c99p-3);
     p = fma(p, r, 0x1.000000000004bp-1);
     p = fma(p, r, 0x1.0000000000029p+0);
+    p = fma(p, r, 1.0);
+    return ldexp(p, static_cast<int>(__double2loint(nr)));
+}
+
+// Degree 8 (relative error 1.08e-12, 100 x inside the per-step tolerance of
+// 1e-10): the five exponentials of every ion-atom pair term.  The ZBL sums
+// and the density weight add positive terms only, so the pair term keeps
+// that relative accuracy; two FMAs less per exponential than exp_neg.
+__device__ __forceinline__ double exp_neg_pair(double y)
+{
+    double r;
+    const double nr = exp_reduce(y, r);
+    double p = 0x1.a4275a97cf0cep-16;
+    p = fma(p, r, 0x1.a1c7569b21ff2p-13);
+    p = fma(p, r, 0x1.6c1424101dad7p-10);
+    p = fma(p, r, 0x1.11106aa784cd6p-7);
+    p = fma(p, r, 0x1.55555661fc0a5p-5);
+    p = fma(p, r, 0x1.555555b50647cp-3);
+    p = fma(p, r, 0x1.ffffffff9520fp-2);
+    p = fma(p, r, 0x1.ffffffffc4a24p-1);
     p = fma(p, r, 1.0);
     return ldexp(p, static_cast<int>(__double2loint(nr)));
 }
@@ -254,14 +282,14 @@ __device__ __forceinline__ void zbl_pair(const PC& c, double dx, double dy, doub
     const double r2 = dx * dx + dy * dy + dz * dz;
     const double inv_r = rsqrt_pos(r2);
     const double r = r2 * inv_r;
-    const double e0 = exp_neg(r * c.rate[0]);
-    const double e1 = exp_neg(r * c.rate[1]);
-    const double e2 = exp_neg(r * c.rate[2]);
-    const double e3 = exp_neg(r * c.rate[3]);
+    const double e0 = exp_neg_pair(r * c.rate[0]);
+    const double e1 = exp_neg_pair(r * c.rate[1]);
+    const double e2 = exp_neg_pair(r * c.rate[2]);
+    const double e3 = exp_neg_pair(r * c.rate[3]);
     const double phi = c.amp[0] * e0 + c.amp[1] * e1 + c.amp[2] * e2 + c.amp[3] * e3;
     const double dphi = c.damp[0] * e0 + c.damp[1] * e1 + c.damp[2] * e2 + c.damp[3] * e3;
     coef = fma(phi, inv_r, dphi) * (inv_r * inv_r);
-    ew = exp_neg(r * c.inv_lambda);
+    ew = exp_neg_pair(r * c.inv_lambda);
 }
 
 // FP32 variant of the pair term (force precision option; tolerance 1e-5

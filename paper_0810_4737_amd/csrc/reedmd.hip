@@ -702,10 +702,10 @@ __global__ void sample_kernel(const SamplerArgs S)
     S.key[q] = primary_key(S.seed, id);
 }
 
-__global__ void exp_neg_kernel(const double* y, double* out, long long n)
+__global__ void exp_neg_kernel(const double* y, double* out, long long n, int pair)
 {
     const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i < n) out[i] = exp_neg(y[i]);
+    if (i < n) out[i] = pair ? exp_neg_pair(y[i]) : exp_neg(y[i]);
 }
 
 }  // namespace
@@ -944,15 +944,25 @@ reedmd_status reedmd_grad(reedmd_ctx* ctx, const reedmd_species* species, const 
     return REEDMD_OK;
 }
 
-reedmd_status reedmd_eval_exp_neg(const double* d_y, double* d_out, int64_t n, hipStream_t stream)
+static reedmd_status eval_exp(const double* d_y, double* d_out, int64_t n, int pair, hipStream_t stream)
 {
     if (n < 0 || (n > 0 && (!d_y || !d_out))) return fail(nullptr, REEDMD_EINVAL, "bad arguments");
     if (n == 0) return REEDMD_OK;
     hipLaunchKernelGGL(exp_neg_kernel, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, stream, d_y,
-                       d_out, static_cast<long long>(n));
+                       d_out, static_cast<long long>(n), pair);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(nullptr, REEDMD_EHIP, hipGetErrorString(e));
     return REEDMD_OK;
+}
+
+reedmd_status reedmd_eval_exp_neg(const double* d_y, double* d_out, int64_t n, hipStream_t stream)
+{
+    return eval_exp(d_y, d_out, n, 0, stream);
+}
+
+reedmd_status reedmd_eval_exp_neg_pair(const double* d_y, double* d_out, int64_t n, hipStream_t stream)
+{
+    return eval_exp(d_y, d_out, n, 1, stream);
 }
 
 reedmd_status reedmd_autotune(reedmd_ctx* ctx, const reedmd_species* species, const reedmd_batch* batch,
