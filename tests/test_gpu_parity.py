@@ -155,6 +155,19 @@ def test_empty_batch_and_argument_errors(R, ctx):
         R.run(ctx, ("B",), R.empty_batch(4), rcfg(R, n_bins=0))
     with pytest.raises(R.ReedmdError):
         R.run(ctx, ("B",), R.empty_batch(4), rcfg(R, thresholds=[[10.0, 20.0]], n_clones=1))
+    # recoil options are fluorite-only; unknown modes and precisions are rejected
+    with pytest.raises(R.ReedmdError, match="fluorite"):
+        R.run(ctx, ("B",), R.empty_batch(4), rcfg(R, range_mode=R.RANGE_RADIAL))
+    with pytest.raises(R.ReedmdError, match="fluorite"):
+        R.run(ctx, ("B",), R.empty_batch(4), rcfg(R, vacancy=1))
+    with pytest.raises(R.ReedmdError, match="range_mode"):
+        R.run(ctx, ("B",), R.empty_batch(4), rcfg(R, range_mode=7))
+    with pytest.raises(R.ReedmdError, match="force_precision"):
+        R.run(ctx, ("B",), R.empty_batch(4), rcfg(R, force_precision=3))
+    with pytest.raises(R.ReedmdError, match="start mode"):
+        R.sample_primaries(ctx, R.SamplerConfig(start_mode=5), 0, 4)
+    with pytest.raises(R.ReedmdError, match="direction mode"):
+        R.sample_primaries(ctx, R.SamplerConfig(dir_mode=9), 0, 4)
 
 
 # ----------------------------------------------------------------------------- per step
