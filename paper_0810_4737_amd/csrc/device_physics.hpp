@@ -55,12 +55,12 @@ struct SpeciesConst {
     double dg_rho;        // d g_rho / d k
     double inv_M1sq;      // 1 / M1^2
     // The screened-Coulomb sum with its constants folded per species:
-    //   rate_i = d_i / a,  amp_i = zz c_i,  damp_i = zz c_i d_i / a
+    //   rate_i = log2(e) d_i / a (base-2 rate),  amp_i = zz c_i,  damp_i = zz c_i d_i / a
     double rate[4], amp[4], damp[4];
-    // The same in FP32 for the FP32 pair term, the rates (and 1/lambda) times
-    // log2(e) for the hardware 2^x
+    // The same in FP32 for the FP32 pair term (base-2 rates for the hardware 2^x)
     float rate2f[4], amp_f[4], damp_f[4];
     float lam2f, pad_f;
+    double lam2;          // log2(e) / lambda, the base-2 rate of the density weight
 };
 
 // Pair-term constants of an ion species against the second target species
@@ -68,8 +68,8 @@ struct SpeciesConst {
 // Lindhard-Scharff constants of the two target species (stopping-weighted
 // density, Bragg additivity).
 struct PairConst {
-    double rate[4], amp[4], damp[4];
-    double inv_lambda, wnorm;
+    double rate[4], amp[4], damp[4];   // rate: base 2, as in SpeciesConst
+    double lam2, wnorm;
     float rate2f[4], amp_f[4], damp_f[4];
     float lam2f, pad_f;
 };
@@ -235,29 +235,38 @@ __device__ __forceinline__ double exp_neg(double y)
     return ldexp(p, static_cast<int>(__double2loint(nr)));
 }
 
-// Degree 8 (relative error 1.08e-12, 90 x inside the per-step tolerance of
-// 1e-10): the five exponentials of every ion-atom pair term.  The reduction
-// uses ln 2 rounded to a double in one FMA (its 2.3e-17 error times |n| <= 1075
-// adds at most 2.5e-14); the ZBL sums and the density weight add positive
-// terms only, so the pair term keeps that relative accuracy.  Three FMAs less
-// per exponential than exp_neg.
+// 2^(-r k) for the five exponentials of every ion-atom pair term, with the
+// base-2 rate k = log2(e) / length folded into the species constants: n, the
+// nearest integer to -r k, from one FMA against 1.5 * 2^52, and f = -r k - n in
+// [-1/2, 1/2] from a second FMA (r k never rounds on its own); 2^f from the
+// degree-8 polynomial that minimises the largest relative error (the Remez
+// polynomial of e^x on |x| <= ln2/2, rescaled to 2^f: 1.08e-12), ldexp for the
+// scaling.  With the rounding of k (at most 2^-53 r k), the relative error
+// stays below 1.15e-12, 90 x inside the per-step tolerance of 1e-10; the ZBL
+// sums and the density weight add positive terms only, so the pair term keeps
+// that relative accuracy.  Valid for finite 0 <= r k < 1e9.
+__device__ __forceinline__ double exp2_neg_pair(double r, double k)
+{
+    constexpr double kRound = 0x1.8p52;
+    const double nr = fma(-r, k, kRound);   // kRound + nearest integer to -r k
+    const double n = nr - kRound;
+    const double f = fma(-r, k, -n);
+    double p = 0x1.66348837e364bp-20;
+    p = fma(p, f, 0x1.00ee071f31fb7p-16);
+    p = fma(p, f, 0x1.4306c115f9e23p-13);
+    p = fma(p, f, 0x1.5d872975bfdb7p-10);
+    p = fma(p, f, 0x1.3b2ab7f3b35e8p-7);
+    p = fma(p, f, 0x1.c6b08defc2655p-5);
+    p = fma(p, f, 0x1.ebfbdff7c5a77p-3);
+    p = fma(p, f, 0x1.62e42fef7a78bp-1);
+    p = fma(p, f, 1.0);
+    return ldexp(p, static_cast<int>(__double2loint(nr)));
+}
+
+// exp(-y) with the pair terms' accuracy (the adjoint's pair terms and tests).
 __device__ __forceinline__ double exp_neg_pair(double y)
 {
-    constexpr double kLog2e = 1.4426950408889634;
-    constexpr double kLn2 = 0x1.62e42fefa39efp-1;
-    constexpr double kRound = 0x1.8p52;
-    const double nr = fma(-y, kLog2e, kRound);   // kRound + nearest integer to -y / ln2
-    const double r = fma(-(nr - kRound), kLn2, -y);
-    double p = 0x1.a4275a97cf0cep-16;
-    p = fma(p, r, 0x1.a1c7569b21ff2p-13);
-    p = fma(p, r, 0x1.6c1424101dad7p-10);
-    p = fma(p, r, 0x1.11106aa784cd6p-7);
-    p = fma(p, r, 0x1.55555661fc0a5p-5);
-    p = fma(p, r, 0x1.555555b50647cp-3);
-    p = fma(p, r, 0x1.ffffffff9520fp-2);
-    p = fma(p, r, 0x1.ffffffffc4a24p-1);
-    p = fma(p, r, 1.0);
-    return ldexp(p, static_cast<int>(__double2loint(nr)));
+    return exp2_neg_pair(y, 1.4426950408889634);
 }
 
 // 1/sqrt(x) for finite x > 0: the hardware estimate refined by one
@@ -287,14 +296,14 @@ __device__ __forceinline__ void zbl_pair(const PC& c, double dx, double dy, doub
     const double r2 = dx * dx + dy * dy + dz * dz;
     const double inv_r = rsqrt_pos(r2);
     const double r = r2 * inv_r;
-    const double e0 = exp_neg_pair(r * c.rate[0]);
-    const double e1 = exp_neg_pair(r * c.rate[1]);
-    const double e2 = exp_neg_pair(r * c.rate[2]);
-    const double e3 = exp_neg_pair(r * c.rate[3]);
+    const double e0 = exp2_neg_pair(r, c.rate[0]);
+    const double e1 = exp2_neg_pair(r, c.rate[1]);
+    const double e2 = exp2_neg_pair(r, c.rate[2]);
+    const double e3 = exp2_neg_pair(r, c.rate[3]);
     const double phi = c.amp[0] * e0 + c.amp[1] * e1 + c.amp[2] * e2 + c.amp[3] * e3;
     const double dphi = c.damp[0] * e0 + c.damp[1] * e1 + c.damp[2] * e2 + c.damp[3] * e3;
     coef = fma(phi, inv_r, dphi) * (inv_r * inv_r);
-    ew = exp_neg_pair(r * c.inv_lambda);
+    ew = exp2_neg_pair(r, c.lam2);
 }
 
 // FP32 variant of the pair term (force precision option; tolerance 1e-5

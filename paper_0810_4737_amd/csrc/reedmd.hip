@@ -111,7 +111,8 @@ void prepare_species(const reedmd_ctx* ctx, const reedmd_species* sp, KernelArgs
         if (i >= sp->n_species) {
             c = SpeciesConst{1.0, 0.5, 1.0, 0.0, 1.0, 0.0, 0.0, 0.0, 0.0, 0.0, 1.0};
             c2 = PairConst{};
-            c2.inv_lambda = 1.0;
+            c2.lam2 = 1.0;
+            c.lam2 = 1.0;
             continue;
         }
         const double Z1 = sp->Z1[i], M1 = sp->M1[i];
@@ -126,31 +127,32 @@ void prepare_species(const reedmd_ctx* ctx, const reedmd_species* sp, KernelArgs
         c.inv_lambda = t0.inv_lambda;
         c.wnorm = t0.wnorm;
         for (int j = 0; j < 4; ++j) {
-            c.rate[j] = zd[j] * c.inv_a;
+            c.rate[j] = zd[j] * c.inv_a * M_LOG2E;
             c.amp[j] = c.zz * zc[j];
             c.damp[j] = c.zz * zc[j] * zd[j] * c.inv_a;
-            c.rate2f[j] = static_cast<float>(c.rate[j] * M_LOG2E);
+            c.rate2f[j] = static_cast<float>(c.rate[j]);
             c.amp_f[j] = static_cast<float>(c.amp[j]);
             c.damp_f[j] = static_cast<float>(c.damp[j]);
         }
-        c.lam2f = static_cast<float>(c.inv_lambda * M_LOG2E);
-        min_rate = std::min(min_rate, std::min(c.rate[3], c.inv_lambda));
+        c.lam2 = c.inv_lambda * M_LOG2E;
+        c.lam2f = static_cast<float>(c.lam2);
+        min_rate = std::min(min_rate, std::min(zd[3] * c.inv_a, c.inv_lambda));
         c2 = PairConst{};
-        c2.inv_lambda = 1.0;
+        c2.lam2 = 1.0;
         if (fl) {
             const Target t1 = target(Z1, M1, ctx->lat.Z2b);
-            c2.inv_lambda = t1.inv_lambda;
+            c2.lam2 = t1.inv_lambda * M_LOG2E;
             c2.wnorm = t1.wnorm * (t1.kL / t0.kL);
             for (int j = 0; j < 4; ++j) {
-                c2.rate[j] = zd[j] * t1.inv_a;
+                c2.rate[j] = zd[j] * t1.inv_a * M_LOG2E;
                 c2.amp[j] = t1.zz * zc[j];
                 c2.damp[j] = t1.zz * zc[j] * zd[j] * t1.inv_a;
-                c2.rate2f[j] = static_cast<float>(c2.rate[j] * M_LOG2E);
+                c2.rate2f[j] = static_cast<float>(c2.rate[j]);
                 c2.amp_f[j] = static_cast<float>(c2.amp[j]);
                 c2.damp_f[j] = static_cast<float>(c2.damp[j]);
             }
-            c2.lam2f = static_cast<float>(c2.inv_lambda * M_LOG2E);
-            min_rate = std::min(min_rate, std::min(c2.rate[3], c2.inv_lambda));
+            c2.lam2f = static_cast<float>(c2.lam2);
+            min_rate = std::min(min_rate, std::min(zd[3] * t1.inv_a, t1.inv_lambda));
         }
         c.g_const = 0.0;
         c.g_rho = 0.0;

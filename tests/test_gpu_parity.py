@@ -103,9 +103,9 @@ def assert_records_close(got, ref, rtol=1e-10, what=""):
 def test_library_exponential_is_accurate(R, pair):
     """The kernels' exp(-y) (Cody-Waite + minimax polynomial) against numpy's exp over the
     argument range of the force terms and the gradual-underflow tail: the friction factors'
-    exponential to <= 4 ulp; the pair terms' degree-8 one to its minimax bound 1.08e-12 plus
-    the one-FMA reduction (<= 2.5e-14) and rounding (<= 1.15e-12), 90 x inside the per-step
-    tolerance of 1e-10."""
+    exponential to <= 4 ulp; the pair terms' base-2 one (degree 8) to its minimax bound
+    1.08e-12 plus the rounding of the base-2 rate and of the result (<= 1.15e-12), 90 x inside
+    the per-step tolerance of 1e-10."""
     y = np.concatenate([np.linspace(0.0, 50.0, 200001), np.geomspace(1e-12, 700.0, 100001),
                         np.linspace(700.0, 745.0, 1001)])
     got = R.eval_exp_neg(torch.as_tensor(y, device="cuda"), pair=pair).cpu().numpy()
