@@ -77,6 +77,8 @@ def parse():
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 pair-term variant leg")
     ap.add_argument("--no-uo2", action="store_true", help="skip the 85 keV U recoil in UO2 leg")
     ap.add_argument("--uo2-n", type=int, default=0, help="primaries of the UO2 leg (default: the workload's 5,120)")
+    ap.add_argument("--pipelined", type=int, default=0,
+                    help="also time this many batches back to back on two streams and contexts (tail overlap)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (HBM counter calibration)")
     return ap.parse_args()
@@ -158,6 +160,58 @@ def profile_accuracy(R, torch, np, ctx, w, sampler, n, cfg, reed_log, t_reed, ta
     out["nosplit_s"] = t_ns
     out["method"] = "32 sub-batches (primary id mod 32), batch means; FOM = 1/(T s^2) with the launch wall time"
     return out
+
+
+def pipelined_leg(R, torch, w, sampler, n, cfg, k_steps, species):
+    """Batches back to back on two streams, each with its own context (clone queue, stacks,
+    graphs), histogram and statistics, with no host synchronisation between them: the next
+    batch's workgroups start on the compute units that the previous batch's tail leaves
+    idle.  The ledger of each context's accumulated batches is checked afterwards."""
+    ctxs = [R.Context(), R.Context()]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    hists = [torch.zeros(w["n_bins"], dtype=torch.float64, device="cuda") for _ in range(2)]
+    stats = [R.new_stats() for _ in range(2)]
+    # one warm batch per context allocates its scratch and builds its graph; every batch is
+    # allocated (zero-filled), sampled and run with its own stream current, so the three are
+    # ordered on that stream
+    for j in range(2):
+        with torch.cuda.stream(streams[j]):
+            b = R.sample_primaries(ctxs[j], sampler, 0, n, stream=streams[j])
+            R.run(ctxs[j], species, b, cfg, hist=hists[j], stats=stats[j], stream=streams[j])
+    torch.cuda.synchronize()
+    for j in range(2):
+        hists[j].zero_()
+        stats[j].zero_()
+    torch.cuda.synchronize()
+    # every batch's arrays stay referenced until the end, so no later allocation can reuse
+    # them while a persistent kernel still claims primaries from them, whatever stream it is on
+    keep = []
+    t0 = time.perf_counter()
+    for k in range(k_steps):
+        j = k % 2
+        with torch.cuda.stream(streams[j]):
+            b = R.sample_primaries(ctxs[j], sampler, 0, n, stream=streams[j])
+            keep.append(b)
+            R.run(ctxs[j], species, b, cfg, hist=hists[j], stats=stats[j], stream=streams[j])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    pairs = 0
+    per_ctx = []
+    for j in range(2):
+        st = R.parse_stats(stats[j])
+        per_ctx.append({k: st[k] for k in ("primaries", "finished", "clones", "pair_evals", "n_cancelled",
+                                            "w_quarantined", "error_flags")})
+        pairs += st["pair_evals"]
+        batches = (k_steps + 1 - j) // 2
+        tot = float(hists[j].sum().item()) + st["w_underflow"] + st["w_overflow"] + st["w_backscattered"] + \
+            st["w_quarantined"] + st["w_cancelled"]
+        assert tot == float(n * batches), ("weight ledger broken", j, tot)
+        assert st["primaries"] == n * batches and st["error_flags"] == 0, ("batches incomplete", j, st)
+    for c in ctxs:
+        c.close()
+    return dict(batches=k_steps, ms_per_batch=1e3 * wall / k_steps, force_evals_per_s=pairs / wall,
+                per_context=per_ctx,
+                method="two streams and contexts, batches alternate, no host synchronisation between them")
 
 
 def fp32_leg(R, ctx, torch, w, sampler, n, base, stream, hist, stats, form, lanes=0, waves=0):
@@ -485,6 +539,8 @@ def main():
                               tracks=sr["finished"], last_depths=[round(x, 1) for x in depths[-1, 0].tolist()])
     if reed_log is not None and cfg.thresholds is not None:
         out["profile_accuracy"] = profile_accuracy(R, torch, np, ctx, w, sampler, n, cfg, reed_log, t_w, tail_depth)
+    if args.pipelined > 0:
+        out["pipelined"] = pipelined_leg(R, torch, w, sampler, n, cfg, args.pipelined, w["species"])
     if not args.no_fp32:
         out["fp32_pair_variant"] = fp32_leg(R, ctx, torch, w, sampler, n, base, stream, hist, stats, args.form,
                                             args.lanes, args.waves)

@@ -7,6 +7,7 @@ is missing, importing the binding's functions raises: there is no CPU path.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes as C
 import math
 from dataclasses import dataclass, field
@@ -42,6 +43,12 @@ def _check(rc, ctx=None):
 def _stream(stream=None):
     s = stream if stream is not None else torch.cuda.current_stream()
     return C.c_void_p(s.cuda_stream)
+
+
+def _on(stream):
+    """Makes `stream` current while a call allocates its outputs, so that their zero fills are
+    ordered before the launches on that stream (torch fills on the current stream)."""
+    return torch.cuda.stream(stream) if stream is not None else contextlib.nullcontext()
 
 
 def _ptr(t):
@@ -192,7 +199,8 @@ def batch_from_numpy(d, device="cuda"):
 
 def sample_primaries(ctx: Context, sampler: SamplerConfig, seed: int, n: int, id0: int = 0,
                      device="cuda", stream=None):
-    batch = empty_batch(n, device)
+    with _on(stream):
+        batch = empty_batch(n, device)
     b = _batch_struct(batch, id0)
     s = sampler.struct()
     ctx.check(ctx._lib.reedmd_sample_primaries(ctx.handle, C.byref(s), int(seed), C.byref(b), _stream(stream)))
@@ -224,15 +232,16 @@ def run(ctx: Context, species, batch, cfg: RunConfig, hist=None, stats=None, id0
     dev = batch["energy"].device
     keep = []
     p = cfg.struct(dev, keep)
-    if hist is None:
-        hist = torch.zeros(cfg.n_bins, dtype=torch.float64, device=dev)
-    if stats is None:
-        stats = new_stats(dev)
     log = None
-    if log_cap > 0:
-        log = torch.zeros((log_cap, 5), dtype=torch.int64, device=dev)
-        p.track_log = log.data_ptr()
-        p.track_log_cap = log_cap
+    with _on(stream):
+        if hist is None:
+            hist = torch.zeros(cfg.n_bins, dtype=torch.float64, device=dev)
+        if stats is None:
+            stats = new_stats(dev)
+        if log_cap > 0:
+            log = torch.zeros((log_cap, 5), dtype=torch.int64, device=dev)
+            p.track_log = log.data_ptr()
+            p.track_log_cap = log_cap
     if cancel is not None:
         p.cancel = cancel.data_ptr()
     sp = species_table(species) if not isinstance(species, _abi.Species) else species
@@ -252,22 +261,24 @@ def run_refined(ctx: Context, species, batch, cfg: RunConfig, n_epochs: int, pro
     dev = batch["energy"].device
     keep = []
     p = cfg.struct(dev, keep)
-    if hist is None:
-        hist = torch.zeros(cfg.n_bins, dtype=torch.float64, device=dev)
-    if stats is None:
-        stats = new_stats(dev)
     log = None
-    if log_cap > 0:
-        log = torch.zeros((log_cap, 5), dtype=torch.int64, device=dev)
-        p.track_log = log.data_ptr()
-        p.track_log_cap = log_cap
+    with _on(stream):
+        if hist is None:
+            hist = torch.zeros(cfg.n_bins, dtype=torch.float64, device=dev)
+        if stats is None:
+            stats = new_stats(dev)
+        if log_cap > 0:
+            log = torch.zeros((log_cap, 5), dtype=torch.int64, device=dev)
+            p.track_log = log.data_ptr()
+            p.track_log_cap = log_cap
     pr = np.ascontiguousarray(np.asarray(probs, dtype=np.float64))
     rf = _abi.Refine()
     rf.n_epochs = int(n_epochs)
     rf.probs = pr.ctypes.data_as(C.POINTER(C.c_double))
     rf.min_gap = float(min_gap)
-    depths = torch.zeros((max(1, min(int(n_epochs), int(batch["energy"].shape[0]))), p.n_tables, p.n_thresh),
-                         dtype=torch.float64, device=dev)
+    with _on(stream):
+        depths = torch.zeros((max(1, min(int(n_epochs), int(batch["energy"].shape[0]))), p.n_tables,
+                              p.n_thresh), dtype=torch.float64, device=dev)
     sp = species_table(species) if not isinstance(species, _abi.Species) else species
     b = _batch_struct(batch, id0)
     ctx.check(ctx._lib.reedmd_run_refined(ctx.handle, C.byref(sp), C.byref(b), C.byref(p), C.byref(rf),
@@ -289,7 +300,8 @@ def track_init(ctx: Context, species, batch, cfg: RunConfig, id0=0, stream=None)
     keep = []
     p = cfg.struct(dev, keep)
     n = int(batch["energy"].shape[0])
-    rec = torch.zeros((n, ctx.record_words), dtype=torch.float64, device=dev)
+    with _on(stream):
+        rec = torch.zeros((n, ctx.record_words), dtype=torch.float64, device=dev)
     sp = species_table(species) if not isinstance(species, _abi.Species) else species
     b = _batch_struct(batch, id0)
     ctx.check(ctx._lib.reedmd_track_init(ctx.handle, C.byref(sp), C.byref(b), C.byref(p), _ptr(rec),
@@ -340,8 +352,9 @@ def grad(ctx: Context, species, batch, cfg: RunConfig, k: float, s: float, per_t
     res = (C.c_double * 4)()
     out = None
     if per_track:
-        out = torch.zeros((int(batch["energy"].shape[0]), 5), dtype=torch.float64,
-                          device=batch["energy"].device)
+        with _on(stream):
+            out = torch.zeros((int(batch["energy"].shape[0]), 5), dtype=torch.float64,
+                              device=batch["energy"].device)
     ctx.check(ctx._lib.reedmd_grad(ctx.handle, C.byref(sp), C.byref(b), C.byref(p), float(k), float(s),
                                    _ptr(out), res, _stream(stream)))
     d = dict(mean=res[0], dk=res[1], ds=res[2], count=int(res[3]))
@@ -371,8 +384,9 @@ def eval_exp_neg(y: torch.Tensor, stream=None, pair=False):
     """The library's exp(-y) on a float64 device tensor: the friction factors' exponential, or
     with pair=True the one of the ion-atom pair terms."""
     L = _abi.load()
-    y = y.contiguous()
-    out = torch.empty_like(y)
+    with _on(stream):
+        y = y.contiguous()
+        out = torch.empty_like(y)
     fn = L.reedmd_eval_exp_neg_pair if pair else L.reedmd_eval_exp_neg
     rc = fn(_ptr(y), _ptr(out), int(y.numel()), _stream(stream))
     if rc != 0:
