@@ -2,13 +2,21 @@
 // respect to the electronic-stopping scale k and the screening-length scale s.
 //
 // One wavefront (64 lanes, the same slot layout as the track kernel) per
-// track.  Forward: the track runs to termination with the ordinary step and a
-// checkpoint of its full state every 64 steps.  Reverse: segment by segment
-// from the last, the segment is recomputed from its checkpoint (bitwise the
-// same trajectory: the stored records carry the step-size maxima) with every
-// state kept, then the adjoint of each step is applied from the last step of
-// the segment to the first.  Adjoint state per domain atom (position,
-// velocity, force) lives in VGPRs; the ion's adjoints are wavefront-uniform.
+// track.  Forward: the track runs to termination with the ordinary step, a
+// checkpoint of its full state every 64 steps, and a log of each step's size
+// (dt and which term of the minimum set it) and of the ion's position and
+// velocity before it.  Reverse: from the final state, step by step, the state
+// before a step is rebuilt from the state after it: the ion from the log, the
+// domain atoms by running their part of the step backwards (they feel only the
+// ion, so the inverse is explicit: undo the second kick and the drift, evaluate
+// the pair terms at the rebuilt positions, undo the first kick), and the
+// adjoint of the step is applied in the same pass over the slots.  The state is re-anchored to the exact checkpoint at every
+// segment boundary, so reconstruction errors never grow over more than 64
+// steps.  A step that moved the domain dropped atoms the reverse cannot
+// rebuild: its starting state is recomputed forward from the segment's
+// checkpoint instead.  Adjoint state per domain atom (position, velocity,
+// force) and the pair terms of the current state live in VGPRs; the ion's
+// adjoints are wavefront-uniform.
 //
 // Per step, forward (see track_step):
 //   dt = min(dt_max, dx vmax^-1, sqrt(2 dx) amax^-1/2); h1 = dt/2M1; h2 = dt/2M2
@@ -259,6 +267,242 @@ __device__ __forceinline__ void reverse_step(AdjIon& ai, AdjAtoms<L>& aa, const 
     }
 }
 
+// The adjoint of a step that moved the domain, from the records of its two
+// states.  Rarely taken and kept out of line, so that its registers do not add
+// to those of the register-resident reverse step; the kernel arguments it
+// reads are passed by value.
+template <int L>
+__device__ __noinline__ void reverse_step_moved(AdjIon* ai, AdjAtoms<L>* aa, const SpeciesConst* c, const double* rn,
+                                                const double* rn1, int sl, double* sb_lane, double dt_max,
+                                                double dx_max, double half_inv_M2, double inv_M2sq, double inv_s)
+{
+    KernelArgs A;
+    A.dt_max = dt_max;
+    A.dx_max = dx_max;
+    A.half_inv_M2 = half_inv_M2;
+    A.inv_M2sq = inv_M2sq;
+    A.inv_s = inv_s;
+    reverse_step<L>(*ai, *aa, A, *c, rn, rn1, sl, *sb_lane);
+}
+
+// Pair terms of the state held in the registers, per register slot: the
+// coefficient c = -V'(r)/r, its derivatives dc/dr and dc/ds, the density
+// weight (with its normalisation) and 1/r.  Zero for empty slots.
+template <int L>
+struct PairState {
+    static constexpr int SL = TrackRegs<L>::SL;
+    double c[SL], cr[SL], cs[SL], w[SL], ir[SL];
+};
+
+template <int L>
+__device__ __forceinline__ void pair_state(const TrackRegs<L>& t, const KernelArgs& A, const SpeciesConst& c,
+                                           PairState<L>& P)
+{
+#pragma unroll
+    for (int i = 0; i < TrackRegs<L>::SL; ++i) {
+        P.c[i] = 0.0; P.cr[i] = 0.0; P.cs[i] = 0.0; P.w[i] = 0.0; P.ir[i] = 0.0;
+        if (!((t.exist >> i) & 1u)) continue;
+        const double dx = t.x - t.ax[i], dy = t.y - t.ay[i], dz = t.z - t.az[i];
+        double r;
+        zbl_pair_adjoint(c.inv_a, c.zz, A.inv_s, c.inv_lambda, c.wnorm, dx * dx + dy * dy + dz * dz, r, P.ir[i],
+                         P.c[i], P.cr[i], P.cs[i], P.w[i]);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+// Adjoint of one step n that did not move the domain, with the state
+// reconstructed in the registers.  On entry t holds S_{n+1} and P its pair
+// terms, and the adjoint arrays hold the adjoint of S_{n+1}; on exit t holds
+// S_n (reconstructed), P the pair terms of S_n, and the adjoints those of S_n.
+// dt and code are the step's logged size (StepInfo).
+template <int L>
+__device__ __forceinline__ void reverse_step_regs(AdjIon& ai, AdjAtoms<L>& aa, PairState<L>& P, TrackRegs<L>& t,
+                                                  const KernelArgs& A, const SpeciesConst& c, const double* lgn,
+                                                  int sl, double& sb_lane)
+{
+    constexpr int SL = TrackRegs<L>::SL;
+    constexpr int FS = TrackRegs<L>::FS;
+    const double dt = lgn[0];
+    const int code = static_cast<int>(reinterpret_cast<const long long*>(lgn)[1]);
+    const double h1 = dt * c.half_inv_M1;
+    const double h2 = dt * A.half_inv_M2;
+    // ---- ion of S_{n+1}; the ion of S_n is the logged one (the chaotic part of the
+    //      state is never run backwards)
+    const double x1[3] = {t.x, t.y, t.z};
+    const double Fp[3] = {t.Fx, t.Fy, t.Fz};
+    const double rhop = t.rho;
+    const double g2 = c.g_const + c.g_rho * rhop;
+    const double fr2 = exp_neg(g2 * h1);
+    const double x[3] = {lgn[2], lgn[3], lgn[4]};
+    const double v[3] = {lgn[5], lgn[6], lgn[7]};
+    const double vp[3] = {t.vx, t.vy, t.vz};
+    double q[3];
+    for (int k = 0; k < 3; ++k) q[k] = vp[k] / fr2;
+    // ---- adjoint of v' = q fr2
+    double qb[3], v1b[3], Fpb[3];
+    double fr2b = 0.0, h1b = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        qb[k] = ai.vb[k] * fr2;
+        fr2b += ai.vb[k] * q[k];
+        v1b[k] = qb[k];
+        Fpb[k] = ai.Fb[k] + qb[k] * h1;
+        h1b += qb[k] * Fp[k];
+    }
+    const double g2b = -fr2b * fr2 * h1;
+    h1b += -fr2b * fr2 * g2;
+    ai.kb += g2b * (c.dg_const + c.dg_rho * rhop);
+    const double rhopb = ai.rhob + g2b * c.g_rho;
+
+    // ---- per slot: reconstruct the atom of S_n and its pair term; adjoint of the
+    //      second kick, the pair term of S_{n+1}, the drift and the first kick
+    double x1b_l[3] = {0.0, 0.0, 0.0}, F_l[3] = {0.0, 0.0, 0.0};
+    double dtb_l = 0.0, h2b_l = 0.0, rho_l = 0.0, vm_l = 0.0, fm_l = 0.0;
+    double v2s[SL], f2s[SL];   // the slots' |V|^2 and |f|^2 as maximised (the argmax is found by equality)
+#pragma unroll
+    for (int i = 0; i < SL; ++i) {
+        double nXb[3] = {0.0, 0.0, 0.0}, nVb[3] = {0.0, 0.0, 0.0}, nfb[3] = {0.0, 0.0, 0.0};
+        v2s[i] = -1.0;
+        f2s[i] = -1.0;
+        if ((t.exist >> i) & 1u) {
+            double* f = t.fl + (sl + L * i);
+            const double Y[3] = {t.ax[i], t.ay[i], t.az[i]};
+            const double Vp[3] = {t.avx[i], t.avy[i], t.avz[i]};
+            const double fp[3] = {f[0], f[FS], f[2 * FS]};
+            double U[3], X[3], dn[3];
+            for (int k = 0; k < 3; ++k) {
+                U[k] = Vp[k] - fp[k] * h2;
+                X[k] = Y[k] - U[k] * dt;
+                dn[k] = x[k] - X[k];
+            }
+            double rn, irn, cn, crn, csn, wn;
+            zbl_pair_adjoint(c.inv_a, c.zz, A.inv_s, c.inv_lambda, c.wnorm, dn[0] * dn[0] + dn[1] * dn[1] + dn[2] * dn[2],
+                             rn, irn, cn, crn, csn, wn);
+            double fn[3], Vn[3];
+            for (int k = 0; k < 3; ++k) {
+                fn[k] = -cn * dn[k];
+                Vn[k] = U[k] - fn[k] * h2;
+                F_l[k] += cn * dn[k];
+            }
+            rho_l += wn;
+            v2s[i] = Vn[0] * Vn[0] + Vn[1] * Vn[1] + Vn[2] * Vn[2];
+            f2s[i] = fn[0] * fn[0] + fn[1] * fn[1] + fn[2] * fn[2];
+            vm_l = fmax(vm_l, v2s[i]);
+            fm_l = fmax(fm_l, f2s[i]);
+
+            double Ub[3], G[3], d[3], cb = 0.0;
+            for (int k = 0; k < 3; ++k) {
+                Ub[k] = aa.Vb[k][i];
+                h2b_l += aa.Vb[k][i] * fp[k];
+                d[k] = x1[k] - Y[k];
+                G[k] = Fpb[k] - (aa.fb[k][i] + aa.Vb[k][i] * h2);
+                cb += G[k] * d[k];
+            }
+            const double rb = cb * P.cr[i] - rhopb * P.w[i] * c.inv_lambda;
+            sb_lane += cb * P.cs[i];
+            for (int k = 0; k < 3; ++k) {
+                const double db = P.c[i] * G[k] + rb * d[k] * P.ir[i];
+                x1b_l[k] += db;
+                const double Yb = aa.Xb[k][i] - db;
+                nXb[k] = Yb;
+                Ub[k] += Yb * dt;
+                dtb_l += Yb * U[k];
+                nVb[k] = Ub[k];
+                nfb[k] = Ub[k] * h2;
+                h2b_l += Ub[k] * fn[k];
+            }
+            t.ax[i] = X[0]; t.ay[i] = X[1]; t.az[i] = X[2];
+            t.avx[i] = Vn[0]; t.avy[i] = Vn[1]; t.avz[i] = Vn[2];
+            f[0] = fn[0]; f[FS] = fn[1]; f[2 * FS] = fn[2];
+            P.c[i] = cn; P.cr[i] = crn; P.cs[i] = csn; P.w[i] = wn; P.ir[i] = irn;
+        }
+        for (int k = 0; k < 3; ++k) {
+            aa.Xb[k][i] = nXb[k];
+            aa.Vb[k][i] = nVb[k];
+            aa.fb[k][i] = nfb[k];
+        }
+        // one slot at a time: interleaving the slots' pair terms costs more registers than it hides
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    double F[3], x1b[3];
+    for (int k = 0; k < 3; ++k) {
+        F[k] = SegReduce<L>::sum(F_l[k]);
+        x1b[k] = ai.xb[k] + SegReduce<L>::sum(x1b_l[k]);
+    }
+    const double rho = SegReduce<L>::sum(rho_l);
+    const double vm = SegReduce<L>::max(vm_l);
+    const double fm = SegReduce<L>::max(fm_l);
+    double dtb = SegReduce<L>::sum(dtb_l);
+    const double h2b = SegReduce<L>::sum(h2b_l);
+
+    // ---- first friction half and kick of the step
+    const double g1 = c.g_const + c.g_rho * rho;
+    const double fr1 = exp_neg(g1 * h1);
+    double v1[3];
+    for (int k = 0; k < 3; ++k) v1[k] = v[k] * fr1 + F[k] * h1;
+
+    // ---- adjoint of x1 = x + v1 dt, v1 = v fr1 + F h1, fr1 = exp(-g1 h1)
+    double fr1b = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        v1b[k] += x1b[k] * dt;
+        dtb += x1b[k] * v1[k];
+        ai.xb[k] = x1b[k];
+        ai.vb[k] = v1b[k] * fr1;
+        fr1b += v1b[k] * v[k];
+        ai.Fb[k] = v1b[k] * h1;
+        h1b += v1b[k] * F[k];
+    }
+    const double g1b = -fr1b * fr1 * h1;
+    h1b += -fr1b * fr1 * g1;
+    ai.kb += g1b * (c.dg_const + c.dg_rho * rho);
+    ai.rhob = g1b * c.g_rho;
+    dtb += h1b * c.half_inv_M1 + h2b * A.half_inv_M2;
+
+    t.x = x[0]; t.y = x[1]; t.z = x[2];
+    t.vx = v[0]; t.vy = v[1]; t.vz = v[2];
+    t.Fx = F[0]; t.Fy = F[1]; t.Fz = F[2];
+    t.rho = rho;
+    t.vmax2a = vm;
+    t.amax2a = fm * A.inv_M2sq;
+
+    // ---- the active term of the step-size minimum and its maximising particle
+    const int branch = code & 3;
+    if (branch == 1) {
+        const bool ion = (code & 4) != 0;
+        const double v2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+        const double vmax2b = -0.5 * dtb * dt / (ion ? v2 : vm);
+        if (ion) {
+            for (int k = 0; k < 3; ++k) ai.vb[k] += 2.0 * vmax2b * v[k];
+        } else {
+#pragma unroll
+            for (int i = 0; i < SL; ++i) {
+                if (v2s[i] == vm) {
+                    aa.Vb[0][i] += 2.0 * vmax2b * t.avx[i];
+                    aa.Vb[1][i] += 2.0 * vmax2b * t.avy[i];
+                    aa.Vb[2][i] += 2.0 * vmax2b * t.avz[i];
+                }
+            }
+        }
+    } else if (branch == 2) {
+        const bool ion = (code & 8) != 0;
+        const double f2 = F[0] * F[0] + F[1] * F[1] + F[2] * F[2];
+        const double amax2b = -0.25 * dtb * dt / (ion ? f2 * c.inv_M1sq : fm * A.inv_M2sq);
+        if (ion) {
+            for (int k = 0; k < 3; ++k) ai.Fb[k] += 2.0 * amax2b * F[k] * c.inv_M1sq;
+        } else {
+#pragma unroll
+            for (int i = 0; i < SL; ++i) {
+                if (f2s[i] == fm) {
+                    const double* f = t.fl + (sl + L * i);
+                    const double fx = f[0], fy = f[FS], fz = f[2 * FS];
+                    aa.fb[0][i] += 2.0 * amax2b * fx * A.inv_M2sq;
+                    aa.fb[1][i] += 2.0 * amax2b * fy * A.inv_M2sq;
+                    aa.fb[2][i] += 2.0 * amax2b * fz * A.inv_M2sq;
+                }
+            }
+        }
+    }
+}
+
 template <int L>
 __device__ __forceinline__ void stash_adjoint(const AdjAtoms<L>& aa, double* buf, int sl)
 {
@@ -312,8 +556,9 @@ __global__ void __launch_bounds__(64, REEDMD_GRAD_WAVES_PER_SIMD) grad_kernel(co
     const long long q = A.q0 + local;
     if (q >= A.q_end) return;
     double* ck = A.ckpt + static_cast<size_t>(local) * A.ckpt_cap * kRecWords;
-    double* sbuf = A.segbuf + static_cast<size_t>(local) * 65 * kRecWords;
+    double* sbuf = A.segbuf + static_cast<size_t>(local) * 2 * kRecWords;
     double* abuf = A.adjbuf + static_cast<size_t>(local) * kRecWords;
+    double* lg = A.steplog + static_cast<size_t>(local) * A.ckpt_cap * 512;
     double* out = A.gout + static_cast<size_t>(q) * 5;
 
     TrackRegs<L> t;
@@ -328,10 +573,23 @@ __global__ void __launch_bounds__(64, REEDMD_GRAD_WAVES_PER_SIMD) grad_kernel(co
     track_step<L>(t, A, sp, sl, true, ke0, z0);
     store_record<L>(t, ck, sl);
 
-    // ---- forward with a checkpoint every 64 steps
+    // ---- forward with a checkpoint every 64 steps and the log of step sizes
+    //      and the ion of the state it starts from (steps < ckpt_cap * 64: the loop
+    //      ends at the checkpoint capacity)
     int st = REEDMD_ACTIVE;
     for (;;) {
-        track_step<L>(t, A, sp, sl, false, ke0, z0);
+        const long long n = t.steps;
+        const int ocx = t.cx, ocy = t.cy, ocz = t.cz;
+        const double ion[6] = {t.x, t.y, t.z, t.vx, t.vy, t.vz};
+        StepInfo si;
+        track_step<L>(t, A, sp, sl, false, ke0, z0, &si);
+        if (sl == 0) {
+            const bool moved = t.cx != ocx || t.cy != ocy || t.cz != ocz;
+            double* e = lg + 8 * n;
+            e[0] = si.dt;
+            reinterpret_cast<long long*>(e)[1] = si.code | (moved ? 16 : 0);
+            for (int k = 0; k < 6; ++k) e[2 + k] = ion[k];
+        }
         st = track_events<L>(t, A, sp, ke0, z0);
         if (st != REEDMD_ACTIVE) break;
         if ((t.steps & 63) == 0) {
@@ -374,27 +632,51 @@ __global__ void __launch_bounds__(64, REEDMD_GRAD_WAVES_PER_SIMD) grad_kernel(co
         for (int k = 0; k < 3; ++k) { aa.Xb[k][i] = 0.0; aa.Vb[k][i] = 0.0; aa.fb[k][i] = 0.0; }
     double sb_lane = 0.0;
 
-    // ---- reverse, segment by segment
+    // ---- reverse, step by step from the final state (t holds S_N)
+    __threadfence();   // the step log written by lane 0 is read by every lane
+    PairState<L> P;
+    double ke0d, z0d;
     for (long long seg = (N - 1) >> 6; seg >= 0; --seg) {
         const long long start = seg << 6;
         const long long end = (start + 64 < N) ? start + 64 : N;
-        stash_adjoint<L>(aa, abuf, sl);
-        load_record<L>(t, ck + static_cast<size_t>(seg) * kRecWords, sl, A);
-        store_record<L>(t, sbuf, sl);
-        for (long long n = start; n < end; ++n) {
-            track_step<L>(t, A, sp, sl, false, ke0, z0);
-            store_record<L>(t, sbuf + static_cast<size_t>(n + 1 - start) * kRecWords, sl);
-        }
-        __threadfence();   // the records just written are read back by every lane
-        unstash_adjoint<L>(aa, abuf, sl);
+        // re-anchor to the exact state at the end of the segment
+        if (end != N) load_record<L>(t, ck + static_cast<size_t>(end >> 6) * kRecWords, sl, A);
+        pair_state<L>(t, A, c, P);
         for (long long n = end - 1; n >= start; --n) {
-            const double* rn = sbuf + static_cast<size_t>(n - start) * kRecWords;
-            const double* rn1 = rn + kRecWords;
-            reverse_step<L>(ai, aa, A, c, rn, rn1, sl, sb_lane);
+            const double* lgn = lg + 8 * n;
+            if (reinterpret_cast<const long long*>(lgn)[1] & 16) {
+                // the step moved the domain: recompute S_n from the segment's checkpoint
+                store_record<L>(t, sbuf + kRecWords, sl);
+                stash_adjoint<L>(aa, abuf, sl);
+                load_record<L>(t, ck + static_cast<size_t>(seg) * kRecWords, sl, A);
+                for (long long m = start; m < n; ++m) track_step<L>(t, A, sp, sl, false, ke0d, z0d);
+                store_record<L>(t, sbuf, sl);
+                __threadfence();   // the records just written are read back by every lane
+                unstash_adjoint<L>(aa, abuf, sl);
+                {
+                    AdjIon ai2 = ai;
+                    AdjAtoms<L> aa2 = aa;
+                    double sb2 = sb_lane;
+                    reverse_step_moved<L>(&ai2, &aa2, &c, sbuf, sbuf + kRecWords, sl, &sb2, A.dt_max, A.dx_max,
+                                          A.half_inv_M2, A.inv_M2sq, A.inv_s);
+                    ai = ai2;
+                    aa = aa2;
+                    sb_lane = sb2;
+                }
+                // S_n is taken back from its record (so that neither it nor the pair terms
+                // are held in registers through the recompute and the record-based step),
+                // also at the segment's first step, where it is not needed
+                load_record<L>(t, sbuf, sl, A);
+                pair_state<L>(t, A, c, P);
+            } else {
+                reverse_step_regs<L>(ai, aa, P, t, A, c, lgn, sl, sb_lane);
+            }
             if (n == N - 1) {
                 // the stopping depth also depends on the state at the start of the last step
                 ai.xb[2] += z0b;
-                for (int k = 0; k < 3; ++k) ai.vb[k] += ke0b * M1 * rn[3 + k];
+                ai.vb[0] += ke0b * M1 * t.vx;
+                ai.vb[1] += ke0b * M1 * t.vy;
+                ai.vb[2] += ke0b * M1 * t.vz;
             }
         }
     }

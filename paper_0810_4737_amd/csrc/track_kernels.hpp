@@ -90,8 +90,9 @@ struct KernelArgs {
     // gradient entry point
     double inv_s;           // 1 / screening-length scale
     double* ckpt;           // [n][ckpt_cap][kRecWords]  state every 64 steps
-    double* segbuf;         // [n][65][kRecWords]        states of the segment being reversed
-    double* adjbuf;         // [n][kRecWords]            adjoint state while a segment is recomputed
+    double* segbuf;         // [n][2][kRecWords]         the two states of a step that moved the domain
+    double* adjbuf;         // [n][kRecWords]            adjoint state while such a step is recomputed
+    double* steplog;        // [n][ckpt_cap * 64][8]     per step: dt, StepInfo code, ion x and v before it
     int ckpt_cap;
     double* gout;           // [n][5]: z_stop, dz/dk, dz/ds, status, steps
     long long q0, q_end;    // batch entries [q0, q_end) handled by this launch
@@ -383,12 +384,22 @@ __device__ __forceinline__ double range_coord(const TrackRegs<L, LAT>& t, int ra
     return sqrt(dx * dx + dy * dy + dz * dz);
 }
 
+// What the reverse sweep of the adjoint needs to know of a step's size: dt,
+// and in code which term of the minimum set it (0: dt_max, 1: the speed term,
+// 2: the acceleration term) plus whether the ion (rather than an atom) holds
+// the largest speed (bit 2) and the largest acceleration (bit 3).
+struct StepInfo {
+    double dt;
+    int code;
+};
+
 // One integration step (velocity Verlet with symmetric friction halves); a
 // step with fresh == true has dt = 0 and builds the whole domain (start of a
-// primary).  Returns the kinetic energy before the step via ke0.
+// primary).  Returns the kinetic energy before the step via ke0, and the
+// step's size via info when given.
 template <int L, bool F32 = false, int LAT = kDiamond>
 __device__ __forceinline__ void track_step(TrackRegs<L, LAT>& t, const KernelArgs& A, const SpeciesConst* sp, int sl,
-                                           bool fresh, double& ke0, double& z0)
+                                           bool fresh, double& ke0, double& z0, StepInfo* info = nullptr)
 {
     constexpr int FS = TrackRegs<L, LAT>::FS;
     constexpr bool FL = LAT == kFluorite;
@@ -403,6 +414,13 @@ __device__ __forceinline__ void track_step(TrackRegs<L, LAT>& t, const KernelArg
     if (vmax2 > 0.0) dt = fmin(dt, A.dx_max * rsqrt_pos(vmax2));
     if (amax2 > 0.0) dt = fmin(dt, sqrt(2.0 * A.dx_max * rsqrt_pos(amax2)));
     if (fresh) dt = 0.0;
+    if (info != nullptr) {
+        const bool by_a = amax2 > 0.0 && dt == sqrt(2.0 * A.dx_max * rsqrt_pos(amax2));
+        const bool by_v = vmax2 > 0.0 && dt == A.dx_max * rsqrt_pos(vmax2);
+        info->dt = dt;
+        info->code = (by_a ? 2 : (by_v ? 1 : 0)) | ((v2 >= t.vmax2a) ? 4 : 0) |
+                     ((f2 * c.inv_M1sq >= t.amax2a) ? 8 : 0);
+    }
     ke0 = 0.5 * M1 * v2;
     z0 = range_coord(t, A.range_mode);
 
