@@ -10,13 +10,13 @@
 // domain atoms by running their part of the step backwards (they feel only the
 // ion, so the inverse is explicit: undo the second kick and the drift, evaluate
 // the pair terms at the rebuilt positions, undo the first kick), and the
-// adjoint of the step is applied in the same pass over the slots.  The state is re-anchored to the exact checkpoint at every
-// segment boundary, so reconstruction errors never grow over more than 64
-// steps.  A step that moved the domain dropped atoms the reverse cannot
-// rebuild: its starting state is recomputed forward from the segment's
-// checkpoint instead.  Adjoint state per domain atom (position, velocity,
-// force) and the pair terms of the current state live in VGPRs; the ion's
-// adjoints are wavefront-uniform.
+// adjoint of the step is applied in the same pass over the slots.  Atoms that
+// a domain move dropped come back from a log the forward writes at each move;
+// atoms it created are constants and leave.  The state is re-anchored to the
+// exact checkpoint at every segment boundary, so reconstruction errors never
+// grow over more than 64 steps.  Adjoint state per domain atom (position,
+// velocity, force) and the pair terms of the current state live in VGPRs; the
+// ion's adjoints are wavefront-uniform.
 //
 // Per step, forward (see track_step):
 //   dt = min(dt_max, dx vmax^-1, sqrt(2 dx) amax^-1/2); h1 = dt/2M1; h2 = dt/2M2
@@ -34,8 +34,7 @@
 
 namespace reedmd {
 
-// Adjoint of one step n (S_n -> S_{n+1}).  rn, rn1: records of S_n and S_{n+1}.
-// On entry the adjoint arrays hold the adjoint of S_{n+1}; on exit of S_n.
+// Adjoint of the ion (wavefront-uniform) and of the domain atoms (by register slot).
 struct AdjIon {
     double xb[3], vb[3], Fb[3], rhob;
     double kb;            // d z_stop / d k (wavefront-uniform)
@@ -71,219 +70,19 @@ __device__ __forceinline__ void zbl_pair_adjoint(double inv_a, double zz, double
     w = wnorm * exp_neg_pair(r * inv_lambda);
 }
 
-template <int L>
-__device__ __forceinline__ void reverse_step(AdjIon& ai, AdjAtoms<L>& aa, const KernelArgs& A,
-                                             const SpeciesConst& c, const double* rn, const double* rn1,
-                                             int sl, double& sb_lane)
+// The stopping depth also depends on the state at the start of the last step
+// (z0b: d z_stop / d z there; kmb: d z_stop / d ke0 times M1).
+__device__ __forceinline__ void seed_last_step(AdjIon& ai, double z0b, double kmb, double vx, double vy, double vz)
 {
-    constexpr int SL = TrackRegs<L>::SL;
-    const long long* irn = reinterpret_cast<const long long*>(rn);
-    const long long* irn1 = reinterpret_cast<const long long*>(rn1);
-    const double M1 = c.M1;
-    // ---- primal values of the step
-    const double v[3] = {rn[3], rn[4], rn[5]};
-    const double F[3] = {rn[6], rn[7], rn[8]};
-    const double rho = rn[9];
-    const double x1[3] = {rn1[0], rn1[1], rn1[2]};
-    const double vp[3] = {rn1[3], rn1[4], rn1[5]};
-    const double Fp[3] = {rn1[6], rn1[7], rn1[8]};
-    const double rhop = rn1[9];
-    (void)vp;
-    const int cx = static_cast<int>(irn[12]), cy = static_cast<int>(irn[13]), cz = static_cast<int>(irn[14]);
-    const int dx1 = static_cast<int>(irn1[12]), dy1 = static_cast<int>(irn1[13]), dz1 = static_cast<int>(irn1[14]);
-    const double vmax2a = rn[22], amax2a = rn[23];
-
-    const double v2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
-    const double f2 = F[0] * F[0] + F[1] * F[1] + F[2] * F[2];
-    const double vmax2 = fmax(v2, vmax2a);
-    const double amax2 = fmax(f2 * c.inv_M1sq, amax2a);
-    double dt = A.dt_max, dtv = 0.0, dta = 0.0;
-    if (vmax2 > 0.0) { dtv = A.dx_max * rsqrt(vmax2); dt = fmin(dt, dtv); }
-    if (amax2 > 0.0) { dta = sqrt(2.0 * A.dx_max * rsqrt(amax2)); dt = fmin(dt, dta); }
-    const int branch = (amax2 > 0.0 && dt == dta) ? 2 : ((vmax2 > 0.0 && dt == dtv) ? 1 : 0);
-
-    const double h1 = dt * c.half_inv_M1;
-    const double h2 = dt * A.half_inv_M2;
-    const double g1 = c.g_const + c.g_rho * rho;
-    const double fr1 = exp_neg(g1 * h1);
-    double v1[3];
-    for (int k = 0; k < 3; ++k) v1[k] = v[k] * fr1 + F[k] * h1;
-    const double g2 = c.g_const + c.g_rho * rhop;
-    const double fr2 = exp_neg(g2 * h1);
-    double q[3];
-    for (int k = 0; k < 3; ++k) q[k] = v1[k] + Fp[k] * h1;
-
-    // ---- R9: v' = q fr2
-    double qb[3], v1b[3], Fpb[3];
-    double fr2b = 0.0, h1b = 0.0;
-    for (int k = 0; k < 3; ++k) {
-        qb[k] = ai.vb[k] * fr2;
-        fr2b += ai.vb[k] * q[k];
-        v1b[k] = qb[k];
-        Fpb[k] = ai.Fb[k] + qb[k] * h1;
-        h1b += qb[k] * Fp[k];
-    }
-    const double g2b = -fr2b * fr2 * h1;
-    h1b += -fr2b * fr2 * g2;
-    ai.kb += g2b * (c.dg_const + c.dg_rho * rhop);
-    const double rhopb = ai.rhob + g2b * c.g_rho;
-
-    // ---- per slot: R8 (atom kick), R7 (pair term), R6 (atom drift and first kick)
-    const double inv_a = c.inv_a, zz = c.zz, inv_lambda = c.inv_lambda, wnorm = c.wnorm;
-    const double* an = rn + kHdr;
-    const double* an1 = rn1 + kHdr;
-    double x1b_l[3] = {0.0, 0.0, 0.0};
-    double dtb_l = 0.0, h2b_l = 0.0;
-    double vm_l = 0.0, fm_l = 0.0;   // slot maxima of S_n (argmax of the step-size terms)
-#pragma unroll
-    for (int i = 0; i < SL; ++i) {
-        const int s = sl + L * i;
-        double nXb[3] = {0.0, 0.0, 0.0}, nVb[3] = {0.0, 0.0, 0.0}, nfb[3] = {0.0, 0.0, 0.0};
-        if (s < kSlots) {
-            const int cell = s >> 3;
-            const int rx = cell / 9, ry = (cell / 3) % 3, rz = cell % 3;
-            const int ox = cell_of_residue(rx, cx), oy = cell_of_residue(ry, cy), oz = cell_of_residue(rz, cz);
-            const int nx = cell_of_residue(rx, dx1), ny = cell_of_residue(ry, dy1), nz = cell_of_residue(rz, dz1);
-            const bool exist_new = nz >= 0;
-            const bool kept = exist_new && nx == ox && ny == oy && nz == oz;
-            if (oz >= 0) {
-                const double Vx = an[3 * kSlots + s], Vy = an[4 * kSlots + s], Vz = an[5 * kSlots + s];
-                const double fx = an[6 * kSlots + s], fy = an[7 * kSlots + s], fz = an[8 * kSlots + s];
-                vm_l = fmax(vm_l, Vx * Vx + Vy * Vy + Vz * Vz);
-                fm_l = fmax(fm_l, fx * fx + fy * fy + fz * fz);
-            }
-            if (exist_new) {
-                const double Y[3] = {an1[0 * kSlots + s], an1[1 * kSlots + s], an1[2 * kSlots + s]};
-                const double fpj[3] = {an1[6 * kSlots + s], an1[7 * kSlots + s], an1[8 * kSlots + s]};
-                double Ub[3], fpb[3], d[3];
-                for (int k = 0; k < 3; ++k) {
-                    Ub[k] = aa.Vb[k][i];
-                    fpb[k] = aa.fb[k][i] + aa.Vb[k][i] * h2;
-                    h2b_l += aa.Vb[k][i] * fpj[k];
-                    d[k] = x1[k] - Y[k];
-                }
-                const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-                double r, inv_r, cc, c_r, c_s, w;
-                zbl_pair_adjoint(inv_a, zz, A.inv_s, inv_lambda, wnorm, r2, r, inv_r, cc, c_r, c_s, w);
-                double G[3], cb = 0.0;
-                for (int k = 0; k < 3; ++k) {
-                    G[k] = Fpb[k] - fpb[k];
-                    cb += G[k] * d[k];
-                }
-                const double rb = cb * c_r - rhopb * w * inv_lambda;
-                sb_lane += cb * c_s;
-                double Yb[3];
-                for (int k = 0; k < 3; ++k) {
-                    const double db = cc * G[k] + rb * d[k] * inv_r;
-                    x1b_l[k] += db;
-                    Yb[k] = aa.Xb[k][i] - db;
-                }
-                if (kept) {
-                    const double Xn[3] = {an[0 * kSlots + s], an[1 * kSlots + s], an[2 * kSlots + s]};
-                    const double Vn[3] = {an[3 * kSlots + s], an[4 * kSlots + s], an[5 * kSlots + s]};
-                    const double fn[3] = {an[6 * kSlots + s], an[7 * kSlots + s], an[8 * kSlots + s]};
-                    (void)Xn;
-                    for (int k = 0; k < 3; ++k) {
-                        const double U = Vn[k] + fn[k] * h2;
-                        nXb[k] = Yb[k];
-                        Ub[k] += Yb[k] * dt;
-                        dtb_l += Yb[k] * U;
-                        nVb[k] = Ub[k];
-                        nfb[k] = Ub[k] * h2;
-                        h2b_l += Ub[k] * fn[k];
-                    }
-                }
-            }
-        }
-        for (int k = 0; k < 3; ++k) {
-            aa.Xb[k][i] = nXb[k];
-            aa.Vb[k][i] = nVb[k];
-            aa.fb[k][i] = nfb[k];
-        }
-    }
-    double x1b[3];
-    for (int k = 0; k < 3; ++k) x1b[k] = ai.xb[k] + SegReduce<L>::sum(x1b_l[k]);
-    double dtb = SegReduce<L>::sum(dtb_l);
-    const double h2b = SegReduce<L>::sum(h2b_l);
-
-    // ---- R5: x1 = x + v1 dt;  R4: v1 = v fr1 + F h1;  R3: fr1 = exp(-g1 h1)
-    double fr1b = 0.0;
-    for (int k = 0; k < 3; ++k) {
-        v1b[k] += x1b[k] * dt;
-        dtb += x1b[k] * v1[k];
-        ai.xb[k] = x1b[k];
-        ai.vb[k] = v1b[k] * fr1;
-        fr1b += v1b[k] * v[k];
-        ai.Fb[k] = v1b[k] * h1;
-        h1b += v1b[k] * F[k];
-    }
-    const double g1b = -fr1b * fr1 * h1;
-    h1b += -fr1b * fr1 * g1;
-    ai.kb += g1b * (c.dg_const + c.dg_rho * rho);
-    ai.rhob = g1b * c.g_rho;
-    dtb += h1b * c.half_inv_M1 + h2b * A.half_inv_M2;
-
-    // ---- R2/R1: the active term of the step-size minimum and its maximising particle
-    if (branch == 1) {
-        const double vmax2b = -0.5 * dtb * dt / vmax2;
-        if (v2 >= vmax2a) {
-            for (int k = 0; k < 3; ++k) ai.vb[k] += 2.0 * vmax2b * v[k];
-        } else {
-            const double vm = SegReduce<L>::max(vm_l);
-#pragma unroll
-            for (int i = 0; i < SL; ++i) {
-                const int s = sl + L * i;
-                if (s >= kSlots) continue;
-                const int oz = cell_of_residue((s >> 3) % 3, cz);
-                if (oz < 0) continue;
-                const double Vx = an[3 * kSlots + s], Vy = an[4 * kSlots + s], Vz = an[5 * kSlots + s];
-                if (Vx * Vx + Vy * Vy + Vz * Vz == vm) {
-                    aa.Vb[0][i] += 2.0 * vmax2b * Vx;
-                    aa.Vb[1][i] += 2.0 * vmax2b * Vy;
-                    aa.Vb[2][i] += 2.0 * vmax2b * Vz;
-                }
-            }
-        }
-    } else if (branch == 2) {
-        const double amax2b = -0.25 * dtb * dt / amax2;
-        if (f2 * c.inv_M1sq >= amax2a) {
-            for (int k = 0; k < 3; ++k) ai.Fb[k] += 2.0 * amax2b * F[k] * c.inv_M1sq;
-        } else {
-            const double fm = SegReduce<L>::max(fm_l);
-#pragma unroll
-            for (int i = 0; i < SL; ++i) {
-                const int s = sl + L * i;
-                if (s >= kSlots) continue;
-                const int oz = cell_of_residue((s >> 3) % 3, cz);
-                if (oz < 0) continue;
-                const double fx = an[6 * kSlots + s], fy = an[7 * kSlots + s], fz = an[8 * kSlots + s];
-                if (fx * fx + fy * fy + fz * fz == fm) {
-                    aa.fb[0][i] += 2.0 * amax2b * fx * A.inv_M2sq;
-                    aa.fb[1][i] += 2.0 * amax2b * fy * A.inv_M2sq;
-                    aa.fb[2][i] += 2.0 * amax2b * fz * A.inv_M2sq;
-                }
-            }
-        }
-    }
+    ai.xb[2] += z0b;
+    ai.vb[0] += kmb * vx;
+    ai.vb[1] += kmb * vy;
+    ai.vb[2] += kmb * vz;
 }
 
-// The adjoint of a step that moved the domain, from the records of its two
-// states.  Rarely taken and kept out of line, so that its registers do not add
-// to those of the register-resident reverse step; the kernel arguments it
-// reads are passed by value.
-template <int L>
-__device__ __noinline__ void reverse_step_moved(AdjIon* ai, AdjAtoms<L>* aa, const SpeciesConst* c, const double* rn,
-                                                const double* rn1, int sl, double* sb_lane, double dt_max,
-                                                double dx_max, double half_inv_M2, double inv_M2sq, double inv_s)
-{
-    KernelArgs A;
-    A.dt_max = dt_max;
-    A.dx_max = dx_max;
-    A.half_inv_M2 = half_inv_M2;
-    A.inv_M2sq = inv_M2sq;
-    A.inv_s = inv_s;
-    reverse_step<L>(*ai, *aa, A, *c, rn, rn1, sl, *sb_lane);
-}
+// Drop-log entry of one domain move: the old centre (3 words, padded to 8),
+// then the dropped atoms' positions and velocities, [6][kSlots] by slot.
+constexpr int kDropWords = 8 + 6 * kSlots;
 
 // Pair terms of the state held in the registers, per register slot: the
 // coefficient c = -V'(r)/r, its derivatives dc/dr and dc/ds, the density
@@ -310,18 +109,35 @@ __device__ __forceinline__ void pair_state(const TrackRegs<L>& t, const KernelAr
     }
 }
 
-// Adjoint of one step n that did not move the domain, with the state
-// reconstructed in the registers.  On entry t holds S_{n+1} and P its pair
-// terms, and the adjoint arrays hold the adjoint of S_{n+1}; on exit t holds
-// S_n (reconstructed), P the pair terms of S_n, and the adjoints those of S_n.
-// dt and code are the step's logged size (StepInfo).
-template <int L>
+// Adjoint of one step n (S_n -> S_{n+1}), with the state rebuilt in the
+// registers.  On entry t holds S_{n+1} and P its pair terms, and the adjoint
+// arrays hold the adjoint of S_{n+1}; on exit t holds S_n (rebuilt), P the pair
+// terms of S_n, and the adjoints those of S_n.  lgn: the step's log entry (dt,
+// StepInfo code, ion position and velocity of S_n).  MOVED: the step moved the
+// domain; de is its drop-log entry.  A slot then holds at S_n the atom it held
+// at S_{n+1} if that atom was kept, the dropped atom if one left, or nothing.
+template <int L, bool MOVED>
 __device__ __forceinline__ void reverse_step_regs(AdjIon& ai, AdjAtoms<L>& aa, PairState<L>& P, TrackRegs<L>& t,
                                                   const KernelArgs& A, const SpeciesConst& c, const double* lgn,
-                                                  int sl, double& sb_lane)
+                                                  const double* de, int sl, double& sb_lane)
 {
     constexpr int SL = TrackRegs<L>::SL;
     constexpr int FS = TrackRegs<L>::FS;
+    // centres of S_{n+1} and S_n; parking place of S_n's empty slots
+    const int c1x = t.cx, c1y = t.cy, c1z = t.cz;
+    int cnx = c1x, cny = c1y, cnz = c1z;
+    double parkx = 0.0, parky = 0.0, parkz = 0.0;
+    if constexpr (MOVED) {
+        cnx = static_cast<int>(de[0]);
+        cny = static_cast<int>(de[1]);
+        cnz = static_cast<int>(de[2]);
+        const KernelArgs C = cold_args();
+        parkx = C.a * (static_cast<double>(cnx) + 0.5);
+        parky = C.a * (static_cast<double>(cny) + 0.5);
+        parkz = C.a * (static_cast<double>(cnz) + 0.5) - C.park;
+    }
+    const double* dropped = de + 8;
+    unsigned ex_n = 0;
     const double dt = lgn[0];
     const int code = static_cast<int>(reinterpret_cast<const long long*>(lgn)[1]);
     const double h1 = dt * c.half_inv_M1;
@@ -363,24 +179,46 @@ __device__ __forceinline__ void reverse_step_regs(AdjIon& ai, AdjAtoms<L>& aa, P
         double nXb[3] = {0.0, 0.0, 0.0}, nVb[3] = {0.0, 0.0, 0.0}, nfb[3] = {0.0, 0.0, 0.0};
         v2s[i] = -1.0;
         f2s[i] = -1.0;
-        if ((t.exist >> i) & 1u) {
-            double* f = t.fl + (sl + L * i);
-            const double Y[3] = {t.ax[i], t.ay[i], t.az[i]};
-            const double Vp[3] = {t.avx[i], t.avy[i], t.avz[i]};
-            const double fp[3] = {f[0], f[FS], f[2 * FS]};
-            double U[3], X[3], dn[3];
-            for (int k = 0; k < 3; ++k) {
-                U[k] = Vp[k] - fp[k] * h2;
-                X[k] = Y[k] - U[k] * dt;
-                dn[k] = x[k] - X[k];
-            }
-            double rn, irn, cn, crn, csn, wn;
+        const int s = sl + L * i;
+        double* f = t.fl + s;
+        const bool e1 = (t.exist >> i) & 1u;   // an atom at S_{n+1}
+        bool en = e1, kept = e1;               // an atom at S_n; the same atom at both
+        if constexpr (MOVED) {
+            const int cell = (s < kSlots) ? (s >> 3) : -1;
+            const int rx = cell / 9, ry = (cell / 3) % 3, rz = cell % 3;
+            const int oz = cell_of_residue(rz, cnz);
+            en = cell >= 0 && oz >= 0;
+            kept = e1 && en && cell_of_residue(rx, cnx) == cell_of_residue(rx, c1x) &&
+                   cell_of_residue(ry, cny) == cell_of_residue(ry, c1y) && oz == cell_of_residue(rz, c1z);
+        }
+        // S_{n+1}'s atom and pair terms in this slot (exact zeros when parked)
+        const double Y[3] = {t.ax[i], t.ay[i], t.az[i]};
+        const double Vp[3] = {t.avx[i], t.avy[i], t.avz[i]};
+        const double fp[3] = {f[0], f[FS], f[2 * FS]};
+        const double pc = P.c[i], pcr = P.cr[i], pcs = P.cs[i], pw = P.w[i], pir = P.ir[i];
+        // S_n's atom: a kept atom runs its part of the step backwards, a dropped one
+        // comes from the drop log
+        double U[3], X[3], Vn[3] = {0.0, 0.0, 0.0}, fn[3] = {0.0, 0.0, 0.0};
+        for (int k = 0; k < 3; ++k) {
+            U[k] = Vp[k] - fp[k] * h2;
+            X[k] = Y[k] - U[k] * dt;
+        }
+        if constexpr (MOVED) {
+            if (en && !kept)
+                for (int k = 0; k < 3; ++k) {
+                    X[k] = dropped[k * kSlots + s];
+                    Vn[k] = dropped[(3 + k) * kSlots + s];
+                }
+        }
+        double cn = 0.0, crn = 0.0, csn = 0.0, wn = 0.0, irn = 0.0;
+        if (en) {
+            double dn[3], rn;
+            for (int k = 0; k < 3; ++k) dn[k] = x[k] - X[k];
             zbl_pair_adjoint(c.inv_a, c.zz, A.inv_s, c.inv_lambda, c.wnorm, dn[0] * dn[0] + dn[1] * dn[1] + dn[2] * dn[2],
                              rn, irn, cn, crn, csn, wn);
-            double fn[3], Vn[3];
             for (int k = 0; k < 3; ++k) {
                 fn[k] = -cn * dn[k];
-                Vn[k] = U[k] - fn[k] * h2;
+                if (kept) Vn[k] = U[k] - fn[k] * h2;
                 F_l[k] += cn * dn[k];
             }
             rho_l += wn;
@@ -388,7 +226,10 @@ __device__ __forceinline__ void reverse_step_regs(AdjIon& ai, AdjAtoms<L>& aa, P
             f2s[i] = fn[0] * fn[0] + fn[1] * fn[1] + fn[2] * fn[2];
             vm_l = fmax(vm_l, v2s[i]);
             fm_l = fmax(fm_l, f2s[i]);
-
+        }
+        // ---- adjoint of the second kick and the pair term of S_{n+1}, and for a kept
+        //      atom of its drift and first kick (a created atom is a constant)
+        if (e1) {
             double Ub[3], G[3], d[3], cb = 0.0;
             for (int k = 0; k < 3; ++k) {
                 Ub[k] = aa.Vb[k][i];
@@ -397,23 +238,34 @@ __device__ __forceinline__ void reverse_step_regs(AdjIon& ai, AdjAtoms<L>& aa, P
                 G[k] = Fpb[k] - (aa.fb[k][i] + aa.Vb[k][i] * h2);
                 cb += G[k] * d[k];
             }
-            const double rb = cb * P.cr[i] - rhopb * P.w[i] * c.inv_lambda;
-            sb_lane += cb * P.cs[i];
+            const double rb = cb * pcr - rhopb * pw * c.inv_lambda;
+            sb_lane += cb * pcs;
             for (int k = 0; k < 3; ++k) {
-                const double db = P.c[i] * G[k] + rb * d[k] * P.ir[i];
+                const double db = pc * G[k] + rb * d[k] * pir;
                 x1b_l[k] += db;
-                const double Yb = aa.Xb[k][i] - db;
-                nXb[k] = Yb;
-                Ub[k] += Yb * dt;
-                dtb_l += Yb * U[k];
-                nVb[k] = Ub[k];
-                nfb[k] = Ub[k] * h2;
-                h2b_l += Ub[k] * fn[k];
+                if (kept) {
+                    const double Yb = aa.Xb[k][i] - db;
+                    nXb[k] = Yb;
+                    Ub[k] += Yb * dt;
+                    dtb_l += Yb * U[k];
+                    nVb[k] = Ub[k];
+                    nfb[k] = Ub[k] * h2;
+                    h2b_l += Ub[k] * fn[k];
+                }
             }
+        }
+        // ---- S_n into the slot
+        if (en) {
             t.ax[i] = X[0]; t.ay[i] = X[1]; t.az[i] = X[2];
             t.avx[i] = Vn[0]; t.avy[i] = Vn[1]; t.avz[i] = Vn[2];
             f[0] = fn[0]; f[FS] = fn[1]; f[2 * FS] = fn[2];
             P.c[i] = cn; P.cr[i] = crn; P.cs[i] = csn; P.w[i] = wn; P.ir[i] = irn;
+            ex_n |= 1u << i;
+        } else if constexpr (MOVED) {
+            t.ax[i] = parkx; t.ay[i] = parky; t.az[i] = parkz;
+            t.avx[i] = 0.0; t.avy[i] = 0.0; t.avz[i] = 0.0;
+            f[0] = 0.0; f[FS] = 0.0; f[2 * FS] = 0.0;
+            P.c[i] = 0.0; P.cr[i] = 0.0; P.cs[i] = 0.0; P.w[i] = 0.0; P.ir[i] = 0.0;
         }
         for (int k = 0; k < 3; ++k) {
             aa.Xb[k][i] = nXb[k];
@@ -457,6 +309,11 @@ __device__ __forceinline__ void reverse_step_regs(AdjIon& ai, AdjAtoms<L>& aa, P
     ai.rhob = g1b * c.g_rho;
     dtb += h1b * c.half_inv_M1 + h2b * A.half_inv_M2;
 
+    if constexpr (MOVED) {
+        t.exist = ex_n;
+        t.cx = cnx; t.cy = cny; t.cz = cnz;
+        t.n_exist = SegReduce<L>::isum(__popc(ex_n));
+    }
     t.x = x[0]; t.y = x[1]; t.z = x[2];
     t.vx = v[0]; t.vy = v[1]; t.vz = v[2];
     t.Fx = F[0]; t.Fy = F[1]; t.Fz = F[2];
@@ -503,35 +360,6 @@ __device__ __forceinline__ void reverse_step_regs(AdjIon& ai, AdjAtoms<L>& aa, P
     }
 }
 
-template <int L>
-__device__ __forceinline__ void stash_adjoint(const AdjAtoms<L>& aa, double* buf, int sl)
-{
-#pragma unroll
-    for (int i = 0; i < TrackRegs<L>::SL; ++i) {
-        const int s = sl + L * i;
-        if (s >= kSlots) continue;
-        for (int k = 0; k < 3; ++k) {
-            buf[(0 + k) * kSlots + s] = aa.Xb[k][i];
-            buf[(3 + k) * kSlots + s] = aa.Vb[k][i];
-            buf[(6 + k) * kSlots + s] = aa.fb[k][i];
-        }
-    }
-}
-
-template <int L>
-__device__ __forceinline__ void unstash_adjoint(AdjAtoms<L>& aa, const double* buf, int sl)
-{
-#pragma unroll
-    for (int i = 0; i < TrackRegs<L>::SL; ++i) {
-        const int s = sl + L * i;
-        for (int k = 0; k < 3; ++k) {
-            aa.Xb[k][i] = (s < kSlots) ? buf[(0 + k) * kSlots + s] : 0.0;
-            aa.Vb[k][i] = (s < kSlots) ? buf[(3 + k) * kSlots + s] : 0.0;
-            aa.fb[k][i] = (s < kSlots) ? buf[(6 + k) * kSlots + s] : 0.0;
-        }
-    }
-}
-
 #ifndef REEDMD_GRAD_WAVES_PER_SIMD
 #define REEDMD_GRAD_WAVES_PER_SIMD 1
 #endif
@@ -556,8 +384,7 @@ __global__ void __launch_bounds__(64, REEDMD_GRAD_WAVES_PER_SIMD) grad_kernel(co
     const long long q = A.q0 + local;
     if (q >= A.q_end) return;
     double* ck = A.ckpt + static_cast<size_t>(local) * A.ckpt_cap * kRecWords;
-    double* sbuf = A.segbuf + static_cast<size_t>(local) * 2 * kRecWords;
-    double* abuf = A.adjbuf + static_cast<size_t>(local) * kRecWords;
+    double* dl = A.droplog + static_cast<size_t>(local) * A.drop_cap * kDropWords;
     double* lg = A.steplog + static_cast<size_t>(local) * A.ckpt_cap * 512;
     double* out = A.gout + static_cast<size_t>(q) * 5;
 
@@ -576,22 +403,33 @@ __global__ void __launch_bounds__(64, REEDMD_GRAD_WAVES_PER_SIMD) grad_kernel(co
     // ---- forward with a checkpoint every 64 steps and the log of step sizes
     //      and the ion of the state it starts from (steps < ckpt_cap * 64: the loop
     //      ends at the checkpoint capacity)
+    //      and, at each domain move, the old centre and the atoms dropped (at most
+    //      drop_cap moves: a track that makes more ends as capped)
     int st = REEDMD_ACTIVE;
+    int moves = 0;
     for (;;) {
         const long long n = t.steps;
         const int ocx = t.cx, ocy = t.cy, ocz = t.cz;
         const double ion[6] = {t.x, t.y, t.z, t.vx, t.vy, t.vz};
+        double* de = dl + static_cast<size_t>(moves) * kDropWords;
         StepInfo si;
-        track_step<L>(t, A, sp, sl, false, ke0, z0, &si);
+        track_step<L>(t, A, sp, sl, false, ke0, z0, &si, de + 8);
+        const bool moved = t.cx != ocx || t.cy != ocy || t.cz != ocz;
         if (sl == 0) {
-            const bool moved = t.cx != ocx || t.cy != ocy || t.cz != ocz;
             double* e = lg + 8 * n;
             e[0] = si.dt;
             reinterpret_cast<long long*>(e)[1] = si.code | (moved ? 16 : 0);
             for (int k = 0; k < 6; ++k) e[2 + k] = ion[k];
+            if (moved) {
+                de[0] = static_cast<double>(ocx);
+                de[1] = static_cast<double>(ocy);
+                de[2] = static_cast<double>(ocz);
+            }
         }
+        if (moved) ++moves;
         st = track_events<L>(t, A, sp, ke0, z0);
         if (st != REEDMD_ACTIVE) break;
+        if (moves >= A.drop_cap) { st = REEDMD_STEPCAP; break; }
         if ((t.steps & 63) == 0) {
             const long long k = t.steps >> 6;
             if (k >= A.ckpt_cap) { st = REEDMD_STEPCAP; break; }
@@ -633,9 +471,8 @@ __global__ void __launch_bounds__(64, REEDMD_GRAD_WAVES_PER_SIMD) grad_kernel(co
     double sb_lane = 0.0;
 
     // ---- reverse, step by step from the final state (t holds S_N)
-    __threadfence();   // the step log written by lane 0 is read by every lane
+    __threadfence();   // the logs written by the forward are read by every lane
     PairState<L> P;
-    double ke0d, z0d;
     for (long long seg = (N - 1) >> 6; seg >= 0; --seg) {
         const long long start = seg << 6;
         const long long end = (start + 64 < N) ? start + 64 : N;
@@ -645,39 +482,13 @@ __global__ void __launch_bounds__(64, REEDMD_GRAD_WAVES_PER_SIMD) grad_kernel(co
         for (long long n = end - 1; n >= start; --n) {
             const double* lgn = lg + 8 * n;
             if (reinterpret_cast<const long long*>(lgn)[1] & 16) {
-                // the step moved the domain: recompute S_n from the segment's checkpoint
-                store_record<L>(t, sbuf + kRecWords, sl);
-                stash_adjoint<L>(aa, abuf, sl);
-                load_record<L>(t, ck + static_cast<size_t>(seg) * kRecWords, sl, A);
-                for (long long m = start; m < n; ++m) track_step<L>(t, A, sp, sl, false, ke0d, z0d);
-                store_record<L>(t, sbuf, sl);
-                __threadfence();   // the records just written are read back by every lane
-                unstash_adjoint<L>(aa, abuf, sl);
-                {
-                    AdjIon ai2 = ai;
-                    AdjAtoms<L> aa2 = aa;
-                    double sb2 = sb_lane;
-                    reverse_step_moved<L>(&ai2, &aa2, &c, sbuf, sbuf + kRecWords, sl, &sb2, A.dt_max, A.dx_max,
-                                          A.half_inv_M2, A.inv_M2sq, A.inv_s);
-                    ai = ai2;
-                    aa = aa2;
-                    sb_lane = sb2;
-                }
-                // S_n is taken back from its record (so that neither it nor the pair terms
-                // are held in registers through the recompute and the record-based step),
-                // also at the segment's first step, where it is not needed
-                load_record<L>(t, sbuf, sl, A);
-                pair_state<L>(t, A, c, P);
+                --moves;
+                reverse_step_regs<L, true>(ai, aa, P, t, A, c, lgn, dl + static_cast<size_t>(moves) * kDropWords, sl,
+                                           sb_lane);
             } else {
-                reverse_step_regs<L>(ai, aa, P, t, A, c, lgn, sl, sb_lane);
+                reverse_step_regs<L, false>(ai, aa, P, t, A, c, lgn, dl, sl, sb_lane);
             }
-            if (n == N - 1) {
-                // the stopping depth also depends on the state at the start of the last step
-                ai.xb[2] += z0b;
-                ai.vb[0] += ke0b * M1 * t.vx;
-                ai.vb[1] += ke0b * M1 * t.vy;
-                ai.vb[2] += ke0b * M1 * t.vz;
-            }
+            if (n == N - 1) seed_last_step(ai, z0b, ke0b * M1, t.vx, t.vy, t.vz);
         }
     }
     // ---- the starting forces depend on s (positions and velocities are constants)

@@ -892,9 +892,10 @@ reedmd_status reedmd_grad(reedmd_ctx* ctx, const reedmd_species* species, const 
     if (n == 0) return REEDMD_OK;
     const long long max_steps = params->max_steps > 0 ? params->max_steps : kDefaultGradSteps;
     const int ckpt_cap = static_cast<int>(max_steps / 64 + 1);
-    // checkpoints, the two records of a recomputed step, the adjoint stash, the step log
-    const size_t per_track = ((static_cast<size_t>(ckpt_cap) + 2 + 1) * kRecWords +
-                              static_cast<size_t>(ckpt_cap) * 512) * sizeof(double);
+    // checkpoints, the step log, and the drop log (up to one domain move per 32 steps)
+    const int drop_cap = 2 * ckpt_cap;
+    const size_t per_track = (static_cast<size_t>(ckpt_cap) * kRecWords + static_cast<size_t>(ckpt_cap) * 512 +
+                              static_cast<size_t>(drop_cap) * kDropWords) * sizeof(double);
     const long long chunk = std::max<long long>(1, std::min<long long>(n, static_cast<long long>(kGradScratchBytes / per_track)));
     const size_t out_bytes = static_cast<size_t>(n) * 5 * sizeof(double) + 64;
     const size_t need = static_cast<size_t>(chunk) * per_track + out_bytes;
@@ -922,10 +923,10 @@ reedmd_status reedmd_grad(reedmd_ctx* ctx, const reedmd_species* species, const 
     A.ckpt_cap = ckpt_cap;
     double* base = ctx->gscratch;
     A.ckpt = base;
-    A.segbuf = base + static_cast<size_t>(chunk) * ckpt_cap * kRecWords;
-    A.adjbuf = A.segbuf + static_cast<size_t>(chunk) * 2 * kRecWords;
-    A.steplog = A.adjbuf + static_cast<size_t>(chunk) * kRecWords;
-    double* own_out = A.steplog + static_cast<size_t>(chunk) * ckpt_cap * 512;
+    A.steplog = base + static_cast<size_t>(chunk) * ckpt_cap * kRecWords;
+    A.droplog = A.steplog + static_cast<size_t>(chunk) * ckpt_cap * 512;
+    A.drop_cap = drop_cap;
+    double* own_out = A.droplog + static_cast<size_t>(chunk) * drop_cap * kDropWords;
     double* res = own_out + static_cast<size_t>(n) * 5;
     A.gout = d_track_out ? d_track_out : own_out;
     for (long long q0 = 0; q0 < n; q0 += chunk) {

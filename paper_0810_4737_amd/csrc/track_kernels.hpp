@@ -90,9 +90,9 @@ struct KernelArgs {
     // gradient entry point
     double inv_s;           // 1 / screening-length scale
     double* ckpt;           // [n][ckpt_cap][kRecWords]  state every 64 steps
-    double* segbuf;         // [n][2][kRecWords]         the two states of a step that moved the domain
-    double* adjbuf;         // [n][kRecWords]            adjoint state while such a step is recomputed
     double* steplog;        // [n][ckpt_cap * 64][8]     per step: dt, StepInfo code, ion x and v before it
+    double* droplog;        // [n][drop_cap][kDropWords] per domain move: the old centre, the dropped atoms
+    int drop_cap;
     int ckpt_cap;
     double* gout;           // [n][5]: z_stop, dz/dk, dz/ds, status, steps
     long long q0, q_end;    // batch entries [q0, q_end) handled by this launch
@@ -316,7 +316,7 @@ __device__ __forceinline__ bool vacant_site(const double* h, int cx, int cy, int
 
 template <int L, int LAT>
 __device__ __forceinline__ void regenerate(TrackRegs<L, LAT>& t, const KernelArgs& A, int sl, int ncx,
-                                           int ncy, int ncz, bool all)
+                                           int ncy, int ncz, bool all, double* drop = nullptr)
 {
     using Lat = Lattice<LAT>;
     constexpr int FS = TrackRegs<L, LAT>::FS;
@@ -352,6 +352,18 @@ __device__ __forceinline__ void regenerate(TrackRegs<L, LAT>& t, const KernelArg
     for (int i = 0; i < TrackRegs<L, LAT>::SL; ++i) {
         const int s = sl + L * i;
         const int cell = (s < Lat::kSlots) ? Lat::cell_of_slot(s) : -1;
+        if (drop != nullptr && ((t.exist >> i) & 1u)) {
+            // the atom leaves the domain when its cell does: its position and velocity
+            // go to the drop log, [6][kSlots] by slot (the adjoint restores them)
+            const int rx = cell / 9, ry = (cell / 3) % 3, rz = cell % 3;
+            if (cell_of_residue(rx, ncx) != cell_of_residue(rx, t.cx) ||
+                cell_of_residue(ry, ncy) != cell_of_residue(ry, t.cy) ||
+                cell_of_residue(rz, ncz) != cell_of_residue(rz, t.cz)) {
+                constexpr int NS = Lat::kSlots;
+                drop[0 * NS + s] = t.ax[i]; drop[1 * NS + s] = t.ay[i]; drop[2 * NS + s] = t.az[i];
+                drop[3 * NS + s] = t.avx[i]; drop[4 * NS + s] = t.avy[i]; drop[5 * NS + s] = t.avz[i];
+            }
+        }
         if (cell < 0 || cell_of_residue(cell % 3, ncz) < 0 ||
             (LAT == kFluorite &&
              vacant_site(h, cell_of_residue(cell / 9, ncx), cell_of_residue((cell / 3) % 3, ncy),
@@ -396,10 +408,12 @@ struct StepInfo {
 // One integration step (velocity Verlet with symmetric friction halves); a
 // step with fresh == true has dt = 0 and builds the whole domain (start of a
 // primary).  Returns the kinetic energy before the step via ke0, and the
-// step's size via info when given.
+// step's size via info when given, and the atoms a domain move drops via drop
+// when given (see regenerate).
 template <int L, bool F32 = false, int LAT = kDiamond>
 __device__ __forceinline__ void track_step(TrackRegs<L, LAT>& t, const KernelArgs& A, const SpeciesConst* sp, int sl,
-                                           bool fresh, double& ke0, double& z0, StepInfo* info = nullptr)
+                                           bool fresh, double& ke0, double& z0, StepInfo* info = nullptr,
+                                           double* drop = nullptr)
 {
     constexpr int FS = TrackRegs<L, LAT>::FS;
     constexpr bool FL = LAT == kFluorite;
@@ -436,7 +450,7 @@ __device__ __forceinline__ void track_step(TrackRegs<L, LAT>& t, const KernelArg
     if (fresh || !inside_cell(t.x, t.cx, A.a, A.inv_a) || !inside_cell(t.y, t.cy, A.a, A.inv_a) ||
         !inside_cell(t.z, t.cz, A.a, A.inv_a)) {
         const int ncx = floor_cell(t.x, A.a), ncy = floor_cell(t.y, A.a), ncz = floor_cell(t.z, A.a);
-        if (fresh || ncx != t.cx || ncy != t.cy || ncz != t.cz) regenerate<L, LAT>(t, A, sl, ncx, ncy, ncz, fresh);
+        if (fresh || ncx != t.cx || ncy != t.cy || ncz != t.cz) regenerate<L, LAT>(t, A, sl, ncx, ncy, ncz, fresh, drop);
     }
 
     // fused pass over every register slot (parked slots contribute exact zeros):
