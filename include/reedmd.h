@@ -302,9 +302,15 @@ reedmd_status reedmd_debug_step(reedmd_ctx* ctx, const reedmd_species* species,
  * of the batch that stop; backscattered and capped tracks are excluded) with
  * respect to the electronic-stopping scale k and the ZBL screening-length
  * scale s, evaluated at (k, s) (they replace the context's values for this
- * call; k >= 0 and s in [0.01, 100], EINVAL otherwise).  Reverse mode: every track runs forward with a checkpoint of its full
- * state every 64 steps, then each 64-step segment is recomputed from its
- * checkpoint and the adjoint of its steps applied from last to first.  The
+ * call; k >= 0 and s in [0.01, 100], EINVAL otherwise).  Reverse mode: every
+ * track runs forward with a checkpoint of its full state every 64 steps, a log
+ * of each step's size and starting ion state, and a log of the atoms each
+ * domain move drops; the reverse sweep then rebuilds each step's starting
+ * state from the state after it (domain atoms run backwards, the ion from the
+ * log, dropped atoms from their log; re-anchored to the checkpoint every 64
+ * steps) and applies the adjoint of the steps from last to first.  A track
+ * that moves its domain more than 2 (max_steps/64 + 1) times ends as capped.
+ * The
  * derivative is pathwise: branches (active step-size term, domain updates,
  * which step stops the ion) are held fixed, created atoms are constants.
  * Requires params->n_thresh == 0, FP64 pair terms, a diamond context, the
