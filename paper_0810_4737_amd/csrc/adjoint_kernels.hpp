@@ -12,7 +12,7 @@
 // the pair terms at the rebuilt positions, undo the first kick), and the
 // adjoint of the step is applied in the same pass over the slots.  Atoms that
 // a domain move dropped come back from a log the forward writes at each move;
-// atoms it created are constants and leave.  The state is re-anchored to the
+// atoms it created are constants, so their adjoints end at the move.  The state is re-anchored to the
 // exact checkpoint at every segment boundary, so reconstruction errors never
 // grow over more than 64 steps.  Adjoint state per domain atom (position,
 // velocity, force) and the pair terms of the current state live in VGPRs; the
@@ -46,17 +46,19 @@ struct AdjAtoms {
     double Xb[3][SL], Vb[3][SL], fb[3][SL];
 };
 
-__device__ __forceinline__ void zbl_pair_adjoint(double inv_a, double zz, double inv_s, double inv_lambda,
-                                                 double wnorm, double r2, double& r, double& inv_r, double& c,
-                                                 double& c_r, double& c_s, double& w)
+// Pair term of one atom at squared distance r2 with its derivatives: the force
+// coefficient c = -V'(r)/r, dc/dr and dc/ds, the density weight w (normalised)
+// and r, 1/r.  The exponentials are the step's (base-2 rates folded per species).
+__device__ __forceinline__ void zbl_pair_adjoint(const SpeciesConst& sc, double inv_s, double r2, double& r,
+                                                 double& inv_r, double& c, double& c_r, double& c_s, double& w)
 {
-    inv_r = rsqrt(r2);
+    const double inv_a = sc.inv_a, zz = sc.zz;
+    inv_r = rsqrt_pos(r2);
     r = r2 * inv_r;
-    const double xs = r * inv_a;
-    const double e0 = exp_neg_pair(kZd0 * xs);
-    const double e1 = exp_neg_pair(kZd1 * xs);
-    const double e2 = exp_neg_pair(kZd2 * xs);
-    const double e3 = exp_neg_pair(kZd3 * xs);
+    const double e0 = exp2_neg_pair(r, sc.rate[0]);
+    const double e1 = exp2_neg_pair(r, sc.rate[1]);
+    const double e2 = exp2_neg_pair(r, sc.rate[2]);
+    const double e3 = exp2_neg_pair(r, sc.rate[3]);
     const double phi = kZc0 * e0 + kZc1 * e1 + kZc2 * e2 + kZc3 * e3;
     const double dphi = -(kZc0 * kZd0 * e0 + kZc1 * kZd1 * e1 + kZc2 * kZd2 * e2 + kZc3 * kZd3 * e3);
     const double d2phi = kZc0 * kZd0 * kZd0 * e0 + kZc1 * kZd1 * kZd1 * e1 + kZc2 * kZd2 * kZd2 * e2 +
@@ -67,7 +69,7 @@ __device__ __forceinline__ void zbl_pair_adjoint(double inv_a, double zz, double
     c = -dVdr * inv_r;
     c_r = zz * ir2 * (3.0 * dphi * inv_a * inv_r - 3.0 * phi * ir2 - d2phi * inv_a * inv_a);
     c_s = zz * d2phi * inv_a * inv_a * inv_s * inv_r;
-    w = wnorm * exp_neg_pair(r * inv_lambda);
+    w = sc.wnorm * exp2_neg_pair(r, sc.lam2);
 }
 
 // The stopping depth also depends on the state at the start of the last step
@@ -103,7 +105,7 @@ __device__ __forceinline__ void pair_state(const TrackRegs<L>& t, const KernelAr
         if (!((t.exist >> i) & 1u)) continue;
         const double dx = t.x - t.ax[i], dy = t.y - t.ay[i], dz = t.z - t.az[i];
         double r;
-        zbl_pair_adjoint(c.inv_a, c.zz, A.inv_s, c.inv_lambda, c.wnorm, dx * dx + dy * dy + dz * dz, r, P.ir[i],
+        zbl_pair_adjoint(c, A.inv_s, dx * dx + dy * dy + dz * dz, r, P.ir[i],
                          P.c[i], P.cr[i], P.cs[i], P.w[i]);
         __builtin_amdgcn_sched_barrier(0);
     }
@@ -214,7 +216,7 @@ __device__ __forceinline__ void reverse_step_regs(AdjIon& ai, AdjAtoms<L>& aa, P
         if (en) {
             double dn[3], rn;
             for (int k = 0; k < 3; ++k) dn[k] = x[k] - X[k];
-            zbl_pair_adjoint(c.inv_a, c.zz, A.inv_s, c.inv_lambda, c.wnorm, dn[0] * dn[0] + dn[1] * dn[1] + dn[2] * dn[2],
+            zbl_pair_adjoint(c, A.inv_s, dn[0] * dn[0] + dn[1] * dn[1] + dn[2] * dn[2],
                              rn, irn, cn, crn, csn, wn);
             for (int k = 0; k < 3; ++k) {
                 fn[k] = -cn * dn[k];
@@ -509,7 +511,7 @@ __global__ void __launch_bounds__(64, REEDMD_GRAD_WAVES_PER_SIMD) grad_kernel(co
             }
             const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
             double r, inv_r, cc, c_r, c_s, w;
-            zbl_pair_adjoint(c.inv_a, c.zz, A.inv_s, c.inv_lambda, c.wnorm, r2, r, inv_r, cc, c_r, c_s, w);
+            zbl_pair_adjoint(c, A.inv_s, r2, r, inv_r, cc, c_r, c_s, w);
             sb_lane += cb * c_s;
         }
     }
