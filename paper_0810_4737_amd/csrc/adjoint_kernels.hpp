@@ -285,8 +285,8 @@ __device__ __forceinline__ void reverse_step_regs(AdjIon& ai, AdjAtoms<L>& aa, P
     const double rho = SegReduce<L>::sum(rho_l);
     const double vm = SegReduce<L>::max(vm_l);
     const double fm = SegReduce<L>::max(fm_l);
-    double dtb = SegReduce<L>::sum(dtb_l);
-    const double h2b = SegReduce<L>::sum(h2b_l);
+    // d/dt through the atoms' drifts and, via h2 = dt / 2M2, their kicks: one reduction
+    double dtb = SegReduce<L>::sum(dtb_l + h2b_l * A.half_inv_M2);
 
     // ---- first friction half and kick of the step
     const double g1 = c.g_const + c.g_rho * rho;
@@ -309,7 +309,7 @@ __device__ __forceinline__ void reverse_step_regs(AdjIon& ai, AdjAtoms<L>& aa, P
     h1b += -fr1b * fr1 * g1;
     ai.kb += g1b * (c.dg_const + c.dg_rho * rho);
     ai.rhob = g1b * c.g_rho;
-    dtb += h1b * c.half_inv_M1 + h2b * A.half_inv_M2;
+    dtb += h1b * c.half_inv_M1;
 
     if constexpr (MOVED) {
         t.exist = ex_n;
