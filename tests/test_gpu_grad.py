@@ -67,6 +67,40 @@ def test_adjoint_matches_oracle_forward_mode(R, ctx):
     assert checked >= 24
 
 
+def test_adjoint_short_tracks_under_a_small_step_cap(R, ctx):
+    """40 eV B (99-300 steps) under max_steps = 200: a few 64-step segments, a last segment
+    of any length, small checkpoint and drop-log capacities, and tracks ending as capped or
+    backscattered.  Status and step count equal the oracle's for every track; stopped tracks
+    have the oracle's forward-mode derivatives (1e-6), capped ones are excluded from the mean."""
+    species = ("B",)
+    pr = _batch(64, 0, 40.0, 9)
+    b = R.batch_from_numpy(pr)
+    cfg = R.RunConfig(max_steps=200)
+    g = R.grad(ctx, species, b, cfg, 1.0, 1.0, per_track=True)
+    tr = g["tracks"].cpu().numpy()
+    oc = oracle.Config(species=species)
+    seen = {oracle.STOPPED: 0, oracle.STEPCAP: 0}
+    checked = 0
+    for i in range(len(tr)):
+        st, z, dk, ds, n = oracle.grad_track(oc, 0, pr["E0"][i], pr["pos"][:, i], pr["dir"][:, i],
+                                             int(pr["key"][i]), max_steps=200)
+        assert int(tr[i, 3]) == st, i
+        assert int(tr[i, 4]) == n, i
+        if st in seen:
+            seen[st] += 1
+        if st != oracle.STOPPED:
+            assert tr[i, 1] == 0.0 and tr[i, 2] == 0.0
+            continue
+        if abs(tr[i, 0] - z) > 1e-9 * abs(z):
+            continue
+        checked += 1
+        for gv, ov, name in ((tr[i, 1], dk, "dk"), (tr[i, 2], ds, "ds")):
+            assert abs(gv - ov) <= 1e-6 * max(abs(ov), 1e-3 * abs(z)), (i, name, gv, ov, n)
+    _say(f"stopped {seen[oracle.STOPPED]}, capped {seen[oracle.STEPCAP]}, compared {checked}")
+    assert seen[oracle.STOPPED] >= 8 and seen[oracle.STEPCAP] >= 8 and checked >= 8
+    assert g["count"] == seen[oracle.STOPPED]
+
+
 def _fd(R, ctx, species, b, cfg, k, s, h, which):
     up = dict(k=k, s=s)
     dn = dict(k=k, s=s)
