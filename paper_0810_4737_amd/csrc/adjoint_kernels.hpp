@@ -82,6 +82,10 @@ __device__ __forceinline__ void seed_last_step(AdjIon& ai, double z0b, double km
     ai.vb[2] += kmb * vz;
 }
 
+// Step-log entry of one step: dt, the StepInfo code (bit 4: the step moved the
+// domain), and the ion's position, velocity, force and density before it.
+constexpr int kLogWords = 12;
+
 // Drop-log entry of one domain move: the old centre (3 words, padded to 8),
 // then the dropped atoms' positions and velocities, [6][kSlots] by slot.
 constexpr int kDropWords = 8 + 6 * kSlots;
@@ -115,8 +119,8 @@ __device__ __forceinline__ void pair_state(const TrackRegs<L>& t, const KernelAr
 // registers.  On entry t holds S_{n+1} and P its pair terms, and the adjoint
 // arrays hold the adjoint of S_{n+1}; on exit t holds S_n (rebuilt), P the pair
 // terms of S_n, and the adjoints those of S_n.  lgn: the step's log entry (dt,
-// StepInfo code, ion position and velocity of S_n).  MOVED: the step moved the
-// domain; de is its drop-log entry.  A slot then holds at S_n the atom it held
+// StepInfo code, ion position, velocity, force and density of S_n).  MOVED: the
+// step moved the domain; de is its drop-log entry.  A slot then holds at S_n the atom it held
 // at S_{n+1} if that atom was kept, the dropped atom if one left, or nothing.
 template <int L, bool MOVED>
 __device__ __forceinline__ void reverse_step_regs(AdjIon& ai, AdjAtoms<L>& aa, PairState<L>& P, TrackRegs<L>& t,
@@ -153,6 +157,8 @@ __device__ __forceinline__ void reverse_step_regs(AdjIon& ai, AdjAtoms<L>& aa, P
     const double fr2 = exp_neg(g2 * h1);
     const double x[3] = {lgn[2], lgn[3], lgn[4]};
     const double v[3] = {lgn[5], lgn[6], lgn[7]};
+    const double F[3] = {lgn[8], lgn[9], lgn[10]};
+    const double rho = lgn[11];
     const double vp[3] = {t.vx, t.vy, t.vz};
     double q[3];
     for (int k = 0; k < 3; ++k) q[k] = vp[k] / fr2;
@@ -173,8 +179,8 @@ __device__ __forceinline__ void reverse_step_regs(AdjIon& ai, AdjAtoms<L>& aa, P
 
     // ---- per slot: reconstruct the atom of S_n and its pair term; adjoint of the
     //      second kick, the pair term of S_{n+1}, the drift and the first kick
-    double x1b_l[3] = {0.0, 0.0, 0.0}, F_l[3] = {0.0, 0.0, 0.0};
-    double dtb_l = 0.0, h2b_l = 0.0, rho_l = 0.0, vm_l = 0.0, fm_l = 0.0;
+    double x1b_l[3] = {0.0, 0.0, 0.0};
+    double dtb_l = 0.0, h2b_l = 0.0, vm_l = 0.0, fm_l = 0.0;
     double v2s[SL], f2s[SL];   // the slots' |V|^2 and |f|^2 as maximised (the argmax is found by equality)
 #pragma unroll
     for (int i = 0; i < SL; ++i) {
@@ -221,9 +227,7 @@ __device__ __forceinline__ void reverse_step_regs(AdjIon& ai, AdjAtoms<L>& aa, P
             for (int k = 0; k < 3; ++k) {
                 fn[k] = -cn * dn[k];
                 if (kept) Vn[k] = U[k] - fn[k] * h2;
-                F_l[k] += cn * dn[k];
             }
-            rho_l += wn;
             v2s[i] = Vn[0] * Vn[0] + Vn[1] * Vn[1] + Vn[2] * Vn[2];
             f2s[i] = fn[0] * fn[0] + fn[1] * fn[1] + fn[2] * fn[2];
             vm_l = fmax(vm_l, v2s[i]);
@@ -277,14 +281,12 @@ __device__ __forceinline__ void reverse_step_regs(AdjIon& ai, AdjAtoms<L>& aa, P
         // one slot at a time: interleaving the slots' pair terms costs more registers than it hides
         __builtin_amdgcn_sched_barrier(0);
     }
-    double F[3], x1b[3];
-    for (int k = 0; k < 3; ++k) {
-        F[k] = SegReduce<L>::sum(F_l[k]);
-        x1b[k] = ai.xb[k] + SegReduce<L>::sum(x1b_l[k]);
-    }
-    const double rho = SegReduce<L>::sum(rho_l);
-    const double vm = SegReduce<L>::max(vm_l);
-    const double fm = SegReduce<L>::max(fm_l);
+    double x1b[3];
+    for (int k = 0; k < 3; ++k) x1b[k] = ai.xb[k] + SegReduce<L>::sum(x1b_l[k]);
+    // the atoms' maxima are reduced only when an atom's speed or acceleration set dt
+    const int branch = code & 3;
+    const double vm = (branch == 1 && !(code & 4)) ? SegReduce<L>::max(vm_l) : 0.0;
+    const double fm = (branch == 2 && !(code & 8)) ? SegReduce<L>::max(fm_l) : 0.0;
     // d/dt through the atoms' drifts and, via h2 = dt / 2M2, their kicks: one reduction
     double dtb = SegReduce<L>::sum(dtb_l + h2b_l * A.half_inv_M2);
 
@@ -319,12 +321,9 @@ __device__ __forceinline__ void reverse_step_regs(AdjIon& ai, AdjAtoms<L>& aa, P
     t.x = x[0]; t.y = x[1]; t.z = x[2];
     t.vx = v[0]; t.vy = v[1]; t.vz = v[2];
     t.Fx = F[0]; t.Fy = F[1]; t.Fz = F[2];
-    t.rho = rho;
-    t.vmax2a = vm;
-    t.amax2a = fm * A.inv_M2sq;
+    t.rho = rho;   // (the atom maxima of t are not kept up to date in the reverse)
 
     // ---- the active term of the step-size minimum and its maximising particle
-    const int branch = code & 3;
     if (branch == 1) {
         const bool ion = (code & 4) != 0;
         const double v2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
@@ -387,7 +386,7 @@ __global__ void __launch_bounds__(64, REEDMD_GRAD_WAVES_PER_SIMD) grad_kernel(co
     if (q >= A.q_end) return;
     double* ck = A.ckpt + static_cast<size_t>(local) * A.ckpt_cap * kRecWords;
     double* dl = A.droplog + static_cast<size_t>(local) * A.drop_cap * kDropWords;
-    double* lg = A.steplog + static_cast<size_t>(local) * A.ckpt_cap * 512;
+    double* lg = A.steplog + static_cast<size_t>(local) * A.ckpt_cap * 64 * kLogWords;
     double* out = A.gout + static_cast<size_t>(q) * 5;
 
     TrackRegs<L> t;
@@ -412,16 +411,16 @@ __global__ void __launch_bounds__(64, REEDMD_GRAD_WAVES_PER_SIMD) grad_kernel(co
     for (;;) {
         const long long n = t.steps;
         const int ocx = t.cx, ocy = t.cy, ocz = t.cz;
-        const double ion[6] = {t.x, t.y, t.z, t.vx, t.vy, t.vz};
+        const double ion[10] = {t.x, t.y, t.z, t.vx, t.vy, t.vz, t.Fx, t.Fy, t.Fz, t.rho};
         double* de = dl + static_cast<size_t>(moves) * kDropWords;
         StepInfo si;
         track_step<L>(t, A, sp, sl, false, ke0, z0, &si, de + 8);
         const bool moved = t.cx != ocx || t.cy != ocy || t.cz != ocz;
         if (sl == 0) {
-            double* e = lg + 8 * n;
+            double* e = lg + kLogWords * n;
             e[0] = si.dt;
             reinterpret_cast<long long*>(e)[1] = si.code | (moved ? 16 : 0);
-            for (int k = 0; k < 6; ++k) e[2 + k] = ion[k];
+            for (int k = 0; k < 10; ++k) e[2 + k] = ion[k];
             if (moved) {
                 de[0] = static_cast<double>(ocx);
                 de[1] = static_cast<double>(ocy);
@@ -482,7 +481,7 @@ __global__ void __launch_bounds__(64, REEDMD_GRAD_WAVES_PER_SIMD) grad_kernel(co
         if (end != N) load_record<L>(t, ck + static_cast<size_t>(end >> 6) * kRecWords, sl, A);
         pair_state<L>(t, A, c, P);
         for (long long n = end - 1; n >= start; --n) {
-            const double* lgn = lg + 8 * n;
+            const double* lgn = lg + kLogWords * n;
             if (reinterpret_cast<const long long*>(lgn)[1] & 16) {
                 --moves;
                 reverse_step_regs<L, true>(ai, aa, P, t, A, c, lgn, dl + static_cast<size_t>(moves) * kDropWords, sl,

@@ -894,7 +894,7 @@ reedmd_status reedmd_grad(reedmd_ctx* ctx, const reedmd_species* species, const 
     const int ckpt_cap = static_cast<int>(max_steps / 64 + 1);
     // checkpoints, the step log, and the drop log (up to one domain move per 32 steps)
     const int drop_cap = 2 * ckpt_cap;
-    const size_t per_track = (static_cast<size_t>(ckpt_cap) * kRecWords + static_cast<size_t>(ckpt_cap) * 512 +
+    const size_t per_track = (static_cast<size_t>(ckpt_cap) * kRecWords + static_cast<size_t>(ckpt_cap) * 64 * kLogWords +
                               static_cast<size_t>(drop_cap) * kDropWords) * sizeof(double);
     const long long chunk = std::max<long long>(1, std::min<long long>(n, static_cast<long long>(kGradScratchBytes / per_track)));
     const size_t out_bytes = static_cast<size_t>(n) * 5 * sizeof(double) + 64;
@@ -924,7 +924,7 @@ reedmd_status reedmd_grad(reedmd_ctx* ctx, const reedmd_species* species, const 
     double* base = ctx->gscratch;
     A.ckpt = base;
     A.steplog = base + static_cast<size_t>(chunk) * ckpt_cap * kRecWords;
-    A.droplog = A.steplog + static_cast<size_t>(chunk) * ckpt_cap * 512;
+    A.droplog = A.steplog + static_cast<size_t>(chunk) * ckpt_cap * 64 * kLogWords;
     A.drop_cap = drop_cap;
     double* own_out = A.droplog + static_cast<size_t>(chunk) * drop_cap * kDropWords;
     double* res = own_out + static_cast<size_t>(n) * 5;

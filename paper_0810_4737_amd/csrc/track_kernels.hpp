@@ -90,7 +90,7 @@ struct KernelArgs {
     // gradient entry point
     double inv_s;           // 1 / screening-length scale
     double* ckpt;           // [n][ckpt_cap][kRecWords]  state every 64 steps
-    double* steplog;        // [n][ckpt_cap * 64][8]     per step: dt, StepInfo code, ion x and v before it
+    double* steplog;        // [n][ckpt_cap * 64][12]    per step: dt, StepInfo code, ion x, v, F, rho before it
     double* droplog;        // [n][drop_cap][kDropWords] per domain move: the old centre, the dropped atoms
     int drop_cap;
     int ckpt_cap;
