@@ -37,10 +37,10 @@ FLOP_PER_PAIR_F32_PART = 38
 # WRITE x 1.000); reported only while the track kernel's device sources (track_kernels.hpp,
 # device_physics.hpp) and the launch match the ones the counters were taken on.
 MEASURED_TRAFFIC = {
-    "sources_sha256_prefix": "f4e1711fa6436bb7",
+    "sources_sha256_prefix": "0ab5b717fc6cb522",
     "workload": "c1", "form": "persistent", "lanes": 16,
-    "fetch_bytes": 2607269.6875 * 1024 * 2.000,
-    "write_bytes": 5176687.0 * 1024 * 1.000,
+    "fetch_bytes": 2610341.6875 * 1024 * 2.000,
+    "write_bytes": 5175379.78125 * 1024 * 1.000,
 }
 
 
