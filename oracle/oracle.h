@@ -36,8 +36,10 @@
  * screening length and nuclear stopping against closed forms and published
  * fits; the stopping constant against Lindhard's reduced form; pure friction
  * and the collision-free stopping depth and its k-derivative against closed
- * forms; head-on turning points and scattering angles against root finding and
- * quadrature; energy, momentum and weight ledgers; splitting against brute
+ * forms; the time step's speed, acceleration (ion and atom masses) and dt_max
+ * branches against their closed forms; the backscatter rule on free ions
+ * crossing z_start in both directions; head-on turning points and scattering
+ * angles against root finding and quadrature; energy, momentum and weight ledgers; splitting against brute
  * force; the forward-mode derivative against finite differences of the
  * oracle's own stopping depth.  Fluorite (tests/test_oracle_fluorite.py):
  * textbook geometry and coordination, the anion pair and stopping constants

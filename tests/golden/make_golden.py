@@ -13,6 +13,10 @@ Usage:  python tests/golden/make_golden.py [pilot|pilot2|pilot4|c0|c1|c2|c4|refi
   c1:    1,024 As at 10 keV with the 8 cloning depths: ids 0..511 (channel) and 32768..33279 (tilt)
   refine: 2,048 B at 1 keV (the c0 sampler, ids 0..2047) with 6 adaptive cloning depths at
          survival 2^-k, re-placed between 4 epochs from a deliberately shallow first table
+  c1big: 8,192 As at 10 keV with the 8 cloning depths: ids 0..4095 (channel) and 32768..36863 (tilt)
+  c2big: 16,384 primaries of the mixed B/P/As 1-100 keV workload (ids 0..16383), 6 x 12 depths
+  c4big: 1,024 As at 100 keV along [001] (ids 0..1023), 16 depths to 1e-6
+  (the *big runs use the library's default step cap of 2,000,000 steps per track)
 Outputs go next to this file as JSON (histogram, totals, moments) plus gzipped text of every
 stopped track's depth and weight.
 """
@@ -36,13 +40,16 @@ def sampler(w):
     return oracle.SamplerCfg(**w["sampler"])
 
 
-def save(name, cfg_desc, r, extra=None):
+def save(name, cfg_desc, r, extra=None, lineage=False):
+    """lineage=True adds each stopped track's primary id as a third column (standard errors
+    by primary family)."""
     st = r["stats"]
     log = r["log"]
     stopped = log[log["status"] == oracle.STOPPED]
-    order = np.lexsort((stopped["w"], stopped["z_stop"]))
+    order = np.lexsort((stopped["lineage"], stopped["w"], stopped["z_stop"]))
     z = stopped["z_stop"][order]
     w = stopped["w"][order]
+    lin = stopped["lineage"][order]
     W = w.sum()
     mean = float((w * z).sum() / W)
     std = float(math.sqrt((w * (z - mean) ** 2).sum() / W))
@@ -53,8 +60,12 @@ def save(name, cfg_desc, r, extra=None):
     with open(os.path.join(HERE, name + ".json"), "w") as f:
         json.dump(out, f, indent=0)
     with gzip.open(os.path.join(HERE, name + "_stopped.txt.gz"), "wt") as f:
-        for zi, wi in zip(z, w):
-            f.write(f"{zi:.17g} {wi:.17g}\n")
+        if lineage:
+            for zi, wi, li in zip(z, w, lin):
+                f.write(f"{zi:.17g} {wi:.17g} {int(li)}\n")
+        else:
+            for zi, wi in zip(z, w):
+                f.write(f"{zi:.17g} {wi:.17g}\n")
 
 
 def pilot():
@@ -241,8 +252,57 @@ def c4():
     save("c4_subset", dict(name="c4_as100kev", ids=[[0, 32]], seed=0), r)
 
 
+# step cap of the larger stored runs: the HIP library's default, so that both sides quarantine
+# the same (rare) tracks that never slow below the stopping energy
+BIG_MAX_STEPS = 2_000_000
+
+
+def c1big():
+    """8,192 primaries of the 10 keV As workload: ids 0..4095 (channel) and 32768..36863 (tilt)."""
+    w = WORKLOADS["c1_as10kev"]
+    sc = sampler(w)
+    a = oracle.sample_primaries(sc, 0, 4096, id0=0)
+    b = oracle.sample_primaries(sc, 0, 4096, id0=32768)
+    prim = {k: np.concatenate([a[k], b[k]], axis=-1) for k in a}
+    lineage = np.concatenate([np.arange(4096), 32768 + np.arange(4096)]).astype(np.int64)
+    cfg = oracle.Config(species=w["species"], n_bins=w["n_bins"], bin_width=w["bin_width"],
+                        thresholds=[list(C1_THRESHOLDS)], max_steps=BIG_MAX_STEPS)
+    t = time.time()
+    r = oracle.run(cfg, prim, log=True, lineage=lineage)
+    print("c1big oracle seconds", time.time() - t, r["stats"], flush=True)
+    save("c1_accept", dict(name="c1_as10kev", ids=[[0, 4096], [32768, 36864]], seed=0,
+                           thresholds=list(C1_THRESHOLDS), max_steps=BIG_MAX_STEPS), r,
+         lineage=True)
+
+
+def c2big():
+    """16,384 primaries of the mixed workload (ids 0..16383), all 12-depth tables."""
+    w = WORKLOADS["c2_mixed"]
+    prim = oracle.sample_primaries(sampler(w), 0, 16384)
+    cfg = oracle.Config(species=w["species"], n_bins=w["n_bins"], bin_width=w["bin_width"],
+                        thresholds=C2_THRESHOLDS, max_steps=BIG_MAX_STEPS)
+    t = time.time()
+    r = oracle.run(cfg, prim, log=True)
+    print("c2big oracle seconds", time.time() - t, r["stats"], flush=True)
+    save("c2_accept", dict(name="c2_mixed", ids=[[0, 16384]], seed=0, max_steps=BIG_MAX_STEPS), r, lineage=True)
+
+
+def c4big():
+    """1,024 primaries of the 100 keV As channeling workload (ids 0..1023), 16 depths."""
+    w = WORKLOADS["c4_as100kev"]
+    prim = oracle.sample_primaries(sampler(w), 0, 1024)
+    cfg = oracle.Config(species=w["species"], n_bins=w["n_bins"], bin_width=w["bin_width"],
+                        thresholds=[list(C4_THRESHOLDS)], max_steps=BIG_MAX_STEPS)
+    t = time.time()
+    r = oracle.run(cfg, prim, log=True)
+    print("c4big oracle seconds", time.time() - t, r["stats"], flush=True)
+    save("c4_accept", dict(name="c4_as100kev", ids=[[0, 1024]], seed=0, max_steps=BIG_MAX_STEPS), r,
+         lineage=True)
+
+
 if __name__ == "__main__":
     what = sys.argv[1:] or ["c0", "c1"]
     for w in what:
         {"pilot": pilot, "pilot2": pilot2, "pilot4": pilot4, "pilot5": pilot5, "c0": c0, "c1": c1, "c2": c2,
-         "c4": c4, "c5": c5, "c5refine": c5refine, "refine": refine}[w]()
+         "c4": c4, "c5": c5, "c5refine": c5refine, "refine": refine, "c1big": c1big, "c2big": c2big,
+         "c4big": c4big}[w]()

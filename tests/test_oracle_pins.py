@@ -165,6 +165,75 @@ def test_time_step_follows_kinetic_scale():
         assert abs(dt * v0 / c.dx_max - 1.0) < 1e-12
 
 
+@pytest.mark.parametrize("r", [0.4, 1.0, 2.0])
+@pytest.mark.parametrize("dx_max", [0.05, 0.01])
+def test_time_step_acceleration_branch(r, dx_max):
+    """Fig. 2 / collisional scale: an ion at rest at distance r from one free atom moves by
+    a t^2 / 2 in a step, so the step that keeps that below dx_max is
+    dt = sqrt(2 dx_max / a) with a = |V'(r)| / M of the particle that accelerates most.
+    B (10.81 u) on Si (28.0855 u): the ion, a = |V'| / M1.  B on a light target (4 u): the
+    atom, a = |V'| / M2.  |V'(r)| is the ZBL derivative, itself pinned against Richardson
+    differences of V(r) (test_zbl_force_is_derivative_of_potential)."""
+    for M2 in (28.0855, 4.0):
+        c = cfg(structure=oracle.ISOLATED, stop_mode=oracle.STOP_OFF, dx_max=dx_max, M2=M2)
+        t = oracle.Track.start(c, B, 0.0, [0.0, 0.0, -r], [0.0, 0.0, 1.0], 1)
+        F = abs(oracle.zbl(c, B, r)[1])
+        M = min(10.81, M2)                     # the lighter particle accelerates most
+        ref = math.sqrt(2.0 * dx_max * M / F)
+        assert ref < c.dt_max
+        dt = t.step()
+        assert abs(dt / ref - 1.0) < 1e-13, (M2, dt, ref)
+    # far from the atom and at rest nothing limits the step but dt_max
+    c = cfg(structure=oracle.ISOLATED, stop_mode=oracle.STOP_OFF, dx_max=dx_max)
+    t = oracle.Track.start(c, B, 0.0, [0.0, 0.0, -200.0], [0.0, 0.0, 1.0], 1)
+    assert t.step() == c.dt_max
+
+
+def test_time_step_takes_the_smaller_branch():
+    """A slow ion near an atom: the acceleration branch is below the speed branch and wins;
+    a fast one far away: dx_max / |v|."""
+    c = cfg(structure=oracle.ISOLATED, stop_mode=oracle.STOP_OFF)
+    r, E = 0.6, 0.5
+    t = oracle.Track.start(c, B, E, [0.0, 0.0, -r], [1.0, 0.0, 0.0], 1)
+    F = abs(oracle.zbl(c, B, r)[1])
+    da = math.sqrt(2.0 * c.dx_max * 10.81 / F)
+    dv = c.dx_max / math.sqrt(2.0 * E / 10.81)
+    assert da < dv
+    assert abs(t.step() / da - 1.0) < 1e-13
+    t = oracle.Track.start(c, B, 5000.0, [0.0, 0.0, -40.0], [1.0, 0.0, 0.0], 1)
+    assert abs(t.step() * math.sqrt(2.0 * 5000.0 / 10.81) / c.dx_max - 1.0) < 1e-12
+
+
+def _free_track_status(c, z0, dz, nsteps):
+    t = oracle.Track.start(c, B, 1000.0, [1.7, 2.3, z0], [0.0, 0.0, dz], 5)
+    t.advance(nsteps, events=True)
+    st = t.state()
+    return st["status"], st["steps"], st["x"][2]
+
+
+def test_backscatter_rule():
+    """Termination on backscatter (z < z_start while moving outward, v_z < 0), decided after
+    each step.  A free ion (no forces, no stopping) moves exactly dx_max per step:
+    - from z = -2.93 A outward it is at -2.98 A after one step (still above z_start = -3 A,
+      active) and at -3.03 A after the second, where it ends as backscattered;
+    - from z = -5 A (below z_start) moving inward it never backscatters;
+    - moving parallel to the surface below z_start (v_z = 0) it never backscatters."""
+    c = cfg(pot_mode=oracle.POT_NONE, stop_mode=oracle.STOP_OFF)
+    st, n, z = _free_track_status(c, -2.93, -1.0, 50)
+    assert st == oracle.BACKSCATTERED and n == 2 and z < c.z_start
+    st, n, z = _free_track_status(c, -2.93, -1.0, 1)
+    assert st == oracle.ACTIVE and n == 1 and z > c.z_start
+    st, n, z = _free_track_status(c, -5.0, 1.0, 30)
+    assert st == oracle.ACTIVE and n == 30 and z < c.z_start
+    t = oracle.Track.start(c, B, 1000.0, [1.7, 2.3, -3.5], [1.0, 0.0, 0.0], 5)
+    t.advance(30, events=True)
+    assert t.state()["status"] == oracle.ACTIVE and t.state()["steps"] == 30
+    # the rule follows z_start: with z_start = -4 A the outward ion from -3.93 A ends on step 2
+    c4 = cfg(pot_mode=oracle.POT_NONE, stop_mode=oracle.STOP_OFF, z_start=-4.0)
+    st, n, z = _free_track_status(c4, -3.93, -1.0, 50)
+    assert st == oracle.BACKSCATTERED and n == 2
+
+
 def test_local_density_averages_to_atomic_density():
     """rho(x) = sum_j w(|x - x_j|) with a unit-integral kernel: its mean over ion positions in
     a cell equals the atomic density N up to the kernel mass outside the domain (midpoint grid)."""
