@@ -1,12 +1,17 @@
 """Throughput benchmark of the REED-MD hot path on one MI355X.
 
-One step = sample the 65,536 primaries of the 10 keV As workload on the device and run
-every primary with all of its clones to termination (domain following, ZBL forces, local
-stopping, adaptive velocity Verlet, cloning at 8 depths, weighted histogram).  Prints one
-JSON line: ion-atom force evaluations per second (value), tracks per second, the FP64
-VALU roofline fraction of the track kernel, the FP32 pair-term variant and the 85 keV U
-recoil in fluorite UO2 beside it, and the FP64 CPU oracle timed on a bounded sample of the
-same workload on the host cores.
+Headline workload: the uneven batch, 1,048,576 primaries with species uniform over B, P and
+As and energies log-uniform in 1-100 keV into diamond Si at 7 degree tilt, 6 cloning-depth
+tables (species x energy decade) of 12 depths each, run by the persistent kernel with its
+device work queue, kept as a HIP graph, in the launch shape the autotuner picks.  One step =
+sample the next 1/K of the primaries on the device (K = --steps) and run each of them with
+all of its clones to termination (domain following, ZBL forces, local stopping, adaptive
+velocity Verlet, cloning, weighted histogram); the K timed steps together run the whole
+workload, warm-up steps use primaries from a disjoint id range.  Prints one JSON line:
+ion-atom force evaluations per second (value), tracks per second, the FP64 VALU roofline
+fraction of the track kernel, the FP64 CPU oracle on a bounded sample of the same workload,
+and beside them the 10 keV As workload with its profile accuracy, the FP32 pair-term
+variant, the 85 keV U recoils in fluorite UO2 and the adjoint gradient.
 """
 from __future__ import annotations
 
@@ -38,7 +43,7 @@ FLOP_PER_PAIR_F32_PART = 38
 # device_physics.hpp) and the launch match the ones the counters were taken on.
 MEASURED_TRAFFIC = {
     "sources_sha256_prefix": "0ab5b717fc6cb522",
-    "workload": "c1", "form": "persistent", "lanes": 16,
+    "workload": "c1", "form": "persistent", "lanes": 16, "primaries": 65536, "slice": 65536,
     "fetch_bytes": 2610341.6875 * 1024 * 2.000,
     "write_bytes": 5175379.78125 * 1024 * 1.000,
 }
@@ -60,59 +65,85 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", choices=["c1", "c2", "c4"], default="c2",
+                    help="c2: mixed B/P/As 1-100 keV, 1,048,576 primaries (default, the benchmark line); "
+                         "c1: 10 keV As, 65,536 primaries; c4: 100 keV As [001] channeling, 262,144 primaries")
+    ap.add_argument("--n", type=int, default=0, help="primaries of the workload (default: its full size)")
+    ap.add_argument("--whole", action="store_true",
+                    help="every step runs the whole workload (default for c1) instead of the next 1/steps of it")
     ap.add_argument("--form", choices=["auto", "plain", "persistent"], default="persistent")
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--waves", type=int, default=0, help="resident waves per CU with --lanes (0: by occupancy)")
     ap.add_argument("--queue", type=int, default=0, help="clone-queue capacity in records (0: library default)")
     ap.add_argument("--refine-epochs", type=int, default=0,
-                    help="also time one run with the cloning depths re-placed between this many epochs "
-                         "(10 keV As workload: targets 2^-k, first table the stored depths); reported apart")
-    ap.add_argument("--n", type=int, default=0, help="primaries (default: the workload's full size)")
-    ap.add_argument("--workload", choices=["c1", "c2", "c4"], default="c1",
-                    help="c1: 10 keV As (default, the benchmark line); c2: mixed B/P/As 1-100 keV, "
-                         "1,048,576 tracks; c4: 100 keV As [001] channeling, 262,144 tracks")
+                    help="also time one run of the 10 keV As workload with the cloning depths re-placed "
+                         "between this many epochs (targets 2^-k, first table the stored depths); reported apart")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-c1", action="store_true", help="skip the 10 keV As leg")
     ap.add_argument("--no-grad", action="store_true", help="skip the gradient / forward time ratio")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 pair-term variant leg")
     ap.add_argument("--no-uo2", action="store_true", help="skip the 85 keV U recoil in UO2 leg")
     ap.add_argument("--uo2-n", type=int, default=0, help="primaries of the UO2 leg (default: the workload's 5,120)")
     ap.add_argument("--pipelined", type=int, default=0,
-                    help="also time this many batches back to back on two streams and contexts (tail overlap)")
+                    help="also time this many 10 keV As batches back to back on two streams and contexts")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (HBM counter calibration)")
     return ap.parse_args()
 
 
-def cpu_baseline(target_seconds):
-    """The FP64 oracle on the host cores, on the first ids of both halves of the workload."""
+WORKLOAD_NAMES = {"c1": "c1_as10kev", "c2": "c2_mixed", "c4": "c4_as100kev"}
+
+
+def workload_setup(R, key, n):
+    """(workload dict, sampler, depth tables, tail depth) of a benchmark workload."""
+    from tests.workloads import C1_THRESHOLDS, C2_THRESHOLDS, C4_THRESHOLDS, WORKLOADS
+    w = WORKLOADS[WORKLOAD_NAMES[key]]
+    if key == "c1":
+        return w, R.SamplerConfig(**dict(w["sampler"], n_cone=n // 2)), [list(C1_THRESHOLDS)], C1_THRESHOLDS[6]
+    if key == "c2":
+        return w, R.SamplerConfig(**w["sampler"]), [list(t) for t in C2_THRESHOLDS], 2000.0
+    return w, R.SamplerConfig(**w["sampler"]), [list(C4_THRESHOLDS)], 4000.0
+
+
+def cpu_baseline(key, target_seconds):
+    """The FP64 oracle on the host cores, on the first primaries of the same workload (for the
+    10 keV As workload the first ids of both halves), run in chunks of one primary per core
+    until the time box is used."""
     import numpy as np
 
     import oracle
-    from tests.workloads import C1_THRESHOLDS, WORKLOADS
-    w = WORKLOADS["c1_as10kev"]
+    from tests.workloads import C1_THRESHOLDS, C2_THRESHOLDS, C4_THRESHOLDS, WORKLOADS
+    w = WORKLOADS[WORKLOAD_NAMES[key]]
+    thr = {"c1": [list(C1_THRESHOLDS)], "c2": [list(t) for t in C2_THRESHOLDS], "c4": [list(C4_THRESHOLDS)]}[key]
     sc = oracle.SamplerCfg(**w["sampler"])
-    cfg = oracle.Config(species=w["species"], n_bins=w["n_bins"], bin_width=w["bin_width"],
-                        thresholds=[list(C1_THRESHOLDS)])
+    cfg = oracle.Config(species=w["species"], n_bins=w["n_bins"], bin_width=w["bin_width"], thresholds=thr,
+                        max_steps=2_000_000)
     cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
-    k = max(1, cores // 2)
     total_pairs, total_tracks, total_prim, t_all = 0, 0, 0, 0.0
     offset = 0
+    half = w["n"] // 2
     while t_all < target_seconds and offset < 4096:
-        a = oracle.sample_primaries(sc, 0, k, id0=offset)
-        b = oracle.sample_primaries(sc, 0, k, id0=32768 + offset)
-        prim = {q: np.concatenate([a[q], b[q]], axis=-1) for q in a}
-        lin = np.concatenate([offset + np.arange(k), 32768 + offset + np.arange(k)]).astype(np.int64)
+        if key == "c1":
+            k = max(1, cores // 2)
+            a = oracle.sample_primaries(sc, 0, k, id0=offset)
+            b = oracle.sample_primaries(sc, 0, k, id0=half + offset)
+            prim = {q: np.concatenate([a[q], b[q]], axis=-1) for q in a}
+            lin = np.concatenate([offset + np.arange(k), half + offset + np.arange(k)]).astype(np.int64)
+        else:
+            k = cores
+            prim = oracle.sample_primaries(sc, 0, k, id0=offset)
+            lin = (offset + np.arange(k)).astype(np.int64)
         t0 = time.perf_counter()
         r = oracle.run(cfg, prim, nthreads=cores, lineage=lin)
         t_all += time.perf_counter() - t0
         total_pairs += r["stats"]["pair_evals"]
         total_tracks += r["stats"]["finished"]
-        total_prim += 2 * k
+        total_prim += len(lin)
         offset += k
+    ids = (f"ids 0..{offset - 1} and {half}..{half + offset - 1}" if key == "c1" else f"ids 0..{offset - 1}")
     return dict(value=total_pairs / t_all, unit="force evals/s", cores=cores, kind="oracle",
-                sample=f"{total_prim} primaries of the same workload (ids 0..{offset - 1} and "
-                       f"32768..{32768 + offset - 1}, all clones), {t_all:.1f} s wall, "
+                sample=f"{total_prim} primaries of the same workload ({ids}, all clones), {t_all:.1f} s wall, "
                        f"{total_tracks / t_all:.1f} tracks/s")
 
 
@@ -214,29 +245,32 @@ def pipelined_leg(R, torch, w, sampler, n, cfg, k_steps, species):
                 method="two streams and contexts, batches alternate, no host synchronisation between them")
 
 
-def fp32_leg(R, ctx, torch, w, sampler, n, base, stream, hist, stats, form, lanes=0, waves=0):
+def fp32_leg(R, ctx, torch, w, sampler, slices, base, stream, form, lanes=0, waves=0):
     """The same workload with the FP32 pair term (FP64 integration and step control): its
-    own autotuned shape (or the one given), one warm launch, two timed launches.  Reported
-    beside the FP64 headline, never as it."""
+    own autotuned shape (or the one given), one warm launch, then the given (id0, n) slices
+    timed.  Reported beside the FP64 headline, never as it."""
     f = R.FORM_PLAIN if form == "plain" else R.FORM_PERSISTENT
-    batch = R.sample_primaries(ctx, sampler, 0, n)
+    id0, n = slices[0]
+    batch = R.sample_primaries(ctx, sampler, 0, n, id0=id0)
     if lanes == 0:
         lanes, waves = R.autotune(ctx, w["species"], batch,
                                   R.RunConfig(form=f, force_precision=R.FORCE_FP32, **base), pilot=n)
     cfg = R.RunConfig(form=f, lanes_per_track=lanes, waves_per_cu=waves, force_precision=R.FORCE_FP32, **base)
-    R.run(ctx, w["species"], batch, cfg)
+    R.run(ctx, w["species"], batch, cfg, id0=id0)
     torch.cuda.synchronize()
     kms, pairs, tracks = [], 0, 0
     t_all = 0.0
-    for _ in range(2):
-        b = R.sample_primaries(ctx, sampler, 0, n, stream=stream)
+    hist = torch.zeros(w["n_bins"], dtype=torch.float64, device="cuda")
+    stats = R.new_stats()
+    for id0, n in slices:
+        b = R.sample_primaries(ctx, sampler, 0, n, id0=id0, stream=stream)
         hist.zero_()
         stats.zero_()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         e0.record(stream)
-        R.run(ctx, w["species"], b, cfg, hist=hist, stats=stats, stream=stream)
+        R.run(ctx, w["species"], b, cfg, hist=hist, stats=stats, id0=id0, stream=stream)
         e1.record(stream)
         torch.cuda.synchronize()
         t_all += time.perf_counter() - t0
@@ -244,17 +278,17 @@ def fp32_leg(R, ctx, torch, w, sampler, n, base, stream, hist, stats, form, lane
         pairs += st["pair_evals"]
         tracks += st["finished"]
         kms.append(e0.elapsed_time(e1))
-    k = sum(kms) / len(kms)
-    ppl = pairs / 2
+    k_total = sum(kms) * 1e-3
     # ideal time at the two vector peaks over the measured kernel time
-    t_ideal = ppl * ((FLOP_PER_PAIR - FLOP_PER_PAIR_F32_PART) / FP64_VECTOR_PEAK_TFLOPS +
-                     FLOP_PER_PAIR_F32_PART / FP32_VECTOR_PEAK_TFLOPS) * 1e-12
+    t_ideal = pairs * ((FLOP_PER_PAIR - FLOP_PER_PAIR_F32_PART) / FP64_VECTOR_PEAK_TFLOPS +
+                       FLOP_PER_PAIR_F32_PART / FP32_VECTOR_PEAK_TFLOPS) * 1e-12
     return dict(force_evals_per_s=pairs / t_all, tracks_per_s=tracks / t_all,
                 kernel_ms_per_step=[round(x, 1) for x in kms], lanes_per_track=lanes, waves_per_cu=waves,
+                slices=[list(x) for x in slices],
                 roofline={"bound": "alu", "peak": f"FP64 {FP64_VECTOR_PEAK_TFLOPS} + FP32 {FP32_VECTOR_PEAK_TFLOPS} TFLOP/s",
                           "fp64_flop_per_pair": FLOP_PER_PAIR - FLOP_PER_PAIR_F32_PART,
                           "fp32_flop_per_pair": FLOP_PER_PAIR_F32_PART,
-                          "frac": t_ideal / (k * 1e-3)},
+                          "frac": t_ideal / k_total},
                 tolerance="1e-5 relative per step against the FP64 oracle")
 
 
@@ -338,6 +372,117 @@ def grad_forward_ratio(R, ctx, torch):
                 stopped=g["count"])
 
 
+def plan_steps(N, K, W, whole):
+    """(primaries per step, timed (id0, n) slices, warm-up slices).  Sliced: timed step k runs
+    ids [k s, (k+1) s) with s = ceil(N / K), so the timed steps together run ids 0..N-1 once;
+    warm-up step j runs ids [N + j s, N + (j+1) s), disjoint from them.  Whole: every step runs
+    ids 0..N-1."""
+    K = max(1, K)
+    if whole:
+        return N, [(0, N)] * K, [(0, N)] * W
+    s = -(-N // K)
+    return s, [(j * s, min(s, N - j * s)) for j in range(K) if j * s < N], [(N + j * s, s) for j in range(W)]
+
+
+def timed_launches(R, torch, ctx, w, sampler, cfg, slices, stream, log_first=False):
+    """Runs each (id0, n) slice: sample on the device, clear the outputs, run; HIP events on
+    the launch stream bracket the run.  Returns per-launch kernel ms, summed statistics and
+    the wall time, and checks every launch's weight ledger."""
+    hist = torch.zeros(w["n_bins"], dtype=torch.float64, device="cuda")
+    stats = R.new_stats()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in slices]
+    tot = dict(pairs=0, tracks=0, prims=0, steps=0)
+    kms, queue_use, log = [], [], None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k, (id0, n) in enumerate(slices):
+        b = R.sample_primaries(ctx, sampler, 0, n, id0=id0, stream=stream)
+        hist.zero_()
+        stats.zero_()
+        ev[k][0].record(stream)
+        if log_first and k == 0:
+            _, _, lg, _ = R.run(ctx, w["species"], b, cfg, hist=hist, stats=stats, id0=id0, log_cap=40 * n,
+                                stream=stream)
+        else:
+            R.run(ctx, w["species"], b, cfg, hist=hist, stats=stats, id0=id0, stream=stream)
+        ev[k][1].record(stream)
+        torch.cuda.synchronize()
+        st = R.parse_stats(stats)
+        if log_first and k == 0:
+            log = R.parse_log(lg, min(st["log_count"], 40 * n))
+        ledger = float(hist.sum().item()) + st["w_underflow"] + st["w_overflow"] + st["w_backscattered"] + \
+            st["w_quarantined"] + st["w_cancelled"]
+        assert ledger == float(n) and st["primaries"] == n, ("weight ledger broken", k, ledger, n)
+        tot["pairs"] += st["pair_evals"]
+        tot["tracks"] += st["finished"]
+        tot["prims"] += st["primaries"]
+        tot["steps"] += st["track_steps"]
+        kms.append(ev[k][0].elapsed_time(ev[k][1]))
+        queue_use.append([st["max_queue"], st["stack_overflow"]])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return kms, tot, wall, queue_use, log
+
+
+def c1_leg(R, torch, np, args):
+    """The 10 keV As workload (65,536 primaries, 8 cloning depths) in its autotuned persistent
+    shape: one warm launch that logs every finished track (profile accuracy against the same
+    primaries without cloning), then two timed launches of the whole batch."""
+    n = 65536
+    ctx = R.Context()
+    w, sampler, thr, tail_depth = workload_setup(R, "c1", n)
+    base = dict(n_bins=w["n_bins"], bin_width=w["bin_width"], thresholds=thr, queue_capacity=args.queue)
+    batch = R.sample_primaries(ctx, sampler, 0, n)
+    lanes, waves = R.autotune(ctx, w["species"], batch, R.RunConfig(form=R.FORM_PERSISTENT, **base), pilot=n)
+    cfg = R.RunConfig(form=R.FORM_PERSISTENT, lanes_per_track=lanes, waves_per_cu=waves, **base)
+    stream = torch.cuda.current_stream()
+    kw, _, t_w, _, reed_log = timed_launches(R, torch, ctx, w, sampler, cfg, [(0, n)], stream, log_first=True)
+    kms, tot, wall, queue_use, _ = timed_launches(R, torch, ctx, w, sampler, cfg, [(0, n)] * 2, stream)
+    k = sum(kms) / len(kms)
+    achieved = FLOP_PER_PAIR * tot["pairs"] / len(kms) / (k * 1e-3) / 1e12
+    out = dict(workload="65,536 As at 10 keV into Si, half within 0.5 deg of [110], half at 7 deg tilt; "
+                        "8 cloning depths x 2 clones; 1 A bins 0-8192 A",
+               force_evals_per_s=tot["pairs"] / wall, tracks_per_s=tot["tracks"] / wall,
+               kernel_ms_per_step=[round(x, 1) for x in kms], launch=R.launch_shape(ctx, batch, cfg),
+               queue_max_and_overflow_per_step=queue_use,
+               roofline={"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": achieved / FP64_VECTOR_PEAK_TFLOPS})
+    out["profile_accuracy"] = profile_accuracy(R, torch, np, ctx, w, sampler, n, cfg, reed_log, kw[0] * 1e-3,
+                                               tail_depth)
+    if args.refine_epochs > 0:
+        from tests.workloads import C1_THRESHOLDS
+        b = R.sample_primaries(ctx, sampler, 0, n, stream=stream)
+        hist = torch.zeros(w["n_bins"], dtype=torch.float64, device="cuda")
+        stats = R.new_stats()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, depths = R.run_refined(ctx, w["species"], b, cfg, args.refine_epochs,
+                                     [2.0 ** -j for j in range(1, len(C1_THRESHOLDS) + 1)], 1.0,
+                                     hist=hist, stats=stats, stream=stream)
+        torch.cuda.synchronize()
+        tr = time.perf_counter() - t0
+        sr = R.parse_stats(stats)
+        out["refined"] = dict(epochs=args.refine_epochs, ms=1e3 * tr, force_evals_per_s=sr["pair_evals"] / tr,
+                              tracks=sr["finished"], last_depths=[round(x, 1) for x in depths[-1, 0].tolist()])
+    if args.pipelined > 0:
+        out["pipelined"] = pipelined_leg(R, torch, w, sampler, n, cfg, args.pipelined, w["species"])
+    ctx.close()
+    return out
+
+
+DESCR = {
+    "c1": "c1_as10kev: 65,536 As at 10 keV into diamond Si (a=5.431 A, sigma=0.076 A), "
+          "half within 0.5 deg of [110], half at 7 deg tilt; ZBL + local LSS k=1; "
+          "dx_max 0.05 A; 8 cloning depths x 2 clones; 1 A bins 0-8192 A",
+    "c2": "c2_mixed: 1,048,576 primaries, species uniform over B/P/As, energy log-uniform 1-100 keV, "
+          "7 deg tilt into diamond Si (a=5.431 A, sigma=0.076 A); ZBL + local LSS k=1; dx_max 0.05 A; "
+          "12 cloning depths x 2 clones per (species, energy decade) table; 1 A bins 0-8192 A; "
+          "persistent kernel, device queue, hipGraph, autotuned shape",
+    "c4": "c4_as100kev: 262,144 As at 100 keV along [001] (0 deg); 16 cloning depths to 1e-6; "
+          "0-500 nm in 0.5 nm bins",
+}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -358,136 +503,53 @@ def main():
         return
 
     import paper_0810_4737_amd as R
-    from tests.workloads import C1_THRESHOLDS, C2_THRESHOLDS, C4_THRESHOLDS, WORKLOADS
+    from tests.workloads import WORKLOADS
 
     assert torch.cuda.is_available(), "bench needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    wname = {"c1": "c1_as10kev", "c2": "c2_mixed", "c4": "c4_as100kev"}[args.workload]
-    w = WORKLOADS[wname]
-    n = args.n if args.n > 0 else w["n"]
+    key = args.workload
+    N = args.n if args.n > 0 else WORKLOADS[WORKLOAD_NAMES[key]]["n"]
+    whole = args.whole or key == "c1"
+    sl, timed, warm = plan_steps(N, args.steps, args.warmup, whole)
     ctx = R.Context()
-    if args.workload == "c1":
-        sampler = R.SamplerConfig(**dict(w["sampler"], n_cone=n // 2))
-        thr = [list(C1_THRESHOLDS)]
-        tail_depth = C1_THRESHOLDS[6]
-    elif args.workload == "c2":
-        sampler = R.SamplerConfig(**w["sampler"])
-        thr = [list(t) for t in C2_THRESHOLDS]
-        tail_depth = 2000.0
-    else:
-        sampler = R.SamplerConfig(**w["sampler"])
-        thr = [list(C4_THRESHOLDS)]
-        tail_depth = 4000.0
+    w, sampler, thr, _ = workload_setup(R, key, N)
     base = dict(n_bins=w["n_bins"], bin_width=w["bin_width"], thresholds=thr, queue_capacity=args.queue)
     stream = torch.cuda.current_stream()
 
-    # launch shape: explicit, or the autotuner on a pilot of the same workload
-    batch = R.sample_primaries(ctx, sampler, 0, n)
-    if args.form == "auto" or args.lanes == 0:
-        forms = [R.FORM_PLAIN, R.FORM_PERSISTENT] if args.form == "auto" else \
-            [R.FORM_PLAIN if args.form == "plain" else R.FORM_PERSISTENT]
-        best = None
-        for f in forms:
-            # the autotuner measures steady-state throughput on the batch itself
-            # (time-boxed candidate launches), then the choice is run once to compare forms
-            lanes, waves = R.autotune(ctx, w["species"], batch, R.RunConfig(form=f, lanes_per_track=args.lanes, **base),
-                                      pilot=n)
-            cfg_try = R.RunConfig(form=f, lanes_per_track=lanes, waves_per_cu=waves, **base)
-            if len(forms) == 1:
-                best = (0.0, cfg_try)
-                break
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            R.run(ctx, w["species"], batch, cfg_try)
-            torch.cuda.synchronize()
-            dt = time.perf_counter() - t1
-            if best is None or dt < best[0]:
-                best = (dt, cfg_try)
-        cfg = best[1]
+    # launch shape: explicit, or the autotuner on a batch of the same workload (the first
+    # warm-up slice, or the first timed one when there is no warm-up)
+    tid0, tn = (warm or timed)[0]
+    tb = R.sample_primaries(ctx, sampler, 0, tn, id0=tid0)
+    if args.lanes == 0:
+        f = R.FORM_PLAIN if args.form == "plain" else R.FORM_PERSISTENT
+        lanes, waves = R.autotune(ctx, w["species"], tb, R.RunConfig(form=f, **base), pilot=tn)
     else:
-        cfg = R.RunConfig(form=R.FORM_PLAIN if args.form == "plain" else R.FORM_PERSISTENT,
-                          lanes_per_track=args.lanes, waves_per_cu=args.waves, **base)
+        f, lanes, waves = (R.FORM_PLAIN if args.form == "plain" else R.FORM_PERSISTENT), args.lanes, args.waves
+    cfg = R.RunConfig(form=f, lanes_per_track=lanes, waves_per_cu=waves, **base)
+    shape = R.launch_shape(ctx, tb, cfg)
 
-    shape = R.launch_shape(ctx, batch, cfg)
-    hist = torch.zeros(w["n_bins"], dtype=torch.float64, device=dev)
-    stats = R.new_stats(dev)
+    if warm:
+        timed_launches(R, torch, ctx, w, sampler, cfg, warm, stream)
+    kernel_ms, tot, wall, queue_use, _ = timed_launches(R, torch, ctx, w, sampler, cfg, timed, stream)
 
-    def step(timed_events=None):
-        b = R.sample_primaries(ctx, sampler, 0, n, stream=stream)
-        hist.zero_()
-        stats.zero_()
-        if timed_events is not None:
-            timed_events[0].record(stream)
-        R.run(ctx, w["species"], b, cfg, hist=hist, stats=stats, stream=stream)
-        if timed_events is not None:
-            timed_events[1].record(stream)
-
-    # warmup (the first one also keeps the track log for the profile accuracy below)
-    reed_log, t_w = None, None
-    for i in range(args.warmup):
-        if i == 0:
-            b = R.sample_primaries(ctx, sampler, 0, n)
-            hist.zero_()
-            stats.zero_()
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            _, _, log, _ = R.run(ctx, w["species"], b, cfg, hist=hist, stats=stats, log_cap=40 * n)
-            torch.cuda.synchronize()
-            t_w = time.perf_counter() - t0
-            st = R.parse_stats(stats)
-            reed_log = R.parse_log(log, min(st["log_count"], 40 * n))
-        else:
-            step()
-    torch.cuda.synchronize()
-
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-    pairs = tracks = prims = 0
-    kernel_ms = []
-    queue_use = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        step(ev[k])
-        torch.cuda.synchronize()
-        st = R.parse_stats(stats)
-        pairs += st["pair_evals"]
-        tracks += st["finished"]
-        prims += st["primaries"]
-        kernel_ms.append(ev[k][0].elapsed_time(ev[k][1]))
-        queue_use.append([st["max_queue"], st["stack_overflow"]])
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    st_last = st
-    ledger = float(hist.sum().item()) + st_last["w_underflow"] + st_last["w_overflow"] + \
-        st_last["w_backscattered"] + st_last["w_quarantined"] + st_last["w_cancelled"]
-    assert ledger == float(n), ("weight ledger broken", ledger)
-
-    ms_step = wall * 1e3 / args.steps
-    value = pairs / wall
-    kms = sum(kernel_ms) / len(kernel_ms)
-    pairs_per_launch = pairs / args.steps
-    achieved = FLOP_PER_PAIR * pairs_per_launch / (kms * 1e-3) / 1e12
+    steps = len(timed)
+    ms_step = wall * 1e3 / steps
+    value = tot["pairs"] / wall
+    k_sum = sum(kernel_ms) * 1e-3
+    achieved = FLOP_PER_PAIR * tot["pairs"] / k_sum / 1e12
     m = MEASURED_TRAFFIC
     traffic = None
-    if (kernel_sources_hash() == m["sources_sha256_prefix"] and args.workload == m["workload"]
-            and cfg.form == R.FORM_PERSISTENT and shape["lanes"] == m["lanes"] and n == WORKLOADS[wname]["n"]):
+    if (kernel_sources_hash() == m["sources_sha256_prefix"] and key == m["workload"] and not whole
+            and cfg.form == R.FORM_PERSISTENT and shape["lanes"] == m["lanes"] and N == m["primaries"]
+            and sl == m["slice"]):
         traffic = m["fetch_bytes"] + m["write_bytes"]
-    descr = {
-        "c1": "c1_as10kev: 65,536 As at 10 keV into diamond Si (a=5.431 A, sigma=0.076 A), "
-              "half within 0.5 deg of [110], half at 7 deg tilt; ZBL + local LSS k=1; "
-              "dx_max 0.05 A; 8 cloning depths x 2 clones; 1 A bins 0-8192 A",
-        "c2": "c2_mixed: 1,048,576 tracks, species uniform over B/P/As, energy log-uniform 1-100 keV, "
-              "7 deg tilt; 12 cloning depths per (species, energy decade) table; 1 A bins 0-8192 A",
-        "c4": "c4_as100kev: 262,144 As at 100 keV along [001] (0 deg); 16 cloning depths to 1e-6; "
-              "0-500 nm in 0.5 nm bins",
-    }[args.workload]
     out = {
         "metric": "ion-atom force evaluations per second (REED-MD track throughput)",
         "value": value,
         "unit": "force evals/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": steps,
         "warmup": args.warmup,
         "ms_per_step": ms_step,
         "higher_is_better": True,
@@ -496,19 +558,22 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": descr,
-            "primaries": n,
+            "workload": DESCR[key],
+            "primaries": N,
+            "primaries_per_step": sl,
+            "step": ("the whole batch" if whole else
+                     f"ids [k*{sl}, (k+1)*{sl}) of step k; the {steps} timed steps run all {N} primaries, "
+                     f"warm-up steps ids from {N} on"),
             "form": "persistent" if cfg.form == R.FORM_PERSISTENT else "plain",
-            "lanes_per_track": cfg.lanes_per_track,
-            "waves_per_cu": cfg.waves_per_cu,
+            "lanes_per_track": lanes,
+            "waves_per_cu": waves,
             "launch": shape,
         },
-        "tracks_per_s": tracks / wall,
-        "primaries_per_s": prims / wall,
-        "track_steps_per_s": st_last["track_steps"] * args.steps / wall,
+        "tracks_per_s": tot["tracks"] / wall,
+        "primaries_per_s": tot["prims"] / wall,
+        "track_steps_per_s": tot["steps"] / wall,
         "kernel_ms_per_step": [round(x, 1) for x in kernel_ms],
         "queue_max_and_overflow_per_step": queue_use,
-        "profile_accuracy": None,
         "grad_fwd_ratio": None,
         "roofline": {
             "bound": "alu",
@@ -518,40 +583,27 @@ def main():
             "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
             "traffic": traffic,
             "kernel": "track_kernel (reedmd_run)",
-            "kernel_ms": kms,
+            "kernel_ms": k_sum * 1e3 / steps,
             "flop_per_pair": FLOP_PER_PAIR,
-            "pairs_per_launch": pairs_per_launch,
+            "pairs_per_launch": tot["pairs"] / steps,
         },
     }
-    if args.refine_epochs > 0 and args.workload == "c1":
-        b = R.sample_primaries(ctx, sampler, 0, n, stream=stream)
-        hist.zero_()
-        stats.zero_()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        _, _, depths = R.run_refined(ctx, w["species"], b, cfg, args.refine_epochs,
-                                     [2.0 ** -k for k in range(1, len(C1_THRESHOLDS) + 1)], 1.0,
-                                     hist=hist, stats=stats, stream=stream)
-        torch.cuda.synchronize()
-        tr = time.perf_counter() - t0
-        sr = R.parse_stats(stats)
-        out["refined"] = dict(epochs=args.refine_epochs, ms=1e3 * tr, force_evals_per_s=sr["pair_evals"] / tr,
-                              tracks=sr["finished"], last_depths=[round(x, 1) for x in depths[-1, 0].tolist()])
-    if reed_log is not None and cfg.thresholds is not None:
-        out["profile_accuracy"] = profile_accuracy(R, torch, np, ctx, w, sampler, n, cfg, reed_log, t_w, tail_depth)
-    if args.pipelined > 0:
-        out["pipelined"] = pipelined_leg(R, torch, w, sampler, n, cfg, args.pipelined, w["species"])
     if not args.no_fp32:
-        out["fp32_pair_variant"] = fp32_leg(R, ctx, torch, w, sampler, n, base, stream, hist, stats, args.form,
+        out["fp32_pair_variant"] = fp32_leg(R, ctx, torch, w, sampler, timed[:2], base, stream, args.form,
                                             args.lanes, args.waves)
+    ctx.close()
+    if key != "c1" and not args.no_c1:
+        out["c1_as10kev"] = c1_leg(R, torch, np, args)
     if not args.no_uo2:
         out["uo2_recoil"] = uo2_leg(R, torch, args.uo2_n)
     if not args.no_grad:
-        gr = grad_forward_ratio(R, ctx, torch)
+        gctx = R.Context()
+        gr = grad_forward_ratio(R, gctx, torch)
+        gctx.close()
         out["grad_fwd_ratio"] = gr["ratio"]
         out["grad"] = gr
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(key, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 

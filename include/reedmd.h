@@ -184,7 +184,7 @@ typedef struct {
     int32_t reserved;
 } reedmd_run_params;
 
-/* Finished-track entry of the optional log (40 bytes). */
+/* Finished-track entry of the optional log (48 bytes). */
 typedef struct {
     int64_t lineage;
     int32_t status;
@@ -192,6 +192,10 @@ typedef struct {
     double z_stop;
     double w;
     int64_t steps;
+    uint64_t key;        /* crystal-realisation key the track ended with: the primary's key,
+                            re-derived at every cloning depth k as the key of copy i (copy 0
+                            continues the parent; Sec. 2, clones differ only in material
+                            created after the cloning) */
 } reedmd_result;
 
 /* Run statistics (device struct owned by the caller; reedmd_run adds to it). */
@@ -215,6 +219,14 @@ reedmd_status reedmd_create(const reedmd_lattice* lattice, const reedmd_potentia
 /* Frees the context and all memory it owns; NULL is ignored.  Synchronises
  * the device first. */
 void reedmd_destroy(reedmd_ctx* ctx);
+
+/* Number of persistent-form pipelines (queue reset, track kernel, statistics)
+ * the context keeps as instantiated HIP graphs: one per launch shape (lanes per
+ * track, precision, target, workgroups, queue capacity), at most 16 (the cache
+ * is emptied when a 17th shape arrives or the scratch memory grows).  Every call
+ * writes its own arguments into the graph's kernel nodes, so fresh buffers do
+ * not add entries.  Host call; 0 for NULL. */
+int32_t reedmd_cached_graphs(const reedmd_ctx* ctx);
 
 /* Message for the last non-OK status returned on this context (never NULL;
  * ctx may be NULL for errors of reedmd_create). */

@@ -141,6 +141,11 @@ def lib():
                              C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
                              C.c_void_p, P(Stats), C.c_void_p, C.c_int64, P(C.c_int64)]
         L.or_run.restype = C.c_int32
+        L.or_primary_key.argtypes = [C.c_uint64, C.c_int64]
+        L.or_primary_key.restype = C.c_uint64
+        L.or_child_key.argtypes = [C.c_uint64, C.c_uint64, C.c_int32, C.c_int32]
+        L.or_child_key.restype = C.c_uint64
+        L.or_child_keys.argtypes = [C.c_void_p, C.c_int64, C.c_uint64, C.c_int32, C.c_int32, C.c_void_p]
         L.or_grad_track.argtypes = [P(Params), C.c_int32, C.c_double, P(C.c_double), P(C.c_double),
                                     C.c_uint64, C.c_int64, P(C.c_double), P(C.c_int64)]
         L.or_grad_track.restype = C.c_int32
@@ -225,6 +230,36 @@ def philox4x64(ctr, key):
     o = (C.c_uint64 * 4)()
     L.or_philox4x64(c, k, o)
     return [int(x) for x in o]
+
+
+def primary_key(seed: int, id: int) -> int:
+    """Crystal-realisation key of primary `id`."""
+    return int(lib().or_primary_key(int(seed) & (2**64 - 1), int(id)))
+
+
+def child_key(key: int, seed: int, k: int, i: int) -> int:
+    """Key of clone i made when a track with key `key` crosses cloning depth k (Sec. 2: the
+    clones share the material that exists and differ in what is created later; copy 0
+    continues the parent)."""
+    return int(lib().or_child_key(int(key) & (2**64 - 1), int(seed) & (2**64 - 1), int(k), int(i)))
+
+
+def child_keys(keys, seed: int, k: int, n_clones: int = 2) -> np.ndarray:
+    """Keys of the next cloning level: entry j * n_clones + i is copy i of keys[j] at depth k."""
+    src = np.ascontiguousarray(np.asarray(keys, dtype=np.uint64))
+    out = np.zeros(src.size * n_clones, np.uint64)
+    lib().or_child_keys(src.ctypes.data, src.size, int(seed) & (2**64 - 1), int(k), int(n_clones),
+                        out.ctypes.data)
+    return out
+
+
+def descendant_keys(key: int, seed: int, depth: int, n_clones: int = 2):
+    """Every key a track of the family can hold after crossing cloning depths 0 .. depth-1
+    (n_clones ** depth keys; index = the copy numbers in base n_clones, depth 0 first)."""
+    keys = np.array([int(key)], np.uint64)
+    for k in range(depth):
+        keys = child_keys(keys, seed, k, n_clones)
+    return [int(x) for x in keys]
 
 
 def zbl(cfg: Config, species: int, r: float, type: int = 0):

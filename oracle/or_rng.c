@@ -83,6 +83,14 @@ uint64_t or_child_key(uint64_t key, uint64_t seed, int32_t k, int32_t i)
     return r[0];
 }
 
+/* Keys of the next cloning level: out[j * n_clones + i] = key of copy i made
+ * when a track with key in[j] crosses cloning depth k. */
+void or_child_keys(const uint64_t* in, int64_t n, uint64_t seed, int32_t k, int32_t n_clones, uint64_t* out)
+{
+    for (int64_t j = 0; j < n; ++j)
+        for (int32_t i = 0; i < n_clones; ++i) out[j * n_clones + i] = or_child_key(in[j], seed, k, i);
+}
+
 /* Crystal-realisation key of primary `id`. */
 uint64_t or_primary_key(uint64_t seed, int64_t id)
 {

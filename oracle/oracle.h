@@ -188,6 +188,11 @@ typedef struct {
 /* RNG (counter-based Philox4x64-10) */
 void or_philox4x64(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);
 double or_u01(uint64_t w);
+/* crystal-realisation keys: of primary `id`, and of clone i made when a track
+ * with key `key` crosses cloning depth k (copy 0 continues the parent) */
+uint64_t or_primary_key(uint64_t seed, int64_t id);
+uint64_t or_child_key(uint64_t key, uint64_t seed, int32_t k, int32_t i);
+void or_child_keys(const uint64_t* in, int64_t n, uint64_t seed, int32_t k, int32_t n_clones, uint64_t* out);
 
 /* physics primitives */
 /* `type` is the target species (0, or 1 for the fluorite anions) */

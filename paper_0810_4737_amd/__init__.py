@@ -87,6 +87,10 @@ class Context:
         except Exception:
             pass
 
+    def cached_graphs(self):
+        """Persistent-form pipelines kept as instantiated graphs (one per launch shape)."""
+        return int(self._lib.reedmd_cached_graphs(self.handle))
+
     def check(self, rc):
         if rc != 0:
             raise ReedmdError(f"reedmd status {rc}: {self._lib.reedmd_last_error(self.handle).decode()}")
@@ -231,15 +235,17 @@ def run(ctx: Context, species, batch, cfg: RunConfig, hist=None, stats=None, id0
     """Runs every primary of `batch` with all its clones; returns (hist, stats[, log])."""
     dev = batch["energy"].device
     keep = []
-    p = cfg.struct(dev, keep)
     log = None
     with _on(stream):
+        # the depth tables are allocated on the launch stream, so their memory cannot be
+        # handed to work on another stream while the kernel may still read them
+        p = cfg.struct(dev, keep)
         if hist is None:
             hist = torch.zeros(cfg.n_bins, dtype=torch.float64, device=dev)
         if stats is None:
             stats = new_stats(dev)
         if log_cap > 0:
-            log = torch.zeros((log_cap, 5), dtype=torch.int64, device=dev)
+            log = torch.zeros((log_cap, _abi.RESULT_WORDS), dtype=torch.int64, device=dev)
             p.track_log = log.data_ptr()
             p.track_log_cap = log_cap
     if cancel is not None:
@@ -260,15 +266,17 @@ def run_refined(ctx: Context, species, batch, cfg: RunConfig, n_epochs: int, pro
     Returns (hist, stats, depths[n_epochs, n_tables, n_thresh][, log])."""
     dev = batch["energy"].device
     keep = []
-    p = cfg.struct(dev, keep)
     log = None
     with _on(stream):
+        # the depth tables are allocated on the launch stream, so their memory cannot be
+        # handed to work on another stream while the kernel may still read them
+        p = cfg.struct(dev, keep)
         if hist is None:
             hist = torch.zeros(cfg.n_bins, dtype=torch.float64, device=dev)
         if stats is None:
             stats = new_stats(dev)
         if log_cap > 0:
-            log = torch.zeros((log_cap, 5), dtype=torch.int64, device=dev)
+            log = torch.zeros((log_cap, _abi.RESULT_WORDS), dtype=torch.int64, device=dev)
             p.track_log = log.data_ptr()
             p.track_log_cap = log_cap
     pr = np.ascontiguousarray(np.asarray(probs, dtype=np.float64))
@@ -291,16 +299,16 @@ def run_refined(ctx: Context, species, batch, cfg: RunConfig, n_epochs: int, pro
 def parse_log(log: torch.Tensor, count: int):
     raw = log[:count].detach().cpu().numpy()
     dt = np.dtype([("lineage", np.int64), ("status", np.int32), ("next_k", np.int32),
-                   ("z_stop", np.float64), ("w", np.float64), ("steps", np.int64)])
+                   ("z_stop", np.float64), ("w", np.float64), ("steps", np.int64), ("key", np.uint64)])
     return raw.copy().view(dt).reshape(-1)
 
 
 def track_init(ctx: Context, species, batch, cfg: RunConfig, id0=0, stream=None):
     dev = batch["energy"].device
     keep = []
-    p = cfg.struct(dev, keep)
     n = int(batch["energy"].shape[0])
     with _on(stream):
+        p = cfg.struct(dev, keep)
         rec = torch.zeros((n, ctx.record_words), dtype=torch.float64, device=dev)
     sp = species_table(species) if not isinstance(species, _abi.Species) else species
     b = _batch_struct(batch, id0)
@@ -311,7 +319,8 @@ def track_init(ctx: Context, species, batch, cfg: RunConfig, id0=0, stream=None)
 
 def debug_step(ctx: Context, species, records: torch.Tensor, cfg: RunConfig, nsteps=1, stream=None):
     keep = []
-    p = cfg.struct(records.device, keep)
+    with _on(stream):
+        p = cfg.struct(records.device, keep)
     sp = species_table(species) if not isinstance(species, _abi.Species) else species
     assert records.is_contiguous() and records.dtype == torch.float64
     if records.dim() != 2 or records.shape[1] != ctx.record_words:

@@ -76,7 +76,10 @@ class Refine(C.Structure):
 
 class Result(C.Structure):
     _fields_ = [("lineage", C.c_int64), ("status", C.c_int32), ("next_k", C.c_int32),
-                ("z_stop", C.c_double), ("w", C.c_double), ("steps", C.c_int64)]
+                ("z_stop", C.c_double), ("w", C.c_double), ("steps", C.c_int64), ("key", C.c_uint64)]
+
+
+RESULT_WORDS = 6   # 64-bit words per finished-track log entry
 
 
 STATS_INT_A = ("primaries", "finished", "clones", "track_steps", "pair_evals", "n_stopped",
@@ -90,7 +93,7 @@ STATS_WORDS = len(STATS_INT_A) + len(STATS_DBL) + len(STATS_INT_B)
 EXPORTS = ("reedmd_version", "reedmd_create", "reedmd_destroy", "reedmd_last_error",
            "reedmd_sample_primaries", "reedmd_run", "reedmd_track_init", "reedmd_debug_step",
            "reedmd_autotune", "reedmd_grad", "reedmd_eval_exp_neg", "reedmd_eval_exp_neg_pair", "reedmd_launch_shape",
-           "reedmd_run_refined")
+           "reedmd_run_refined", "reedmd_cached_graphs")
 
 _lib = None
 
@@ -112,6 +115,8 @@ def load():
     L.reedmd_destroy.argtypes = [V]
     L.reedmd_last_error.argtypes = [V]
     L.reedmd_last_error.restype = C.c_char_p
+    L.reedmd_cached_graphs.argtypes = [V]
+    L.reedmd_cached_graphs.restype = C.c_int32
     L.reedmd_sample_primaries.argtypes = [V, P(Sampler), C.c_uint64, P(Batch), V]
     L.reedmd_sample_primaries.restype = C.c_int
     L.reedmd_run.argtypes = [V, P(Species), P(Batch), P(RunParams), V, V, V]

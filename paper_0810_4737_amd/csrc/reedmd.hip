@@ -29,6 +29,7 @@ constexpr double kMaxScreening = 100.0;        // keeps every exponent argument 
 constexpr long long kDefaultGradSteps = 16384;    // gradient step cap when the caller sets none
 constexpr int kTuneBoxMs = 400;                   // autotuner: time box of each candidate launch
 constexpr size_t kGradScratchBytes = size_t(48) << 30;   // checkpoint memory per launch chunk
+constexpr size_t kMaxGraphs = 16;                 // instantiated persistent pipelines kept per context
 
 thread_local std::string g_create_error;
 
@@ -46,16 +47,20 @@ struct reedmd_ctx {
     size_t scratch_bytes = 0;
     double* stack = nullptr;
     size_t stack_bytes = 0;
+    int* ordbuf = nullptr;         // claim order: bucket counts, offsets, order of the batch
+    size_t ordbuf_bytes = 0;
     double* gscratch = nullptr;    // adjoint checkpoints, segment states, outputs
     size_t gscratch_bytes = 0;
     // autotune cache: config hash -> (lanes, waves per CU)
     std::map<unsigned long long, std::pair<int, int>> tune;
-    // captured persistent pipelines
+    // persistent pipelines (reset -> claim order -> track kernel -> statistics) as instantiated graphs,
+    // one per launch shape; the kernel arguments of every call are written into the nodes
     struct Graph {
         hipGraph_t graph = nullptr;
         hipGraphExec_t exec = nullptr;
+        hipGraphNode_t node[6] = {};   // reset, order count, scan, scatter, track kernel, statistics
     };
-    std::map<std::vector<unsigned long long>, Graph> graphs;
+    std::map<std::vector<long long>, Graph> graphs;
 };
 
 namespace {
@@ -276,39 +281,29 @@ void fill_batch(const reedmd_batch* b, KernelArgs& A)
 
 // Kernel variants: lanes per track (64, 32, 16; fluorite 64, 32) x form x
 // pair-term precision x target structure.
-template <int L, int MODE, bool F32, int LAT>
-hipError_t launch_track(const KernelArgs& A, long long blocks, hipStream_t s)
-{
-    hipLaunchKernelGGL((track_kernel<L, MODE, F32, LAT>), dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s, A);
-    return hipGetLastError();
-}
-
 template <int MODE, bool F32, int LAT>
-hipError_t launch_track_l(int L, const KernelArgs& A, long long blocks, hipStream_t s)
+const void* track_ptr_l(int L)
 {
-    if (L == 64) return launch_track<64, MODE, F32, LAT>(A, blocks, s);
+    if (L == 64) return reinterpret_cast<const void*>(&track_kernel<64, MODE, F32, LAT>);
     if constexpr (LAT == kFluorite) {
-        return launch_track<32, MODE, F32, LAT>(A, blocks, s);
+        return reinterpret_cast<const void*>(&track_kernel<32, MODE, F32, LAT>);
     } else {
-        if (L == 32) return launch_track<32, MODE, F32, LAT>(A, blocks, s);
-        return launch_track<16, MODE, F32, LAT>(A, blocks, s);
+        if (L == 32) return reinterpret_cast<const void*>(&track_kernel<32, MODE, F32, LAT>);
+        return reinterpret_cast<const void*>(&track_kernel<16, MODE, F32, LAT>);
     }
 }
 
-template <int LAT>
-hipError_t launch_track_lat(int L, int mode, bool f32, const KernelArgs& A, long long blocks, hipStream_t s)
+// The track kernel of a launch shape (launches and graph nodes take the function itself).
+const void* track_kernel_ptr(int L, int mode, bool f32, int lat)
 {
-    if (mode == kModePlain)
-        return f32 ? launch_track_l<kModePlain, true, LAT>(L, A, blocks, s)
-                   : launch_track_l<kModePlain, false, LAT>(L, A, blocks, s);
-    return f32 ? launch_track_l<kModePersistent, true, LAT>(L, A, blocks, s)
-               : launch_track_l<kModePersistent, false, LAT>(L, A, blocks, s);
-}
-
-hipError_t launch_track_any(int L, int mode, bool f32, int lat, const KernelArgs& A, long long blocks, hipStream_t s)
-{
-    return lat == kFluorite ? launch_track_lat<kFluorite>(L, mode, f32, A, blocks, s)
-                            : launch_track_lat<kDiamond>(L, mode, f32, A, blocks, s);
+    if (mode == kModePlain) {
+        if (lat == kFluorite)
+            return f32 ? track_ptr_l<kModePlain, true, kFluorite>(L) : track_ptr_l<kModePlain, false, kFluorite>(L);
+        return f32 ? track_ptr_l<kModePlain, true, kDiamond>(L) : track_ptr_l<kModePlain, false, kDiamond>(L);
+    }
+    if (lat == kFluorite)
+        return f32 ? track_ptr_l<kModePersistent, true, kFluorite>(L) : track_ptr_l<kModePersistent, false, kFluorite>(L);
+    return f32 ? track_ptr_l<kModePersistent, true, kDiamond>(L) : track_ptr_l<kModePersistent, false, kDiamond>(L);
 }
 
 template <int MODE, bool F32, int LAT>
@@ -389,10 +384,15 @@ void launch_step_any(int L, bool f32, int lat, const KernelArgs& A, long long bl
     }
 }
 
-// Queue state reset (a kernel, not a memset, so the pipeline can be captured).
-__global__ void queue_reset_kernel(QueueState* q, unsigned long long* seq, int cap, long long n)
+constexpr int kOrderBuckets = 512;
+constexpr int kOrderBlocks = 256;   // grid of the order kernels (grid-stride over the batch)
+
+// Queue state reset and the claim-order counters (a kernel, not a memset, so the
+// pipeline can be kept as a graph).
+__global__ void queue_reset_kernel(QueueState* q, unsigned long long* seq, int cap, long long n, int* counts)
 {
     const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    for (long long c = i; c < kOrderBuckets; c += static_cast<long long>(gridDim.x) * blockDim.x) counts[c] = 0;
     if (i == 0) {
         q->head = 0;
         q->tail = 0;
@@ -405,10 +405,72 @@ __global__ void queue_reset_kernel(QueueState* q, unsigned long long* seq, int c
     if (i < cap) seq[i] = static_cast<unsigned long long>(i);
 }
 
+// Claim order of the primaries: longest expected tracks first, so that the
+// long clone families of a batch start early instead of ending it.  The cost
+// proxy is E0 / M1 (the ion's speed squared sets the number of steps of a
+// track, dx_max per step, and with it the number of cloning depths it
+// crosses); a counting sort into 16 buckets per octave of E0 / M1, largest
+// first.  The order inside a bucket is whatever the atomics give: every
+// primary family is computed the same way wherever and whenever it runs, so
+// the order changes no result.
+struct OrderArgs {
+    long long n;
+    const int* species;
+    const double* energy;
+    double inv_M1[kMaxSpecies];
+    int n_species;
+    int pad;
+    int* counts;    // [kOrderBuckets]
+    int* offsets;   // [kOrderBuckets]
+    int* order;     // [n]
+};
+
+__device__ __forceinline__ int order_bucket(const OrderArgs& O, long long q)
+{
+    const int sp = O.species[q];
+    const double r = O.energy[q] * ((sp >= 0 && sp < O.n_species) ? O.inv_M1[sp] : 1.0);
+    double b = (r > 0.0) ? floor(16.0 * log2(r)) + 128.0 : 0.0;
+    b = fmin(fmax(b, 0.0), static_cast<double>(kOrderBuckets - 1));   // NaN goes to bucket 0
+    return kOrderBuckets - 1 - static_cast<int>(b);
+}
+
+__global__ void order_count_kernel(const OrderArgs O)
+{
+    for (long long q = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; q < O.n;
+         q += static_cast<long long>(gridDim.x) * blockDim.x)
+        atomicAdd(&O.counts[order_bucket(O, q)], 1);
+}
+
+__global__ void order_scan_kernel(const OrderArgs O)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int run = 0;
+    for (int b = 0; b < kOrderBuckets; ++b) {
+        O.offsets[b] = run;
+        run += O.counts[b];
+    }
+}
+
+__global__ void order_scatter_kernel(const OrderArgs O)
+{
+    for (long long q = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; q < O.n;
+         q += static_cast<long long>(gridDim.x) * blockDim.x)
+        O.order[atomicAdd(&O.offsets[order_bucket(O, q)], 1)] = static_cast<int>(q);
+}
+
 // Copies the number of logged results into the caller's stats at the end.
 __global__ void stats_finalize_kernel(const QueueState* q, reedmd_stats* st)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) st->log_count += q->log_next;
+}
+
+void drop_graphs(reedmd_ctx* ctx)
+{
+    for (auto& g : ctx->graphs) {
+        (void)hipGraphExecDestroy(g.second.exec);
+        (void)hipGraphDestroy(g.second.graph);
+    }
+    ctx->graphs.clear();
 }
 
 reedmd_status ensure_scratch(reedmd_ctx* ctx, int qcap, size_t stack_records)
@@ -420,11 +482,7 @@ reedmd_status ensure_scratch(reedmd_ctx* ctx, int qcap, size_t stack_records)
         if (ctx->scratch) (void)hipFree(ctx->scratch);
         ctx->scratch = nullptr;
         ctx->scratch_bytes = 0;
-        for (auto& g : ctx->graphs) {
-            (void)hipGraphExecDestroy(g.second.exec);
-            (void)hipGraphDestroy(g.second.graph);
-        }
-        ctx->graphs.clear();
+        drop_graphs(ctx);
         if (hipMalloc(&ctx->scratch, need_q) != hipSuccess) {
             ctx->scratch = nullptr;
             return fail(ctx, REEDMD_ENOMEM, "cannot allocate the clone queue");
@@ -437,17 +495,30 @@ reedmd_status ensure_scratch(reedmd_ctx* ctx, int qcap, size_t stack_records)
         if (ctx->stack) (void)hipFree(ctx->stack);
         ctx->stack = nullptr;
         ctx->stack_bytes = 0;
-        for (auto& g : ctx->graphs) {
-            (void)hipGraphExecDestroy(g.second.exec);
-            (void)hipGraphDestroy(g.second.graph);
-        }
-        ctx->graphs.clear();
+        drop_graphs(ctx);
         if (hipMalloc(reinterpret_cast<void**>(&ctx->stack), need_s) != hipSuccess) {
             ctx->stack = nullptr;
             return fail(ctx, REEDMD_ENOMEM, "cannot allocate clone stacks");
         }
         ctx->stack_bytes = need_s;
     }
+    return REEDMD_OK;
+}
+
+reedmd_status ensure_order(reedmd_ctx* ctx, long long n)
+{
+    const size_t need = (2 * static_cast<size_t>(kOrderBuckets) + static_cast<size_t>(std::max<long long>(n, 1))) * sizeof(int);
+    if (need <= ctx->ordbuf_bytes) return REEDMD_OK;
+    HIP_TRY(ctx, hipDeviceSynchronize());
+    if (ctx->ordbuf) (void)hipFree(ctx->ordbuf);
+    ctx->ordbuf = nullptr;
+    ctx->ordbuf_bytes = 0;
+    const size_t grow = std::max(need, need + need / 4);
+    if (hipMalloc(reinterpret_cast<void**>(&ctx->ordbuf), grow) != hipSuccess) {
+        ctx->ordbuf = nullptr;
+        return fail(ctx, REEDMD_ENOMEM, "cannot allocate the claim order");
+    }
+    ctx->ordbuf_bytes = grow;
     return REEDMD_OK;
 }
 
@@ -543,51 +614,86 @@ reedmd_status run_impl(reedmd_ctx* ctx, const reedmd_species* sp, const reedmd_b
     A.seg_total = s.seg_total;
 
     if (b->n == 0) return REEDMD_OK;
+    st = ensure_order(ctx, b->n);
+    if (st != REEDMD_OK) return st;
 
-    auto enqueue = [&](hipStream_t sm) -> hipError_t {
-        const int rb = (qcap + 255) / 256;
-        hipLaunchKernelGGL(queue_reset_kernel, dim3(rb), dim3(256), 0, sm, A.q, A.qseq, qcap, b->n);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        e = launch_track_any(s.L, s.mode, s.f32, lattice_of(ctx), A, s.blocks, sm);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(stats_finalize_kernel, dim3(1), dim3(64), 0, sm, A.q, d_stats);
-        return hipGetLastError();
-    };
+    // The pipeline of a run: queue and counter reset, claim order (count, scan,
+    // scatter), the track kernel, statistics.  Each call fills one argument set;
+    // the persistent form keeps the pipeline as an instantiated graph per launch
+    // shape and writes this call's arguments into its nodes, the other forms (and
+    // calls made inside a caller's stream capture) launch the kernels directly.
+    OrderArgs O{};
+    O.n = b->n;
+    O.species = b->species;
+    O.energy = b->energy;
+    for (int i = 0; i < kMaxSpecies; ++i) O.inv_M1[i] = 1.0 / A.sp[i].M1;
+    O.n_species = sp->n_species;
+    O.counts = ctx->ordbuf;
+    O.offsets = ctx->ordbuf + kOrderBuckets;
+    O.order = ctx->ordbuf + 2 * kOrderBuckets;
+    A.order = O.order;
+    QueueState* q = A.q;
+    unsigned long long* seq = A.qseq;
+    int cap = qcap;
+    long long nq = b->n;
+    int* counts = O.counts;
+    reedmd_stats* st_out = d_stats;
+    void* reset_args[] = {&q, &seq, &cap, &nq, &counts};
+    void* order_args[] = {&O};
+    void* track_args[] = {&A};
+    void* fin_args[] = {&q, &st_out};
+    constexpr int kNodes = 6;
+    hipKernelNodeParams np[kNodes] = {};
+    const void* funcs[kNodes] = {reinterpret_cast<const void*>(queue_reset_kernel),
+                                 reinterpret_cast<const void*>(order_count_kernel),
+                                 reinterpret_cast<const void*>(order_scan_kernel),
+                                 reinterpret_cast<const void*>(order_scatter_kernel),
+                                 track_kernel_ptr(s.L, s.mode, s.f32, lattice_of(ctx)),
+                                 reinterpret_cast<const void*>(stats_finalize_kernel)};
+    const dim3 grids[kNodes] = {dim3((std::max(qcap, kOrderBuckets) + 255) / 256), dim3(kOrderBlocks), dim3(1),
+                                dim3(kOrderBlocks), dim3(static_cast<unsigned>(s.blocks)), dim3(1)};
+    const dim3 blocks[kNodes] = {dim3(256), dim3(256), dim3(64), dim3(256), dim3(kBlock), dim3(64)};
+    void** args[kNodes] = {reset_args, order_args, order_args, order_args, track_args, fin_args};
+    for (int k = 0; k < kNodes; ++k) {
+        np[k].func = const_cast<void*>(funcs[k]);
+        np[k].gridDim = grids[k];
+        np[k].blockDim = blocks[k];
+        np[k].kernelParams = args[k];
+    }
 
-    if (s.mode == kModePersistent && !forced) {
-        // The persistent pipeline (queue reset, persistent kernel, stats) is
-        // captured once per argument set and replayed.
+    bool as_graph = s.mode == kModePersistent && !forced;
+    if (as_graph) {
         hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
         HIP_TRY(ctx, hipStreamIsCapturing(stream, &cs));
-        if (cs == hipStreamCaptureStatusNone) {
-            std::vector<unsigned long long> key;
-            const unsigned long long* raw = reinterpret_cast<const unsigned long long*>(&A);
-            key.assign(raw, raw + sizeof(A) / 8);
-            key.push_back(static_cast<unsigned long long>(s.L));
-            key.push_back(static_cast<unsigned long long>(s.f32));
-            key.push_back(static_cast<unsigned long long>(s.blocks));
-            auto it = ctx->graphs.find(key);
-            if (it == ctx->graphs.end()) {
-                hipStream_t cap_stream;
-                HIP_TRY(ctx, hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking));
-                reedmd_ctx::Graph g;
-                hipError_t e = hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal);
-                if (e == hipSuccess) {
-                    hipError_t e2 = enqueue(cap_stream);
-                    e = hipStreamEndCapture(cap_stream, &g.graph);
-                    if (e2 != hipSuccess) e = e2;
-                }
-                if (e == hipSuccess) e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
-                (void)hipStreamDestroy(cap_stream);
-                if (e != hipSuccess) return hip_fail(ctx, e, "capturing the persistent pipeline");
-                it = ctx->graphs.emplace(key, g).first;
-            }
-            HIP_TRY(ctx, hipGraphLaunch(it->second.exec, stream));
-            return REEDMD_OK;
-        }
+        as_graph = cs == hipStreamCaptureStatusNone;
     }
-    HIP_TRY(ctx, enqueue(stream));
+    if (!as_graph) {
+        for (int k = 0; k < kNodes; ++k)
+            HIP_TRY(ctx, hipLaunchKernel(np[k].func, np[k].gridDim, np[k].blockDim, np[k].kernelParams, 0, stream));
+        return REEDMD_OK;
+    }
+    const std::vector<long long> key = {s.L, s.f32 ? 1 : 0, lattice_of(ctx), s.blocks, qcap};
+    auto it = ctx->graphs.find(key);
+    if (it == ctx->graphs.end()) {
+        if (ctx->graphs.size() >= kMaxGraphs) drop_graphs(ctx);
+        reedmd_ctx::Graph g;
+        hipError_t e = hipGraphCreate(&g.graph, 0);
+        for (int k = 0; k < kNodes && e == hipSuccess; ++k) {
+            hipGraphNode_t* prev = k > 0 ? &g.node[k - 1] : nullptr;
+            e = hipGraphAddKernelNode(&g.node[k], g.graph, prev, k > 0 ? 1 : 0, &np[k]);
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            if (g.exec) (void)hipGraphExecDestroy(g.exec);
+            if (g.graph) (void)hipGraphDestroy(g.graph);
+            return hip_fail(ctx, e, "building the persistent pipeline graph");
+        }
+        it = ctx->graphs.emplace(key, g).first;
+    } else {
+        for (int k = 0; k < kNodes; ++k)
+            HIP_TRY(ctx, hipGraphExecKernelNodeSetParams(it->second.exec, it->second.node[k], &np[k]));
+    }
+    HIP_TRY(ctx, hipGraphLaunch(it->second.exec, stream));
     return REEDMD_OK;
 }
 
@@ -752,17 +858,20 @@ reedmd_status reedmd_create(const reedmd_lattice* lattice, const reedmd_potentia
     return REEDMD_OK;
 }
 
+int32_t reedmd_cached_graphs(const reedmd_ctx* ctx)
+{
+    return ctx ? static_cast<int32_t>(ctx->graphs.size()) : 0;
+}
+
 void reedmd_destroy(reedmd_ctx* ctx)
 {
     if (!ctx) return;
     (void)hipDeviceSynchronize();
-    for (auto& g : ctx->graphs) {
-        (void)hipGraphExecDestroy(g.second.exec);
-        (void)hipGraphDestroy(g.second.graph);
-    }
+    drop_graphs(ctx);
     if (ctx->scratch) (void)hipFree(ctx->scratch);
     if (ctx->stack) (void)hipFree(ctx->stack);
     if (ctx->gscratch) (void)hipFree(ctx->gscratch);
+    if (ctx->ordbuf) (void)hipFree(ctx->ordbuf);
     delete ctx;
 }
 

@@ -83,6 +83,7 @@ struct KernelArgs {
     unsigned long long* qseq;
     double* qrec;
     const int* cancel;
+    const int* order;       // optional: batch entry of the i-th claimed primary (longest expected first)
     long long seg_total;
     // debug entry points
     double* records;
@@ -187,17 +188,54 @@ constexpr int kQuadXor2 = 0x4E;      // quad_perm [2,3,0,1]
 constexpr int kRowHalfMirror = 0x141;
 constexpr int kRowMirror = 0x140;
 
+__device__ __forceinline__ double xor32_f64(double v)
+{
+    const int src = ((threadIdx.x & 63) ^ 32) << 2;
+    return __hiloint2double(__builtin_amdgcn_ds_bpermute(src, __double2hiint(v)),
+                            __builtin_amdgcn_ds_bpermute(src, __double2loint(v)));
+}
+
+// Sums over a track's slots use one fixed order for every lane layout, so that
+// results do not depend on the lanes per track (or on anything else the
+// autotuner chooses).  Slot s belongs to column q = s mod 64; a lane keeps one
+// partial per column it holds (G = 64 / L of them: column q = lane + L m in
+// acc[m]), each summed over its slots in increasing order; the 64 column
+// partials are then combined as a butterfly over the column index, bit 4
+// first, then bit 5, then bits 0 to 3.  Addition is commutative in IEEE
+// arithmetic, so both partners of every stage hold the same value and every
+// lane ends with bitwise the same sum.
 template <int L>
 struct SegReduce {
-    __device__ __forceinline__ static double sum(double v)
+    static constexpr int G = 64 / L;
+    __device__ __forceinline__ static double lanes16(double v)
     {
         v += dpp_f64<kQuadXor1>(v);
         v += dpp_f64<kQuadXor2>(v);
-        v += dpp_f64<kRowHalfMirror>(v);
-        v += dpp_f64<kRowMirror>(v);
+        v += dpp_f64<kRowHalfMirror>(v);   // pairs quads: on equal quad values the same as xor 4
+        v += dpp_f64<kRowMirror>(v);       // pairs half rows: the same as xor 8
+        return v;
+    }
+    // Plain segment sum of one value per lane (the adjoint's sums, which need no
+    // agreement between layouts).
+    __device__ __forceinline__ static double sum(double v)
+    {
+        v = lanes16(v);
         if (L >= 32) v += swz16_f64(v);
         if (L == 64) v = lane_f64(v, 0) + lane_f64(v, 32);
         return v;
+    }
+    __device__ __forceinline__ static double csum(const double (&acc)[G])
+    {
+        double v;
+        if constexpr (L == 16) {
+            v = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+        } else if constexpr (L == 32) {
+            v = (acc[0] + swz16_f64(acc[0])) + (acc[1] + swz16_f64(acc[1]));
+        } else {
+            v = acc[0] + swz16_f64(acc[0]);
+            v += xor32_f64(v);
+        }
+        return lanes16(v);
     }
     __device__ __forceinline__ static double max(double v)
     {
@@ -459,9 +497,14 @@ __device__ __forceinline__ void track_step(TrackRegs<L, LAT>& t, const KernelArg
     // of one target species, so the choice of constants and mass is static)
     const double h2a = dt * A.half_inv_M2;
     const double h2b = FL ? dt * A.half_inv_M2b : h2a;
-    double Fx = 0.0, Fy = 0.0, Fz = 0.0, rho = 0.0, rho1 = 0.0, vm = 0.0, fm = 0.0;
+    constexpr int G = SegReduce<L>::G;
+    double Fx[G], Fy[G], Fz[G], rho[G], rho1[G];
+#pragma unroll
+    for (int m = 0; m < G; ++m) Fx[m] = Fy[m] = Fz[m] = rho[m] = rho1[m] = 0.0;
+    double vm = 0.0, fm = 0.0;
 #pragma unroll
     for (int i = 0; i < TrackRegs<L, LAT>::SL; ++i) {
+        const int m = i % G;   // column group of register slot i
         const bool anion = FL && L * i >= Lattice<LAT>::kAnion0;
         const double h2 = anion ? h2b : h2a;
         double* f = t.fl + (sl + L * i);
@@ -481,9 +524,9 @@ __device__ __forceinline__ void track_step(TrackRegs<L, LAT>& t, const KernelArg
             else zbl_pair(c, dx, dy, dz, coef, ew);
         }
         const double fx = -coef * dx, fy = -coef * dy, fz = -coef * dz;   // force on the atom
-        Fx -= fx; Fy -= fy; Fz -= fz;
-        if (anion) rho1 += ew;
-        else rho += ew;
+        Fx[m] -= fx; Fy[m] -= fy; Fz[m] -= fz;
+        if (anion) rho1[m] += ew;
+        else rho[m] += ew;
         vx += fx * h2; vy += fy * h2; vz += fz * h2;
         t.ax[i] = px; t.ay[i] = py; t.az[i] = pz;
         t.avx[i] = vx; t.avy[i] = vy; t.avz[i] = vz;
@@ -495,15 +538,15 @@ __device__ __forceinline__ void track_step(TrackRegs<L, LAT>& t, const KernelArg
         __builtin_amdgcn_sched_barrier(0);
 #endif
     }
-    t.Fx = SegReduce<L>::sum(Fx);
-    t.Fy = SegReduce<L>::sum(Fy);
-    t.Fz = SegReduce<L>::sum(Fz);
+    t.Fx = SegReduce<L>::csum(Fx);
+    t.Fy = SegReduce<L>::csum(Fy);
+    t.Fz = SegReduce<L>::csum(Fz);
     if constexpr (FL) {
-        t.rho = SegReduce<L>::sum(rho) * c.wnorm + SegReduce<L>::sum(rho1) * c1.wnorm;
+        t.rho = SegReduce<L>::csum(rho) * c.wnorm + SegReduce<L>::csum(rho1) * c1.wnorm;
         t.vmax2a = SegReduce<L>::max(vm);
         t.amax2a = SegReduce<L>::max(fm);
     } else {
-        t.rho = SegReduce<L>::sum(rho) * c.wnorm;
+        t.rho = SegReduce<L>::csum(rho) * c.wnorm;
         t.vmax2a = SegReduce<L>::max(vm);
         t.amax2a = SegReduce<L>::max(fm) * A.inv_M2sq;
     }
@@ -700,7 +743,8 @@ __device__ __forceinline__ void add_i64(int64_t* p, long long v)
 // Books a finished track (segment leader only).
 __device__ __forceinline__ void book_finished(const KernelArgs& A, int status, double w, double zstop,
                                               long long lineage, int next_k, long long steps,
-                                              long long exec_steps, long long pairs, int table)
+                                              long long exec_steps, long long pairs, int table,
+                                              unsigned long long key)
 {
     reedmd_stats* S = A.stats;
     if (A.tstat != nullptr && table >= 0 && table < A.n_tables) {
@@ -750,6 +794,7 @@ __device__ __forceinline__ void book_finished(const KernelArgs& A, int status, d
             r->z_stop = zstop;
             r->w = w;
             r->steps = steps;
+            r->key = key;
         }
     }
 }
@@ -882,7 +927,7 @@ __global__ void __launch_bounds__(256, REEDMD_WAVES_PER_SIMD(L, LAT)) track_kern
                     if (qi >= A.n) qi = -1;
                 }
                 if (qi >= 0) {
-                    start_primary<L, LAT>(t, A, sp, qi);
+                    start_primary<L, LAT>(t, A, sp, A.order != nullptr ? A.order[qi] : qi);
                     if (t.status != REEDMD_LOST) refresh_threshold(t, A);
                     if (sl == 0) add_i64(&A.stats->primaries, 1);
                     fresh = true;
@@ -896,7 +941,7 @@ __global__ void __launch_bounds__(256, REEDMD_WAVES_PER_SIMD(L, LAT)) track_kern
                 if (t.status == REEDMD_LOST) {
                     // invalid species or table index: weight quarantined, error flagged
                     if (sl == 0) {
-                        book_finished(A, REEDMD_LOST, t.w, 0.0, t.lineage, t.next_k, t.steps, 0, 0, -1);
+                        book_finished(A, REEDMD_LOST, t.w, 0.0, t.lineage, t.next_k, t.steps, 0, 0, -1, t.key);
                         add_i64(&A.stats->error_flags, 1);
                         if (MODE == kModePersistent) add_i64(&A.q->live, -1);
                     }
@@ -905,7 +950,7 @@ __global__ void __launch_bounds__(256, REEDMD_WAVES_PER_SIMD(L, LAT)) track_kern
                 } else if (cancelled) {
                     // drain: the track ends where it is, its weight is booked as cancelled
                     if (sl == 0) {
-                        book_finished(A, REEDMD_CANCELLED, t.w, 0.0, t.lineage, t.next_k, t.steps, 0, 0, t.table);
+                        book_finished(A, REEDMD_CANCELLED, t.w, 0.0, t.lineage, t.next_k, t.steps, 0, 0, t.table, t.key);
                         if (MODE == kModePersistent) add_i64(&A.q->live, -1);
                     }
                     mode = kSegNeed;
@@ -948,7 +993,7 @@ __global__ void __launch_bounds__(256, REEDMD_WAVES_PER_SIMD(L, LAT)) track_kern
         if (st != REEDMD_ACTIVE) {
             const KernelArgs A = cold_args();
             if (sl == 0) {
-                book_finished(A, st, t.w, t.zstop, t.lineage, t.next_k, t.steps, exec_steps, pairs, t.table);
+                book_finished(A, st, t.w, t.zstop, t.lineage, t.next_k, t.steps, exec_steps, pairs, t.table, t.key);
                 if (MODE == kModePersistent) add_i64(&A.q->live, -1);
             }
             mode = kSegNeed;

@@ -129,3 +129,27 @@ def weighted_ks(x1, w1, x2, w2):
     from scipy.stats import kstwobign
     p = float(kstwobign.sf(D * math.sqrt(ne)))
     return D, p
+
+
+def family_moments(z, w, family):
+    """Weighted mean and standard deviation of z, with standard errors that treat primary
+    families (a primary and all of its clones, which share their early path) as the
+    independent units: per family W_f = sum w, S_f = sum w z, Q_f = sum w z^2; the mean
+    m = sum S / sum W and std = sqrt(sum Q / sum W - m^2) are ratio estimators, and their
+    standard errors come from the first-order (delta-method) expansion over families,
+    SE(m)^2 = sum_f (S_f - m W_f)^2 / (sum W)^2 and
+    SE(std)^2 = sum_f ((Q_f - E2 W_f) - 2 m (S_f - m W_f))^2 / (2 std sum W)^2."""
+    z, w = np.asarray(z, float), np.asarray(w, float)
+    fam = np.unique(np.asarray(family), return_inverse=True)[1]
+    nf = fam.max() + 1
+    Wf = np.bincount(fam, weights=w, minlength=nf)
+    Sf = np.bincount(fam, weights=w * z, minlength=nf)
+    Qf = np.bincount(fam, weights=w * z * z, minlength=nf)
+    W = Wf.sum()
+    m = Sf.sum() / W
+    E2 = Qf.sum() / W
+    sd = math.sqrt(max(E2 - m * m, 0.0))
+    se_m = math.sqrt(((Sf - m * Wf) ** 2).sum()) / W
+    r = (Qf - E2 * Wf) - 2.0 * m * (Sf - m * Wf)
+    se_sd = math.sqrt((r ** 2).sum()) / (2.0 * sd * W) if sd > 0 else float("nan")
+    return m, sd, se_m, se_sd

@@ -40,7 +40,8 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_sizes_match_header_layout():
     from paper_0810_4737_amd import _abi
-    assert C.sizeof(_abi.Result) == 40
+    assert C.sizeof(_abi.Result) == 48
+    assert _abi.RESULT_WORDS * 8 == C.sizeof(_abi.Result)
     assert C.sizeof(_abi.Species) == 8 + 4 * 8 + 8 * 8
     assert _abi.STATS_WORDS * 8 == 10 * 8 + 8 * 8 + 4 * 8
     assert _abi.RECORD_WORDS == 32 + 9 * 216

@@ -17,6 +17,7 @@ import pytest
 
 import oracle
 from tests import physref
+from tests.clone_keys import check_clone_keys as _check_clone_keys
 from tests.workloads import C1_THRESHOLDS, WORKLOADS
 
 torch = pytest.importorskip("torch")
@@ -237,7 +238,10 @@ def test_twenty_steps_match_oracle(R, ctx):
 
 
 @pytest.mark.parametrize("lanes", [32, 16])
-def test_lane_layouts_agree(R, ctx, lanes):
+def test_lane_layouts_agree_bitwise(R, ctx, lanes):
+    """The segment sums (ion force, density) follow one fixed order over the domain slots for
+    every lane layout, so starting records and steps are bitwise identical at 64, 32 and 16
+    lanes per track (the launch shape the autotuner picks changes no result)."""
     c, recs = _oracle_states(16, seed=11)
     a = torch.as_tensor(recs.copy(), device="cuda")
     b = torch.as_tensor(recs.copy(), device="cuda")
@@ -245,7 +249,11 @@ def test_lane_layouts_agree(R, ctx, lanes):
     R.debug_step(ctx, SPECIES3, b, rcfg(R, lanes_per_track=lanes), nsteps=5)
     ga, gb = a.cpu().numpy(), b.cpu().numpy()
     for i in range(len(recs)):
-        assert_records_close(gb[i], ga[i], rtol=1e-11, what=f"lanes {lanes} {i}")
+        assert np.array_equal(gb[i].view(np.int64), ga[i].view(np.int64)), f"lanes {lanes} record {i}"
+    pr = _prims(24, seed=13)
+    ia = R.track_init(ctx, SPECIES3, R.batch_from_numpy(pr), rcfg(R, lanes_per_track=64)).cpu().numpy()
+    ib = R.track_init(ctx, SPECIES3, R.batch_from_numpy(pr), rcfg(R, lanes_per_track=lanes)).cpu().numpy()
+    assert np.array_equal(ia.view(np.int64), ib.view(np.int64))
 
 
 # ------------------------------------------------------------------ FP32 pair-term variant
@@ -393,7 +401,9 @@ def _run_c1_subset(R, ctx, **kw):
 
 def test_splitting_run_matches_oracle_and_forms_agree_bitwise(R, ctx):
     """1,024 As at 10 keV with 8 cloning depths: exact weight ledger; plain and persistent
-    forms (and a tiny queue that forces the overflow path) give bitwise-identical histograms;
+    forms (and a tiny queue that forces the overflow path), at 16, 32 and 64 lanes per track,
+    give bitwise-identical histograms and equal totals; every clone key derives from its
+    primary's key as the oracle derives it;
     the weighted depth distribution agrees with the stored oracle run (KS p > 0.01)."""
     meta, zo, wo = _load_golden("c1_subset")
     _say("c1 subset plain")
@@ -412,13 +422,22 @@ def test_splitting_run_matches_oracle_and_forms_agree_bitwise(R, ctx):
     ht, stt, _ = _run_c1_subset(R, ctx, form=R.FORM_PERSISTENT, queue_capacity=2)
     assert np.array_equal(hp, ht)
     assert stt["stack_overflow"] > 0
+    for lanes in (16, 32, 64):
+        _say(f"c1 subset persistent, {lanes} lanes per track")
+        hl, sl, _ = _run_c1_subset(R, ctx, form=R.FORM_PERSISTENT, lanes_per_track=lanes)
+        assert np.array_equal(hp, hl), lanes
+        for k in ("finished", "clones", "track_steps", "pair_evals", "n_stopped", "n_backscattered"):
+            assert sp[k] == sl[k], (lanes, k)
     # statistics vs the oracle
     allg = np.concatenate([R.parse_log(l, l.shape[0]) for l in logs])
     allg = allg[allg["status"] != 0]          # unused log rows are all zero
     assert len(allg) == sp["finished"]
+    fam = _check_clone_keys(allg)
+    assert fam == 1024
     g = allg[allg["status"] == R.STOPPED]
     D, p = physref.weighted_ks(g["z_stop"], g["w"], zo, wo)
-    _say(f"c1 KS D={D:.4g} p={p:.3g}; gpu clones {sp['clones']} oracle {meta['stats']['clones']}")
+    _say(f"c1 KS D={D:.4g} p={p:.3g}; gpu clones {sp['clones']} oracle {meta['stats']['clones']}; "
+         f"clone keys checked on {len(allg)} tracks of {fam} families")
     assert p > 0.01
 
 
@@ -459,6 +478,45 @@ def test_graph_replay_and_autotune_are_consistent(R, ctx):
     h, s, _ = R.run(ctx, w["species"], b, rcfg(R, form=R.FORM_PERSISTENT))
     torch.cuda.synchronize()
     assert R.parse_stats(s)["finished"] == 512
+
+
+def test_graph_cache_keeps_one_pipeline_for_fresh_buffers(R):
+    """The persistent pipeline graph is cached per launch shape, not per buffer address:
+    50 runs whose batch, histogram and statistics are freshly allocated each time (all kept
+    alive, so every call sees new addresses) keep one cached graph and give bitwise-equal
+    histograms and equal statistics."""
+    w = WORKLOADS["c0_b1kev"]
+    c = R.Context()
+    try:
+        sc = R.SamplerConfig(**w["sampler"])
+        cfg = rcfg(R, form=R.FORM_PERSISTENT, lanes_per_track=64, n_bins=w["n_bins"],
+                   thresholds=[[20.0, 40.0, 60.0]])
+        keep, hists, finished = [], [], set()
+        for i in range(50):
+            b = R.sample_primaries(c, sc, 0, 128)
+            h, st, k = R.run(c, w["species"], b, cfg)
+            keep.append((b, h, st, k))
+            hists.append(h)
+        torch.cuda.synchronize()
+        assert len({h.data_ptr() for h in hists}) == 50
+        assert c.cached_graphs() == 1
+        ref = hists[0].cpu().numpy()
+        for (b, h, st, k) in keep:
+            assert np.array_equal(h.cpu().numpy(), ref)
+            s = R.parse_stats(st)
+            finished.add((s["finished"], s["clones"], s["track_steps"]))
+            assert s["primaries"] == 128
+        assert len(finished) == 1
+        # a second launch shape adds a second graph (its larger clone stacks first empty the
+        # cache, so the first shape is built again after it)
+        R.run(c, w["species"], b, rcfg(R, form=R.FORM_PERSISTENT, lanes_per_track=16, n_bins=w["n_bins"],
+                                        thresholds=[[20.0, 40.0, 60.0]]))
+        h2, _, _ = R.run(c, w["species"], b, cfg)
+        torch.cuda.synchronize()
+        assert c.cached_graphs() == 2
+        assert np.array_equal(h2.cpu().numpy(), ref)
+    finally:
+        c.close()
 
 
 def _run_subset(R, ctx, wname, thresholds, ids, **kw):
@@ -502,7 +560,8 @@ def test_mixed_and_deep_tail_workloads_match_oracle(R, ctx, wname, thr_name, gol
                                                          thresholds=thr, form=R.FORM_PERSISTENT),
                               pilot=min(64, n))
     _say(f"autotuned lanes {lanes} waves/CU {waves}")
-    hq, sq, lq = _run_subset(R, ctx, wname, thr, ids, form=R.FORM_PERSISTENT, lanes_per_track=64)
+    hq, sq, lq = _run_subset(R, ctx, wname, thr, ids, form=R.FORM_PERSISTENT, lanes_per_track=lanes,
+                             waves_per_cu=waves)
     assert np.array_equal(hp, hq)
     assert sp["finished"] == sq["finished"] and sp["track_steps"] == sq["track_steps"]
     s = lp[lp["status"] == R.STOPPED]

@@ -597,3 +597,22 @@ def test_refined_depths_keep_unresolved_targets_and_spacing():
     # targets keep 2.0 and 50.0, raised by the 3 A spacing where needed
     assert np.allclose(d[0], [7.5, 10.5, 50.0], rtol=0, atol=1e-12)
     assert np.array_equal(d[1], [7.0, 10.0, 13.0])
+
+
+def test_family_moment_errors_reduce_to_textbook_forms():
+    """The family-grouped standard errors used by the statistical parity tests: with one
+    unit-weight sample per family they are the textbook SE of a mean, s / sqrt(n), and (to
+    first order) of a standard deviation, sqrt(mu4 - sigma^4) / (2 sigma sqrt(n)); duplicating
+    every sample inside its family (a clone pair of half weight each) changes nothing."""
+    from tests.physref import family_moments
+    rng = np.random.default_rng(4)
+    z = rng.gamma(3.0, 20.0, 20000)
+    m, sd, se_m, se_sd = family_moments(z, np.ones_like(z), np.arange(z.size))
+    assert abs(m - z.mean()) < 1e-9 * m and abs(sd - z.std()) < 1e-9 * sd
+    assert abs(se_m / (z.std() / math.sqrt(z.size)) - 1.0) < 1e-9
+    mu4 = ((z - z.mean()) ** 4).mean()
+    ref = math.sqrt(mu4 - z.var() ** 2) / (2.0 * z.std() * math.sqrt(z.size))
+    assert abs(se_sd / ref - 1.0) < 1e-9
+    z2 = np.repeat(z, 2)
+    out2 = family_moments(z2, np.full(z2.size, 0.5), np.repeat(np.arange(z.size), 2))
+    assert np.allclose(out2, (m, sd, se_m, se_sd), rtol=1e-9)
