@@ -141,6 +141,7 @@ def cpu_baseline(key, target_seconds):
         total_tracks += r["stats"]["finished"]
         total_prim += len(lin)
         offset += k
+        progress(f"oracle chunk of {len(lin)} primaries: {r['stats']['pair_evals']} pairs, {t_all:.1f} s so far")
     ids = (f"ids 0..{offset - 1} and {half}..{half + offset - 1}" if key == "c1" else f"ids 0..{offset - 1}")
     return dict(value=total_pairs / t_all, unit="force evals/s", cores=cores, kind="oracle",
                 sample=f"{total_prim} primaries of the same workload ({ids}, all clones), {t_all:.1f} s wall, "
@@ -372,6 +373,11 @@ def grad_forward_ratio(R, ctx, torch):
                 stopped=g["count"])
 
 
+def progress(msg):
+    """One line per finished launch or leg on stderr (the JSON result goes to stdout)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
 def plan_steps(N, K, W, whole):
     """(primaries per step, timed (id0, n) slices, warm-up slices).  Sliced: timed step k runs
     ids [k s, (k+1) s) with s = ceil(N / K), so the timed steps together run ids 0..N-1 once;
@@ -418,7 +424,9 @@ def timed_launches(R, torch, ctx, w, sampler, cfg, slices, stream, log_first=Fal
         tot["prims"] += st["primaries"]
         tot["steps"] += st["track_steps"]
         kms.append(ev[k][0].elapsed_time(ev[k][1]))
-        queue_use.append([st["max_queue"], st["stack_overflow"]])
+        queue_use.append([st["max_queue"], st["stack_overflow"], st["handed_off"]])
+        progress(f"launch {k + 1}/{len(slices)} ids {id0}..{id0 + n - 1}: {kms[-1]:.1f} ms, "
+                 f"{st['pair_evals'] / (kms[-1] * 1e-3):.4g} force evals/s")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     return kms, tot, wall, queue_use, log
@@ -444,7 +452,7 @@ def c1_leg(R, torch, np, args):
                         "8 cloning depths x 2 clones; 1 A bins 0-8192 A",
                force_evals_per_s=tot["pairs"] / wall, tracks_per_s=tot["tracks"] / wall,
                kernel_ms_per_step=[round(x, 1) for x in kms], launch=R.launch_shape(ctx, batch, cfg),
-               queue_max_and_overflow_per_step=queue_use,
+               queue_max_overflow_handoff_per_step=queue_use,
                roofline={"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                          "frac": achieved / FP64_VECTOR_PEAK_TFLOPS})
     out["profile_accuracy"] = profile_accuracy(R, torch, np, ctx, w, sampler, n, cfg, reed_log, kw[0] * 1e-3,
@@ -529,8 +537,11 @@ def main():
     cfg = R.RunConfig(form=f, lanes_per_track=lanes, waves_per_cu=waves, **base)
     shape = R.launch_shape(ctx, tb, cfg)
 
+    progress(f"workload {key}: {N} primaries, {sl} per step, shape {shape}")
     if warm:
+        progress("warm-up")
         timed_launches(R, torch, ctx, w, sampler, cfg, warm, stream)
+    progress("timed steps")
     kernel_ms, tot, wall, queue_use, _ = timed_launches(R, torch, ctx, w, sampler, cfg, timed, stream)
 
     steps = len(timed)
@@ -573,7 +584,7 @@ def main():
         "primaries_per_s": tot["prims"] / wall,
         "track_steps_per_s": tot["steps"] / wall,
         "kernel_ms_per_step": [round(x, 1) for x in kernel_ms],
-        "queue_max_and_overflow_per_step": queue_use,
+        "queue_max_overflow_handoff_per_step": queue_use,
         "grad_fwd_ratio": None,
         "roofline": {
             "bound": "alu",
@@ -589,20 +600,25 @@ def main():
         },
     }
     if not args.no_fp32:
+        progress("fp32 leg")
         out["fp32_pair_variant"] = fp32_leg(R, ctx, torch, w, sampler, timed[:2], base, stream, args.form,
                                             args.lanes, args.waves)
     ctx.close()
     if key != "c1" and not args.no_c1:
+        progress("c1 leg")
         out["c1_as10kev"] = c1_leg(R, torch, np, args)
     if not args.no_uo2:
+        progress("uo2 leg")
         out["uo2_recoil"] = uo2_leg(R, torch, args.uo2_n)
     if not args.no_grad:
+        progress("grad leg")
         gctx = R.Context()
         gr = grad_forward_ratio(R, gctx, torch)
         gctx.close()
         out["grad_fwd_ratio"] = gr["ratio"]
         out["grad"] = gr
     if not args.no_cpu:
+        progress("cpu leg")
         out["cpu_baseline"] = cpu_baseline(key, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 

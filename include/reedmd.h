@@ -167,7 +167,8 @@ typedef struct {
     int32_t form;        /* REEDMD_FORM_PLAIN or REEDMD_FORM_PERSISTENT */
     int32_t lanes_per_track;   /* 64, 32 or 16; 0 = from the autotune cache (default 64) */
     int32_t waves_per_cu;      /* persistent form: resident waves per CU (0 = default) */
-    int32_t queue_capacity;    /* persistent form: clone-queue records (0 = default 4096) */
+    int32_t queue_capacity;    /* persistent form: clone-queue records (0 = default: 4 per primary of the
+                                  batch, at least 4,096 and at most 65,536) */
     const int32_t* cancel;     /* device word polled by the kernel, non-zero = cancel; may be NULL */
     void* track_log;           /* optional device array of reedmd_result, may be NULL */
     int64_t track_log_cap;
@@ -181,7 +182,11 @@ typedef struct {
                                   whose origin is nearest its start point (floor(x/a + 1/4) per
                                   axis); that site stays empty for the whole track and its clones;
                                   fluorite only (diamond: REEDMD_EUNSUPPORTED) */
-    int32_t reserved;
+    int32_t no_tail_handoff;   /* persistent form with 16 or 32 lanes per track: 0 (default) hands the
+                                  tail to a 64-lane launch of the track kernel in the same pipeline
+                                  once every primary is claimed and no more tracks are live than that
+                                  launch has segments (running tracks move through the clone queue,
+                                  exactly: results are the same bit for bit); 1: no handoff */
 } reedmd_run_params;
 
 /* Finished-track entry of the optional log (48 bytes). */
@@ -205,6 +210,7 @@ typedef struct {
     double w_stopped, w_backscattered, w_underflow, w_overflow, w_quarantined;
     double sum_wz, sum_wz2, w_cancelled;
     int64_t max_queue, stack_overflow, log_count, error_flags;
+    int64_t handed_off;  /* tracks moved to the 64-lane tail launch (see no_tail_handoff) */
 } reedmd_stats;
 
 /* Library version, e.g. 100 for 0.1.0. */

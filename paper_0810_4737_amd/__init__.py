@@ -124,6 +124,7 @@ class RunConfig:
     force_precision: int = FORCE_FP64
     range_mode: int = RANGE_DEPTH
     vacancy: int = 0
+    no_tail_handoff: int = 0
 
     def struct(self, device, keep):
         p = _abi.RunParams()
@@ -139,6 +140,7 @@ class RunConfig:
         p.waves_per_cu, p.queue_capacity = self.waves_per_cu, self.queue_capacity
         p.force_precision = self.force_precision
         p.range_mode, p.vacancy = self.range_mode, self.vacancy
+        p.no_tail_handoff = self.no_tail_handoff
         return p
 
 

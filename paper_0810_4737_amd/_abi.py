@@ -66,7 +66,7 @@ class RunParams(C.Structure):
                 ("form", C.c_int32), ("lanes_per_track", C.c_int32), ("waves_per_cu", C.c_int32),
                 ("queue_capacity", C.c_int32), ("cancel", C.c_void_p), ("track_log", C.c_void_p),
                 ("track_log_cap", C.c_int64), ("force_precision", C.c_int32), ("range_mode", C.c_int32),
-                ("vacancy", C.c_int32), ("reserved2", C.c_int32)]
+                ("vacancy", C.c_int32), ("no_tail_handoff", C.c_int32)]
 
 
 class Refine(C.Structure):
@@ -86,7 +86,7 @@ STATS_INT_A = ("primaries", "finished", "clones", "track_steps", "pair_evals", "
                "n_backscattered", "n_nonfinite", "n_stepcap", "n_cancelled")
 STATS_DBL = ("w_stopped", "w_backscattered", "w_underflow", "w_overflow", "w_quarantined",
              "sum_wz", "sum_wz2", "w_cancelled")
-STATS_INT_B = ("max_queue", "stack_overflow", "log_count", "error_flags")
+STATS_INT_B = ("max_queue", "stack_overflow", "log_count", "error_flags", "handed_off")
 STATS_WORDS = len(STATS_INT_A) + len(STATS_DBL) + len(STATS_INT_B)
 
 # every entry point declared in include/reedmd.h

@@ -29,7 +29,8 @@ constexpr double kMaxScreening = 100.0;        // keeps every exponent argument 
 constexpr long long kDefaultGradSteps = 16384;    // gradient step cap when the caller sets none
 constexpr int kTuneBoxMs = 400;                   // autotuner: time box of each candidate launch
 constexpr size_t kGradScratchBytes = size_t(48) << 30;   // checkpoint memory per launch chunk
-constexpr size_t kMaxGraphs = 16;                 // instantiated persistent pipelines kept per context
+constexpr size_t kMaxGraphs = 16;
+constexpr long long kMaxQueue = 65536;            // default clone-queue capacity cap (1.0 GB of diamond records)                 // instantiated persistent pipelines kept per context
 
 thread_local std::string g_create_error;
 
@@ -58,7 +59,7 @@ struct reedmd_ctx {
     struct Graph {
         hipGraph_t graph = nullptr;
         hipGraphExec_t exec = nullptr;
-        hipGraphNode_t node[6] = {};   // reset, order count, scan, scatter, track kernel, statistics
+        hipGraphNode_t node[7] = {};   // reset, order count, scan, scatter, track kernel, [64-lane tail], statistics
     };
     std::map<std::vector<long long>, Graph> graphs;
 };
@@ -220,6 +221,7 @@ reedmd_status check_params(reedmd_ctx* ctx, const reedmd_run_params* p, bool nee
     if (p->waves_per_cu < 0 || p->waves_per_cu > 32) return fail(ctx, REEDMD_EINVAL, "waves_per_cu must be in 0..32");
     if (p->queue_capacity < 0) return fail(ctx, REEDMD_EINVAL, "queue_capacity must be >= 0");
     if (p->track_log && p->track_log_cap < 0) return fail(ctx, REEDMD_EINVAL, "track_log_cap must be >= 0");
+    if (p->no_tail_handoff != 0 && p->no_tail_handoff != 1) return fail(ctx, REEDMD_EINVAL, "no_tail_handoff must be 0 or 1");
     if (p->force_precision != REEDMD_FORCE_FP64 && p->force_precision != REEDMD_FORCE_FP32)
         return fail(ctx, REEDMD_EINVAL, "force_precision must be REEDMD_FORCE_FP64 or REEDMD_FORCE_FP32");
     return REEDMD_OK;
@@ -387,12 +389,10 @@ void launch_step_any(int L, bool f32, int lat, const KernelArgs& A, long long bl
 constexpr int kOrderBuckets = 512;
 constexpr int kOrderBlocks = 256;   // grid of the order kernels (grid-stride over the batch)
 
-// Queue state reset and the claim-order counters (a kernel, not a memset, so the
-// pipeline can be kept as a graph).
-__global__ void queue_reset_kernel(QueueState* q, unsigned long long* seq, int cap, long long n, int* counts)
+// Queue state reset (a kernel, not a memset, so the pipeline can be kept as a graph).
+__global__ void queue_reset_kernel(QueueState* q, unsigned long long* seq, int cap, long long n)
 {
     const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
-    for (long long c = i; c < kOrderBuckets; c += static_cast<long long>(gridDim.x) * blockDim.x) counts[c] = 0;
     if (i == 0) {
         q->head = 0;
         q->tail = 0;
@@ -400,7 +400,8 @@ __global__ void queue_reset_kernel(QueueState* q, unsigned long long* seq, int c
         q->prim_next = 0;
         q->depth_max = 0;
         q->log_next = 0;
-        q->pad[0] = q->pad[1] = 0;
+        q->handoff = 0;
+        q->pad = 0;
     }
     if (i < cap) seq[i] = static_cast<unsigned long long>(i);
 }
@@ -410,9 +411,10 @@ __global__ void queue_reset_kernel(QueueState* q, unsigned long long* seq, int c
 // proxy is E0 / M1 (the ion's speed squared sets the number of steps of a
 // track, dx_max per step, and with it the number of cloning depths it
 // crosses); a counting sort into 16 buckets per octave of E0 / M1, largest
-// first.  The order inside a bucket is whatever the atomics give: every
+// first.  Every
 // primary family is computed the same way wherever and whenever it runs, so
-// the order changes no result.
+// the order changes no result.  The sort is stable, so primaries of one bucket
+// keep the batch order.
 struct OrderArgs {
     long long n;
     const int* species;
@@ -420,8 +422,8 @@ struct OrderArgs {
     double inv_M1[kMaxSpecies];
     int n_species;
     int pad;
-    int* counts;    // [kOrderBuckets]
-    int* offsets;   // [kOrderBuckets]
+    int* counts;    // [kOrderBuckets][kOrderBlocks]
+    int* offsets;   // [kOrderBuckets][kOrderBlocks]
     int* order;     // [n]
 };
 
@@ -434,28 +436,66 @@ __device__ __forceinline__ int order_bucket(const OrderArgs& O, long long q)
     return kOrderBuckets - 1 - static_cast<int>(b);
 }
 
-__global__ void order_count_kernel(const OrderArgs O)
+// The sort is stable (batch order inside a bucket): block g owns the contiguous
+// chunk [g c, (g+1) c) of the batch, c = ceil(n / kOrderBlocks).
+__device__ __forceinline__ void order_chunk(const OrderArgs& O, long long& lo, long long& hi)
 {
-    for (long long q = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; q < O.n;
-         q += static_cast<long long>(gridDim.x) * blockDim.x)
-        atomicAdd(&O.counts[order_bucket(O, q)], 1);
+    const long long c = (O.n + kOrderBlocks - 1) / kOrderBlocks;
+    lo = static_cast<long long>(blockIdx.x) * c;
+    hi = lo + c < O.n ? lo + c : O.n;
 }
 
-__global__ void order_scan_kernel(const OrderArgs O)
+// Counts of every bucket in every chunk: counts[bucket * kOrderBlocks + block].
+__global__ void __launch_bounds__(256) order_count_kernel(const OrderArgs O)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    __shared__ int c[kOrderBuckets];
+    for (int i = threadIdx.x; i < kOrderBuckets; i += blockDim.x) c[i] = 0;
+    __syncthreads();
+    long long lo, hi;
+    order_chunk(O, lo, hi);
+    for (long long q = lo + threadIdx.x; q < hi; q += blockDim.x) atomicAdd(&c[order_bucket(O, q)], 1);
+    __syncthreads();
+    for (int i = threadIdx.x; i < kOrderBuckets; i += blockDim.x) O.counts[i * kOrderBlocks + blockIdx.x] = c[i];
+}
+
+// Exclusive prefix over (bucket, block) in that order: the start of every
+// chunk's run of every bucket.  One thread per bucket sums its chunks, the
+// bucket totals are scanned in LDS.
+__global__ void __launch_bounds__(kOrderBuckets) order_scan_kernel(const OrderArgs O)
+{
+    __shared__ int tot[kOrderBuckets];
+    const int b = threadIdx.x;
     int run = 0;
-    for (int b = 0; b < kOrderBuckets; ++b) {
-        O.offsets[b] = run;
-        run += O.counts[b];
+    for (int g = 0; g < kOrderBlocks; ++g) {
+        const int c = O.counts[b * kOrderBlocks + g];
+        O.offsets[b * kOrderBlocks + g] = run;
+        run += c;
     }
+    tot[b] = run;
+    __syncthreads();
+    if (b == 0) {
+        int acc = 0;
+        for (int i = 0; i < kOrderBuckets; ++i) {
+            const int t = tot[i];
+            tot[i] = acc;
+            acc += t;
+        }
+    }
+    __syncthreads();
+    for (int g = 0; g < kOrderBlocks; ++g) O.offsets[b * kOrderBlocks + g] += tot[b];
 }
 
-__global__ void order_scatter_kernel(const OrderArgs O)
+// One thread per chunk places its primaries in batch order (the chunk's bucket
+// offsets staged in LDS).
+__global__ void __launch_bounds__(64) order_scatter_kernel(const OrderArgs O)
 {
-    for (long long q = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; q < O.n;
-         q += static_cast<long long>(gridDim.x) * blockDim.x)
-        O.order[atomicAdd(&O.offsets[order_bucket(O, q)], 1)] = static_cast<int>(q);
+    __shared__ int off[kOrderBuckets];
+    for (int i = threadIdx.x; i < kOrderBuckets; i += blockDim.x) off[i] = O.offsets[i * kOrderBlocks + blockIdx.x];
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    long long lo, hi;
+    order_chunk(O, lo, hi);
+    for (long long q = lo; q < hi; ++q) O.order[off[order_bucket(O, q)]++] = static_cast<int>(q);
 }
 
 // Copies the number of logged results into the caller's stats at the end.
@@ -507,7 +547,8 @@ reedmd_status ensure_scratch(reedmd_ctx* ctx, int qcap, size_t stack_records)
 
 reedmd_status ensure_order(reedmd_ctx* ctx, long long n)
 {
-    const size_t need = (2 * static_cast<size_t>(kOrderBuckets) + static_cast<size_t>(std::max<long long>(n, 1))) * sizeof(int);
+    const size_t need = (2 * static_cast<size_t>(kOrderBuckets) * kOrderBlocks + static_cast<size_t>(std::max<long long>(n, 1))) *
+                        sizeof(int);
     if (need <= ctx->ordbuf_bytes) return REEDMD_OK;
     HIP_TRY(ctx, hipDeviceSynchronize());
     if (ctx->ordbuf) (void)hipFree(ctx->ordbuf);
@@ -547,6 +588,10 @@ struct Shape {
     long long blocks;
     int stack_cap;
     int qcap;
+    // tail handoff to a 64-lane launch (persistent form with fewer lanes): its workgroups
+    // and segments; 0 when off
+    long long tail_blocks;
+    long long tail_segs;
 };
 
 Shape choose_shape(reedmd_ctx* ctx, const reedmd_run_params* p, const reedmd_batch* b)
@@ -580,8 +625,15 @@ Shape choose_shape(reedmd_ctx* ctx, const reedmd_run_params* p, const reedmd_bat
         if (waves > 0) bpc = std::max(1, std::min(bpc, (waves + per_wave_block - 1) / per_wave_block));
         s.blocks = static_cast<long long>(bpc) * ctx->cu_count;
         s.seg_total = s.blocks * per_wave_block * T;
-        s.qcap = p->queue_capacity > 0 ? p->queue_capacity : 4096;
-        if (p->n_thresh == 0) s.qcap = 1;
+        // default: room for every clone a burst of long families can have pending (a full
+        // queue sends clones to the creating segment's stack, where they run one after another)
+        s.qcap = p->queue_capacity > 0 ? p->queue_capacity
+                                       : static_cast<int>(std::min<long long>(kMaxQueue, std::max<long long>(4096, 4 * b->n)));
+        if (L < 64 && p->no_tail_handoff == 0) {
+            s.tail_blocks = static_cast<long long>(resident_blocks_per_cu(64, s.mode, s.f32, lattice_of(ctx))) * ctx->cu_count;
+            s.tail_segs = s.tail_blocks * per_wave_block;
+        }
+        if (p->n_thresh == 0 && s.tail_blocks == 0) s.qcap = 1;
     }
     return s;
 }
@@ -592,7 +644,7 @@ reedmd_status run_impl(reedmd_ctx* ctx, const reedmd_species* sp, const reedmd_b
 {
     Shape s = forced ? *forced : choose_shape(ctx, p, b);
     const int qcap = s.qcap > 0 ? s.qcap : 1;
-    const size_t stack_records = static_cast<size_t>(s.seg_total) * static_cast<size_t>(std::max(s.stack_cap, 0));
+    const size_t stack_records = static_cast<size_t>(std::max(s.seg_total, s.tail_segs)) * static_cast<size_t>(std::max(s.stack_cap, 0));
     reedmd_status st = ensure_scratch(ctx, qcap, stack_records);
     if (st != REEDMD_OK) return st;
 
@@ -609,7 +661,8 @@ reedmd_status run_impl(reedmd_ctx* ctx, const reedmd_species* sp, const reedmd_b
     A.q = static_cast<QueueState*>(ctx->scratch);
     A.qseq = reinterpret_cast<unsigned long long*>(static_cast<char*>(ctx->scratch) + 256);
     A.qrec = reinterpret_cast<double*>(static_cast<char*>(ctx->scratch) + 256 + static_cast<size_t>(qcap) * 8);
-    A.qcap = (s.mode == kModePersistent && p->n_thresh > 0) ? qcap : 0;
+    A.qcap = (s.mode == kModePersistent && (p->n_thresh > 0 || s.tail_blocks > 0)) ? qcap : 0;
+    A.handoff_live = s.tail_segs;
     A.cancel = p->cancel;
     A.seg_total = s.seg_total;
 
@@ -629,31 +682,43 @@ reedmd_status run_impl(reedmd_ctx* ctx, const reedmd_species* sp, const reedmd_b
     for (int i = 0; i < kMaxSpecies; ++i) O.inv_M1[i] = 1.0 / A.sp[i].M1;
     O.n_species = sp->n_species;
     O.counts = ctx->ordbuf;
-    O.offsets = ctx->ordbuf + kOrderBuckets;
-    O.order = ctx->ordbuf + 2 * kOrderBuckets;
+    O.offsets = ctx->ordbuf + kOrderBuckets * kOrderBlocks;
+    O.order = ctx->ordbuf + 2 * kOrderBuckets * kOrderBlocks;
     A.order = O.order;
     QueueState* q = A.q;
     unsigned long long* seq = A.qseq;
     int cap = qcap;
     long long nq = b->n;
-    int* counts = O.counts;
     reedmd_stats* st_out = d_stats;
-    void* reset_args[] = {&q, &seq, &cap, &nq, &counts};
+    KernelArgs T = A;   // the 64-lane tail launch: queue only, no handoff of its own
+    T.seg_total = s.tail_segs;
+    T.handoff_live = 0;
+    T.tail = 1;
+    void* reset_args[] = {&q, &seq, &cap, &nq};
     void* order_args[] = {&O};
     void* track_args[] = {&A};
+    void* tail_args[] = {&T};
     void* fin_args[] = {&q, &st_out};
-    constexpr int kNodes = 6;
-    hipKernelNodeParams np[kNodes] = {};
-    const void* funcs[kNodes] = {reinterpret_cast<const void*>(queue_reset_kernel),
-                                 reinterpret_cast<const void*>(order_count_kernel),
-                                 reinterpret_cast<const void*>(order_scan_kernel),
-                                 reinterpret_cast<const void*>(order_scatter_kernel),
-                                 track_kernel_ptr(s.L, s.mode, s.f32, lattice_of(ctx)),
-                                 reinterpret_cast<const void*>(stats_finalize_kernel)};
-    const dim3 grids[kNodes] = {dim3((std::max(qcap, kOrderBuckets) + 255) / 256), dim3(kOrderBlocks), dim3(1),
-                                dim3(kOrderBlocks), dim3(static_cast<unsigned>(s.blocks)), dim3(1)};
-    const dim3 blocks[kNodes] = {dim3(256), dim3(256), dim3(64), dim3(256), dim3(kBlock), dim3(64)};
-    void** args[kNodes] = {reset_args, order_args, order_args, order_args, track_args, fin_args};
+    const bool tail = s.tail_blocks > 0;
+    const int kNodes = tail ? 7 : 6;
+    hipKernelNodeParams np[7] = {};
+    const void* funcs[7] = {reinterpret_cast<const void*>(queue_reset_kernel),
+                            reinterpret_cast<const void*>(order_count_kernel),
+                            reinterpret_cast<const void*>(order_scan_kernel),
+                            reinterpret_cast<const void*>(order_scatter_kernel),
+                            track_kernel_ptr(s.L, s.mode, s.f32, lattice_of(ctx)),
+                            track_kernel_ptr(64, s.mode, s.f32, lattice_of(ctx)),
+                            reinterpret_cast<const void*>(stats_finalize_kernel)};
+    dim3 grids[7] = {dim3((qcap + 255) / 256), dim3(kOrderBlocks), dim3(1), dim3(kOrderBlocks),
+                     dim3(static_cast<unsigned>(s.blocks)), dim3(static_cast<unsigned>(std::max(s.tail_blocks, 1ll))), dim3(1)};
+    dim3 blocks[7] = {dim3(256), dim3(256), dim3(kOrderBuckets), dim3(64), dim3(kBlock), dim3(kBlock), dim3(64)};
+    void** args[7] = {reset_args, order_args, order_args, order_args, track_args, tail_args, fin_args};
+    if (!tail) {   // no tail launch: the statistics node follows the track kernel
+        funcs[5] = funcs[6];
+        grids[5] = grids[6];
+        blocks[5] = blocks[6];
+        args[5] = args[6];
+    }
     for (int k = 0; k < kNodes; ++k) {
         np[k].func = const_cast<void*>(funcs[k]);
         np[k].gridDim = grids[k];
@@ -672,7 +737,7 @@ reedmd_status run_impl(reedmd_ctx* ctx, const reedmd_species* sp, const reedmd_b
             HIP_TRY(ctx, hipLaunchKernel(np[k].func, np[k].gridDim, np[k].blockDim, np[k].kernelParams, 0, stream));
         return REEDMD_OK;
     }
-    const std::vector<long long> key = {s.L, s.f32 ? 1 : 0, lattice_of(ctx), s.blocks, qcap};
+    const std::vector<long long> key = {s.L, s.f32 ? 1 : 0, lattice_of(ctx), s.blocks, qcap, s.tail_blocks};
     auto it = ctx->graphs.find(key);
     if (it == ctx->graphs.end()) {
         if (ctx->graphs.size() >= kMaxGraphs) drop_graphs(ctx);

@@ -38,7 +38,8 @@ struct QueueState {
     long long prim_next;    // next unclaimed primary
     long long depth_max;
     long long log_next;     // next free entry of the optional result log
-    long long pad[2];
+    long long handoff;      // 1: running tracks move to the queue for the wider tail kernel
+    long long pad;
 };
 
 struct KernelArgs {
@@ -85,6 +86,13 @@ struct KernelArgs {
     const int* cancel;
     const int* order;       // optional: batch entry of the i-th claimed primary (longest expected first)
     long long seg_total;
+    // tail handoff (persistent form with fewer than 64 lanes per track): once every primary
+    // is claimed and at most handoff_live tracks are live, running tracks are stored in the
+    // queue and finished by a 64-lane launch of the same kernel (tail = 1), which takes work
+    // from the queue only; 0: no handoff
+    long long handoff_live;
+    int tail;
+    int pad_tail;
     // debug entry points
     double* records;
     int nsteps;
@@ -805,7 +813,7 @@ __device__ __forceinline__ long long queue_reserve_push(const KernelArgs& A)
 {
     QueueState* q = A.q;
     unsigned long long pos = __hip_atomic_load(&q->tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    for (int tries = 0; tries < 64; ++tries) {
+    for (int tries = 0; tries < 256; ++tries) {
         const unsigned long long seq =
             __hip_atomic_load(&A.qseq[pos % A.qcap], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
         if (seq == pos) {
@@ -827,7 +835,7 @@ __device__ __forceinline__ long long queue_reserve_pop(const KernelArgs& A)
 {
     QueueState* q = A.q;
     unsigned long long pos = __hip_atomic_load(&q->head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    for (int tries = 0; tries < 64; ++tries) {
+    for (int tries = 0; tries < 256; ++tries) {
         const unsigned long long seq =
             __hip_atomic_load(&A.qseq[pos % A.qcap], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
         if (seq == pos + 1) {
@@ -878,16 +886,25 @@ __global__ void __launch_bounds__(256, REEDMD_WAVES_PER_SIMD(L, LAT)) track_kern
     long long exec_steps = 0, pairs = 0;
     int since_poll = 0;
     bool cancelled = false;
+    bool handoff_now = false;
     double* my_stack = A.stack + static_cast<size_t>(seg < A.seg_total ? seg : 0) *
                                      static_cast<size_t>(A.stack_cap) * RW;
 
     for (;;) {
         if (mode == kSegNeed) {
+            handoff_now = false;
             const KernelArgs A = cold_args();
             if (A.cancel != nullptr) {
                 int cv = 0;
                 if (sl == 0) cv = __hip_atomic_load(A.cancel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
                 cancelled = __shfl(cv, leader, 64) != 0;
+            }
+            // after the tail handoff this launch takes nothing from the queue: what is there
+            // (and whatever its segments still hold) is for the 64-lane tail launch
+            int hflag = 0;
+            if (MODE == kModePersistent && A.handoff_live > 0 && !A.tail) {
+                if (sl == 0) hflag = static_cast<int>(__hip_atomic_load(&A.q->handoff, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                hflag = __shfl(hflag, leader, 64);
             }
             bool got = false;
             if (top > 0) {
@@ -895,7 +912,8 @@ __global__ void __launch_bounds__(256, REEDMD_WAVES_PER_SIMD(L, LAT)) track_kern
                 load_record<L, LAT>(t, my_stack + static_cast<size_t>(top) * RW, sl, A);
                 refresh_threshold(t, A);
                 got = true;
-            } else if (MODE == kModePersistent && A.qcap > 0) {
+                handoff_now = hflag != 0;
+            } else if (MODE == kModePersistent && A.qcap > 0 && !hflag) {
                 long long slot = -1;
                 if (sl == 0) slot = queue_reserve_pop(A);
                 slot = __shfl(slot, leader, 64);
@@ -918,7 +936,7 @@ __global__ void __launch_bounds__(256, REEDMD_WAVES_PER_SIMD(L, LAT)) track_kern
                         next_primary += A.seg_total;
                     }
                 } else {
-                    if (sl == 0) {
+                    if (sl == 0 && !A.tail && !hflag) {
                         const long long cur = __hip_atomic_load(&A.q->prim_next, __ATOMIC_RELAXED,
                                                                 __HIP_MEMORY_SCOPE_AGENT);
                         if (cur < A.n) qi = atomicAdd(reinterpret_cast<unsigned long long*>(&A.q->prim_next), 1ull);
@@ -959,10 +977,25 @@ __global__ void __launch_bounds__(256, REEDMD_WAVES_PER_SIMD(L, LAT)) track_kern
             } else if (MODE == kModePlain) {
                 mode = kSegDone;
             } else {
+                // nothing to take: leave when no track is live, or when the tail is handed to the
+                // wider kernel (every primary claimed and few tracks live; this segment's stack
+                // is empty and what is in the queue stays there for the tail kernel)
                 long long live = 0;
-                if (sl == 0) live = __hip_atomic_load(&A.q->live, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                int h = 0;
+                if (sl == 0) {
+                    live = __hip_atomic_load(&A.q->live, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (A.handoff_live > 0 && !A.tail && live > 0) {
+                        h = hflag;
+                        if (!h && live <= A.handoff_live &&
+                            __hip_atomic_load(&A.q->prim_next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= A.n) {
+                            __hip_atomic_store(&A.q->handoff, 1ll, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            h = 1;
+                        }
+                    }
+                }
                 live = __shfl(live, leader, 64);
-                if (live <= 0) mode = kSegDone;
+                h = __shfl(h, leader, 64);
+                if (live <= 0 || h) mode = kSegDone;
             }
         }
         if (__all(mode == kSegDone)) break;
@@ -989,8 +1022,14 @@ __global__ void __launch_bounds__(256, REEDMD_WAVES_PER_SIMD(L, LAT)) track_kern
                 if (sl == 0) cv = __hip_atomic_load(C.cancel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
                 if (__shfl(cv, leader, 64) != 0) st = REEDMD_CANCELLED;
             }
+            if (MODE == kModePersistent && C.handoff_live > 0 && !C.tail) {
+                int h = 0;
+                if (sl == 0) h = static_cast<int>(__hip_atomic_load(&C.q->handoff, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                handoff_now = __shfl(h, leader, 64) != 0;
+            }
         }
         if (st != REEDMD_ACTIVE) {
+            handoff_now = false;
             const KernelArgs A = cold_args();
             if (sl == 0) {
                 book_finished(A, st, t.w, t.zstop, t.lineage, t.next_k, t.steps, exec_steps, pairs, t.table, t.key);
@@ -1046,6 +1085,30 @@ __global__ void __launch_bounds__(256, REEDMD_WAVES_PER_SIMD(L, LAT)) track_kern
                 }
                 t.key = child_key(parent, A.seed, k, 0);
                 refresh_threshold(t, A);
+            }
+        }
+        if (MODE == kModePersistent && handoff_now) {
+            // tail handoff, after this step's events and cloning: the track goes to the queue
+            // as it stands (the record round trip is exact and the segment sums do not depend
+            // on the lanes per track, so the wider kernel continues it bit for bit); its steps
+            // and pairs so far are booked here.  If the queue has no room the track goes on
+            // here and tries again at the next poll.
+            handoff_now = false;
+            const KernelArgs C = cold_args();
+            long long slot = -1;
+            if (sl == 0) slot = queue_reserve_push(C);
+            slot = __shfl(slot, leader, 64);
+            if (slot >= 0) {
+                store_record<L, LAT>(t, C.qrec + static_cast<size_t>(slot % C.qcap) * RW, sl);
+                __threadfence();
+                if (sl == 0) {
+                    __hip_atomic_store(&C.qseq[slot % C.qcap], static_cast<unsigned long long>(slot) + 1,
+                                       __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                    add_i64(&C.stats->track_steps, exec_steps);
+                    add_i64(&C.stats->pair_evals, pairs);
+                    add_i64(&C.stats->handed_off, 1);
+                }
+                mode = kSegNeed;
             }
         }
     }

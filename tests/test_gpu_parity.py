@@ -542,8 +542,9 @@ def _run_subset(R, ctx, wname, thresholds, ids, **kw):
 def test_mixed_and_deep_tail_workloads_match_oracle(R, ctx, wname, thr_name, golden):
     """Subsets of the mixed B/P/As 1-100 keV workload (6 cloning tables of 12 depths) and of
     the 100 keV As [001] channeling workload (16 depths to 1e-6): exact weight ledger; the
-    persistent form with the autotuned launch shape gives the same histogram bitwise as the
-    plain form; the weighted depth distribution agrees with the stored oracle run."""
+    persistent form with the autotuned launch shape, and with 16 lanes per track with and
+    without the 64-lane tail launch, gives the same histogram and totals bitwise as the plain
+    form; the weighted depth distribution agrees with the stored oracle run."""
     from tests.workloads import C2_THRESHOLDS, C4_THRESHOLDS
     thr = C2_THRESHOLDS if thr_name == "c2" else [list(C4_THRESHOLDS)]
     meta, zo, wo = _load_golden(golden)
@@ -564,6 +565,15 @@ def test_mixed_and_deep_tail_workloads_match_oracle(R, ctx, wname, thr_name, gol
                              waves_per_cu=waves)
     assert np.array_equal(hp, hq)
     assert sp["finished"] == sq["finished"] and sp["track_steps"] == sq["track_steps"]
+    # 16 lanes with and without the 64-lane tail launch: the handed-off tracks continue
+    # bit for bit, so histograms and totals are equal
+    hh, sh, _ = _run_subset(R, ctx, wname, thr, ids, form=R.FORM_PERSISTENT, lanes_per_track=16)
+    hn, sn, _ = _run_subset(R, ctx, wname, thr, ids, form=R.FORM_PERSISTENT, lanes_per_track=16, no_tail_handoff=1)
+    _say(f"{wname}: tracks handed to the 64-lane tail launch {sh['handed_off']} (off: {sn['handed_off']})")
+    assert sh["handed_off"] > 0 and sn["handed_off"] == 0
+    assert np.array_equal(hp, hh) and np.array_equal(hp, hn)
+    for k in ("finished", "clones", "track_steps", "pair_evals", "n_stopped", "n_backscattered", "n_stepcap"):
+        assert sp[k] == sh[k] == sn[k], k
     s = lp[lp["status"] == R.STOPPED]
     D, p = physref.weighted_ks(s["z_stop"], s["w"], zo, wo)
     _say(f"{wname} KS D={D:.4g} p={p:.3g}; gpu tracks {sp['finished']} oracle {meta['stats']['finished']}")
