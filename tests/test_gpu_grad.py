@@ -101,9 +101,39 @@ def test_adjoint_short_tracks_under_a_small_step_cap(R, ctx):
     assert g["count"] == seen[oracle.STOPPED]
 
 
-def _fd(R, ctx, species, b, cfg, k, s, h, which):
-    up = dict(k=k, s=s)
-    dn = dict(k=k, s=s)
+def test_adjoint_matches_oracle_forward_mode_on_5kev_p(R, ctx):
+    """The adjoint workload's species and energy (P at 5 keV, 7 degree tilt), with the tracks
+    ended early by a raised stopping energy (3 keV, a few hundred steps: several 64-step
+    segments, domain moves and hard collisions): per track the reverse-mode derivatives equal
+    the oracle's forward-mode ones to 1e-6 where the two paths have not separated (stopping
+    depths equal to 1e-9)."""
+    species = ("P",)
+    pr = _batch(64, 0, 5000.0, 0)
+    b = R.batch_from_numpy(pr)
+    cfg = R.RunConfig(max_steps=20000, E_stop=3000.0)
+    g = R.grad(ctx, species, b, cfg, 1.0, 1.0, per_track=True)
+    tr = g["tracks"].cpu().numpy()
+    oc = oracle.Config(species=species, E_stop=3000.0)
+    checked, steps = 0, []
+    for i in range(len(tr)):
+        st, z, dk, ds, n = oracle.grad_track(oc, 0, pr["E0"][i], pr["pos"][:, i], pr["dir"][:, i],
+                                             int(pr["key"][i]), max_steps=20000)
+        assert int(tr[i, 3]) == st
+        if st != oracle.STOPPED or abs(tr[i, 0] - z) > 1e-9 * abs(z):
+            continue
+        checked += 1
+        steps.append(n)
+        assert int(tr[i, 4]) == n
+        for gv, ov, name in ((tr[i, 1], dk, "dk"), (tr[i, 2], ds, "ds")):
+            assert abs(gv - ov) <= 1e-6 * max(abs(ov), 1e-3 * abs(z)), (i, name, gv, ov, n)
+    _say(f"5 keV P to 3 keV: compared {checked} of {len(tr)} tracks, {min(steps)}-{max(steps)} steps")
+    assert checked >= 32
+
+
+def _per_track_fd(R, ctx, species, b, cfg, which, h, k=1.0, s=1.0):
+    """Central difference of every track's stopping depth on the same seeded crystal, and the
+    tracks that stop in both runs."""
+    up, dn = dict(k=k, s=s), dict(k=k, s=s)
     up[which] += h
     dn[which] -= h
     zu = R.grad(ctx, species, b, cfg, up["k"], up["s"], per_track=True)["tracks"].cpu().numpy()
@@ -112,50 +142,59 @@ def _fd(R, ctx, species, b, cfg, k, s, h, which):
     return (zu[:, 0] - zd[:, 0]) / (2 * h), ok
 
 
-def _fd_check(R, ctx, species, pr, cfg, min_linear_frac):
-    """min_linear_frac: {'k': fraction, 's': fraction} of stopped tracks that must be linear."""
+def _fd_check(R, ctx, species, pr, cfg, min_linear, h1=1e-7, h2=1e-8, lin_tol=1e-5):
+    """Per-track pathwise derivatives against central differences.  A track counts as linear
+    when its central differences at h1 and h2 agree to lin_tol (relative); on linear tracks
+    the adjoint must agree with the h1 difference to 1e-3 per track and to 1e-4 on their mean,
+    and at least min_linear[k or s] tracks must be linear.  The h = 1e-4 difference is
+    reported beside it, with the all-track mean of the adjoint and its standard error."""
     b = R.batch_from_numpy(pr)
     g = R.grad(ctx, species, b, cfg, 1.0, 1.0, per_track=True)
     tr = g["tracks"].cpu().numpy()
     stopped = tr[:, 3] == R.STOPPED
     report = {}
     for col, which in ((1, "k"), (2, "s")):
-        f1, ok1 = _fd(R, ctx, species, b, cfg, 1.0, 1.0, 1e-4, which)
-        f2, ok2 = _fd(R, ctx, species, b, cfg, 1.0, 1.0, 1e-5, which)
+        f1, ok1 = _per_track_fd(R, ctx, species, b, cfg, which, h1)
+        f2, ok2 = _per_track_fd(R, ctx, species, b, cfg, which, h2)
+        f4, ok4 = _per_track_fd(R, ctx, species, b, cfg, which, 1e-4)
         ok = stopped & ok1 & ok2
-        lin = ok & (np.abs(f1 - f2) <= 2e-5 * np.maximum(np.abs(f1), 1e-6))
-        frac = lin.sum() / max(ok.sum(), 1)
-        report[which] = (int(lin.sum()), int(ok.sum()))
-        msg = f"d/d{which}: {lin.sum()} linear of {ok.sum()} stopped ({100 * frac:.1f} %)"
-        rel = mean_rel = 0.0
+        lin = ok & (np.abs(f1 - f2) <= lin_tol * np.maximum(np.maximum(np.abs(f1), np.abs(f2)), 1e-3))
+        adj = tr[:, col]
+        allm = adj[stopped].mean()
+        alls = adj[stopped].std(ddof=1) / math.sqrt(max(stopped.sum(), 2))
+        msg = (f"d/d{which}: {lin.sum()} of {ok.sum()} stopped tracks linear at h = {h1:g} / {h2:g}; "
+               f"all-track adjoint mean {allm:.6g} +- {alls:.3g}")
+        report[which] = dict(linear=int(lin.sum()), stopped=int(ok.sum()))
         if lin.any():
-            rel = np.abs(tr[lin, col] - f1[lin]) / np.maximum(np.abs(f1[lin]), 1e-6)
-            # the per-track derivatives have both signs: the mean is compared on the scale of
-            # the mean magnitude
-            mean_rel = abs(tr[lin, col].mean() - f1[lin].mean()) / max(np.abs(f1[lin]).mean(), 1e-6)
-            msg += (f"; per-track worst {rel.max():.3g} median {np.median(rel):.3g}; mean over linear "
-                    f"tracks: adjoint {tr[lin, col].mean():.6g} vs FD {f1[lin].mean():.6g} "
-                    f"(diff / mean |FD| = {mean_rel:.3g})")
-        msg += f"; all-track adjoint mean {tr[ok, col].mean():.6g}"
+            rel = np.abs(adj[lin] - f1[lin]) / np.maximum(np.abs(f1[lin]), 1e-3)
+            # per-track derivatives have both signs: the mean is compared on the scale of the
+            # mean magnitude
+            mean_rel = abs(adj[lin].mean() - f1[lin].mean()) / max(np.abs(f1[lin]).mean(), 1e-3)
+            l4 = lin & ok4
+            rel4 = np.abs(adj[l4] - f4[l4]) / np.maximum(np.abs(f4[l4]), 1e-3)
+            msg += (f"; on linear tracks per-track worst {rel.max():.3g}, mean adjoint {adj[lin].mean():.8g} vs "
+                    f"FD {f1[lin].mean():.8g} (relative {mean_rel:.3g}); at h = 1e-4 {int((rel4 <= 1e-4).sum())} "
+                    f"of them agree to 1e-4 (median {np.median(rel4):.3g})")
+            report[which].update(worst=float(rel.max()), mean_rel=float(mean_rel))
         _say(msg)
+        assert lin.sum() >= min_linear[which], (which, int(lin.sum()))
         if lin.any():
-            assert (rel <= 1e-3).all(), (which, rel)
+            assert (rel <= 1e-3).all(), (which, rel.max())
             assert mean_rel <= 1e-4, (which, mean_rel)
-        assert frac >= min_linear_frac[which], (which, frac)
     return report
 
 
 def test_adjoint_matches_central_differences_on_linear_tracks(R, ctx):
-    """Pathwise derivatives of chaotic tracks match finite differences only where a track is
-    in its linear regime: a track counts as linear when central differences at h = 1e-4 and
-    h = 1e-5 (same seeded crystal) agree to 2e-5.  On linear tracks the adjoint agrees with the
-    h = 1e-4 difference to 1e-3 per track and to 1e-4 on their mean.  Short 300 eV B tracks are
-    mostly linear; the 5 keV P adjoint workload (~2,500 steps, many hard collisions) is
-    almost entirely non-linear at h = 1e-4, and its linear fraction is only reported.  The
-    screening-scale derivative is far more chaotic than the stopping-scale one (every hard
-    collision depends on s), so fewer of its tracks are linear."""
-    _fd_check(R, ctx, ("B",), _batch(128, 0, 300.0, 5), R.RunConfig(max_steps=16384), dict(k=0.1, s=0.01))
-    _fd_check(R, ctx, ("P",), _batch(256, 0, 5000.0, 0), R.RunConfig(max_steps=16384), dict(k=0.0, s=0.0))
+    """Pathwise derivatives of chaotic tracks match finite differences where a track is in its
+    linear regime.  Tracks are classified by central differences at h = 1e-7 and 1e-8 on the
+    same seeded crystal (agreement to 1e-5: on strongly amplifying tracks the branches of the
+    step-size minimum switch within a few 1e-9 of k = 1, so differences over such steps average
+    slopes the pathwise derivative does not see); on linear tracks the adjoint agrees with the
+    h = 1e-7 difference to 1e-3 per track and to 1e-4 on the mean.  Short 300 eV B tracks, and
+    the adjoint workload itself (P at 5 keV, ~2,500-3,500 steps with many hard collisions),
+    each with a required minimum of linear tracks for both derivatives."""
+    _fd_check(R, ctx, ("B",), _batch(128, 0, 300.0, 5), R.RunConfig(max_steps=16384), dict(k=32, s=8))
+    _fd_check(R, ctx, ("P",), _batch(256, 0, 5000.0, 0), R.RunConfig(max_steps=16384), dict(k=1, s=1))
 
 
 def test_autograd_function_returns_the_adjoint(R, ctx):
