@@ -216,21 +216,32 @@ __device__ __forceinline__ double exp_reduce(double y, double& r)
     return nr;
 }
 
+// A constant put into scalar registers where it is used.  FP64 FMAs take no
+// 64-bit literal operand, so a polynomial's coefficients live in registers; left
+// to itself the compiler hoists the coefficients of an exponential evaluated once
+// per step out of the step loop into vector registers, and under register
+// pressure spills them to scratch memory and reloads them one by one.
+__device__ __forceinline__ double sconst(double v)
+{
+    asm volatile("" : "+s"(v));
+    return v;
+}
+
 // Degree 10 (relative error 3.0e-16): the friction factors and other scalars.
 __device__ __forceinline__ double exp_neg(double y)
 {
     double r;
     const double nr = exp_reduce(y, r);
-    double p = 0x1.2a475a7d4ddb2p-22;
-    p = fma(p, r, 0x1.730bd57070546p-19);
-    p = fma(p, r, 0x1.a017fb6001714p-16);
-    p = fma(p, r, 0x1.a01967c4ef7f8p-13);
-    p = fma(p, r, 0x1.6c16c20da969ep-10);
-    p = fma(p, r, 0x1.11111133719d9p-7);
-    p = fma(p, r, 0x1.555555552f919p-5);
-    p = fma(p, r, 0x1.5555555548c99p-3);
-    p = fma(p, r, 0x1.000000000004bp-1);
-    p = fma(p, r, 0x1.0000000000029p+0);
+    double p = sconst(0x1.2a475a7d4ddb2p-22);
+    p = fma(p, r, sconst(0x1.730bd57070546p-19));
+    p = fma(p, r, sconst(0x1.a017fb6001714p-16));
+    p = fma(p, r, sconst(0x1.a01967c4ef7f8p-13));
+    p = fma(p, r, sconst(0x1.6c16c20da969ep-10));
+    p = fma(p, r, sconst(0x1.11111133719d9p-7));
+    p = fma(p, r, sconst(0x1.555555552f919p-5));
+    p = fma(p, r, sconst(0x1.5555555548c99p-3));
+    p = fma(p, r, sconst(0x1.000000000004bp-1));
+    p = fma(p, r, sconst(0x1.0000000000029p+0));
     p = fma(p, r, 1.0);
     return ldexp(p, static_cast<int>(__double2loint(nr)));
 }
