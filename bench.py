@@ -351,7 +351,7 @@ def grad_forward_ratio(R, ctx, torch):
     [001] at 7 degree tilt, no cloning, d(mean range)/d(k, s) with a checkpoint every 64 steps.
     Beside the cost: per-track derivatives against central differences on the same seeded
     crystal.  A track is linear in k (or s) where the differences at h = 1e-7 and 1e-8 agree to
-    1e-5; the fraction of such tracks, the adjoint's agreement with the h = 1e-7 difference on
+    1e-4; the fraction of such tracks, the adjoint's agreement with the h = 1e-7 difference on
     them, and the all-track mean of the pathwise derivative with its standard error (which the
     few exploding, non-linear tracks dominate) are reported."""
     import math
@@ -392,7 +392,7 @@ def grad_forward_ratio(R, ctx, torch):
         f2, ok2, _ = fd(which, 1e-8)
         _, _, mean4 = fd(which, 1e-4)
         ok = stopped & ok1 & ok2
-        lin = ok & (np.abs(f1 - f2) <= 1e-5 * np.maximum(np.maximum(np.abs(f1), np.abs(f2)), 1e-3))
+        lin = ok & (np.abs(f1 - f2) <= 1e-4 * np.maximum(np.maximum(np.abs(f1), np.abs(f2)), 1e-3))
         adj = tr[:, col]
         d = dict(tracks_stopped=int(ok.sum()), linear=int(lin.sum()), linear_fraction=float(lin.sum() / max(ok.sum(), 1)),
                  all_track_mean=float(adj[stopped].mean()),
@@ -401,7 +401,8 @@ def grad_forward_ratio(R, ctx, torch):
         if lin.any():
             d.update(linear_mean_adjoint=float(adj[lin].mean()), linear_mean_fd_h_1em7=float(f1[lin].mean()),
                      linear_mean_rel_diff=float(abs(adj[lin].mean() - f1[lin].mean()) / max(np.abs(f1[lin]).mean(), 1e-3)),
-                     linear_worst_track_rel_diff=float((np.abs(adj[lin] - f1[lin]) / np.maximum(np.abs(f1[lin]), 1e-3)).max()))
+                     linear_worst_track_rel_diff=float((np.abs(adj[lin] - f1[lin]) / np.maximum(np.abs(f1[lin]), 1e-3)).max()),
+                     linear_tracks_beyond_1e_3=int(((np.abs(adj[lin] - f1[lin]) / np.maximum(np.abs(f1[lin]), 1e-3)) > 1e-3).sum()))
         check["d_d" + which] = d
     return dict(workload="4,096 P at 5 keV, 7 deg tilt, no cloning, checkpoint every 64 steps",
                 forward_ms=1e3 * min(tf), grad_ms=1e3 * min(tg), ratio=min(tg) / min(tf),
@@ -409,7 +410,9 @@ def grad_forward_ratio(R, ctx, torch):
                 stopped=g["count"], finite_difference_check=check,
                 note="the pathwise mean over all tracks is dominated by a few exploding chaotic tracks and is "
                      "not an estimate of the derivative of the expected range; the FD agreement is shown on "
-                     "the tracks that are linear at h = 1e-7 / 1e-8 (agreement 1e-5)")
+                     "the tracks that are linear at h = 1e-7 / 1e-8 (agreement 1e-4); a few strongly amplifying "
+                     "tracks among them have step-size branches that switch within ~1e-9 of k = 1, so their "
+                     "differences average slopes the pathwise derivative does not see (counted beyond 1e-3)")
 
 
 def progress(msg):
