@@ -258,6 +258,25 @@ reedmd_status reedmd_run(reedmd_ctx* ctx, const reedmd_species* species, const r
                          const reedmd_run_params* params, double* d_hist, reedmd_stats* d_stats,
                          hipStream_t stream);
 
+/* The plain form of reedmd_run for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): it calls no hipMalloc, hipFree or allocating library routine.
+ * Its scratch memory (queue state, claim order, clone stacks) is one static
+ * device array of 128 MiB that the library defines and every GPU it runs on
+ * holds until the process ends; the caller still passes the inputs and the
+ * outputs (d_hist, d_stats, the optional track log), with the meanings of
+ * reedmd_run.  params->form must be REEDMD_FORM_PLAIN (EUNSUPPORTED
+ * otherwise).  The number of track segments is cut to what fits the array
+ * (results do not depend on it); EINVAL when a batch's claim order (4 bytes
+ * per primary) or one segment's clone stack (n_thresh * (n_clones - 1) + 1
+ * records) does not fit.  Every call on a GPU uses that GPU's one array and
+ * leaves its contents behind (each call clears what must start at zero), so
+ * calls that overlap on one GPU race: run them in order on one stream.
+ * Enqueued on stream. */
+reedmd_status reedmd_run_noalloc(reedmd_ctx* ctx, const reedmd_species* species, const reedmd_batch* batch,
+                                 const reedmd_run_params* params, double* d_hist, reedmd_stats* d_stats,
+                                 hipStream_t stream);
+
 /* Adaptive cloning depths (Sec. 2: the depths are placed from the statistics
  * gathered so far; Sec. 3: criteria are updated between complete tracks). */
 typedef struct {

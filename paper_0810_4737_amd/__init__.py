@@ -261,6 +261,30 @@ def run(ctx: Context, species, batch, cfg: RunConfig, hist=None, stats=None, id0
     return hist, stats, keep
 
 
+def run_noalloc(ctx: Context, species, batch, cfg: RunConfig, hist, stats, thresholds=None, id0=0, stream=None):
+    """The plain form through the library's allocation-free entry point, whose scratch memory is
+    a static device array.  Every device buffer is the caller's: hist, stats, and the cloning
+    depth tables as a float64 device tensor [n_tables, n_thresh] (cfg.thresholds must be None).
+    Returns (hist, stats)."""
+    if cfg.thresholds is not None:
+        raise ReedmdError("give an allocation-free run its depth tables as the device tensor `thresholds`")
+    p = cfg.struct(batch["energy"].device, [])
+    if thresholds is not None:
+        assert thresholds.is_cuda and thresholds.dtype == torch.float64 and thresholds.dim() == 2
+        assert thresholds.is_contiguous()
+        p.n_tables, p.n_thresh = thresholds.shape
+        p.thresholds = thresholds.data_ptr()
+    return _run_noalloc(ctx, species, batch, p, hist, stats, id0, stream)
+
+
+def _run_noalloc(ctx, species, batch, p, hist, stats, id0, stream):
+    sp = species_table(species) if not isinstance(species, _abi.Species) else species
+    b = _batch_struct(batch, id0)
+    ctx.check(ctx._lib.reedmd_run_noalloc(ctx.handle, C.byref(sp), C.byref(b), C.byref(p), _ptr(hist), _ptr(stats),
+                                          _stream(stream)))
+    return hist, stats
+
+
 def run_refined(ctx: Context, species, batch, cfg: RunConfig, n_epochs: int, probs, min_gap: float = 1.0,
                 hist=None, stats=None, id0=0, log_cap=0, stream=None):
     """Runs the batch in n_epochs epochs with the cloning depths re-placed between epochs from

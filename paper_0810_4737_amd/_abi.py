@@ -93,7 +93,7 @@ STATS_WORDS = len(STATS_INT_A) + len(STATS_DBL) + len(STATS_INT_B)
 EXPORTS = ("reedmd_version", "reedmd_create", "reedmd_destroy", "reedmd_last_error",
            "reedmd_sample_primaries", "reedmd_run", "reedmd_track_init", "reedmd_debug_step",
            "reedmd_autotune", "reedmd_grad", "reedmd_eval_exp_neg", "reedmd_eval_exp_neg_pair", "reedmd_launch_shape",
-           "reedmd_run_refined", "reedmd_cached_graphs")
+           "reedmd_run_refined", "reedmd_cached_graphs", "reedmd_run_noalloc")
 
 _lib = None
 
@@ -121,6 +121,8 @@ def load():
     L.reedmd_sample_primaries.restype = C.c_int
     L.reedmd_run.argtypes = [V, P(Species), P(Batch), P(RunParams), V, V, V]
     L.reedmd_run.restype = C.c_int
+    L.reedmd_run_noalloc.argtypes = [V, P(Species), P(Batch), P(RunParams), V, V, V]
+    L.reedmd_run_noalloc.restype = C.c_int
     L.reedmd_track_init.argtypes = [V, P(Species), P(Batch), P(RunParams), V, V]
     L.reedmd_track_init.restype = C.c_int
     L.reedmd_debug_step.argtypes = [V, P(Species), P(RunParams), V, C.c_int64, C.c_int32, V]

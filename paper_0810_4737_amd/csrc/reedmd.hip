@@ -16,7 +16,14 @@
 #include "adjoint_kernels.hpp"
 #include "track_kernels.hpp"
 
+// Scratch memory of the allocation-free entry point (reedmd_run_noalloc): one
+// static device array of this size, which every GPU the library runs on holds
+// (its own copy) until the process ends.
+constexpr unsigned long long kNoAllocBytes = 128ull << 20;   // 128 MiB
+
 using namespace reedmd;
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
 
 namespace {
 
@@ -33,6 +40,12 @@ constexpr size_t kMaxGraphs = 16;
 constexpr long long kMaxQueue = 65536;            // default clone-queue capacity cap (1.0 GB of diamond records)                 // instantiated persistent pipelines kept per context
 
 thread_local std::string g_create_error;
+
+// Host code never uses the name of the allocation-free entry point's scratch
+// array as an address: its device address is taken once per device with
+// hipGetSymbolAddress at context creation and kept here.
+constexpr int kMaxDevices = 64;
+void* g_noalloc_ptr[kMaxDevices] = {};
 
 }  // namespace
 
@@ -913,6 +926,16 @@ reedmd_status reedmd_create(const reedmd_lattice* lattice, const reedmd_potentia
     int cus = 0;
     e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return fail(nullptr, REEDMD_EHIP, std::string("device attribute: ") + hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices) return fail(nullptr, REEDMD_EUNSUPPORTED, "device index beyond the supported range");
+    if (g_noalloc_ptr[dev] == nullptr) {
+        // once per device, with that device current: the device address of the
+        // allocation-free entry point's scratch array
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || ptr == nullptr)
+            return fail(nullptr, REEDMD_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_noalloc_ptr[dev] = ptr;
+    }
     reedmd_ctx* ctx = new reedmd_ctx();
     ctx->device = dev;
     ctx->cu_count = cus;
@@ -997,6 +1020,83 @@ reedmd_status reedmd_run(reedmd_ctx* ctx, const reedmd_species* species, const r
     if ((st = check_params(ctx, params, true)) != REEDMD_OK) return st;
     if (!d_hist || !d_stats) return fail(ctx, REEDMD_EINVAL, "d_hist and d_stats must be non-NULL");
     return run_impl(ctx, species, batch, params, d_hist, d_stats, stream, nullptr);
+}
+
+reedmd_status reedmd_run_noalloc(reedmd_ctx* ctx, const reedmd_species* species, const reedmd_batch* batch,
+                                 const reedmd_run_params* params, double* d_hist, reedmd_stats* d_stats,
+                                 hipStream_t stream)
+{
+    if (!ctx) return fail(nullptr, REEDMD_EINVAL, "ctx is NULL");
+    reedmd_status st;
+    if ((st = check_species(ctx, species)) != REEDMD_OK) return st;
+    if ((st = check_batch(ctx, batch)) != REEDMD_OK) return st;
+    if ((st = check_params(ctx, params, true)) != REEDMD_OK) return st;
+    if (!d_hist || !d_stats) return fail(ctx, REEDMD_EINVAL, "d_hist and d_stats must be non-NULL");
+    if (params->form != REEDMD_FORM_PLAIN)
+        return fail(ctx, REEDMD_EUNSUPPORTED, "the allocation-free run is the plain form (form = REEDMD_FORM_PLAIN)");
+    if (batch->n == 0) return REEDMD_OK;
+    char* base = static_cast<char*>(g_noalloc_ptr[ctx->device]);
+    if (base == nullptr) return fail(ctx, REEDMD_EHIP, "the scratch array has no device address");
+    // layout of the scratch array: queue state and its one sequence word, the claim
+    // order's counters and offsets, the claim order, then the clone stacks
+    auto up = [](size_t x) { return (x + 255) / 256 * 256; };
+    const size_t off_seq = 256;
+    const size_t off_counts = 512;
+    const size_t off_offsets = off_counts + sizeof(int) * kOrderBuckets * kOrderBlocks;
+    const size_t off_order = off_offsets + sizeof(int) * kOrderBuckets * kOrderBlocks;
+    const size_t off_stack = up(off_order + sizeof(int) * static_cast<size_t>(batch->n));
+    if (off_stack > kNoAllocBytes)
+        return fail(ctx, REEDMD_EINVAL, "batch too large for the allocation-free run: its claim order needs more than the "
+                                        "128 MiB scratch array (at most about 33 million primaries)");
+    Shape s = choose_shape(ctx, params, batch);
+    const size_t per_seg = static_cast<size_t>(std::max(s.stack_cap, 0)) * record_words(ctx) * sizeof(double);
+    const long long fit = per_seg > 0 ? static_cast<long long>((kNoAllocBytes - off_stack) / per_seg) : s.seg_total;
+    if (fit < 1)
+        return fail(ctx, REEDMD_EINVAL, "one segment's clone stack (n_thresh * (n_clones - 1) + 1 records) does not fit "
+                                        "the 128 MiB scratch array of the allocation-free run");
+    s.seg_total = std::min(s.seg_total, fit);   // fewer segments, same results (plain static assignment)
+    const int T = 64 / s.L;
+    s.blocks = (s.seg_total + static_cast<long long>(T) * (kBlock / 64) - 1) / (static_cast<long long>(T) * (kBlock / 64));
+
+    KernelArgs A;
+    fill_common(ctx, species, params, A);
+    fill_batch(batch, A);
+    A.hist = d_hist;
+    A.stats = d_stats;
+    A.log = static_cast<reedmd_result*>(params->track_log);
+    A.log_cap = params->track_log ? params->track_log_cap : 0;
+    A.q = reinterpret_cast<QueueState*>(base);
+    A.qseq = reinterpret_cast<unsigned long long*>(base + off_seq);
+    A.qrec = nullptr;
+    A.qcap = 0;
+    A.stack = reinterpret_cast<double*>(base + off_stack);
+    A.stack_cap = s.stack_cap;
+    A.cancel = params->cancel;
+    A.seg_total = s.seg_total;
+    OrderArgs O{};
+    O.n = batch->n;
+    O.species = batch->species;
+    O.energy = batch->energy;
+    for (int i = 0; i < kMaxSpecies; ++i) O.inv_M1[i] = 1.0 / A.sp[i].M1;
+    O.n_species = species->n_species;
+    O.counts = reinterpret_cast<int*>(base + off_counts);
+    O.offsets = reinterpret_cast<int*>(base + off_offsets);
+    O.order = reinterpret_cast<int*>(base + off_order);
+    A.order = O.order;
+    // the same kernels as reedmd_run's plain form, launched directly (the queue reset
+    // kernel clears the state that must start at zero: no memset)
+    hipLaunchKernelGGL(queue_reset_kernel, dim3(1), dim3(256), 0, stream, A.q, A.qseq, 1, batch->n);
+    HIP_TRY(ctx, hipGetLastError());
+    hipLaunchKernelGGL(order_count_kernel, dim3(kOrderBlocks), dim3(256), 0, stream, O);
+    hipLaunchKernelGGL(order_scan_kernel, dim3(1), dim3(kOrderBuckets), 0, stream, O);
+    hipLaunchKernelGGL(order_scatter_kernel, dim3(kOrderBlocks), dim3(64), 0, stream, O);
+    HIP_TRY(ctx, hipGetLastError());
+    void* track_args[] = {&A};
+    HIP_TRY(ctx, hipLaunchKernel(track_kernel_ptr(s.L, s.mode, s.f32, lattice_of(ctx)), dim3(static_cast<unsigned>(s.blocks)),
+                                 dim3(kBlock), track_args, 0, stream));
+    hipLaunchKernelGGL(stats_finalize_kernel, dim3(1), dim3(64), 0, stream, A.q, d_stats);
+    HIP_TRY(ctx, hipGetLastError());
+    return REEDMD_OK;
 }
 
 reedmd_status reedmd_track_init(reedmd_ctx* ctx, const reedmd_species* species, const reedmd_batch* batch,
