@@ -64,7 +64,7 @@ class Params(C.Structure):
         ("n_species", C.c_int32), ("Z1", C.c_int32 * MAX_SPECIES),
         ("M1", C.c_double * MAX_SPECIES),
         ("M2b", C.c_double), ("sigma_b", C.c_double), ("Z2b", C.c_int32),
-        ("range_mode", C.c_int32), ("vacancy", C.c_int32), ("pad_", C.c_int32),
+        ("range_mode", C.c_int32), ("vacancy", C.c_int32), ("pad_", C.c_int32), ("r_cut", C.c_double),
     ]
 
 
@@ -197,6 +197,7 @@ class Config:
     sigma_b: float = 0.0
     range_mode: int = RANGE_DEPTH
     vacancy: int = 0
+    r_cut: float = 0.0
 
     def params(self):
         """Returns (Params, keepalive) where keepalive holds referenced arrays."""
@@ -212,6 +213,7 @@ class Config:
         p.n_clones, p.n_bins, p.bin_width = self.n_clones, self.n_bins, self.bin_width
         p.Z2b, p.M2b, p.sigma_b = self.Z2b, self.M2b, self.sigma_b
         p.range_mode, p.vacancy = self.range_mode, self.vacancy
+        p.r_cut = self.r_cut
         sp = [s[0] if isinstance(s, tuple) else s for s in self.species]
         p.n_species = len(sp)
         for i, name in enumerate(sp):

@@ -146,8 +146,11 @@ static int maintain_domain(const or_params* p, or_track* t, int fresh)
 }
 
 /* Ion-atom forces and the local density at the ion.  Every atom of the
- * domain interacts with the ion (no cut-off); atoms do not interact with
- * each other, and each feels the reaction of its own pair force. */
+ * domain interacts with the ion (Sec. 2: the 27 cells); atoms do not interact
+ * with each other, and each feels the reaction of its own pair force.  With a
+ * cut-off r_cut > 0 (an interaction set smaller than the paper's 27 cells, a
+ * variant to be checked against it), atoms farther than r_cut from the ion
+ * are skipped: no force on either side and no density. */
 void or_compute_forces(const or_params* p, or_track* t)
 {
     or_pair_consts pcs[2];
@@ -160,6 +163,10 @@ void or_compute_forces(const or_params* p, or_track* t)
         if (!at->exists) continue;
         double d[3];
         double r = ion_atom_distance(t, at, d);
+        if (p->r_cut > 0.0 && r > p->r_cut) {
+            for (int k = 0; k < 3; ++k) at->f[k] = 0.0;
+            continue;
+        }
         const or_pair_consts* pc = &pcs[at->type];
         double V, dVdr;
         or_zbl_c(pc, r, &V, &dVdr);

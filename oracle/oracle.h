@@ -115,6 +115,8 @@ typedef struct {
     int32_t vacancy;     /* 1: the primary is the recoil of the basis-0 atom of the cell whose
                             origin is nearest its start point; that site stays empty */
     int32_t pad_;
+    double r_cut;        /* interaction cut-off (A): domain atoms farther than r_cut from the ion
+                            exert no force and add no density; 0: every atom of the 27 cells */
 } or_params;
 
 /* One domain atom. */

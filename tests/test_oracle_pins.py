@@ -616,3 +616,53 @@ def test_family_moment_errors_reduce_to_textbook_forms():
     z2 = np.repeat(z, 2)
     out2 = family_moments(z2, np.full(z2.size, 0.5), np.repeat(np.arange(z.size), 2))
     assert np.allclose(out2, (m, sd, se_m, se_sd), rtol=1e-9)
+
+
+# --------------------------------------------------------------------------- interaction cut-off
+def test_cutoff_beyond_the_domain_changes_nothing():
+    """A cut-off larger than any ion-atom distance in the 27-cell domain (whose diagonal is
+    3 a sqrt(3) = 28.2 A) skips no atom: every record of a track with domain moves equals the
+    27-cell one bit for bit."""
+    pr = oracle.sample_primaries(oracle.SamplerCfg(choice=(0, 1, 2), E_min=2000.0, E_max=20000.0), 4, 6)
+    for i in range(6):
+        args = (int(pr["species"][i]), float(pr["E0"][i]), pr["pos"][:, i], pr["dir"][:, i], int(pr["key"][i]))
+        a = oracle.Track.start(cfg(), *args)
+        b = oracle.Track.start(cfg(r_cut=1000.0), *args)
+        for _ in range(4):
+            a.advance(60, events=True)
+            b.advance(60, events=True)
+            assert np.array_equal(a.record().view(np.int64), b.record().view(np.int64))
+
+
+@pytest.mark.parametrize("rc", [4.0, 5.0, 6.0])
+def test_cutoff_keeps_exactly_the_atoms_within_range(rc):
+    """With a cut-off, the ion force and density are the sums over the atoms within rc only
+    (pair force -V'(r) (x_ion - x_j)/r and density weight from the pinned ZBL and density
+    routines), atoms beyond rc carry zero force, atoms within carry their pair force."""
+    c = cfg(r_cut=rc)
+    c0 = cfg()
+    pr = oracle.sample_primaries(oracle.SamplerCfg(choice=(0, 1, 2), E_min=1000.0, E_max=1000.0), 6, 4)
+    for i in range(4):
+        sp = int(pr["species"][i])
+        x = np.array([30.1, 27.4, 40.3]) + np.array([0.37, 0.11, 0.73]) * i
+        st = oracle.Track.start(c, sp, 1000.0, x, pr["dir"][:, i], int(pr["key"][i])).state()
+        full = oracle.Track.start(c0, sp, 1000.0, x, pr["dir"][:, i], int(pr["key"][i])).state()
+        ex = oracle.slot_exists(st["center"])
+        assert np.array_equal(st["ax"], full["ax"])      # same crystal
+        F = np.zeros(3)
+        rho = 0.0
+        n_in = 0
+        for s in np.nonzero(ex)[0]:
+            d = st["x"] - st["ax"][:, s]
+            r = float(np.sqrt(d @ d))
+            if r > rc:
+                assert np.all(st["af"][:, s] == 0.0)
+                continue
+            n_in += 1
+            _, dV = oracle.zbl(c, sp, r)
+            F += -dV * d / r
+            rho += oracle.density_weight(c, sp, r)
+            assert np.allclose(st["af"][:, s], dV * d / r, rtol=1e-12, atol=0)
+        assert 10 < n_in < int(ex.sum())
+        assert np.allclose(st["F"], F, rtol=1e-12, atol=1e-12 * np.abs(full["F"]).max())
+        assert abs(st["rho"] / rho - 1.0) < 1e-12
