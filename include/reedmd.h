@@ -187,6 +187,17 @@ typedef struct {
                                   once every primary is claimed and no more tracks are live than that
                                   launch has segments (running tracks move through the clone queue,
                                   exactly: results are the same bit for bit); 1: no handoff */
+    double r_cut;              /* interaction set of the domain (Sec. 2 builds it from the 27 cells
+                                  around the ion): 0 (default) = every atom of the 27 cells; > 0 =
+                                  only atoms within r_cut (A) of the ion exert force on it, are
+                                  pushed by it and add to the electron density (all atoms still
+                                  move; the in-range atoms are compacted so the pair work shrinks
+                                  with the set); diamond target with FP64 forces only, else
+                                  REEDMD_EUNSUPPORTED; < 0 = the set reedmd_autotune_domain recorded
+                                  for this configuration and batch size (27 cells if none),
+                                  resolved by reedmd_run, reedmd_run_noalloc, reedmd_run_refined
+                                  and reedmd_autotune (REEDMD_EINVAL for reedmd_track_init and
+                                  reedmd_debug_step); reedmd_grad: 0 only (REEDMD_EUNSUPPORTED) */
 } reedmd_run_params;
 
 /* Finished-track entry of the optional log (48 bytes). */
@@ -385,6 +396,37 @@ reedmd_status reedmd_autotune(reedmd_ctx* ctx, const reedmd_species* species,
                               const reedmd_batch* batch, const reedmd_run_params* params,
                               int64_t pilot, hipStream_t stream, int32_t* best_lanes,
                               int32_t* best_waves);
+
+/* Interaction-set autotuner (Sec. 2: the ion interacts with the atoms of
+ * the 27 cells around it; a cut-off keeps those within r_cut, fewer pair
+ * terms, which must leave the range distribution unchanged).
+ * candidates (host, n_candidates values, 1..8): 0 = the 27 cells, > 0 = a
+ * cut-off radius (A).  The first `pilot` primaries of the batch run to the
+ * end (params as given, finished-track log kept internally) once with the 27
+ * cells, the reference, and once per cut-off candidate.  A candidate passes
+ * its gate when the weighted two-sample Kolmogorov-Smirnov test of its
+ * stopping depths against the reference's (effective sizes (sum w)^2 /
+ * sum w^2, asymptotic Kolmogorov distribution) gives p > gate_p and its
+ * weighted mean and standard deviation of the depth differ from the
+ * reference's by at most gate_rel relative, or by at most three standard
+ * errors of the difference where those exceed gate_rel (a pilot too small
+ * to resolve gate_rel cannot fail on noise; use a pilot whose standard
+ * errors are below gate_rel / 3 for a strict gate).  Of the passing
+ * candidates (the 27 cells always pass) the one whose pilot run took the
+ * least GPU time is recorded in the context's cache under this
+ * configuration and batch size class (the lanes and waves entry of
+ * reedmd_autotune is kept) and written to *best_r_cut (host).  report
+ * (host, may be NULL): 5 values per candidate in input order, the pilot
+ * run's GPU milliseconds, the KS p value, the relative difference of the
+ * mean, of the standard deviation, and 1 if the gate passed else 0.  Caller
+ * histogram and statistics are not touched; synchronises the stream.
+ * EINVAL: NULL arguments, n_candidates outside 1..8, a negative or
+ * non-finite candidate, pilot <= 0, gate_p outside [0, 1), gate_rel < 0. */
+reedmd_status reedmd_autotune_domain(reedmd_ctx* ctx, const reedmd_species* species,
+                                     const reedmd_batch* batch, const reedmd_run_params* params,
+                                     const double* candidates, int32_t n_candidates, int64_t pilot,
+                                     double gate_p, double gate_rel, hipStream_t stream,
+                                     double* best_r_cut, double* report);
 
 /* The launch shape reedmd_run would use for this batch size and these
  * parameters (after the autotune cache), written to out (host, 5 values):

@@ -125,6 +125,8 @@ class RunConfig:
     range_mode: int = RANGE_DEPTH
     vacancy: int = 0
     no_tail_handoff: int = 0
+    # interaction set: 0 = the 27 cells, > 0 = cut-off radius (A), < 0 = the domain autotuner's choice
+    r_cut: float = 0.0
 
     def struct(self, device, keep):
         p = _abi.RunParams()
@@ -141,6 +143,7 @@ class RunConfig:
         p.force_precision = self.force_precision
         p.range_mode, p.vacancy = self.range_mode, self.vacancy
         p.no_tail_handoff = self.no_tail_handoff
+        p.r_cut = float(self.r_cut)
         return p
 
 
@@ -365,6 +368,27 @@ def autotune(ctx: Context, species, batch, cfg: RunConfig, pilot: int, stream=No
     ctx.check(ctx._lib.reedmd_autotune(ctx.handle, C.byref(sp), C.byref(b), C.byref(p), int(pilot),
                                        _stream(stream), C.byref(bl), C.byref(bw)))
     return bl.value, bw.value
+
+
+def autotune_domain(ctx: Context, species, batch, cfg: RunConfig, candidates=(0.0, 5.0, 6.0), pilot: int = 4096,
+                    gate_p: float = 0.01, gate_rel: float = 0.01, stream=None):
+    """Interaction-set autotuner: runs the pilot with the 27 cells and with each cut-off
+    candidate, gates each (weighted KS p > gate_p, mean and std within gate_rel or three
+    standard errors) and records the fastest passing one for cfg.r_cut < 0.  Returns
+    (best r_cut, report rows (r_cut, ms, ks_p, rel mean diff, rel std diff, passed))."""
+    keep = []
+    p = cfg.struct(batch["energy"].device, keep)
+    sp = species_table(species) if not isinstance(species, _abi.Species) else species
+    b = _batch_struct(batch)
+    nc = len(candidates)
+    cand = (C.c_double * max(nc, 1))(*[float(c) for c in candidates])
+    rep = (C.c_double * (5 * max(nc, 1)))()
+    best = C.c_double()
+    ctx.check(ctx._lib.reedmd_autotune_domain(ctx.handle, C.byref(sp), C.byref(b), C.byref(p), cand, nc, int(pilot),
+                                              float(gate_p), float(gate_rel), _stream(stream), C.byref(best), rep))
+    rows = [(float(candidates[i]), rep[5 * i], rep[5 * i + 1], rep[5 * i + 2], rep[5 * i + 3], bool(rep[5 * i + 4]))
+            for i in range(nc)]
+    return best.value, rows
 
 
 def launch_shape(ctx: Context, batch, cfg: RunConfig):

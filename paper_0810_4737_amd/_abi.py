@@ -66,7 +66,7 @@ class RunParams(C.Structure):
                 ("form", C.c_int32), ("lanes_per_track", C.c_int32), ("waves_per_cu", C.c_int32),
                 ("queue_capacity", C.c_int32), ("cancel", C.c_void_p), ("track_log", C.c_void_p),
                 ("track_log_cap", C.c_int64), ("force_precision", C.c_int32), ("range_mode", C.c_int32),
-                ("vacancy", C.c_int32), ("no_tail_handoff", C.c_int32)]
+                ("vacancy", C.c_int32), ("no_tail_handoff", C.c_int32), ("r_cut", C.c_double)]
 
 
 class Refine(C.Structure):
@@ -93,7 +93,7 @@ STATS_WORDS = len(STATS_INT_A) + len(STATS_DBL) + len(STATS_INT_B)
 EXPORTS = ("reedmd_version", "reedmd_create", "reedmd_destroy", "reedmd_last_error",
            "reedmd_sample_primaries", "reedmd_run", "reedmd_track_init", "reedmd_debug_step",
            "reedmd_autotune", "reedmd_grad", "reedmd_eval_exp_neg", "reedmd_eval_exp_neg_pair", "reedmd_launch_shape",
-           "reedmd_run_refined", "reedmd_cached_graphs", "reedmd_run_noalloc")
+           "reedmd_run_refined", "reedmd_cached_graphs", "reedmd_run_noalloc", "reedmd_autotune_domain")
 
 _lib = None
 
@@ -130,6 +130,9 @@ def load():
     L.reedmd_autotune.argtypes = [V, P(Species), P(Batch), P(RunParams), C.c_int64, V,
                                   P(C.c_int32), P(C.c_int32)]
     L.reedmd_autotune.restype = C.c_int
+    L.reedmd_autotune_domain.argtypes = [V, P(Species), P(Batch), P(RunParams), P(C.c_double), C.c_int32, C.c_int64,
+                                         C.c_double, C.c_double, V, P(C.c_double), P(C.c_double)]
+    L.reedmd_autotune_domain.restype = C.c_int
     L.reedmd_grad.argtypes = [V, P(Species), P(Batch), P(RunParams), C.c_double, C.c_double, V,
                               P(C.c_double), V]
     L.reedmd_grad.restype = C.c_int

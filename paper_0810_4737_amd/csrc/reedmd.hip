@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -66,7 +67,11 @@ struct reedmd_ctx {
     double* gscratch = nullptr;    // adjoint checkpoints, segment states, outputs
     size_t gscratch_bytes = 0;
     // autotune cache: config hash -> (lanes, waves per CU)
-    std::map<unsigned long long, std::pair<int, int>> tune;
+    struct Tuned {
+        int lanes, waves;
+        double r_cut;   // interaction set: 0 = the 27 cells, > 0 = cut-off radius (A)
+    };
+    std::map<unsigned long long, Tuned> tune;
     // persistent pipelines (reset -> claim order -> track kernel -> statistics) as instantiated graphs,
     // one per launch shape; the kernel arguments of every call are written into the nodes
     struct Graph {
@@ -207,9 +212,14 @@ reedmd_status check_species(reedmd_ctx* ctx, const reedmd_species* sp)
     return REEDMD_OK;
 }
 
-reedmd_status check_params(reedmd_ctx* ctx, const reedmd_run_params* p, bool need_hist)
+reedmd_status check_params(reedmd_ctx* ctx, const reedmd_run_params* p, bool need_hist, bool cached_rcut = true)
 {
     if (!p) return fail(ctx, REEDMD_EINVAL, "params is NULL");
+    if (!std::isfinite(p->r_cut)) return fail(ctx, REEDMD_EINVAL, "r_cut must be finite");
+    if (p->r_cut < 0.0 && !cached_rcut)
+        return fail(ctx, REEDMD_EINVAL, "r_cut < 0 (the domain autotuner's choice) is resolved by the run entry points only");
+    if (p->r_cut > 0.0 && (lattice_of(ctx) != kDiamond || p->force_precision != REEDMD_FORCE_FP64))
+        return fail(ctx, REEDMD_EUNSUPPORTED, "the interaction cut-off is built for the diamond target with FP64 forces");
     if (p->range_mode != REEDMD_RANGE_DEPTH && p->range_mode != REEDMD_RANGE_RADIAL)
         return fail(ctx, REEDMD_EINVAL, "range_mode must be REEDMD_RANGE_DEPTH or REEDMD_RANGE_RADIAL");
     if (p->vacancy != 0 && p->vacancy != 1) return fail(ctx, REEDMD_EINVAL, "vacancy must be 0 or 1");
@@ -280,6 +290,7 @@ void fill_common(const reedmd_ctx* ctx, const reedmd_species* sp, const reedmd_r
     A.n_clones = p->n_clones < 2 ? 2 : p->n_clones;
     A.n_bins = p->n_bins;
     A.bin_width = p->bin_width;
+    A.rc2 = p->r_cut > 0.0 ? p->r_cut * p->r_cut : 0.0;
 }
 
 void fill_batch(const reedmd_batch* b, KernelArgs& A)
@@ -308,9 +319,19 @@ const void* track_ptr_l(int L)
     }
 }
 
-// The track kernel of a launch shape (launches and graph nodes take the function itself).
-const void* track_kernel_ptr(int L, int mode, bool f32, int lat)
+// Kernels with the interaction cut-off (diamond, FP64 pair terms).
+template <int MODE>
+const void* cut_track_ptr(int L)
 {
+    if (L == 64) return reinterpret_cast<const void*>(&track_kernel<64, MODE, false, kDiamond, true>);
+    if (L == 32) return reinterpret_cast<const void*>(&track_kernel<32, MODE, false, kDiamond, true>);
+    return reinterpret_cast<const void*>(&track_kernel<16, MODE, false, kDiamond, true>);
+}
+
+// The track kernel of a launch shape (launches and graph nodes take the function itself).
+const void* track_kernel_ptr(int L, int mode, bool f32, int lat, bool cut)
+{
+    if (cut) return mode == kModePlain ? cut_track_ptr<kModePlain>(L) : cut_track_ptr<kModePersistent>(L);
     if (mode == kModePlain) {
         if (lat == kFluorite)
             return f32 ? track_ptr_l<kModePlain, true, kFluorite>(L) : track_ptr_l<kModePlain, false, kFluorite>(L);
@@ -344,8 +365,14 @@ int resident_blocks_lat(int L, int mode, bool f32)
     return f32 ? occupancy_l<kModePersistent, true, LAT>(L) : occupancy_l<kModePersistent, false, LAT>(L);
 }
 
-int resident_blocks_per_cu(int L, int mode, bool f32, int lat)
+int resident_blocks_per_cu(int L, int mode, bool f32, int lat, bool cut = false)
 {
+    if (cut) {
+        int nb = 0;
+        const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, track_kernel_ptr(L, mode, false, kDiamond, true),
+                                                                          kBlock, 0);
+        return (e != hipSuccess || nb < 1) ? 1 : nb;
+    }
     return lat == kFluorite ? resident_blocks_lat<kFluorite>(L, mode, f32) : resident_blocks_lat<kDiamond>(L, mode, f32);
 }
 
@@ -377,8 +404,15 @@ void launch_step_l(int L, const KernelArgs& A, long long blocks, hipStream_t s)
     }
 }
 
-void launch_init_any(int L, bool f32, int lat, const KernelArgs& A, long long blocks, hipStream_t s)
+void launch_init_any(int L, bool f32, int lat, bool cut, const KernelArgs& A, long long blocks, hipStream_t s)
 {
+    if (cut) {
+        const dim3 g(static_cast<unsigned>(blocks)), b(kBlock);
+        if (L == 64) hipLaunchKernelGGL((init_kernel<64, false, kDiamond, true>), g, b, 0, s, A);
+        else if (L == 32) hipLaunchKernelGGL((init_kernel<32, false, kDiamond, true>), g, b, 0, s, A);
+        else hipLaunchKernelGGL((init_kernel<16, false, kDiamond, true>), g, b, 0, s, A);
+        return;
+    }
     if (lat == kFluorite) {
         if (f32) launch_init_l<true, kFluorite>(L, A, blocks, s);
         else launch_init_l<false, kFluorite>(L, A, blocks, s);
@@ -388,8 +422,15 @@ void launch_init_any(int L, bool f32, int lat, const KernelArgs& A, long long bl
     }
 }
 
-void launch_step_any(int L, bool f32, int lat, const KernelArgs& A, long long blocks, hipStream_t s)
+void launch_step_any(int L, bool f32, int lat, bool cut, const KernelArgs& A, long long blocks, hipStream_t s)
 {
+    if (cut) {
+        const dim3 g(static_cast<unsigned>(blocks)), b(kBlock);
+        if (L == 64) hipLaunchKernelGGL((step_kernel<64, false, kDiamond, true>), g, b, 0, s, A);
+        else if (L == 32) hipLaunchKernelGGL((step_kernel<32, false, kDiamond, true>), g, b, 0, s, A);
+        else hipLaunchKernelGGL((step_kernel<16, false, kDiamond, true>), g, b, 0, s, A);
+        return;
+    }
     if (lat == kFluorite) {
         if (f32) launch_step_l<true, kFluorite>(L, A, blocks, s);
         else launch_step_l<false, kFluorite>(L, A, blocks, s);
@@ -576,6 +617,102 @@ reedmd_status ensure_order(reedmd_ctx* ctx, long long n)
     return REEDMD_OK;
 }
 
+// Gate statistics of the interaction-set autotuner, from finished-track logs.
+struct DepthSample {
+    std::vector<std::pair<double, double>> zw;   // (stopping depth, weight) of stopped tracks, sorted
+    double mean = 0.0, sd = 0.0, se_mean = 0.0, se_sd = 0.0, n_eff = 0.0;
+};
+
+// Weighted mean and standard deviation of the stopping depth, with standard errors
+// that take each primary's family (the primary and its clones, which share the early
+// path) as one independent unit: first-order expansion of the two ratio estimators.
+DepthSample depth_sample(const std::vector<reedmd_result>& log)
+{
+    DepthSample d;
+    std::map<int64_t, std::array<double, 3>> fam;
+    double W = 0.0, S = 0.0, Q = 0.0, W2 = 0.0;
+    for (const reedmd_result& r : log) {
+        if (r.status != REEDMD_STOPPED) continue;
+        d.zw.emplace_back(r.z_stop, r.w);
+        auto& f = fam[r.lineage];
+        f[0] += r.w;
+        f[1] += r.w * r.z_stop;
+        f[2] += r.w * r.z_stop * r.z_stop;
+        W += r.w;
+        S += r.w * r.z_stop;
+        Q += r.w * r.z_stop * r.z_stop;
+        W2 += r.w * r.w;
+    }
+    std::sort(d.zw.begin(), d.zw.end());
+    if (!(W > 0.0)) return d;
+    d.n_eff = W * W / W2;
+    d.mean = S / W;
+    const double e2 = Q / W;
+    d.sd = std::sqrt(std::max(e2 - d.mean * d.mean, 0.0));
+    double vm = 0.0, vs = 0.0;
+    for (const auto& kv : fam) {
+        const double a = kv.second[1] - d.mean * kv.second[0];
+        const double b = (kv.second[2] - e2 * kv.second[0]) - 2.0 * d.mean * a;
+        vm += a * a;
+        vs += b * b;
+    }
+    d.se_mean = std::sqrt(vm) / W;
+    d.se_sd = d.sd > 0.0 ? std::sqrt(vs) / (2.0 * d.sd * W) : 0.0;
+    return d;
+}
+
+// Survival function of the Kolmogorov distribution, P(K > x): the alternating series
+// 2 sum_k (-1)^(k-1) exp(-2 k^2 x^2) for x >= 1, the complement of the theta-function
+// series sqrt(2 pi) / x sum_k exp(-(2k-1)^2 pi^2 / (8 x^2)) below (both converge fast there).
+double kolmogorov_sf(double x)
+{
+    if (x <= 0.0) return 1.0;
+    if (x >= 1.0) {
+        double s = 0.0;
+        for (int k = 1; k <= 100; ++k) {
+            const double t = std::exp(-2.0 * k * k * x * x);
+            s += (k & 1) ? t : -t;
+            if (t < 1e-18) break;
+        }
+        return std::min(1.0, std::max(0.0, 2.0 * s));
+    }
+    const double pi = 3.14159265358979323846;
+    double c = 0.0;
+    for (int k = 1; k <= 100; ++k) {
+        const double m = 2.0 * k - 1.0;
+        const double t = std::exp(-m * m * pi * pi / (8.0 * x * x));
+        c += t;
+        if (t < 1e-18) break;
+    }
+    return std::min(1.0, std::max(0.0, 1.0 - std::sqrt(2.0 * pi) / x * c));
+}
+
+// Two-sample Kolmogorov-Smirnov test of weighted samples: the largest distance of
+// the two weighted empirical distribution functions, and its p value at the
+// effective sample sizes (sum w)^2 / sum w^2.
+double weighted_ks_p(const DepthSample& a, const DepthSample& b, double* D_out)
+{
+    if (a.zw.empty() || b.zw.empty()) {
+        if (D_out) *D_out = 1.0;
+        return 0.0;
+    }
+    double Wa = 0.0, Wb = 0.0;
+    for (const auto& e : a.zw) Wa += e.second;
+    for (const auto& e : b.zw) Wb += e.second;
+    size_t i = 0, j = 0;
+    double Fa = 0.0, Fb = 0.0, D = 0.0;
+    while (i < a.zw.size() || j < b.zw.size()) {
+        const double z = (j >= b.zw.size() || (i < a.zw.size() && a.zw[i].first <= b.zw[j].first)) ? a.zw[i].first
+                                                                                                   : b.zw[j].first;
+        while (i < a.zw.size() && a.zw[i].first == z) Fa += a.zw[i++].second;
+        while (j < b.zw.size() && b.zw[j].first == z) Fb += b.zw[j++].second;
+        D = std::max(D, std::fabs(Fa / Wa - Fb / Wb));
+    }
+    if (D_out) *D_out = D;
+    const double ne = a.n_eff * b.n_eff / (a.n_eff + b.n_eff);
+    return kolmogorov_sf(D * std::sqrt(ne));
+}
+
 unsigned long long hash_mix(unsigned long long h, unsigned long long v)
 {
     h ^= v + 0x9E3779B97F4A7C15ULL + (h << 6) + (h >> 2);
@@ -605,6 +742,8 @@ struct Shape {
     // and segments; 0 when off
     long long tail_blocks;
     long long tail_segs;
+    double r_cut;   // interaction set after the autotune cache: 0 = the 27 cells
+    bool cut;
 };
 
 Shape choose_shape(reedmd_ctx* ctx, const reedmd_run_params* p, const reedmd_batch* b)
@@ -617,13 +756,19 @@ Shape choose_shape(reedmd_ctx* ctx, const reedmd_run_params* p, const reedmd_bat
     if (L == 0 || (s.mode == kModePersistent && waves == 0)) {
         auto it = ctx->tune.find(tune_key(p, b));
         if (it != ctx->tune.end()) {
-            if (L == 0) L = it->second.first;
-            if (waves == 0) waves = it->second.second;
+            if (L == 0) L = it->second.lanes;
+            if (waves == 0) waves = it->second.waves;
         }
     }
     if (L == 0) L = 64;
     if (lattice_of(ctx) == kFluorite && L == 16) L = 32;
     s.L = L;
+    s.r_cut = p->r_cut > 0.0 ? p->r_cut : 0.0;
+    if (p->r_cut < 0.0) {
+        auto it = ctx->tune.find(tune_key(p, b));
+        if (it != ctx->tune.end()) s.r_cut = it->second.r_cut;
+    }
+    s.cut = s.r_cut > 0.0;
     const int T = 64 / L;
     const int per_wave_block = kBlock / 64;
     s.stack_cap = p->n_thresh > 0 ? p->n_thresh * (std::max(p->n_clones, 2) - 1) + 1 : 0;
@@ -634,7 +779,7 @@ Shape choose_shape(reedmd_ctx* ctx, const reedmd_run_params* p, const reedmd_bat
         s.blocks = (waves_needed + per_wave_block - 1) / per_wave_block;
         s.qcap = 0;
     } else {
-        int bpc = resident_blocks_per_cu(L, s.mode, s.f32, lattice_of(ctx));
+        int bpc = resident_blocks_per_cu(L, s.mode, s.f32, lattice_of(ctx), s.cut);
         if (waves > 0) bpc = std::max(1, std::min(bpc, (waves + per_wave_block - 1) / per_wave_block));
         s.blocks = static_cast<long long>(bpc) * ctx->cu_count;
         s.seg_total = s.blocks * per_wave_block * T;
@@ -643,7 +788,7 @@ Shape choose_shape(reedmd_ctx* ctx, const reedmd_run_params* p, const reedmd_bat
         s.qcap = p->queue_capacity > 0 ? p->queue_capacity
                                        : static_cast<int>(std::min<long long>(kMaxQueue, std::max<long long>(4096, 4 * b->n)));
         if (L < 64 && p->no_tail_handoff == 0) {
-            s.tail_blocks = static_cast<long long>(resident_blocks_per_cu(64, s.mode, s.f32, lattice_of(ctx))) * ctx->cu_count;
+            s.tail_blocks = static_cast<long long>(resident_blocks_per_cu(64, s.mode, s.f32, lattice_of(ctx), s.cut)) * ctx->cu_count;
             s.tail_segs = s.tail_blocks * per_wave_block;
         }
         if (p->n_thresh == 0 && s.tail_blocks == 0) s.qcap = 1;
@@ -653,7 +798,7 @@ Shape choose_shape(reedmd_ctx* ctx, const reedmd_run_params* p, const reedmd_bat
 
 reedmd_status run_impl(reedmd_ctx* ctx, const reedmd_species* sp, const reedmd_batch* b,
                        const reedmd_run_params* p, double* d_hist, reedmd_stats* d_stats, hipStream_t stream,
-                       const Shape* forced, double* d_tstat = nullptr)
+                       const Shape* forced, double* d_tstat = nullptr, hipEvent_t ev_start = nullptr)
 {
     Shape s = forced ? *forced : choose_shape(ctx, p, b);
     const int qcap = s.qcap > 0 ? s.qcap : 1;
@@ -664,6 +809,7 @@ reedmd_status run_impl(reedmd_ctx* ctx, const reedmd_species* sp, const reedmd_b
     KernelArgs A;
     fill_common(ctx, sp, p, A);
     fill_batch(b, A);
+    A.rc2 = s.r_cut * s.r_cut;
     A.hist = d_hist;
     A.stats = d_stats;
     A.tstat = d_tstat;
@@ -719,8 +865,8 @@ reedmd_status run_impl(reedmd_ctx* ctx, const reedmd_species* sp, const reedmd_b
                             reinterpret_cast<const void*>(order_count_kernel),
                             reinterpret_cast<const void*>(order_scan_kernel),
                             reinterpret_cast<const void*>(order_scatter_kernel),
-                            track_kernel_ptr(s.L, s.mode, s.f32, lattice_of(ctx)),
-                            track_kernel_ptr(64, s.mode, s.f32, lattice_of(ctx)),
+                            track_kernel_ptr(s.L, s.mode, s.f32, lattice_of(ctx), s.cut),
+                            track_kernel_ptr(64, s.mode, s.f32, lattice_of(ctx), s.cut),
                             reinterpret_cast<const void*>(stats_finalize_kernel)};
     dim3 grids[7] = {dim3((qcap + 255) / 256), dim3(kOrderBlocks), dim3(1), dim3(kOrderBlocks),
                      dim3(static_cast<unsigned>(s.blocks)), dim3(static_cast<unsigned>(std::max(s.tail_blocks, 1ll))), dim3(1)};
@@ -746,11 +892,12 @@ reedmd_status run_impl(reedmd_ctx* ctx, const reedmd_species* sp, const reedmd_b
         as_graph = cs == hipStreamCaptureStatusNone;
     }
     if (!as_graph) {
+        if (ev_start) HIP_TRY(ctx, hipEventRecord(ev_start, stream));
         for (int k = 0; k < kNodes; ++k)
             HIP_TRY(ctx, hipLaunchKernel(np[k].func, np[k].gridDim, np[k].blockDim, np[k].kernelParams, 0, stream));
         return REEDMD_OK;
     }
-    const std::vector<long long> key = {s.L, s.f32 ? 1 : 0, lattice_of(ctx), s.blocks, qcap, s.tail_blocks};
+    const std::vector<long long> key = {s.L, s.f32 ? 1 : 0, lattice_of(ctx), s.blocks, qcap, s.tail_blocks, s.cut ? 1 : 0};
     auto it = ctx->graphs.find(key);
     if (it == ctx->graphs.end()) {
         if (ctx->graphs.size() >= kMaxGraphs) drop_graphs(ctx);
@@ -771,6 +918,7 @@ reedmd_status run_impl(reedmd_ctx* ctx, const reedmd_species* sp, const reedmd_b
         for (int k = 0; k < kNodes; ++k)
             HIP_TRY(ctx, hipGraphExecKernelNodeSetParams(it->second.exec, it->second.node[k], &np[k]));
     }
+    if (ev_start) HIP_TRY(ctx, hipEventRecord(ev_start, stream));
     HIP_TRY(ctx, hipGraphLaunch(it->second.exec, stream));
     return REEDMD_OK;
 }
@@ -1061,6 +1209,7 @@ reedmd_status reedmd_run_noalloc(reedmd_ctx* ctx, const reedmd_species* species,
     KernelArgs A;
     fill_common(ctx, species, params, A);
     fill_batch(batch, A);
+    A.rc2 = s.r_cut * s.r_cut;
     A.hist = d_hist;
     A.stats = d_stats;
     A.log = static_cast<reedmd_result*>(params->track_log);
@@ -1092,7 +1241,7 @@ reedmd_status reedmd_run_noalloc(reedmd_ctx* ctx, const reedmd_species* species,
     hipLaunchKernelGGL(order_scatter_kernel, dim3(kOrderBlocks), dim3(64), 0, stream, O);
     HIP_TRY(ctx, hipGetLastError());
     void* track_args[] = {&A};
-    HIP_TRY(ctx, hipLaunchKernel(track_kernel_ptr(s.L, s.mode, s.f32, lattice_of(ctx)), dim3(static_cast<unsigned>(s.blocks)),
+    HIP_TRY(ctx, hipLaunchKernel(track_kernel_ptr(s.L, s.mode, s.f32, lattice_of(ctx), s.cut), dim3(static_cast<unsigned>(s.blocks)),
                                  dim3(kBlock), track_args, 0, stream));
     hipLaunchKernelGGL(stats_finalize_kernel, dim3(1), dim3(64), 0, stream, A.q, d_stats);
     HIP_TRY(ctx, hipGetLastError());
@@ -1106,7 +1255,7 @@ reedmd_status reedmd_track_init(reedmd_ctx* ctx, const reedmd_species* species, 
     reedmd_status st;
     if ((st = check_species(ctx, species)) != REEDMD_OK) return st;
     if ((st = check_batch(ctx, batch)) != REEDMD_OK) return st;
-    if ((st = check_params(ctx, params, false)) != REEDMD_OK) return st;
+    if ((st = check_params(ctx, params, false, false)) != REEDMD_OK) return st;
     if (!d_records && batch->n > 0) return fail(ctx, REEDMD_EINVAL, "d_records is NULL");
     if (batch->n == 0) return REEDMD_OK;
     KernelArgs A;
@@ -1116,7 +1265,7 @@ reedmd_status reedmd_track_init(reedmd_ctx* ctx, const reedmd_species* species, 
     const int L = params->lanes_per_track ? params->lanes_per_track : 64;
     const long long waves = (batch->n + (64 / L) - 1) / (64 / L);
     const long long blocks = (waves + 3) / 4;
-    launch_init_any(L, params->force_precision == REEDMD_FORCE_FP32, lattice_of(ctx), A, blocks, stream);
+    launch_init_any(L, params->force_precision == REEDMD_FORCE_FP32, lattice_of(ctx), params->r_cut > 0.0, A, blocks, stream);
     HIP_TRY(ctx, hipGetLastError());
     return REEDMD_OK;
 }
@@ -1127,7 +1276,7 @@ reedmd_status reedmd_debug_step(reedmd_ctx* ctx, const reedmd_species* species, 
     if (!ctx) return fail(nullptr, REEDMD_EINVAL, "ctx is NULL");
     reedmd_status st;
     if ((st = check_species(ctx, species)) != REEDMD_OK) return st;
-    if ((st = check_params(ctx, params, false)) != REEDMD_OK) return st;
+    if ((st = check_params(ctx, params, false, false)) != REEDMD_OK) return st;
     if (n < 0 || nsteps < 0) return fail(ctx, REEDMD_EINVAL, "n and nsteps must be >= 0");
     if (!d_records && n > 0) return fail(ctx, REEDMD_EINVAL, "d_records is NULL");
     if (n == 0) return REEDMD_OK;
@@ -1139,7 +1288,7 @@ reedmd_status reedmd_debug_step(reedmd_ctx* ctx, const reedmd_species* species, 
     const int L = params->lanes_per_track ? params->lanes_per_track : 64;
     const long long waves = (n + (64 / L) - 1) / (64 / L);
     const long long blocks = (waves + 3) / 4;
-    launch_step_any(L, params->force_precision == REEDMD_FORCE_FP32, lattice_of(ctx), A, blocks, stream);
+    launch_step_any(L, params->force_precision == REEDMD_FORCE_FP32, lattice_of(ctx), params->r_cut > 0.0, A, blocks, stream);
     HIP_TRY(ctx, hipGetLastError());
     return REEDMD_OK;
 }
@@ -1155,6 +1304,7 @@ reedmd_status reedmd_grad(reedmd_ctx* ctx, const reedmd_species* species, const 
     if ((st = check_params(ctx, params, false)) != REEDMD_OK) return st;
     if (!h_result) return fail(ctx, REEDMD_EINVAL, "h_result is NULL");
     if (params->n_thresh != 0) return fail(ctx, REEDMD_EUNSUPPORTED, "the gradient is defined without cloning (n_thresh = 0)");
+    if (params->r_cut != 0.0) return fail(ctx, REEDMD_EUNSUPPORTED, "the adjoint covers the 27-cell interaction set (r_cut = 0)");
     if (params->force_precision != REEDMD_FORCE_FP64)
         return fail(ctx, REEDMD_EUNSUPPORTED, "the adjoint is FP64 only (force_precision = REEDMD_FORCE_FP64)");
     if (lattice_of(ctx) != kDiamond || params->range_mode != REEDMD_RANGE_DEPTH || params->vacancy != 0)
@@ -1267,6 +1417,7 @@ reedmd_status reedmd_autotune(reedmd_ctx* ctx, const reedmd_species* species, co
     p.track_log = nullptr;
     p.track_log_cap = 0;
     p.cancel = cancel;
+    p.r_cut = choose_shape(ctx, params, batch).r_cut;   // the full batch's interaction set
     hipEvent_t e0, e1;
     HIP_TRY(ctx, hipEventCreate(&e0));
     HIP_TRY(ctx, hipEventCreate(&e1));
@@ -1277,8 +1428,9 @@ reedmd_status reedmd_autotune(reedmd_ctx* ctx, const reedmd_species* species, co
     for (int li = 0; li < 3 && st == REEDMD_OK; ++li) {
         // persistent form: the occupancy-sized grid and one workgroup per CU fewer
         if (lattice_of(ctx) == kFluorite && lanes[li] == 16) continue;
+        const bool cut = p.r_cut > 0.0;
         const int occ = resident_blocks_per_cu(lanes[li], persistent ? kModePersistent : kModePlain,
-                                               params->force_precision == REEDMD_FORCE_FP32, lattice_of(ctx));
+                                               params->force_precision == REEDMD_FORCE_FP32, lattice_of(ctx), cut);
         const int nw = (persistent && occ > 1) ? 2 : 1;
         for (int wi = 0; wi < nw && st == REEDMD_OK; ++wi) {
             p.lanes_per_track = lanes[li];
@@ -1320,10 +1472,139 @@ reedmd_status reedmd_autotune(reedmd_ctx* ctx, const reedmd_species* species, co
     (void)hipFree(stats);
     (void)hipHostFree(cancel);
     if (st != REEDMD_OK) return st;
-    ctx->tune[tune_key(params, batch)] = std::make_pair(bl, bw);
+    // the lanes and waves entry of this configuration; a recorded interaction set stays
+    auto prev = ctx->tune.find(tune_key(params, batch));
+    const double rc = prev != ctx->tune.end() ? prev->second.r_cut : 0.0;
+    ctx->tune[tune_key(params, batch)] = reedmd_ctx::Tuned{bl, bw, rc};
     if (best_lanes) *best_lanes = bl;
     if (best_waves) *best_waves = bw;
     return REEDMD_OK;
+}
+
+reedmd_status reedmd_autotune_domain(reedmd_ctx* ctx, const reedmd_species* species, const reedmd_batch* batch,
+                                     const reedmd_run_params* params, const double* candidates, int32_t n_candidates,
+                                     int64_t pilot, double gate_p, double gate_rel, hipStream_t stream,
+                                     double* best_r_cut, double* report)
+{
+    if (!ctx) return fail(nullptr, REEDMD_EINVAL, "ctx is NULL");
+    reedmd_status st;
+    if ((st = check_species(ctx, species)) != REEDMD_OK) return st;
+    if ((st = check_batch(ctx, batch)) != REEDMD_OK) return st;
+    if ((st = check_params(ctx, params, true)) != REEDMD_OK) return st;
+    if (!candidates || !best_r_cut) return fail(ctx, REEDMD_EINVAL, "candidates and best_r_cut must be non-NULL");
+    if (n_candidates < 1 || n_candidates > 8) return fail(ctx, REEDMD_EINVAL, "n_candidates must be in 1..8");
+    bool any_cut = false;
+    for (int c = 0; c < n_candidates; ++c) {
+        if (!(candidates[c] >= 0.0) || !std::isfinite(candidates[c]))
+            return fail(ctx, REEDMD_EINVAL, "candidates must be finite and >= 0 (0 = the 27 cells)");
+        any_cut |= candidates[c] > 0.0;
+    }
+    if (any_cut && (lattice_of(ctx) != kDiamond || params->force_precision != REEDMD_FORCE_FP64))
+        return fail(ctx, REEDMD_EUNSUPPORTED, "the interaction cut-off is built for the diamond target with FP64 forces");
+    if (pilot <= 0) return fail(ctx, REEDMD_EINVAL, "pilot must be positive");
+    if (!(gate_p >= 0.0 && gate_p < 1.0) || !(gate_rel >= 0.0) || !std::isfinite(gate_rel))
+        return fail(ctx, REEDMD_EINVAL, "need gate_p in [0, 1) and gate_rel >= 0");
+    reedmd_batch pb = *batch;
+    pb.n = std::min<int64_t>(pilot, batch->n);
+    if (pb.n == 0) {
+        *best_r_cut = 0.0;
+        return REEDMD_OK;
+    }
+    double* hist = nullptr;
+    reedmd_stats* stats = nullptr;
+    reedmd_result* log = nullptr;
+    int64_t cap = 16 * pb.n;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto release = [&]() {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        (void)hipFree(hist);
+        (void)hipFree(stats);
+        (void)hipFree(log);
+    };
+    // one pilot run of an interaction set to its end: GPU time and the finished-track log
+    auto pilot_run = [&](double rc, float* ms, std::vector<reedmd_result>& out) -> reedmd_status {
+        for (int attempt = 0; attempt < 2; ++attempt) {
+            reedmd_run_params p = *params;
+            p.r_cut = rc;
+            p.track_log = log;
+            p.track_log_cap = cap;
+            reedmd_stats h{};
+            HIP_TRY(ctx, hipMemsetAsync(hist, 0, sizeof(double) * params->n_bins, stream));
+            HIP_TRY(ctx, hipMemsetAsync(stats, 0, sizeof(reedmd_stats), stream));
+            reedmd_status rs = run_impl(ctx, species, &pb, &p, hist, stats, stream, nullptr, nullptr, e0);
+            if (rs != REEDMD_OK) return rs;
+            HIP_TRY(ctx, hipEventRecord(e1, stream));
+            HIP_TRY(ctx, hipEventSynchronize(e1));
+            HIP_TRY(ctx, hipEventElapsedTime(ms, e0, e1));
+            HIP_TRY(ctx, hipMemcpy(&h, stats, sizeof(h), hipMemcpyDeviceToHost));
+            if (h.log_count <= cap) {
+                out.resize(static_cast<size_t>(h.log_count));
+                if (h.log_count > 0)
+                    HIP_TRY(ctx, hipMemcpy(out.data(), log, sizeof(reedmd_result) * h.log_count, hipMemcpyDeviceToHost));
+                return REEDMD_OK;
+            }
+            // more finished tracks than the log holds: grow it and run again
+            (void)hipFree(log);
+            log = nullptr;
+            cap = h.log_count + h.log_count / 4;
+            HIP_TRY(ctx, hipMalloc(reinterpret_cast<void**>(&log), sizeof(reedmd_result) * cap));
+        }
+        return fail(ctx, REEDMD_EHIP, "the pilot run's finished-track count changed between its two runs");
+    };
+    st = [&]() -> reedmd_status {
+        HIP_TRY(ctx, hipMalloc(reinterpret_cast<void**>(&hist), sizeof(double) * params->n_bins));
+        HIP_TRY(ctx, hipMalloc(reinterpret_cast<void**>(&stats), sizeof(reedmd_stats)));
+        HIP_TRY(ctx, hipMalloc(reinterpret_cast<void**>(&log), sizeof(reedmd_result) * cap));
+        HIP_TRY(ctx, hipEventCreate(&e0));
+        HIP_TRY(ctx, hipEventCreate(&e1));
+        std::vector<reedmd_result> lg;
+        float ms_ref = 0.f;
+        reedmd_status rs = pilot_run(0.0, &ms_ref, lg);
+        if (rs != REEDMD_OK) return rs;
+        const DepthSample ref = depth_sample(lg);
+        double best_ms = -1.0, best_rc = 0.0;
+        for (int c = 0; c < n_candidates; ++c) {
+            const double rc = candidates[c];
+            float ms = ms_ref;
+            double p = 1.0, dm = 0.0, ds = 0.0;
+            bool pass = true;
+            if (rc > 0.0) {
+                rs = pilot_run(rc, &ms, lg);
+                if (rs != REEDMD_OK) return rs;
+                const DepthSample d = depth_sample(lg);
+                p = weighted_ks_p(d, ref, nullptr);
+                dm = ref.mean != 0.0 ? std::fabs(d.mean - ref.mean) / std::fabs(ref.mean) : 0.0;
+                ds = ref.sd != 0.0 ? std::fabs(d.sd - ref.sd) / ref.sd : 0.0;
+                const double bm = std::max(gate_rel, 3.0 * std::hypot(d.se_mean, ref.se_mean) / std::fabs(ref.mean));
+                const double bs = std::max(gate_rel, 3.0 * std::hypot(d.se_sd, ref.se_sd) / ref.sd);
+                pass = p > gate_p && dm <= bm && ds <= bs;
+            }
+            if (report) {
+                report[5 * c + 0] = ms;
+                report[5 * c + 1] = p;
+                report[5 * c + 2] = dm;
+                report[5 * c + 3] = ds;
+                report[5 * c + 4] = pass ? 1.0 : 0.0;
+            }
+            if (pass && (best_ms < 0.0 || ms < best_ms)) {
+                best_ms = ms;
+                best_rc = rc;
+            }
+        }
+        if (best_ms < 0.0) best_rc = 0.0;   // only failing cut-offs offered: the 27 cells
+        auto prev = ctx->tune.find(tune_key(params, batch));
+        reedmd_ctx::Tuned t{0, 0, best_rc};
+        if (prev != ctx->tune.end()) {
+            t.lanes = prev->second.lanes;
+            t.waves = prev->second.waves;
+        }
+        ctx->tune[tune_key(params, batch)] = t;
+        *best_r_cut = best_rc;
+        return REEDMD_OK;
+    }();
+    release();
+    return st;
 }
 
 reedmd_status reedmd_run_refined(reedmd_ctx* ctx, const reedmd_species* species, const reedmd_batch* batch,
@@ -1370,6 +1651,7 @@ reedmd_status reedmd_run_refined(reedmd_ctx* ctx, const reedmd_species* species,
         HIP_TRY(ctx, hipMemcpyAsync(probs, rf->probs, pr_b, hipMemcpyHostToDevice, stream));
         reedmd_run_params p = *params;
         p.thresholds = thr;
+        p.r_cut = choose_shape(ctx, params, batch).r_cut;   // the whole batch's interaction set
         reedmd_result* log0 = static_cast<reedmd_result*>(params->track_log);
         int64_t log_done = 0;
         reedmd_stats h0{};
@@ -1440,7 +1722,7 @@ reedmd_status reedmd_launch_shape(reedmd_ctx* ctx, const reedmd_batch* batch, co
     out[0] = s.L;
     out[1] = s.blocks;
     out[2] = s.seg_total;
-    out[3] = resident_blocks_per_cu(s.L, s.mode, s.f32, lattice_of(ctx));
+    out[3] = resident_blocks_per_cu(s.L, s.mode, s.f32, lattice_of(ctx), s.cut);
     out[4] = s.mode == kModePersistent ? s.qcap : 0;
     return REEDMD_OK;
 }

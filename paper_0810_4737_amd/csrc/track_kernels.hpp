@@ -84,6 +84,7 @@ struct KernelArgs {
     unsigned long long* qseq;
     double* qrec;
     const int* cancel;
+    double rc2;             // interaction cut-off squared (A^2); 0: every atom of the 27 cells
     const int* order;       // optional: batch entry of the i-th claimed primary (longest expected first)
     long long seg_total;
     // tail handoff (persistent form with fewer than 64 lanes per track): once every primary
@@ -130,19 +131,21 @@ __device__ __forceinline__ KernelArgs cold_args()
 // forces [3][SL*L] (the slots padded to whole lane rows, so every lane of a row
 // has an entry) followed by kTrackHdr words: the start point (3), the cell of
 // the vacant site (3) and its basis index (-1: none).
+// With an interaction cut-off (CUT) the header is followed by the list of the
+// slots within the cut-off (one int per slot).
 constexpr int kTrackHdr = 8;
-template <int L, int LAT = kDiamond>
+template <int L, int LAT = kDiamond, bool CUT = false>
 struct ForceLds {
     static constexpr int kStride = ((Lattice<LAT>::kSlots + L - 1) / L) * L;
     static constexpr int kTracksPerBlock = 4 * (64 / L);
-    static constexpr int kTrackDoubles = 3 * kStride + kTrackHdr;
+    static constexpr int kTrackDoubles = 3 * kStride + kTrackHdr + (CUT ? kStride / 2 : 0);
     static constexpr int kDoubles = kTracksPerBlock * kTrackDoubles;
 };
-template <int L, int LAT = kDiamond>
+template <int L, int LAT = kDiamond, bool CUT = false>
 __device__ __forceinline__ double* force_slab(double* s_force)
 {
     const int track_in_block = (threadIdx.x >> 6) * (64 / L) + (threadIdx.x & 63) / L;
-    return s_force + track_in_block * ForceLds<L, LAT>::kTrackDoubles;
+    return s_force + track_in_block * ForceLds<L, LAT, CUT>::kTrackDoubles;
 }
 
 // Species constants are staged in LDS once per workgroup (indexed per lane):
@@ -284,6 +287,7 @@ struct TrackRegs {
     long long steps, lineage;
     int species, next_k, table, status;
     int n_exist;             // atoms in the domain (segment-uniform)
+    int n_eval;              // pair terms evaluated by the last pass (n_exist without a cut-off)
 };
 
 template <int L, int LAT>
@@ -456,7 +460,7 @@ struct StepInfo {
 // primary).  Returns the kinetic energy before the step via ke0, and the
 // step's size via info when given, and the atoms a domain move drops via drop
 // when given (see regenerate).
-template <int L, bool F32 = false, int LAT = kDiamond>
+template <int L, bool F32 = false, int LAT = kDiamond, bool CUT = false>
 __device__ __forceinline__ void track_step(TrackRegs<L, LAT>& t, const KernelArgs& A, const SpeciesConst* sp, int sl,
                                            bool fresh, double& ke0, double& z0, StepInfo* info = nullptr,
                                            double* drop = nullptr)
@@ -510,41 +514,122 @@ __device__ __forceinline__ void track_step(TrackRegs<L, LAT>& t, const KernelArg
 #pragma unroll
     for (int m = 0; m < G; ++m) Fx[m] = Fy[m] = Fz[m] = rho[m] = rho1[m] = 0.0;
     double vm = 0.0, fm = 0.0;
+    if constexpr (CUT) {
+        // Interaction cut-off: pair terms only for the atoms within sqrt(rc2) of the ion,
+        // compacted so that the rounds over them take ceil(listed / L) passes instead of one
+        // per register slot.
+        static_assert(LAT == kDiamond && !F32, "the interaction cut-off is built for the diamond FP64 kernels");
+        constexpr int SL = TrackRegs<L, LAT>::SL;
+        int* list = reinterpret_cast<int*>(t.fl + 3 * FS + kTrackHdr);
+        const int base = (threadIdx.x & 63) - sl;
+        int count = 0;   // segment-uniform
+        // (a) first half kick and drift of every slot; the new position of a slot within the
+        //     cut-off is staged in its force entry (the old force is spent), zero otherwise,
+        //     and the slots within are listed in increasing slot order
 #pragma unroll
-    for (int i = 0; i < TrackRegs<L, LAT>::SL; ++i) {
-        const int m = i % G;   // column group of register slot i
-        const bool anion = FL && L * i >= Lattice<LAT>::kAnion0;
-        const double h2 = anion ? h2b : h2a;
-        double* f = t.fl + (sl + L * i);
-        double vx = t.avx[i] + f[0 * FS] * h2;
-        double vy = t.avy[i] + f[1 * FS] * h2;
-        double vz = t.avz[i] + f[2 * FS] * h2;
-        const double px = t.ax[i] + vx * dt;
-        const double py = t.ay[i] + vy * dt;
-        const double pz = t.az[i] + vz * dt;
-        const double dx = t.x - px, dy = t.y - py, dz = t.z - pz;
-        double coef, ew;
-        if (anion) {
-            if constexpr (F32) zbl_pair_f32(c1, dx, dy, dz, coef, ew);
-            else zbl_pair(c1, dx, dy, dz, coef, ew);
-        } else {
-            if constexpr (F32) zbl_pair_f32(c, dx, dy, dz, coef, ew);
-            else zbl_pair(c, dx, dy, dz, coef, ew);
+        for (int i = 0; i < SL; ++i) {
+            double* f = t.fl + (sl + L * i);
+            const double vx = t.avx[i] + f[0 * FS] * h2a;
+            const double vy = t.avy[i] + f[1 * FS] * h2a;
+            const double vz = t.avz[i] + f[2 * FS] * h2a;
+            const double px = t.ax[i] + vx * dt;
+            const double py = t.ay[i] + vy * dt;
+            const double pz = t.az[i] + vz * dt;
+            t.avx[i] = vx; t.avy[i] = vy; t.avz[i] = vz;
+            t.ax[i] = px; t.ay[i] = py; t.az[i] = pz;
+            const double dx = t.x - px, dy = t.y - py, dz = t.z - pz;
+            const bool in = dx * dx + dy * dy + dz * dz <= A.rc2;
+            f[0 * FS] = in ? px : 0.0;
+            f[1 * FS] = in ? py : 0.0;
+            f[2 * FS] = in ? pz : 0.0;
+            const unsigned long long b = __ballot(in);
+            const unsigned long long seg = (L == 64) ? b : ((b >> base) & ((1ull << (L % 64)) - 1ull));
+            if (in) list[count + __popcll(seg & ((1ull << sl) - 1ull))] = sl + L * i;
+            count += __popcll(seg);
         }
-        const double fx = -coef * dx, fy = -coef * dy, fz = -coef * dz;   // force on the atom
-        Fx[m] -= fx; Fy[m] -= fy; Fz[m] -= fz;
-        if (anion) rho1[m] += ew;
-        else rho[m] += ew;
-        vx += fx * h2; vy += fy * h2; vz += fz * h2;
-        t.ax[i] = px; t.ay[i] = py; t.az[i] = pz;
-        t.avx[i] = vx; t.avy[i] = vy; t.avz[i] = vz;
-        f[0 * FS] = fx; f[1 * FS] = fy; f[2 * FS] = fz;
-        vm = fmax(vm, vx * vx + vy * vy + vz * vz);
-        if constexpr (FL) fm = fmax(fm, (fx * fx + fy * fy + fz * fz) * (anion ? A.inv_M2bsq : A.inv_M2sq));
-        else fm = fmax(fm, fx * fx + fy * fy + fz * fz);
-#if REEDMD_PAIR_BARRIER
-        __builtin_amdgcn_sched_barrier(0);
-#endif
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // (b) pair terms over the list: entry j on lane j mod L in round j / L (empty entries
+        //     of the last round take the parking distance, where every term is exactly 0);
+        //     the sums follow the same column tree as the full pass, over list entries
+#pragma unroll
+        for (int k = 0; k < SL; ++k) {
+            if (__all(k * L >= count)) break;
+            const int m = k % G;
+            const int j = k * L + sl;
+            const bool valid = j < count;
+            const int s = valid ? list[j] : 0;
+            double dx = 0.0, dy = 0.0, dz = A.park;
+            if (valid) {
+                dx = t.x - t.fl[0 * FS + s];
+                dy = t.y - t.fl[1 * FS + s];
+                dz = t.z - t.fl[2 * FS + s];
+            }
+            double coef, ew;
+            zbl_pair(c, dx, dy, dz, coef, ew);
+            const double fx = -coef * dx, fy = -coef * dy, fz = -coef * dz;   // force on the atom
+            Fx[m] -= fx; Fy[m] -= fy; Fz[m] -= fz;
+            rho[m] += ew;
+            if (valid) {
+                t.fl[0 * FS + s] = fx;
+                t.fl[1 * FS + s] = fy;
+                t.fl[2 * FS + s] = fz;
+            }
+            fm = fmax(fm, fx * fx + fy * fy + fz * fz);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // (c) second half kick of every slot with its new force (zero beyond the cut-off)
+#pragma unroll
+        for (int i = 0; i < SL; ++i) {
+            const double* f = t.fl + (sl + L * i);
+            const double vx = t.avx[i] + f[0 * FS] * h2a;
+            const double vy = t.avy[i] + f[1 * FS] * h2a;
+            const double vz = t.avz[i] + f[2 * FS] * h2a;
+            t.avx[i] = vx; t.avy[i] = vy; t.avz[i] = vz;
+            vm = fmax(vm, vx * vx + vy * vy + vz * vz);
+        }
+        t.n_eval = count;
+    } else {
+    #pragma unroll
+        for (int i = 0; i < TrackRegs<L, LAT>::SL; ++i) {
+            const int m = i % G;   // column group of register slot i
+            const bool anion = FL && L * i >= Lattice<LAT>::kAnion0;
+            const double h2 = anion ? h2b : h2a;
+            double* f = t.fl + (sl + L * i);
+            double vx = t.avx[i] + f[0 * FS] * h2;
+            double vy = t.avy[i] + f[1 * FS] * h2;
+            double vz = t.avz[i] + f[2 * FS] * h2;
+            const double px = t.ax[i] + vx * dt;
+            const double py = t.ay[i] + vy * dt;
+            const double pz = t.az[i] + vz * dt;
+            const double dx = t.x - px, dy = t.y - py, dz = t.z - pz;
+            double coef, ew;
+            if (anion) {
+                if constexpr (F32) zbl_pair_f32(c1, dx, dy, dz, coef, ew);
+                else zbl_pair(c1, dx, dy, dz, coef, ew);
+            } else {
+                if constexpr (F32) zbl_pair_f32(c, dx, dy, dz, coef, ew);
+                else zbl_pair(c, dx, dy, dz, coef, ew);
+            }
+            const double fx = -coef * dx, fy = -coef * dy, fz = -coef * dz;   // force on the atom
+            Fx[m] -= fx; Fy[m] -= fy; Fz[m] -= fz;
+            if (anion) rho1[m] += ew;
+            else rho[m] += ew;
+            vx += fx * h2; vy += fy * h2; vz += fz * h2;
+            t.ax[i] = px; t.ay[i] = py; t.az[i] = pz;
+            t.avx[i] = vx; t.avy[i] = vy; t.avz[i] = vz;
+            f[0 * FS] = fx; f[1 * FS] = fy; f[2 * FS] = fz;
+            vm = fmax(vm, vx * vx + vy * vy + vz * vz);
+            if constexpr (FL) fm = fmax(fm, (fx * fx + fy * fy + fz * fz) * (anion ? A.inv_M2bsq : A.inv_M2sq));
+            else fm = fmax(fm, fx * fx + fy * fy + fz * fz);
+    #if REEDMD_PAIR_BARRIER
+            __builtin_amdgcn_sched_barrier(0);
+    #endif
+        }
+        t.n_eval = t.n_exist;
     }
     t.Fx = SegReduce<L>::csum(Fx);
     t.Fy = SegReduce<L>::csum(Fy);
@@ -859,12 +944,12 @@ __device__ __forceinline__ long long queue_reserve_pop(const KernelArgs& A)
 // from device counters and the clone queue until no track is live).
 enum : int { kSegNeed = 0, kSegRun = 1, kSegDone = 2 };
 
-template <int L, int MODE, bool F32 = false, int LAT = kDiamond>
+template <int L, int MODE, bool F32 = false, int LAT = kDiamond, bool CUT = false>
 __global__ void __launch_bounds__(256, REEDMD_WAVES_PER_SIMD(L, LAT)) track_kernel(const KernelArgs A0)
 {
     const KernelArgs& A = A0;
     __shared__ double s_sp[kSpeciesLdsDoubles];
-    __shared__ double s_force[ForceLds<L, LAT>::kDoubles];
+    __shared__ double s_force[ForceLds<L, LAT, CUT>::kDoubles];
     const SpeciesConst* sp = stage_species(A, s_sp);
     const int lane = threadIdx.x & 63;
     const int sl = lane % L;
@@ -875,7 +960,7 @@ __global__ void __launch_bounds__(256, REEDMD_WAVES_PER_SIMD(L, LAT)) track_kern
 
     constexpr int RW = Lattice<LAT>::kRecWords;
     TrackRegs<L, LAT> t;
-    t.fl = force_slab<L, LAT>(s_force);
+    t.fl = force_slab<L, LAT, CUT>(s_force);
     t.cx = t.cy = t.cz = kSentinel;
     t.exist = 0;
     t.n_exist = 0;
@@ -1006,8 +1091,8 @@ __global__ void __launch_bounds__(256, REEDMD_WAVES_PER_SIMD(L, LAT)) track_kern
 
         // ---- one step of a running track ----
         double ke0, z0;
-        track_step<L, F32, LAT>(t, A, sp, sl, fresh, ke0, z0);
-        pairs += t.n_exist;
+        track_step<L, F32, LAT, CUT>(t, A, sp, sl, fresh, ke0, z0);
+        pairs += t.n_eval;
         if (fresh) {
             fresh = false;
             continue;
@@ -1115,44 +1200,44 @@ __global__ void __launch_bounds__(256, REEDMD_WAVES_PER_SIMD(L, LAT)) track_kern
 }
 
 // Builds the starting record of every batch entry (debug / parity entry point).
-template <int L, bool F32 = false, int LAT = kDiamond>
+template <int L, bool F32 = false, int LAT = kDiamond, bool CUT = false>
 __global__ void __launch_bounds__(256) init_kernel(const KernelArgs A)
 {
     __shared__ double s_sp[kSpeciesLdsDoubles];
-    __shared__ double s_force[ForceLds<L, LAT>::kDoubles];
+    __shared__ double s_force[ForceLds<L, LAT, CUT>::kDoubles];
     const SpeciesConst* sp = stage_species(A, s_sp);
     const int lane = threadIdx.x & 63;
     const int sl = lane % L;
     const long long seg = (static_cast<long long>(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6)) * (64 / L) + lane / L;
     if (seg >= A.n) return;
     TrackRegs<L, LAT> t;
-    t.fl = force_slab<L, LAT>(s_force);
+    t.fl = force_slab<L, LAT, CUT>(s_force);
     t.exist = 0;
     start_primary<L, LAT>(t, A, sp, seg);
     double ke0, z0;
-    if (t.status != REEDMD_LOST) track_step<L, F32, LAT>(t, A, sp, sl, true, ke0, z0);
+    if (t.status != REEDMD_LOST) track_step<L, F32, LAT, CUT>(t, A, sp, sl, true, ke0, z0);
     store_record<L, LAT>(t, A.records + static_cast<size_t>(seg) * Lattice<LAT>::kRecWords, sl);
 }
 
 // Advances caller records by nsteps steps without events (debug / parity).
-template <int L, bool F32 = false, int LAT = kDiamond>
+template <int L, bool F32 = false, int LAT = kDiamond, bool CUT = false>
 __global__ void __launch_bounds__(256, 2) step_kernel(const KernelArgs A)
 {
     __shared__ double s_sp[kSpeciesLdsDoubles];
-    __shared__ double s_force[ForceLds<L, LAT>::kDoubles];
+    __shared__ double s_force[ForceLds<L, LAT, CUT>::kDoubles];
     const SpeciesConst* sp = stage_species(A, s_sp);
     const int lane = threadIdx.x & 63;
     const int sl = lane % L;
     const long long seg = (static_cast<long long>(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6)) * (64 / L) + lane / L;
     if (seg >= A.n) return;
     TrackRegs<L, LAT> t;
-    t.fl = force_slab<L, LAT>(s_force);
+    t.fl = force_slab<L, LAT, CUT>(s_force);
     double* rec = A.records + static_cast<size_t>(seg) * Lattice<LAT>::kRecWords;
     load_record<L, LAT>(t, rec, sl, A);
     if (t.status == REEDMD_LOST) return;   // invalid species index: record left as it was
     for (int s = 0; s < A.nsteps; ++s) {
         double ke0, z0;
-        track_step<L, F32, LAT>(t, A, sp, sl, false, ke0, z0);
+        track_step<L, F32, LAT, CUT>(t, A, sp, sl, false, ke0, z0);
     }
     store_record<L, LAT>(t, rec, sl);
 }

@@ -48,8 +48,8 @@ def test_struct_sizes_match_header_layout():
     assert _abi.RECORD_WORDS_FLUORITE == 32 + 9 * 344
     # reedmd_run_params: 4 doubles, max_steps, seed, 2 ints, thresholds, 2 ints, bin_width,
     # 4 ints, cancel and track_log, track_log_cap, force_precision + range_mode,
-    # vacancy + reserved
-    assert C.sizeof(_abi.RunParams) == 4 * 8 + 8 + 8 + 8 + 8 + 8 + 8 + 16 + 16 + 8 + 8 + 8
+    # vacancy + no_tail_handoff, r_cut
+    assert C.sizeof(_abi.RunParams) == 4 * 8 + 8 + 8 + 8 + 8 + 8 + 8 + 16 + 16 + 8 + 8 + 8 + 8
     # reedmd_lattice: a, M2, sigma, Z2 + structure, M2b, sigma_b, Z2b + reserved
     assert C.sizeof(_abi.Lattice) == 3 * 8 + 8 + 2 * 8 + 8
 
