@@ -32,7 +32,7 @@ DIAMOND, ISOLATED, FLUORITE = 0, 1, 2
 RANGE_DEPTH, RANGE_RADIAL = 0, 1
 START_SURFACE, START_SITE = 0, 1
 POT_ZBL, POT_NONE = 0, 1
-STOP_OFF, STOP_UNIFORM, STOP_LOCAL = 0, 1, 2
+STOP_OFF, STOP_UNIFORM, STOP_LOCAL, STOP_FKBK = 0, 1, 2, 3
 ACTIVE, STOPPED, BACKSCATTERED, NONFINITE, STEPCAP = 0, 1, 2, 3, 4
 DIR_TILT, DIR_CONE, DIR_MIXED, DIR_ISOTROPIC = 0, 1, 2, 3
 
@@ -65,6 +65,7 @@ class Params(C.Structure):
         ("M1", C.c_double * MAX_SPECIES),
         ("M2b", C.c_double), ("sigma_b", C.c_double), ("Z2b", C.c_int32),
         ("range_mode", C.c_int32), ("vacancy", C.c_int32), ("pad_", C.c_int32), ("r_cut", C.c_double),
+        ("n_e", C.c_double),
     ]
 
 
@@ -120,6 +121,18 @@ def lib():
         L.or_density_weight.restype = C.c_double
         L.or_gamma.argtypes = [P(Params), C.c_int, C.c_double]
         L.or_gamma.restype = C.c_double
+        L.or_stopping_gamma.argtypes = [P(Params), C.c_int, C.c_double, C.c_double]
+        L.or_stopping_gamma.restype = C.c_double
+        for fn in ("or_firsov_b", "or_firsov_norm"):
+            getattr(L, fn).argtypes = [P(Params), C.c_int, C.c_int]
+            getattr(L, fn).restype = C.c_double
+        L.or_firsov_weight.argtypes = [P(Params), C.c_int, C.c_int, C.c_double]
+        L.or_firsov_weight.restype = C.c_double
+        for fn in ("or_bk_zeta", "or_bk_gamma"):
+            getattr(L, fn).argtypes = [P(Params), C.c_int, C.c_double]
+            getattr(L, fn).restype = C.c_double
+        L.or_bk_proton_friction.argtypes = [P(Params)]
+        L.or_bk_proton_friction.restype = C.c_double
         L.or_site.argtypes = [P(Params), C.c_int, P(C.c_double), P(C.c_int)]
         L.or_sample_primaries.argtypes = [P(Sampler), C.c_uint64, C.c_int64, C.c_int64,
                                           C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
@@ -198,6 +211,7 @@ class Config:
     range_mode: int = RANGE_DEPTH
     vacancy: int = 0
     r_cut: float = 0.0
+    n_e: float = 0.0
 
     def params(self):
         """Returns (Params, keepalive) where keepalive holds referenced arrays."""
@@ -214,6 +228,7 @@ class Config:
         p.Z2b, p.M2b, p.sigma_b = self.Z2b, self.M2b, self.sigma_b
         p.range_mode, p.vacancy = self.range_mode, self.vacancy
         p.r_cut = self.r_cut
+        p.n_e = self.n_e
         sp = [s[0] if isinstance(s, tuple) else s for s in self.species]
         p.n_species = len(sp)
         for i, name in enumerate(sp):
@@ -285,6 +300,42 @@ def lss_kL(cfg: Config, species: int = 0, type: int = 0) -> float:
 def density_weight(cfg: Config, species: int, r: float, type: int = 0) -> float:
     p, keep = cfg.params()
     return lib().or_density_weight(C.byref(p), species, type, float(r))
+
+
+def stopping_gamma(cfg: Config, species: int, rho: float, v2: float) -> float:
+    """Friction coefficient with the ion's speed squared (adds the Brandt-Kitagawa part)."""
+    p, _ = cfg.params()
+    return lib().or_stopping_gamma(C.byref(p), species, float(rho), float(v2))
+
+
+def firsov_b(cfg: Config, species: int = 0, type: int = 0) -> float:
+    p, _ = cfg.params()
+    return lib().or_firsov_b(C.byref(p), species, type)
+
+
+def firsov_norm(cfg: Config, species: int = 0, type: int = 0) -> float:
+    p, _ = cfg.params()
+    return lib().or_firsov_norm(C.byref(p), species, type)
+
+
+def firsov_weight(cfg: Config, species: int, r: float, type: int = 0) -> float:
+    p, _ = cfg.params()
+    return lib().or_firsov_weight(C.byref(p), species, type, float(r))
+
+
+def bk_zeta(cfg: Config, species: int, v: float) -> float:
+    p, _ = cfg.params()
+    return lib().or_bk_zeta(C.byref(p), species, float(v))
+
+
+def bk_gamma(cfg: Config, species: int, v: float) -> float:
+    p, _ = cfg.params()
+    return lib().or_bk_gamma(C.byref(p), species, float(v))
+
+
+def bk_proton_friction(cfg: Config) -> float:
+    p, _ = cfg.params()
+    return lib().or_bk_proton_friction(C.byref(p))
 
 
 def gamma(cfg: Config, species: int, rho: float) -> float:

@@ -236,6 +236,7 @@ int32_t or_grad_track(const or_params* p, int32_t species, double E0, const doub
 {
     /* diamond, depth range and no vacancy only (the adjoint's domain) */
     if (p->structure != OR_DIAMOND || p->range_mode != OR_RANGE_DEPTH || p->vacancy) return -3;
+    if (p->stop_mode == OR_STOP_FKBK || p->r_cut > 0.0) return -3;   /* derivatives cover the local LS model, 27 cells */
     gtrack* t = (gtrack*)calloc(1, sizeof(gtrack));
     if (!t) return -1;
     double M1 = p->M1[species];

@@ -19,10 +19,13 @@ uint64_t or_primary_key(uint64_t seed, int64_t id);
 typedef struct {
     int on;
     double a, zz, lambda, wscale;
+    int firsov;           /* OR_STOP_FKBK: the stopping weight is Firsov's kernel */
+    double fk_b, fk_norm;
 } or_pair_consts;
 void or_pair_constants(const or_params* p, int species, int type, or_pair_consts* c);
 void or_zbl_c(const or_pair_consts* c, double r, double* V, double* dVdr);
 double or_density_weight_c(const or_pair_consts* c, double r);
+double or_firsov_weight_c(const or_pair_consts* c, double r);
 
 double or_number_density(const or_params* p, int type);
 double or_pair_potential(const or_params* p, int species, int type, double r);

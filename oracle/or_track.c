@@ -175,7 +175,7 @@ void or_compute_forces(const or_params* p, or_track* t)
             t->F[k] += fk;
             at->f[k] = -fk;
         }
-        t->rho += or_density_weight_c(pc, r);
+        t->rho += pc->firsov ? or_firsov_weight_c(pc, r) : or_density_weight_c(pc, r);
     }
 }
 
@@ -256,7 +256,8 @@ double or_track_step(const or_params* p, or_track* t)
     double M1 = p->M1[t->species];
     double dt = time_step(p, t);
 
-    double fr1 = exp(-or_gamma(p, t->species, t->rho) * dt / (2.0 * M1));
+    double v2 = t->v[0] * t->v[0] + t->v[1] * t->v[1] + t->v[2] * t->v[2];
+    double fr1 = exp(-or_stopping_gamma(p, t->species, t->rho, v2) * dt / (2.0 * M1));
     for (int k = 0; k < 3; ++k) t->v[k] *= fr1;
 
     for (int k = 0; k < 3; ++k) t->v[k] += t->F[k] * dt / (2.0 * M1);
@@ -283,7 +284,8 @@ double or_track_step(const or_params* p, or_track* t)
         for (int k = 0; k < 3; ++k) at->v[k] += at->f[k] * dt / (2.0 * or_type_mass(p, at->type));
     }
 
-    double fr2 = exp(-or_gamma(p, t->species, t->rho) * dt / (2.0 * M1));
+    v2 = t->v[0] * t->v[0] + t->v[1] * t->v[1] + t->v[2] * t->v[2];
+    double fr2 = exp(-or_stopping_gamma(p, t->species, t->rho, v2) * dt / (2.0 * M1));
     for (int k = 0; k < 3; ++k) t->v[k] *= fr2;
 
     t->steps += 1;

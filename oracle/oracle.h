@@ -18,7 +18,9 @@
  *   - nuclear interactions by the ZBL universal screened Coulomb potential
  *     only (Sec. 2, "First" and "Second");
  *   - local electronic stopping (Sec. 2, "Third"; the configured Local
- *     Lindhard-Scharff reading);
+ *     Lindhard-Scharff reading, or the paper's Firsov local loss plus a
+ *     Brandt-Kitagawa loss in the interstitial electron density, read from the
+ *     works it cites, see or_physics.c);
  *   - Verlet-type integration with an adaptive time step derived from the
  *     kinetic and the collisional energy scale (Sec. 2, Fig. 2);
  *   - rare-event enhancement: the system is cloned at cloning depths and the
@@ -47,7 +49,14 @@
  * compound friction paths in closed form, the stopping-weighted mean density,
  * the recoil vacancy, the isotropic on-site sampler, the radial range of a
  * free ion, energy and momentum ledgers with two masses, exact record round
- * trips.  The absolute range profile of a full run is
+ * trips.  Firsov + Brandt-Kitagawa stopping (tests/test_oracle_fkbk.py): Firsov's
+ * cross-section as the impact-parameter integral of his collision loss, the
+ * kernel's volume integral, flybys past one atom against the kernel's line
+ * integral (closed form head on, quadrature off axis) and their speed
+ * independence, the effective-charge limits, the atomic velocity unit, a free
+ * ion's exponential decay under the Brandt-Kitagawa friction, k = 0 against
+ * stopping off; the slow-proton friction of the electron gas is parity
+ * unpinned.  The absolute range profile of a full run is
  * parity unpinned against the paper (it prints no profile values and its
  * figures are not available); it is only compared with the GPU library.
  */
@@ -72,7 +81,7 @@ enum { OR_RANGE_DEPTH = 0, OR_RANGE_RADIAL = 1 };
 /* potential modes */
 enum { OR_POT_ZBL = 0, OR_POT_NONE = 1 };
 /* stopping modes */
-enum { OR_STOP_OFF = 0, OR_STOP_UNIFORM = 1, OR_STOP_LOCAL = 2 };
+enum { OR_STOP_OFF = 0, OR_STOP_UNIFORM = 1, OR_STOP_LOCAL = 2, OR_STOP_FKBK = 3 };
 /* track status */
 enum { OR_ACTIVE = 0, OR_STOPPED = 1, OR_BACKSCATTERED = 2, OR_NONFINITE = 3,
        OR_STEPCAP = 4 };
@@ -117,6 +126,8 @@ typedef struct {
     int32_t pad_;
     double r_cut;        /* interaction cut-off (A): domain atoms farther than r_cut from the ion
                             exert no force and add no density; 0: every atom of the 27 cells */
+    double n_e;          /* OR_STOP_FKBK: interstitial electron density (electrons per A^3) of the
+                            Brandt-Kitagawa term; 0: the local Firsov term alone */
 } or_params;
 
 /* One domain atom. */
@@ -204,6 +215,13 @@ void or_zbl(const or_params* p, int species, int type, double r, double* V, doub
 double or_lss_kL(const or_params* p, int species, int type);
 double or_density_weight(const or_params* p, int species, int type, double r);
 double or_gamma(const or_params* p, int species, double rho);
+double or_stopping_gamma(const or_params* p, int species, double rho, double v2);
+double or_firsov_b(const or_params* p, int species, int type);
+double or_firsov_norm(const or_params* p, int species, int type);
+double or_firsov_weight(const or_params* p, int species, int type, double r);
+double or_bk_zeta(const or_params* p, int species, double v);
+double or_bk_proton_friction(const or_params* p);
+double or_bk_gamma(const or_params* p, int species, double v);
 void or_site(const or_params* p, int b, double f[3], int* type);
 
 /* sampler */
