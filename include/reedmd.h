@@ -54,7 +54,7 @@ enum { REEDMD_DIAMOND = 0, REEDMD_FLUORITE = 1 };
 /* range coordinate used for the cloning depths and the histogram */
 enum { REEDMD_RANGE_DEPTH = 0, REEDMD_RANGE_RADIAL = 1 };
 enum { REEDMD_POT_ZBL = 0, REEDMD_POT_NONE = 1 };
-enum { REEDMD_STOP_OFF = 0, REEDMD_STOP_UNIFORM = 1, REEDMD_STOP_LOCAL = 2 };
+enum { REEDMD_STOP_OFF = 0, REEDMD_STOP_UNIFORM = 1, REEDMD_STOP_LOCAL = 2, REEDMD_STOP_FKBK = 3 };
 enum { REEDMD_FORM_PLAIN = 0, REEDMD_FORM_PERSISTENT = 1 };
 /* Precision of the ion-atom pair term (distance, screening exponentials, force
  * coefficient, density weight).  Positions, velocities, force components and
@@ -99,11 +99,23 @@ typedef struct {
 /* Electronic stopping (Sec. 2, "Third"), read as a local Lindhard-Scharff
  * friction F = -gamma(x) v with gamma = k N kL sqrt(M1/2) rho(x)/N, where
  * rho(x) = sum_j exp(-r_j/lambda)/(8 pi lambda^3), lambda = a_U/0.3 (unscaled a_U),
- * kL = 1.212 Z1^(7/6) Z2 / ((Z1^(2/3)+Z2^(2/3))^(3/2) sqrt(M1)).  UNIFORM uses rho = N. */
+ * kL = 1.212 Z1^(7/6) Z2 / ((Z1^(2/3)+Z2^(2/3))^(3/2) sqrt(M1)).  UNIFORM uses rho = N.
+ * FKBK is the paper's model (Sec. 2, "Third"; parameters not printed there), read
+ * from the works it cites: gamma = k (sum_j C 3 b^3 / (pi (1 + b r_j)^5) + (zeta Z1)^2 gamma_p),
+ * a local Firsov loss over the domain atoms (b = 0.31 (Z1+Z2)^(1/3) per A,
+ * C = 0.3254 (Z1+Z2) / sqrt(2): Firsov's stopping cross-section over the speed in
+ * sqrt(eV/amu)) plus the Brandt-Kitagawa loss of the ion's effective charge zeta Z1
+ * (zeta from the Brandt-Kitagawa formula with the Ziegler-Biersack-Littmark
+ * ionisation fit) in the interstitial electron gas of density n_e, gamma_p being
+ * the slow-proton friction of that gas (Ritchie).  FKBK runs with FP64 pair terms
+ * and the 27-cell interaction set (REEDMD_EUNSUPPORTED otherwise); reedmd_grad
+ * covers OFF, UNIFORM and LOCAL. */
 typedef struct {
-    int32_t mode;        /* REEDMD_STOP_OFF / _UNIFORM / _LOCAL */
+    int32_t mode;        /* REEDMD_STOP_OFF / _UNIFORM / _LOCAL / _FKBK */
     int32_t reserved;
     double k;            /* stopping scale, >= 0 */
+    double n_e;          /* FKBK: interstitial (muffin-tin residual) electron density, electrons per
+                            A^3, finite and >= 0 (0: the Firsov part alone); ignored otherwise */
 } reedmd_stopping;
 
 /* Ion species table (host struct, passed by pointer, copied at the call). */

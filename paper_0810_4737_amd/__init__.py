@@ -19,11 +19,14 @@ from . import _abi
 from ._abi import (ACTIVE, BACKSCATTERED, CANCELLED, DIAMOND, DIR_CONE, DIR_ISOTROPIC, DIR_MIXED,  # noqa: F401
                    DIR_TILT, FLUORITE, FORCE_FP32, FORCE_FP64, FORM_PERSISTENT, FORM_PLAIN, NONFINITE, NSLOT,
                    NSLOT_FLUORITE, POT_NONE, POT_ZBL, RANGE_DEPTH, RANGE_RADIAL, RECORD_WORDS,
-                   RECORD_WORDS_FLUORITE, START_SITE, START_SURFACE, STEPCAP, STOP_LOCAL, STOP_OFF,
-                   STOP_UNIFORM, STOPPED)
+                   RECORD_WORDS_FLUORITE, START_SITE, START_SURFACE, STEPCAP, STOP_FKBK, STOP_LOCAL,
+                   STOP_OFF, STOP_UNIFORM, STOPPED)
 
 SPECIES = {"B": (5, 10.81), "P": (15, 30.97), "As": (33, 74.92), "U": (92, 238.03)}
 SILICON = dict(a=5.431, Z2=14, M2=28.0855, sigma=0.076)
+# valence electron density of silicon (4 per atom, 8 atoms per cubic cell), electrons per A^3:
+# the interstitial electron gas of the Brandt-Kitagawa term when every valence electron counts
+SILICON_VALENCE_DENSITY = 32.0 / 5.431 ** 3
 # Fluorite UO2 (cations U, anions O); rms thermal displacements are representative
 # 300 K Debye-Waller amplitudes
 UO2 = dict(a=5.470, Z2=92, M2=238.03, sigma=0.050, Z2b=8, M2b=15.999, sigma_b=0.067, structure=FLUORITE)
@@ -60,13 +63,13 @@ class Context:
 
     def __init__(self, a=SILICON["a"], Z2=SILICON["Z2"], M2=SILICON["M2"], sigma=SILICON["sigma"],
                  pot_mode=POT_ZBL, s=1.0, stop_mode=STOP_LOCAL, k=1.0, structure=DIAMOND,
-                 Z2b=0, M2b=0.0, sigma_b=0.0):
+                 Z2b=0, M2b=0.0, sigma_b=0.0, n_e=0.0):
         L = _abi.load()
         self._lib = L
         lat = _abi.Lattice(a=a, M2=M2, sigma=sigma, Z2=Z2, structure=structure, M2b=M2b,
                            sigma_b=sigma_b, Z2b=Z2b)
         pot = _abi.Potential(mode=pot_mode, s=s)
-        stp = _abi.Stopping(mode=stop_mode, k=k)
+        stp = _abi.Stopping(mode=stop_mode, k=k, n_e=n_e)
         h = C.c_void_p()
         rc = L.reedmd_create(C.byref(lat), C.byref(pot), C.byref(stp), C.byref(h))
         if rc != 0:

@@ -15,7 +15,7 @@ DIAMOND, FLUORITE = 0, 1
 RANGE_DEPTH, RANGE_RADIAL = 0, 1
 START_SURFACE, START_SITE = 0, 1
 POT_ZBL, POT_NONE = 0, 1
-STOP_OFF, STOP_UNIFORM, STOP_LOCAL = 0, 1, 2
+STOP_OFF, STOP_UNIFORM, STOP_LOCAL, STOP_FKBK = 0, 1, 2, 3
 FORM_PLAIN, FORM_PERSISTENT = 0, 1
 FORCE_FP64, FORCE_FP32 = 0, 1
 DIR_TILT, DIR_CONE, DIR_MIXED, DIR_ISOTROPIC = 0, 1, 2, 3
@@ -36,7 +36,7 @@ class Potential(C.Structure):
 
 
 class Stopping(C.Structure):
-    _fields_ = [("mode", C.c_int32), ("reserved", C.c_int32), ("k", C.c_double)]
+    _fields_ = [("mode", C.c_int32), ("reserved", C.c_int32), ("k", C.c_double), ("n_e", C.c_double)]
 
 
 class Species(C.Structure):

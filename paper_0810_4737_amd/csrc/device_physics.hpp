@@ -298,10 +298,21 @@ constexpr double kZd0 = 3.19980, kZd1 = 0.94229, kZd2 = 0.40290, kZd3 = 0.20162;
 //   coef: force on the ion is coef * (dx,dy,dz) (the atom feels the opposite),
 //         coef = -V'(r) / r = zz (phi(r/a) / r + (-phi'(r/a)) / a) / r^2
 //         with V = zz phi(r/a) / r;
-//   ew:   exp(-r/lambda), the density weight without its normalisation.
+//   ew:   exp(-r/lambda), the density weight without its normalisation; with
+//         FK (Firsov local loss) Firsov's kernel shape 1 / (1 + b r)^5, b in
+//         c.lam2, taken as 0 beyond kFirsovRange.
 // An empty slot sits at the parking distance, where every exponential is 0 and
 // so are coef and ew.
-template <class PC>
+constexpr double kFirsovRange = 1.0e3;   // A; every domain atom is within 30 A, parked slots beyond 1e4 A
+__device__ __forceinline__ double firsov_shape(double r, double b)
+{
+    const double t = fma(b, r, 1.0);
+    const double t2 = t * t;
+    const double w = 1.0 / (t2 * t2 * t);
+    return r < kFirsovRange ? w : 0.0;
+}
+
+template <bool FK = false, class PC>
 __device__ __forceinline__ void zbl_pair(const PC& c, double dx, double dy, double dz, double& coef, double& ew)
 {
     const double r2 = dx * dx + dy * dy + dz * dz;
@@ -314,7 +325,39 @@ __device__ __forceinline__ void zbl_pair(const PC& c, double dx, double dy, doub
     const double phi = c.amp[0] * e0 + c.amp[1] * e1 + c.amp[2] * e2 + c.amp[3] * e3;
     const double dphi = c.damp[0] * e0 + c.damp[1] * e1 + c.damp[2] * e2 + c.damp[3] * e3;
     coef = fma(phi, inv_r, dphi) * (inv_r * inv_r);
-    ew = exp2_neg_pair(r, c.lam2);
+    if constexpr (FK) ew = firsov_shape(r, c.lam2);
+    else ew = exp2_neg_pair(r, c.lam2);
+}
+
+// Brandt-Kitagawa friction of the ion at speed squared v2 (sqrt(eV/amu))^2:
+// pref zeta^2 with pref = k Z1^2 gamma_p (the slow-proton friction of the
+// electron gas), zeta the effective-charge fraction in atomic units,
+//   zeta = q + (1 - q) / (2 vF^2) ln(1 + (2 Lambda vF)^2),
+//   Lambda = 0.48 (1-q)^(2/3) / (Z1^(1/3) (1 - (1-q)/7)),
+//   q = 1 - exp(0.803 y^0.3 - 1.3167 y^0.6 - 0.38157 y - 0.008983 y^2) in [0, 1],
+//   y = v_r / Z1^(2/3), v_r = v (1 + vF^2 / (5 v^2)) (v >= vF),
+//   (3 vF / 4)(1 + 2 v^2 / (3 vF^2) - v^4 / (15 vF^4)) (v < vF)
+// (Brandt and Kitagawa 1982; q from the Ziegler-Biersack-Littmark fit).
+__device__ __noinline__ double bk_friction(double v2, double pref, double z13, double vF, double inv_vunit)
+{
+    const double u = sqrt(v2) * inv_vunit;
+    const double vF2 = vF * vF;
+    double vr;
+    if (u >= vF) {
+        vr = u * (1.0 + vF2 / (5.0 * u * u));
+    } else {
+        const double s = u * u / vF2;
+        vr = 0.75 * vF * (1.0 + (2.0 / 3.0) * s - s * s / 15.0);
+    }
+    const double y = vr / (z13 * z13);
+    const double y3 = pow(y, 0.3);
+    double q = 1.0 - exp(0.803 * y3 - 1.3167 * y3 * y3 - 0.38157 * y - 0.008983 * y * y);
+    q = fmin(fmax(q, 0.0), 1.0);
+    const double nb = 1.0 - q;
+    const double lam = 0.48 * cbrt(nb * nb) / (z13 * (1.0 - nb / 7.0));
+    const double a = 2.0 * lam * vF;
+    const double zeta = q + nb / (2.0 * vF2) * log1p(a * a);
+    return pref * zeta * zeta;
 }
 
 // FP32 variant of the pair term (force precision option; tolerance 1e-5

@@ -30,6 +30,22 @@ namespace {
 
 constexpr double kCoulomb = 14.3996454784;   // e^2 / (4 pi eps0), eV A (CODATA 2018)
 constexpr double kBohr = 0.529177210903;     // A
+constexpr double kHartree = 27.211386245988;  // eV (CODATA 2018)
+constexpr double kAuVelocity = 2.18769126364e6;   // atomic unit of velocity, m/s (CODATA 2018)
+// The velocity unit of the library, sqrt(eV/amu), in m/s (eV and amu of CODATA 2018).
+const double kVelocityUnit = std::sqrt(1.602176634e-19 / 1.66053906660e-27);
+
+// Friction coefficient of a slow proton in an electron gas of density n_e (electrons
+// per A^3), Ritchie (1959): 2 / (3 pi) [ln(1 + pi / (alpha rs)) - 1 / (1 + alpha rs / pi)]
+// in atomic units, alpha = (4 / (9 pi))^(1/3), rs the Wigner-Seitz radius in bohr;
+// returned in eV / A per sqrt(eV/amu).
+double bk_proton_friction(double n_e)
+{
+    const double rs = std::cbrt(3.0 / (4.0 * M_PI * n_e * kBohr * kBohr * kBohr));
+    const double alpha = std::cbrt(4.0 / (9.0 * M_PI));
+    const double g_au = 2.0 / (3.0 * M_PI) * (std::log(1.0 + M_PI / (alpha * rs)) - 1.0 / (1.0 + alpha * rs / M_PI));
+    return g_au * (kHartree / kBohr) / (kAuVelocity / kVelocityUnit);
+}
 constexpr int kBlock = 256;                  // 4 wavefronts per workgroup
 constexpr long long kDefaultMaxSteps = 2000000;   // step cap when the caller sets none
 constexpr double kMinScreening = 0.01;         // accepted range of the screening-length scale s:
@@ -190,6 +206,26 @@ void prepare_species(const reedmd_ctx* ctx, const reedmd_species* sp, KernelArgs
             c.g_rho = ctx->stop.k * gamma0 / N;
             c.dg_rho = gamma0 / N;
         }
+        if (ctx->stop.mode == REEDMD_STOP_FKBK) {
+            // Firsov: the density weight becomes the kernel C 3 b^3 / (pi (1 + b r)^5) with
+            // C = 0.3254 (Z1+Z2) / sqrt(2) (Firsov's cross-section over the speed); b rides in lam2
+            auto firsov = [&](double Z2, double& b, double& norm) {
+                b = 0.31 * std::cbrt(Z1 + Z2);
+                norm = 0.3254 * (Z1 + Z2) / std::sqrt(2.0) * 3.0 * b * b * b / M_PI;
+            };
+            firsov(ctx->lat.Z2, c.lam2, c.wnorm);
+            if (fl) firsov(ctx->lat.Z2b, c2.lam2, c2.wnorm);
+            c.g_rho = ctx->stop.k;
+            c.dg_rho = 1.0;
+            // Brandt-Kitagawa: k Z1^2 gamma_p, gamma_p the slow-proton friction of the electron gas
+            A.bk_z13[i] = std::cbrt(Z1);
+            A.bk_pref[i] = ctx->stop.n_e > 0.0 ? ctx->stop.k * Z1 * Z1 * bk_proton_friction(ctx->stop.n_e) : 0.0;
+        }
+    }
+    if (ctx->stop.mode == REEDMD_STOP_FKBK && ctx->stop.n_e > 0.0) {
+        const double n_au = ctx->stop.n_e * kBohr * kBohr * kBohr;
+        A.bk_vF = std::cbrt(9.0 * M_PI / 4.0) / std::cbrt(3.0 / (4.0 * M_PI * n_au));
+        A.bk_inv_vunit = kVelocityUnit / kAuVelocity;
     }
     // Empty slots are parked where the slowest exponential of every species in use
     // is below e^-1000, so their pair terms are exactly zero (at least 1 um away).
@@ -197,6 +233,13 @@ void prepare_species(const reedmd_ctx* ctx, const reedmd_species* sp, KernelArgs
 }
 
 int lattice_of(const reedmd_ctx* ctx) { return ctx->lat.structure == REEDMD_FLUORITE ? kFluorite : kDiamond; }
+
+// Pass variant of the track kernels for an interaction set (resolved r_cut) and the
+// context's stopping model.
+int pass_variant(const reedmd_ctx* ctx, double r_cut)
+{
+    return (r_cut > 0.0 ? kVarCut : 0) | (ctx->stop.mode == REEDMD_STOP_FKBK ? kVarFirsov : 0);
+}
 size_t record_words(const reedmd_ctx* ctx)
 {
     return lattice_of(ctx) == kFluorite ? Lattice<kFluorite>::kRecWords : Lattice<kDiamond>::kRecWords;
@@ -220,6 +263,8 @@ reedmd_status check_params(reedmd_ctx* ctx, const reedmd_run_params* p, bool nee
         return fail(ctx, REEDMD_EINVAL, "r_cut < 0 (the domain autotuner's choice) is resolved by the run entry points only");
     if (p->r_cut > 0.0 && (lattice_of(ctx) != kDiamond || p->force_precision != REEDMD_FORCE_FP64))
         return fail(ctx, REEDMD_EUNSUPPORTED, "the interaction cut-off is built for the diamond target with FP64 forces");
+    if (ctx->stop.mode == REEDMD_STOP_FKBK && (p->force_precision != REEDMD_FORCE_FP64 || p->r_cut > 0.0))
+        return fail(ctx, REEDMD_EUNSUPPORTED, "the Firsov + Brandt-Kitagawa stopping runs with FP64 pair terms and the 27 cells");
     if (p->range_mode != REEDMD_RANGE_DEPTH && p->range_mode != REEDMD_RANGE_RADIAL)
         return fail(ctx, REEDMD_EINVAL, "range_mode must be REEDMD_RANGE_DEPTH or REEDMD_RANGE_RADIAL");
     if (p->vacancy != 0 && p->vacancy != 1) return fail(ctx, REEDMD_EINVAL, "vacancy must be 0 or 1");
@@ -306,138 +351,80 @@ void fill_batch(const reedmd_batch* b, KernelArgs& A)
 }
 
 // Kernel variants: lanes per track (64, 32, 16; fluorite 64, 32) x form x
-// pair-term precision x target structure.
-template <int MODE, bool F32, int LAT>
+// pair-term precision x target structure x pass variant (kVarCut: diamond with
+// FP64 pair terms; kVarFirsov: FP64 pair terms).
+template <int MODE, bool F32, int LAT, int VAR>
 const void* track_ptr_l(int L)
 {
-    if (L == 64) return reinterpret_cast<const void*>(&track_kernel<64, MODE, F32, LAT>);
+    if (L == 64) return reinterpret_cast<const void*>(&track_kernel<64, MODE, F32, LAT, VAR>);
     if constexpr (LAT == kFluorite) {
-        return reinterpret_cast<const void*>(&track_kernel<32, MODE, F32, LAT>);
+        return reinterpret_cast<const void*>(&track_kernel<32, MODE, F32, LAT, VAR>);
     } else {
-        if (L == 32) return reinterpret_cast<const void*>(&track_kernel<32, MODE, F32, LAT>);
-        return reinterpret_cast<const void*>(&track_kernel<16, MODE, F32, LAT>);
+        if (L == 32) return reinterpret_cast<const void*>(&track_kernel<32, MODE, F32, LAT, VAR>);
+        return reinterpret_cast<const void*>(&track_kernel<16, MODE, F32, LAT, VAR>);
     }
 }
 
-// Kernels with the interaction cut-off (diamond, FP64 pair terms).
 template <int MODE>
-const void* cut_track_ptr(int L)
+const void* track_ptr_m(int L, bool f32, int lat, int var)
 {
-    if (L == 64) return reinterpret_cast<const void*>(&track_kernel<64, MODE, false, kDiamond, true>);
-    if (L == 32) return reinterpret_cast<const void*>(&track_kernel<32, MODE, false, kDiamond, true>);
-    return reinterpret_cast<const void*>(&track_kernel<16, MODE, false, kDiamond, true>);
+    if (var == kVarCut) return track_ptr_l<MODE, false, kDiamond, kVarCut>(L);
+    if (var == kVarFirsov)
+        return lat == kFluorite ? track_ptr_l<MODE, false, kFluorite, kVarFirsov>(L)
+                                : track_ptr_l<MODE, false, kDiamond, kVarFirsov>(L);
+    if (lat == kFluorite)
+        return f32 ? track_ptr_l<MODE, true, kFluorite, 0>(L) : track_ptr_l<MODE, false, kFluorite, 0>(L);
+    return f32 ? track_ptr_l<MODE, true, kDiamond, 0>(L) : track_ptr_l<MODE, false, kDiamond, 0>(L);
 }
 
 // The track kernel of a launch shape (launches and graph nodes take the function itself).
-const void* track_kernel_ptr(int L, int mode, bool f32, int lat, bool cut)
+const void* track_kernel_ptr(int L, int mode, bool f32, int lat, int var)
 {
-    if (cut) return mode == kModePlain ? cut_track_ptr<kModePlain>(L) : cut_track_ptr<kModePersistent>(L);
-    if (mode == kModePlain) {
-        if (lat == kFluorite)
-            return f32 ? track_ptr_l<kModePlain, true, kFluorite>(L) : track_ptr_l<kModePlain, false, kFluorite>(L);
-        return f32 ? track_ptr_l<kModePlain, true, kDiamond>(L) : track_ptr_l<kModePlain, false, kDiamond>(L);
-    }
-    if (lat == kFluorite)
-        return f32 ? track_ptr_l<kModePersistent, true, kFluorite>(L) : track_ptr_l<kModePersistent, false, kFluorite>(L);
-    return f32 ? track_ptr_l<kModePersistent, true, kDiamond>(L) : track_ptr_l<kModePersistent, false, kDiamond>(L);
+    return mode == kModePlain ? track_ptr_m<kModePlain>(L, f32, lat, var) : track_ptr_m<kModePersistent>(L, f32, lat, var);
 }
 
-template <int MODE, bool F32, int LAT>
-int occupancy_l(int L)
+int resident_blocks_per_cu(int L, int mode, bool f32, int lat, int var)
 {
     int nb = 0;
-    hipError_t e = hipSuccess;
-    if (L == 64) {
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, track_kernel<64, MODE, F32, LAT>, kBlock, 0);
-    } else if constexpr (LAT == kFluorite) {
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, track_kernel<32, MODE, F32, LAT>, kBlock, 0);
-    } else {
-        if (L == 32) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, track_kernel<32, MODE, F32, LAT>, kBlock, 0);
-        else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, track_kernel<16, MODE, F32, LAT>, kBlock, 0);
-    }
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, track_kernel_ptr(L, mode, f32, lat, var), kBlock, 0);
     return (e != hipSuccess || nb < 1) ? 1 : nb;
 }
 
-template <int LAT>
-int resident_blocks_lat(int L, int mode, bool f32)
+// The debug kernels (starting records, steps without events) of a variant.
+template <bool INIT, bool F32, int LAT, int VAR>
+const void* aux_ptr_l(int L)
 {
-    if (mode == kModePlain) return f32 ? occupancy_l<kModePlain, true, LAT>(L) : occupancy_l<kModePlain, false, LAT>(L);
-    return f32 ? occupancy_l<kModePersistent, true, LAT>(L) : occupancy_l<kModePersistent, false, LAT>(L);
-}
-
-int resident_blocks_per_cu(int L, int mode, bool f32, int lat, bool cut = false)
-{
-    if (cut) {
-        int nb = 0;
-        const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, track_kernel_ptr(L, mode, false, kDiamond, true),
-                                                                          kBlock, 0);
-        return (e != hipSuccess || nb < 1) ? 1 : nb;
-    }
-    return lat == kFluorite ? resident_blocks_lat<kFluorite>(L, mode, f32) : resident_blocks_lat<kDiamond>(L, mode, f32);
-}
-
-template <bool F32, int LAT>
-void launch_init_l(int L, const KernelArgs& A, long long blocks, hipStream_t s)
-{
-    const dim3 g(static_cast<unsigned>(blocks)), b(kBlock);
-    if (L == 64) {
-        hipLaunchKernelGGL((init_kernel<64, F32, LAT>), g, b, 0, s, A);
-    } else if constexpr (LAT == kFluorite) {
-        hipLaunchKernelGGL((init_kernel<32, F32, LAT>), g, b, 0, s, A);
+    if (L == 64)
+        return INIT ? reinterpret_cast<const void*>(&init_kernel<64, F32, LAT, VAR>)
+                    : reinterpret_cast<const void*>(&step_kernel<64, F32, LAT, VAR>);
+    if constexpr (LAT == kFluorite) {
+        return INIT ? reinterpret_cast<const void*>(&init_kernel<32, F32, LAT, VAR>)
+                    : reinterpret_cast<const void*>(&step_kernel<32, F32, LAT, VAR>);
     } else {
-        if (L == 32) hipLaunchKernelGGL((init_kernel<32, F32, LAT>), g, b, 0, s, A);
-        else hipLaunchKernelGGL((init_kernel<16, F32, LAT>), g, b, 0, s, A);
+        if (L == 32)
+            return INIT ? reinterpret_cast<const void*>(&init_kernel<32, F32, LAT, VAR>)
+                        : reinterpret_cast<const void*>(&step_kernel<32, F32, LAT, VAR>);
+        return INIT ? reinterpret_cast<const void*>(&init_kernel<16, F32, LAT, VAR>)
+                    : reinterpret_cast<const void*>(&step_kernel<16, F32, LAT, VAR>);
     }
 }
 
-template <bool F32, int LAT>
-void launch_step_l(int L, const KernelArgs& A, long long blocks, hipStream_t s)
+template <bool INIT>
+const void* aux_ptr(int L, bool f32, int lat, int var)
 {
-    const dim3 g(static_cast<unsigned>(blocks)), b(kBlock);
-    if (L == 64) {
-        hipLaunchKernelGGL((step_kernel<64, F32, LAT>), g, b, 0, s, A);
-    } else if constexpr (LAT == kFluorite) {
-        hipLaunchKernelGGL((step_kernel<32, F32, LAT>), g, b, 0, s, A);
-    } else {
-        if (L == 32) hipLaunchKernelGGL((step_kernel<32, F32, LAT>), g, b, 0, s, A);
-        else hipLaunchKernelGGL((step_kernel<16, F32, LAT>), g, b, 0, s, A);
-    }
+    if (var == kVarCut) return aux_ptr_l<INIT, false, kDiamond, kVarCut>(L);
+    if (var == kVarFirsov)
+        return lat == kFluorite ? aux_ptr_l<INIT, false, kFluorite, kVarFirsov>(L)
+                                : aux_ptr_l<INIT, false, kDiamond, kVarFirsov>(L);
+    if (lat == kFluorite) return f32 ? aux_ptr_l<INIT, true, kFluorite, 0>(L) : aux_ptr_l<INIT, false, kFluorite, 0>(L);
+    return f32 ? aux_ptr_l<INIT, true, kDiamond, 0>(L) : aux_ptr_l<INIT, false, kDiamond, 0>(L);
 }
 
-void launch_init_any(int L, bool f32, int lat, bool cut, const KernelArgs& A, long long blocks, hipStream_t s)
+hipError_t launch_aux(bool init, int L, bool f32, int lat, int var, const KernelArgs& A, long long blocks, hipStream_t s)
 {
-    if (cut) {
-        const dim3 g(static_cast<unsigned>(blocks)), b(kBlock);
-        if (L == 64) hipLaunchKernelGGL((init_kernel<64, false, kDiamond, true>), g, b, 0, s, A);
-        else if (L == 32) hipLaunchKernelGGL((init_kernel<32, false, kDiamond, true>), g, b, 0, s, A);
-        else hipLaunchKernelGGL((init_kernel<16, false, kDiamond, true>), g, b, 0, s, A);
-        return;
-    }
-    if (lat == kFluorite) {
-        if (f32) launch_init_l<true, kFluorite>(L, A, blocks, s);
-        else launch_init_l<false, kFluorite>(L, A, blocks, s);
-    } else {
-        if (f32) launch_init_l<true, kDiamond>(L, A, blocks, s);
-        else launch_init_l<false, kDiamond>(L, A, blocks, s);
-    }
-}
-
-void launch_step_any(int L, bool f32, int lat, bool cut, const KernelArgs& A, long long blocks, hipStream_t s)
-{
-    if (cut) {
-        const dim3 g(static_cast<unsigned>(blocks)), b(kBlock);
-        if (L == 64) hipLaunchKernelGGL((step_kernel<64, false, kDiamond, true>), g, b, 0, s, A);
-        else if (L == 32) hipLaunchKernelGGL((step_kernel<32, false, kDiamond, true>), g, b, 0, s, A);
-        else hipLaunchKernelGGL((step_kernel<16, false, kDiamond, true>), g, b, 0, s, A);
-        return;
-    }
-    if (lat == kFluorite) {
-        if (f32) launch_step_l<true, kFluorite>(L, A, blocks, s);
-        else launch_step_l<false, kFluorite>(L, A, blocks, s);
-    } else {
-        if (f32) launch_step_l<true, kDiamond>(L, A, blocks, s);
-        else launch_step_l<false, kDiamond>(L, A, blocks, s);
-    }
+    void* args[] = {const_cast<KernelArgs*>(&A)};
+    const void* f = init ? aux_ptr<true>(L, f32, lat, var) : aux_ptr<false>(L, f32, lat, var);
+    return hipLaunchKernel(f, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), args, 0, s);
 }
 
 constexpr int kOrderBuckets = 512;
@@ -743,7 +730,7 @@ struct Shape {
     long long tail_blocks;
     long long tail_segs;
     double r_cut;   // interaction set after the autotune cache: 0 = the 27 cells
-    bool cut;
+    int var;        // pass variant of the track kernel (kVarCut, kVarFirsov)
 };
 
 Shape choose_shape(reedmd_ctx* ctx, const reedmd_run_params* p, const reedmd_batch* b)
@@ -768,7 +755,7 @@ Shape choose_shape(reedmd_ctx* ctx, const reedmd_run_params* p, const reedmd_bat
         auto it = ctx->tune.find(tune_key(p, b));
         if (it != ctx->tune.end()) s.r_cut = it->second.r_cut;
     }
-    s.cut = s.r_cut > 0.0;
+    s.var = pass_variant(ctx, s.r_cut);
     const int T = 64 / L;
     const int per_wave_block = kBlock / 64;
     s.stack_cap = p->n_thresh > 0 ? p->n_thresh * (std::max(p->n_clones, 2) - 1) + 1 : 0;
@@ -779,7 +766,7 @@ Shape choose_shape(reedmd_ctx* ctx, const reedmd_run_params* p, const reedmd_bat
         s.blocks = (waves_needed + per_wave_block - 1) / per_wave_block;
         s.qcap = 0;
     } else {
-        int bpc = resident_blocks_per_cu(L, s.mode, s.f32, lattice_of(ctx), s.cut);
+        int bpc = resident_blocks_per_cu(L, s.mode, s.f32, lattice_of(ctx), s.var);
         if (waves > 0) bpc = std::max(1, std::min(bpc, (waves + per_wave_block - 1) / per_wave_block));
         s.blocks = static_cast<long long>(bpc) * ctx->cu_count;
         s.seg_total = s.blocks * per_wave_block * T;
@@ -788,7 +775,7 @@ Shape choose_shape(reedmd_ctx* ctx, const reedmd_run_params* p, const reedmd_bat
         s.qcap = p->queue_capacity > 0 ? p->queue_capacity
                                        : static_cast<int>(std::min<long long>(kMaxQueue, std::max<long long>(4096, 4 * b->n)));
         if (L < 64 && p->no_tail_handoff == 0) {
-            s.tail_blocks = static_cast<long long>(resident_blocks_per_cu(64, s.mode, s.f32, lattice_of(ctx), s.cut)) * ctx->cu_count;
+            s.tail_blocks = static_cast<long long>(resident_blocks_per_cu(64, s.mode, s.f32, lattice_of(ctx), s.var)) * ctx->cu_count;
             s.tail_segs = s.tail_blocks * per_wave_block;
         }
         if (p->n_thresh == 0 && s.tail_blocks == 0) s.qcap = 1;
@@ -865,8 +852,8 @@ reedmd_status run_impl(reedmd_ctx* ctx, const reedmd_species* sp, const reedmd_b
                             reinterpret_cast<const void*>(order_count_kernel),
                             reinterpret_cast<const void*>(order_scan_kernel),
                             reinterpret_cast<const void*>(order_scatter_kernel),
-                            track_kernel_ptr(s.L, s.mode, s.f32, lattice_of(ctx), s.cut),
-                            track_kernel_ptr(64, s.mode, s.f32, lattice_of(ctx), s.cut),
+                            track_kernel_ptr(s.L, s.mode, s.f32, lattice_of(ctx), s.var),
+                            track_kernel_ptr(64, s.mode, s.f32, lattice_of(ctx), s.var),
                             reinterpret_cast<const void*>(stats_finalize_kernel)};
     dim3 grids[7] = {dim3((qcap + 255) / 256), dim3(kOrderBlocks), dim3(1), dim3(kOrderBlocks),
                      dim3(static_cast<unsigned>(s.blocks)), dim3(static_cast<unsigned>(std::max(s.tail_blocks, 1ll))), dim3(1)};
@@ -897,7 +884,7 @@ reedmd_status run_impl(reedmd_ctx* ctx, const reedmd_species* sp, const reedmd_b
             HIP_TRY(ctx, hipLaunchKernel(np[k].func, np[k].gridDim, np[k].blockDim, np[k].kernelParams, 0, stream));
         return REEDMD_OK;
     }
-    const std::vector<long long> key = {s.L, s.f32 ? 1 : 0, lattice_of(ctx), s.blocks, qcap, s.tail_blocks, s.cut ? 1 : 0};
+    const std::vector<long long> key = {s.L, s.f32 ? 1 : 0, lattice_of(ctx), s.blocks, qcap, s.tail_blocks, s.var};
     auto it = ctx->graphs.find(key);
     if (it == ctx->graphs.end()) {
         if (ctx->graphs.size() >= kMaxGraphs) drop_graphs(ctx);
@@ -1066,8 +1053,10 @@ reedmd_status reedmd_create(const reedmd_lattice* lattice, const reedmd_potentia
         return fail(nullptr, REEDMD_EINVAL, "unknown potential mode");
     if (!(potential->s >= kMinScreening && potential->s <= kMaxScreening))
         return fail(nullptr, REEDMD_EINVAL, "screening scale s must be in [0.01, 100]");
-    if (stopping->mode < REEDMD_STOP_OFF || stopping->mode > REEDMD_STOP_LOCAL || !(stopping->k >= 0.0))
+    if (stopping->mode < REEDMD_STOP_OFF || stopping->mode > REEDMD_STOP_FKBK || !(stopping->k >= 0.0))
         return fail(nullptr, REEDMD_EINVAL, "unknown stopping mode or negative k");
+    if (!(stopping->n_e >= 0.0) || !std::isfinite(stopping->n_e))
+        return fail(nullptr, REEDMD_EINVAL, "the electron density n_e must be finite and >= 0");
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return fail(nullptr, REEDMD_EHIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
@@ -1241,7 +1230,7 @@ reedmd_status reedmd_run_noalloc(reedmd_ctx* ctx, const reedmd_species* species,
     hipLaunchKernelGGL(order_scatter_kernel, dim3(kOrderBlocks), dim3(64), 0, stream, O);
     HIP_TRY(ctx, hipGetLastError());
     void* track_args[] = {&A};
-    HIP_TRY(ctx, hipLaunchKernel(track_kernel_ptr(s.L, s.mode, s.f32, lattice_of(ctx), s.cut), dim3(static_cast<unsigned>(s.blocks)),
+    HIP_TRY(ctx, hipLaunchKernel(track_kernel_ptr(s.L, s.mode, s.f32, lattice_of(ctx), s.var), dim3(static_cast<unsigned>(s.blocks)),
                                  dim3(kBlock), track_args, 0, stream));
     hipLaunchKernelGGL(stats_finalize_kernel, dim3(1), dim3(64), 0, stream, A.q, d_stats);
     HIP_TRY(ctx, hipGetLastError());
@@ -1265,7 +1254,8 @@ reedmd_status reedmd_track_init(reedmd_ctx* ctx, const reedmd_species* species, 
     const int L = params->lanes_per_track ? params->lanes_per_track : 64;
     const long long waves = (batch->n + (64 / L) - 1) / (64 / L);
     const long long blocks = (waves + 3) / 4;
-    launch_init_any(L, params->force_precision == REEDMD_FORCE_FP32, lattice_of(ctx), params->r_cut > 0.0, A, blocks, stream);
+    HIP_TRY(ctx, launch_aux(true, L, params->force_precision == REEDMD_FORCE_FP32, lattice_of(ctx),
+                            pass_variant(ctx, params->r_cut), A, blocks, stream));
     HIP_TRY(ctx, hipGetLastError());
     return REEDMD_OK;
 }
@@ -1288,7 +1278,8 @@ reedmd_status reedmd_debug_step(reedmd_ctx* ctx, const reedmd_species* species, 
     const int L = params->lanes_per_track ? params->lanes_per_track : 64;
     const long long waves = (n + (64 / L) - 1) / (64 / L);
     const long long blocks = (waves + 3) / 4;
-    launch_step_any(L, params->force_precision == REEDMD_FORCE_FP32, lattice_of(ctx), params->r_cut > 0.0, A, blocks, stream);
+    HIP_TRY(ctx, launch_aux(false, L, params->force_precision == REEDMD_FORCE_FP32, lattice_of(ctx),
+                            pass_variant(ctx, params->r_cut), A, blocks, stream));
     HIP_TRY(ctx, hipGetLastError());
     return REEDMD_OK;
 }
@@ -1305,6 +1296,8 @@ reedmd_status reedmd_grad(reedmd_ctx* ctx, const reedmd_species* species, const 
     if (!h_result) return fail(ctx, REEDMD_EINVAL, "h_result is NULL");
     if (params->n_thresh != 0) return fail(ctx, REEDMD_EUNSUPPORTED, "the gradient is defined without cloning (n_thresh = 0)");
     if (params->r_cut != 0.0) return fail(ctx, REEDMD_EUNSUPPORTED, "the adjoint covers the 27-cell interaction set (r_cut = 0)");
+    if (ctx->stop.mode == REEDMD_STOP_FKBK)
+        return fail(ctx, REEDMD_EUNSUPPORTED, "the adjoint covers the OFF, UNIFORM and LOCAL stopping models");
     if (params->force_precision != REEDMD_FORCE_FP64)
         return fail(ctx, REEDMD_EUNSUPPORTED, "the adjoint is FP64 only (force_precision = REEDMD_FORCE_FP64)");
     if (lattice_of(ctx) != kDiamond || params->range_mode != REEDMD_RANGE_DEPTH || params->vacancy != 0)
@@ -1428,9 +1421,9 @@ reedmd_status reedmd_autotune(reedmd_ctx* ctx, const reedmd_species* species, co
     for (int li = 0; li < 3 && st == REEDMD_OK; ++li) {
         // persistent form: the occupancy-sized grid and one workgroup per CU fewer
         if (lattice_of(ctx) == kFluorite && lanes[li] == 16) continue;
-        const bool cut = p.r_cut > 0.0;
+        const int var = pass_variant(ctx, p.r_cut);
         const int occ = resident_blocks_per_cu(lanes[li], persistent ? kModePersistent : kModePlain,
-                                               params->force_precision == REEDMD_FORCE_FP32, lattice_of(ctx), cut);
+                                               params->force_precision == REEDMD_FORCE_FP32, lattice_of(ctx), var);
         const int nw = (persistent && occ > 1) ? 2 : 1;
         for (int wi = 0; wi < nw && st == REEDMD_OK; ++wi) {
             p.lanes_per_track = lanes[li];
@@ -1499,8 +1492,10 @@ reedmd_status reedmd_autotune_domain(reedmd_ctx* ctx, const reedmd_species* spec
             return fail(ctx, REEDMD_EINVAL, "candidates must be finite and >= 0 (0 = the 27 cells)");
         any_cut |= candidates[c] > 0.0;
     }
-    if (any_cut && (lattice_of(ctx) != kDiamond || params->force_precision != REEDMD_FORCE_FP64))
-        return fail(ctx, REEDMD_EUNSUPPORTED, "the interaction cut-off is built for the diamond target with FP64 forces");
+    if (any_cut && (lattice_of(ctx) != kDiamond || params->force_precision != REEDMD_FORCE_FP64 ||
+                    ctx->stop.mode == REEDMD_STOP_FKBK))
+        return fail(ctx, REEDMD_EUNSUPPORTED, "the interaction cut-off is built for the diamond target with FP64 forces "
+                                              "and the Lindhard-Scharff stopping");
     if (pilot <= 0) return fail(ctx, REEDMD_EINVAL, "pilot must be positive");
     if (!(gate_p >= 0.0 && gate_p < 1.0) || !(gate_rel >= 0.0) || !std::isfinite(gate_rel))
         return fail(ctx, REEDMD_EINVAL, "need gate_p in [0, 1) and gate_rel >= 0");
@@ -1722,7 +1717,7 @@ reedmd_status reedmd_launch_shape(reedmd_ctx* ctx, const reedmd_batch* batch, co
     out[0] = s.L;
     out[1] = s.blocks;
     out[2] = s.seg_total;
-    out[3] = resident_blocks_per_cu(s.L, s.mode, s.f32, lattice_of(ctx), s.cut);
+    out[3] = resident_blocks_per_cu(s.L, s.mode, s.f32, lattice_of(ctx), s.var);
     out[4] = s.mode == kModePersistent ? s.qcap : 0;
     return REEDMD_OK;
 }

@@ -85,6 +85,12 @@ struct KernelArgs {
     double* qrec;
     const int* cancel;
     double rc2;             // interaction cut-off squared (A^2); 0: every atom of the 27 cells
+    // Firsov + Brandt-Kitagawa stopping: per species k Z1^2 gamma_p (0: no Brandt-Kitagawa
+    // term) and Z1^(1/3); the electron gas's Fermi speed (atomic units) and the inverse of the
+    // atomic velocity unit in sqrt(eV/amu)
+    double bk_pref[kMaxSpecies];
+    double bk_z13[kMaxSpecies];
+    double bk_vF, bk_inv_vunit;
     const int* order;       // optional: batch entry of the i-th claimed primary (longest expected first)
     long long seg_total;
     // tail handoff (persistent form with fewer than 64 lanes per track): once every primary
@@ -460,13 +466,21 @@ struct StepInfo {
 // primary).  Returns the kinetic energy before the step via ke0, and the
 // step's size via info when given, and the atoms a domain move drops via drop
 // when given (see regenerate).
-template <int L, bool F32 = false, int LAT = kDiamond, bool CUT = false>
+// Variants of the pair pass: bit 0, the interaction cut-off (compacted list);
+// bit 1, the Firsov + Brandt-Kitagawa stopping (Firsov kernel instead of the
+// exponential density weight, and the speed-dependent Brandt-Kitagawa friction).
+constexpr int kVarCut = 1, kVarFirsov = 2;
+
+template <int L, bool F32 = false, int LAT = kDiamond, int VAR = 0>
 __device__ __forceinline__ void track_step(TrackRegs<L, LAT>& t, const KernelArgs& A, const SpeciesConst* sp, int sl,
                                            bool fresh, double& ke0, double& z0, StepInfo* info = nullptr,
                                            double* drop = nullptr)
 {
     constexpr int FS = TrackRegs<L, LAT>::FS;
     constexpr bool FL = LAT == kFluorite;
+    constexpr bool CUT = (VAR & kVarCut) != 0;
+    constexpr bool FK = (VAR & kVarFirsov) != 0;
+    static_assert(!(FK && F32), "the Firsov stopping variant has FP64 pair terms");
     const SpeciesConst& c = sp[t.species];
     const PairConst& c1 = pair_table2(sp)[t.species];
     const double M1 = c.M1;
@@ -489,7 +503,12 @@ __device__ __forceinline__ void track_step(TrackRegs<L, LAT>& t, const KernelArg
     z0 = range_coord(t, A.range_mode);
 
     const double h1 = dt * c.half_inv_M1;
-    const double fr1 = exp_neg((c.g_const + c.g_rho * t.rho) * h1);
+    double g1 = c.g_const + c.g_rho * t.rho;
+    if constexpr (FK) {
+        const double pref = A.bk_pref[t.species];
+        if (pref != 0.0) g1 += bk_friction(v2, pref, A.bk_z13[t.species], A.bk_vF, A.bk_inv_vunit);
+    }
+    const double fr1 = exp_neg(g1 * h1);
     t.vx = t.vx * fr1 + t.Fx * h1;
     t.vy = t.vy * fr1 + t.Fy * h1;
     t.vz = t.vz * fr1 + t.Fz * h1;
@@ -567,7 +586,7 @@ __device__ __forceinline__ void track_step(TrackRegs<L, LAT>& t, const KernelArg
                 dz = t.z - t.fl[2 * FS + s];
             }
             double coef, ew;
-            zbl_pair(c, dx, dy, dz, coef, ew);
+            zbl_pair<FK>(c, dx, dy, dz, coef, ew);
             const double fx = -coef * dx, fy = -coef * dy, fz = -coef * dz;   // force on the atom
             Fx[m] -= fx; Fy[m] -= fy; Fz[m] -= fz;
             rho[m] += ew;
@@ -609,10 +628,10 @@ __device__ __forceinline__ void track_step(TrackRegs<L, LAT>& t, const KernelArg
             double coef, ew;
             if (anion) {
                 if constexpr (F32) zbl_pair_f32(c1, dx, dy, dz, coef, ew);
-                else zbl_pair(c1, dx, dy, dz, coef, ew);
+                else zbl_pair<FK>(c1, dx, dy, dz, coef, ew);
             } else {
                 if constexpr (F32) zbl_pair_f32(c, dx, dy, dz, coef, ew);
-                else zbl_pair(c, dx, dy, dz, coef, ew);
+                else zbl_pair<FK>(c, dx, dy, dz, coef, ew);
             }
             const double fx = -coef * dx, fy = -coef * dy, fz = -coef * dz;   // force on the atom
             Fx[m] -= fx; Fy[m] -= fy; Fz[m] -= fz;
@@ -644,10 +663,20 @@ __device__ __forceinline__ void track_step(TrackRegs<L, LAT>& t, const KernelArg
         t.amax2a = SegReduce<L>::max(fm) * A.inv_M2sq;
     }
 
-    const double fr2 = exp_neg((c.g_const + c.g_rho * t.rho) * h1);
-    t.vx = (t.vx + t.Fx * h1) * fr2;
-    t.vy = (t.vy + t.Fy * h1) * fr2;
-    t.vz = (t.vz + t.Fz * h1) * fr2;
+    // second half kick, then the friction at the kicked speed
+    const double kx = t.vx + t.Fx * h1, ky = t.vy + t.Fy * h1, kz = t.vz + t.Fz * h1;
+    double g2 = c.g_const + c.g_rho * t.rho;
+    if constexpr (FK) {
+        const double pref = A.bk_pref[t.species];
+        if (pref != 0.0) {
+            const double w2 = kx * kx + ky * ky + kz * kz;
+            g2 += bk_friction(w2, pref, A.bk_z13[t.species], A.bk_vF, A.bk_inv_vunit);
+        }
+    }
+    const double fr2 = exp_neg(g2 * h1);
+    t.vx = kx * fr2;
+    t.vy = ky * fr2;
+    t.vz = kz * fr2;
     if (!fresh) t.steps += 1;
 }
 
@@ -944,12 +973,12 @@ __device__ __forceinline__ long long queue_reserve_pop(const KernelArgs& A)
 // from device counters and the clone queue until no track is live).
 enum : int { kSegNeed = 0, kSegRun = 1, kSegDone = 2 };
 
-template <int L, int MODE, bool F32 = false, int LAT = kDiamond, bool CUT = false>
+template <int L, int MODE, bool F32 = false, int LAT = kDiamond, int VAR = 0>
 __global__ void __launch_bounds__(256, REEDMD_WAVES_PER_SIMD(L, LAT)) track_kernel(const KernelArgs A0)
 {
     const KernelArgs& A = A0;
     __shared__ double s_sp[kSpeciesLdsDoubles];
-    __shared__ double s_force[ForceLds<L, LAT, CUT>::kDoubles];
+    __shared__ double s_force[ForceLds<L, LAT, (VAR & kVarCut) != 0>::kDoubles];
     const SpeciesConst* sp = stage_species(A, s_sp);
     const int lane = threadIdx.x & 63;
     const int sl = lane % L;
@@ -960,7 +989,7 @@ __global__ void __launch_bounds__(256, REEDMD_WAVES_PER_SIMD(L, LAT)) track_kern
 
     constexpr int RW = Lattice<LAT>::kRecWords;
     TrackRegs<L, LAT> t;
-    t.fl = force_slab<L, LAT, CUT>(s_force);
+    t.fl = force_slab<L, LAT, (VAR & kVarCut) != 0>(s_force);
     t.cx = t.cy = t.cz = kSentinel;
     t.exist = 0;
     t.n_exist = 0;
@@ -1091,7 +1120,7 @@ __global__ void __launch_bounds__(256, REEDMD_WAVES_PER_SIMD(L, LAT)) track_kern
 
         // ---- one step of a running track ----
         double ke0, z0;
-        track_step<L, F32, LAT, CUT>(t, A, sp, sl, fresh, ke0, z0);
+        track_step<L, F32, LAT, VAR>(t, A, sp, sl, fresh, ke0, z0);
         pairs += t.n_eval;
         if (fresh) {
             fresh = false;
@@ -1200,44 +1229,44 @@ __global__ void __launch_bounds__(256, REEDMD_WAVES_PER_SIMD(L, LAT)) track_kern
 }
 
 // Builds the starting record of every batch entry (debug / parity entry point).
-template <int L, bool F32 = false, int LAT = kDiamond, bool CUT = false>
+template <int L, bool F32 = false, int LAT = kDiamond, int VAR = 0>
 __global__ void __launch_bounds__(256) init_kernel(const KernelArgs A)
 {
     __shared__ double s_sp[kSpeciesLdsDoubles];
-    __shared__ double s_force[ForceLds<L, LAT, CUT>::kDoubles];
+    __shared__ double s_force[ForceLds<L, LAT, (VAR & kVarCut) != 0>::kDoubles];
     const SpeciesConst* sp = stage_species(A, s_sp);
     const int lane = threadIdx.x & 63;
     const int sl = lane % L;
     const long long seg = (static_cast<long long>(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6)) * (64 / L) + lane / L;
     if (seg >= A.n) return;
     TrackRegs<L, LAT> t;
-    t.fl = force_slab<L, LAT, CUT>(s_force);
+    t.fl = force_slab<L, LAT, (VAR & kVarCut) != 0>(s_force);
     t.exist = 0;
     start_primary<L, LAT>(t, A, sp, seg);
     double ke0, z0;
-    if (t.status != REEDMD_LOST) track_step<L, F32, LAT, CUT>(t, A, sp, sl, true, ke0, z0);
+    if (t.status != REEDMD_LOST) track_step<L, F32, LAT, VAR>(t, A, sp, sl, true, ke0, z0);
     store_record<L, LAT>(t, A.records + static_cast<size_t>(seg) * Lattice<LAT>::kRecWords, sl);
 }
 
 // Advances caller records by nsteps steps without events (debug / parity).
-template <int L, bool F32 = false, int LAT = kDiamond, bool CUT = false>
+template <int L, bool F32 = false, int LAT = kDiamond, int VAR = 0>
 __global__ void __launch_bounds__(256, 2) step_kernel(const KernelArgs A)
 {
     __shared__ double s_sp[kSpeciesLdsDoubles];
-    __shared__ double s_force[ForceLds<L, LAT, CUT>::kDoubles];
+    __shared__ double s_force[ForceLds<L, LAT, (VAR & kVarCut) != 0>::kDoubles];
     const SpeciesConst* sp = stage_species(A, s_sp);
     const int lane = threadIdx.x & 63;
     const int sl = lane % L;
     const long long seg = (static_cast<long long>(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6)) * (64 / L) + lane / L;
     if (seg >= A.n) return;
     TrackRegs<L, LAT> t;
-    t.fl = force_slab<L, LAT, CUT>(s_force);
+    t.fl = force_slab<L, LAT, (VAR & kVarCut) != 0>(s_force);
     double* rec = A.records + static_cast<size_t>(seg) * Lattice<LAT>::kRecWords;
     load_record<L, LAT>(t, rec, sl, A);
     if (t.status == REEDMD_LOST) return;   // invalid species index: record left as it was
     for (int s = 0; s < A.nsteps; ++s) {
         double ke0, z0;
-        track_step<L, F32, LAT, CUT>(t, A, sp, sl, false, ke0, z0);
+        track_step<L, F32, LAT, VAR>(t, A, sp, sl, false, ke0, z0);
     }
     store_record<L, LAT>(t, rec, sl);
 }

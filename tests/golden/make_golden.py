@@ -10,6 +10,8 @@ Usage:  python tests/golden/make_golden.py [pilot|pilot2|pilot4|c0|c1|c2|c4|refi
   c5refine: 512 U recoils at 85 keV in UO2 with 8 distances at survival 2^-k re-placed between
          4 epochs from a deliberately short first table
   c0:    65,536 B at 1 keV, 7 degree tilt, no splitting (the c0 sampler, ids 0..65535)
+  c0fkbk: 32,768 B at 1 keV (the c0 sampler, ids 0..32767) with the Firsov + Brandt-Kitagawa
+         stopping, interstitial electron density 32 / a^3 (silicon's valence electrons)
   c1:    1,024 As at 10 keV with the 8 cloning depths: ids 0..511 (channel) and 32768..33279 (tilt)
   refine: 2,048 B at 1 keV (the c0 sampler, ids 0..2047) with 6 adaptive cloning depths at
          survival 2^-k, re-placed between 4 epochs from a deliberately shallow first table
@@ -176,6 +178,18 @@ def c0():
     save("c0_accept", dict(name="c0_b1kev", n=n, seed=0, id0=0), r)
 
 
+def c0fkbk():
+    w = WORKLOADS["c0_b1kev"]
+    n = 32768
+    prim = oracle.sample_primaries(sampler(w), 0, n)
+    n_e = 32.0 / 5.431 ** 3
+    t = time.time()
+    r = oracle.run(oracle.Config(species=w["species"], n_bins=w["n_bins"], bin_width=w["bin_width"],
+                                 stop_mode=oracle.STOP_FKBK, n_e=n_e), prim, log=True)
+    print("c0fkbk oracle seconds", time.time() - t, r["stats"])
+    save("c0_fkbk", dict(name="c0_b1kev", n=n, seed=0, id0=0, stopping="fkbk", n_e=n_e), r)
+
+
 def c1():
     w = WORKLOADS["c1_as10kev"]
     sc = sampler(w)
@@ -303,6 +317,7 @@ def c4big():
 if __name__ == "__main__":
     what = sys.argv[1:] or ["c0", "c1"]
     for w in what:
-        {"pilot": pilot, "pilot2": pilot2, "pilot4": pilot4, "pilot5": pilot5, "c0": c0, "c1": c1, "c2": c2,
+        {"pilot": pilot, "pilot2": pilot2, "pilot4": pilot4, "pilot5": pilot5, "c0": c0, "c0fkbk": c0fkbk,
+         "c1": c1, "c2": c2,
          "c4": c4, "c5": c5, "c5refine": c5refine, "refine": refine, "c1big": c1big, "c2big": c2big,
          "c4big": c4big}[w]()

@@ -43,6 +43,7 @@ def test_struct_sizes_match_header_layout():
     assert C.sizeof(_abi.Result) == 48
     assert _abi.RESULT_WORDS * 8 == C.sizeof(_abi.Result)
     assert C.sizeof(_abi.Species) == 8 + 4 * 8 + 8 * 8
+    assert C.sizeof(_abi.Stopping) == 24
     assert _abi.STATS_WORDS * 8 == 10 * 8 + 8 * 8 + 5 * 8
     assert _abi.RECORD_WORDS == 32 + 9 * 216
     assert _abi.RECORD_WORDS_FLUORITE == 32 + 9 * 344
