@@ -442,7 +442,7 @@ __global__ void queue_reset_kernel(QueueState* q, unsigned long long* seq, int c
         q->depth_max = 0;
         q->log_next = 0;
         q->handoff = 0;
-        q->pad = 0;
+        q->tail_left = 0;
     }
     if (i < cap) seq[i] = static_cast<unsigned long long>(i);
 }

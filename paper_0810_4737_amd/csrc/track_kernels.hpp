@@ -39,8 +39,13 @@ struct QueueState {
     long long depth_max;
     long long log_next;     // next free entry of the optional result log
     long long handoff;      // 1: running tracks move to the queue for the wider tail kernel
-    long long pad;
+    long long tail_left;    // segments of the tail launch that have left early (see kTailReserve)
 };
+
+// The tail launch keeps at least this many idle segments, and twice the live tracks, waiting
+// for clones; the other idle segments leave, so that the compute units are free for other
+// work (the next batch on another stream) while the last long tracks finish.
+constexpr long long kTailReserve = 64;
 
 struct KernelArgs {
     SpeciesConst sp[kMaxSpecies];
@@ -1105,6 +1110,16 @@ __global__ void __launch_bounds__(256, REEDMD_WAVES_PER_SIMD(L, LAT)) track_kern
                             __hip_atomic_store(&A.q->handoff, 1ll, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                             h = 1;
                         }
+                    }
+                    if (A.tail && live > 0) {
+                        // leave if the segments that stay (this one gone) are still at least the
+                        // reserve; the count is taken first, so concurrent leavers cannot
+                        // undercut it
+                        const long long keep = live * 2 > kTailReserve ? live * 2 : kTailReserve;
+                        const long long gone =
+                            static_cast<long long>(atomicAdd(reinterpret_cast<unsigned long long*>(&A.q->tail_left), 1ull)) + 1;
+                        if (A.seg_total - gone >= keep) h = 1;
+                        else add_i64(&A.q->tail_left, -1);
                     }
                 }
                 live = __shfl(live, leader, 64);
