@@ -141,10 +141,12 @@ __device__ __forceinline__ KernelArgs cold_args()
 // Per-track LDS area: [waves per workgroup][tracks per wave] of the atom
 // forces [3][SL*L] (the slots padded to whole lane rows, so every lane of a row
 // has an entry) followed by kTrackHdr words: the start point (3), the cell of
-// the vacant site (3) and its basis index (-1: none).
+// the vacant site (3) and its basis index (-1: none), and the running track's
+// step and pair-term counts not yet booked (two 32-bit words; see track_kernel).
 // With an interaction cut-off (CUT) the header is followed by the list of the
 // slots within the cut-off (one int per slot).
 constexpr int kTrackHdr = 8;
+constexpr int kCountWord = 7;   // header word of the unbooked step and pair-term counts
 template <int L, int LAT = kDiamond, bool CUT = false>
 struct ForceLds {
     static constexpr int kStride = ((Lattice<LAT>::kSlots + L - 1) / L) * L;
@@ -869,8 +871,7 @@ __device__ __forceinline__ void add_i64(int64_t* p, long long v)
 
 // Books a finished track (segment leader only).
 __device__ __forceinline__ void book_finished(const KernelArgs& A, int status, double w, double zstop,
-                                              long long lineage, int next_k, long long steps,
-                                              long long exec_steps, long long pairs, int table,
+                                              long long lineage, int next_k, long long steps, int table,
                                               unsigned long long key)
 {
     reedmd_stats* S = A.stats;
@@ -885,8 +886,6 @@ __device__ __forceinline__ void book_finished(const KernelArgs& A, int status, d
         }
     }
     add_i64(&S->finished, 1);
-    add_i64(&S->track_steps, exec_steps);
-    add_i64(&S->pair_evals, pairs);
     if (status == REEDMD_STOPPED) {
         add_i64(&S->n_stopped, 1);
         add_f64(&S->w_stopped, w);
@@ -1002,8 +1001,18 @@ __global__ void __launch_bounds__(256, REEDMD_WAVES_PER_SIMD(L, LAT)) track_kern
     long long next_primary = seg;
     int top = 0;
     bool fresh = false;
-    long long exec_steps = 0, pairs = 0;
-    int since_poll = 0;
+    // steps and pair terms of the running track not yet booked: two 32-bit counters in the
+    // track's LDS header, added to by the segment leader every step (a fire-and-forget LDS add
+    // instead of a register that the allocator spills and reloads every step) and booked at
+    // every poll, every 256 steps of the track, and when the track ends or moves
+    unsigned* const cnt = reinterpret_cast<unsigned*>(t.fl + 3 * TrackRegs<L, LAT>::FS + kCountWord);
+    auto book_counts = [&](const KernelArgs& C) {
+        const unsigned long long v = *reinterpret_cast<volatile unsigned long long*>(cnt);
+        *reinterpret_cast<volatile unsigned long long*>(cnt) = 0ull;
+        add_i64(&C.stats->track_steps, static_cast<long long>(v & 0xffffffffull));
+        add_i64(&C.stats->pair_evals, static_cast<long long>(v >> 32));
+    };
+    if (sl == 0) *reinterpret_cast<volatile unsigned long long*>(cnt) = 0ull;
     bool cancelled = false;
     bool handoff_now = false;
     double* my_stack = A.stack + static_cast<size_t>(seg < A.seg_total ? seg : 0) *
@@ -1073,12 +1082,10 @@ __global__ void __launch_bounds__(256, REEDMD_WAVES_PER_SIMD(L, LAT)) track_kern
             }
             if (got) {
                 mode = kSegRun;
-                exec_steps = 0;
-                pairs = 0;
                 if (t.status == REEDMD_LOST) {
                     // invalid species or table index: weight quarantined, error flagged
                     if (sl == 0) {
-                        book_finished(A, REEDMD_LOST, t.w, 0.0, t.lineage, t.next_k, t.steps, 0, 0, -1, t.key);
+                        book_finished(A, REEDMD_LOST, t.w, 0.0, t.lineage, t.next_k, t.steps, -1, t.key);
                         add_i64(&A.stats->error_flags, 1);
                         if (MODE == kModePersistent) add_i64(&A.q->live, -1);
                     }
@@ -1087,7 +1094,7 @@ __global__ void __launch_bounds__(256, REEDMD_WAVES_PER_SIMD(L, LAT)) track_kern
                 } else if (cancelled) {
                     // drain: the track ends where it is, its weight is booked as cancelled
                     if (sl == 0) {
-                        book_finished(A, REEDMD_CANCELLED, t.w, 0.0, t.lineage, t.next_k, t.steps, 0, 0, t.table, t.key);
+                        book_finished(A, REEDMD_CANCELLED, t.w, 0.0, t.lineage, t.next_k, t.steps, t.table, t.key);
                         if (MODE == kModePersistent) add_i64(&A.q->live, -1);
                     }
                     mode = kSegNeed;
@@ -1136,16 +1143,19 @@ __global__ void __launch_bounds__(256, REEDMD_WAVES_PER_SIMD(L, LAT)) track_kern
         // ---- one step of a running track ----
         double ke0, z0;
         track_step<L, F32, LAT, VAR>(t, A, sp, sl, fresh, ke0, z0);
-        pairs += t.n_eval;
+        if (sl == 0) {
+            __hip_atomic_fetch_add(&cnt[1], static_cast<unsigned>(t.n_eval), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (!fresh) __hip_atomic_fetch_add(&cnt[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
         if (fresh) {
             fresh = false;
             continue;
         }
-        exec_steps += 1;
         int st = track_events<L, LAT>(t, A, sp, ke0, z0);
-        if (st == REEDMD_ACTIVE && ++since_poll >= 256) {
-            since_poll = 0;
+        // poll (cancel word, tail handoff) and book the counts every 256 steps of the track
+        if (st == REEDMD_ACTIVE && (t.steps & 255) == 0) {
             const KernelArgs C = cold_args();
+            if (sl == 0) book_counts(C);
             if (C.cancel != nullptr) {
                 int cv = 0;
                 if (sl == 0) cv = __hip_atomic_load(C.cancel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
@@ -1161,7 +1171,8 @@ __global__ void __launch_bounds__(256, REEDMD_WAVES_PER_SIMD(L, LAT)) track_kern
             handoff_now = false;
             const KernelArgs A = cold_args();
             if (sl == 0) {
-                book_finished(A, st, t.w, t.zstop, t.lineage, t.next_k, t.steps, exec_steps, pairs, t.table, t.key);
+                book_finished(A, st, t.w, t.zstop, t.lineage, t.next_k, t.steps, t.table, t.key);
+                book_counts(A);
                 if (MODE == kModePersistent) add_i64(&A.q->live, -1);
             }
             mode = kSegNeed;
@@ -1219,9 +1230,8 @@ __global__ void __launch_bounds__(256, REEDMD_WAVES_PER_SIMD(L, LAT)) track_kern
         if (MODE == kModePersistent && handoff_now) {
             // tail handoff, after this step's events and cloning: the track goes to the queue
             // as it stands (the record round trip is exact and the segment sums do not depend
-            // on the lanes per track, so the wider kernel continues it bit for bit); its steps
-            // and pairs so far are booked here.  If the queue has no room the track goes on
-            // here and tries again at the next poll.
+            // on the lanes per track, so the wider kernel continues it bit for bit).  If the
+            // queue has no room the track goes on here and tries again at the next poll.
             handoff_now = false;
             const KernelArgs C = cold_args();
             long long slot = -1;
@@ -1233,9 +1243,8 @@ __global__ void __launch_bounds__(256, REEDMD_WAVES_PER_SIMD(L, LAT)) track_kern
                 if (sl == 0) {
                     __hip_atomic_store(&C.qseq[slot % C.qcap], static_cast<unsigned long long>(slot) + 1,
                                        __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-                    add_i64(&C.stats->track_steps, exec_steps);
-                    add_i64(&C.stats->pair_evals, pairs);
                     add_i64(&C.stats->handed_off, 1);
+                    book_counts(C);
                 }
                 mode = kSegNeed;
             }
