@@ -37,15 +37,16 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3  # 256 CU x 2.4 GHz x 256 FP32 FLOP/clk/CU
 # separation, force components and sums, density sum, kicks and drifts (29) stay FP64.
 FLOP_PER_PAIR_F32_PART = 38
 
-# HBM bytes per launch of the track kernel measured with rocprofv3 --pmc FETCH_SIZE and
-# WRITE_SIZE (separate runs), scaled by the same counters on a 1 GiB copy (FETCH x 2.000,
-# WRITE x 1.000); reported only while the track kernel's device sources (track_kernels.hpp,
-# device_physics.hpp) and the launch match the ones the counters were taken on.
+# HBM bytes per step (the step's main and tail launches of the track kernel) measured with
+# rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (separate runs, mean of the 20 timed steps),
+# scaled by the same counters on a 1 GiB copy (FETCH x 2.000, WRITE x 1.000); reported only
+# while the track kernel's device sources (track_kernels.hpp, device_physics.hpp) and the
+# launch match the ones the counters were taken on.
 MEASURED_TRAFFIC = {
-    "sources_sha256_prefix": "0ab5b717fc6cb522",
-    "workload": "c1", "form": "persistent", "lanes": 16, "primaries": 65536, "slice": 65536,
-    "fetch_bytes": 2610341.6875 * 1024 * 2.000,
-    "write_bytes": 5175379.78125 * 1024 * 1.000,
+    "sources_sha256_prefix": "6d8d589f096bf35b",
+    "workload": "c2", "form": "persistent", "lanes": 32, "primaries": 1048576, "slice": 52429,
+    "fetch_bytes": 2259981.0 * 1024 * 2.000,
+    "write_bytes": 4379010.3 * 1024 * 1.000,
 }
 
 

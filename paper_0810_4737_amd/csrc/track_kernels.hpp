@@ -141,12 +141,15 @@ __device__ __forceinline__ KernelArgs cold_args()
 // Per-track LDS area: [waves per workgroup][tracks per wave] of the atom
 // forces [3][SL*L] (the slots padded to whole lane rows, so every lane of a row
 // has an entry) followed by kTrackHdr words: the start point (3), the cell of
-// the vacant site (3) and its basis index (-1: none), and the running track's
-// step and pair-term counts not yet booked (two 32-bit words; see track_kernel).
+// the vacant site (3) and its basis index (-1: none), the running track's
+// step and pair-term counts not yet booked (two 32-bit words; see track_kernel)
+// and the number of atoms in its domain (kept here rather than in a register
+// that the track kernel would spill and reload every step).
 // With an interaction cut-off (CUT) the header is followed by the list of the
 // slots within the cut-off (one int per slot).
-constexpr int kTrackHdr = 8;
+constexpr int kTrackHdr = 9;
 constexpr int kCountWord = 7;   // header word of the unbooked step and pair-term counts
+constexpr int kExistWord = 8;   // header word of the number of atoms in the domain
 template <int L, int LAT = kDiamond, bool CUT = false>
 struct ForceLds {
     static constexpr int kStride = ((Lattice<LAT>::kSlots + L - 1) / L) * L;
@@ -300,7 +303,7 @@ struct TrackRegs {
     long long steps, lineage;
     int species, next_k, table, status;
     int n_exist;             // atoms in the domain (segment-uniform)
-    int n_eval;              // pair terms evaluated by the last pass (n_exist without a cut-off)
+    int n_eval;              // pair terms evaluated by the last pass with a cut-off (without one: n_exist)
 };
 
 template <int L, int LAT>
@@ -446,6 +449,7 @@ __device__ __forceinline__ void regenerate(TrackRegs<L, LAT>& t, const KernelArg
     t.exist = ex;
     t.cx = ncx; t.cy = ncy; t.cz = ncz;
     t.n_exist = SegReduce<L>::isum(__popc(ex));
+    if (sl == 0) reinterpret_cast<volatile int*>(track_hdr(t) + kExistWord)[0] = t.n_exist;
 }
 
 // The range coordinate: the depth z, or the distance from the start point
@@ -655,7 +659,6 @@ __device__ __forceinline__ void track_step(TrackRegs<L, LAT>& t, const KernelArg
             __builtin_amdgcn_sched_barrier(0);
     #endif
         }
-        t.n_eval = t.n_exist;
     }
     t.Fx = SegReduce<L>::csum(Fx);
     t.Fy = SegReduce<L>::csum(Fy);
@@ -786,6 +789,7 @@ __device__ __forceinline__ void load_record(TrackRegs<L, LAT>& t, const double* 
     }
     t.exist = ex;
     t.n_exist = SegReduce<L>::isum(__popc(ex));
+    if (sl == 0) reinterpret_cast<volatile int*>(track_hdr(t) + kExistWord)[0] = t.n_exist;
     if (ir[24] == 1) {
         // maxima stored by this library: reuse them so that a reloaded record continues
         // bitwise like the track that wrote it
@@ -1144,7 +1148,9 @@ __global__ void __launch_bounds__(256, REEDMD_WAVES_PER_SIMD(L, LAT)) track_kern
         double ke0, z0;
         track_step<L, F32, LAT, VAR>(t, A, sp, sl, fresh, ke0, z0);
         if (sl == 0) {
-            __hip_atomic_fetch_add(&cnt[1], static_cast<unsigned>(t.n_eval), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            const int ne = (VAR & kVarCut) != 0 ? t.n_eval
+                                                 : reinterpret_cast<volatile int*>(track_hdr(t) + kExistWord)[0];
+            __hip_atomic_fetch_add(&cnt[1], static_cast<unsigned>(ne), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             if (!fresh) __hip_atomic_fetch_add(&cnt[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
         if (fresh) {
