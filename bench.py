@@ -86,6 +86,7 @@ def parse():
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 pair-term variant leg")
     ap.add_argument("--no-uo2", action="store_true", help="skip the 85 keV U recoil in UO2 leg")
     ap.add_argument("--no-domain", action="store_true", help="skip the interaction-set (cut-off) autotuner leg")
+    ap.add_argument("--no-c4", action="store_true", help="skip the 100 keV As deep-tail accuracy leg")
     ap.add_argument("--no-fkbk", action="store_true", help="skip the Firsov + Brandt-Kitagawa stopping leg")
     ap.add_argument("--uo2-n", type=int, default=0, help="primaries of the UO2 leg (default: the workload's 5,120)")
     ap.add_argument("--streams", type=int, default=3,
@@ -197,6 +198,69 @@ def profile_accuracy(R, torch, np, ctx, w, sampler, n, cfg, reed_log, t_reed, ta
     out["reed_s"] = t_reed
     out["nosplit_s"] = t_ns
     out["method"] = "32 sub-batches (primary id mod 32), batch means; FOM = 1/(T s^2) with the launch wall time"
+    return out
+
+
+def c4_leg(R, torch, np, n=262144):
+    """The deep-tail workload: 262,144 As at 100 keV exactly along [001] with 16 cloning depths
+    down to 1e-6, persistent form, autotuned; one REED run and one run of the same primaries
+    without cloning, both with every finished track logged.  Probes: the depths where REED's
+    weighted survival is 1e-4 and 1e-5; at each, the probability of stopping beyond it with its
+    relative standard error from 32 sub-batches (primary id mod 32) and the figure of merit
+    1 / (T s^2) of both runs (T the run's wall time)."""
+    ctx = R.Context()
+    w, sampler, thr, _ = workload_setup(R, "c4", n)
+    base = dict(n_bins=w["n_bins"], bin_width=w["bin_width"], form=R.FORM_PERSISTENT)
+    batch = R.sample_primaries(ctx, sampler, 0, n)
+    lanes, waves = R.autotune(ctx, w["species"], batch, R.RunConfig(thresholds=thr, **base), pilot=min(n, 65536))
+    runs = {}
+    for name, t in (("reed", thr), ("nosplit", None)):
+        cfg = R.RunConfig(thresholds=t, lanes_per_track=lanes, waves_per_cu=waves, **base)
+        cap = 8 * n if t is not None else n + 16
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st, log, _ = R.run(ctx, w["species"], batch, cfg, log_cap=cap)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        s = R.parse_stats(st)
+        assert s["log_count"] <= cap, ("track log too small", s["log_count"], cap)
+        lg = R.parse_log(log, s["log_count"])
+        runs[name] = (lg, dt, s)
+        progress(f"c4 {name}: {dt:.1f} s, {s['finished']} tracks, {s['pair_evals'] / dt:.4g} force evals/s")
+    reed = runs["reed"][0]
+    st_ = reed[reed["status"] == R.STOPPED]
+    order = np.argsort(st_["z_stop"])[::-1]
+    surv = np.cumsum(st_["w"][order]) / n          # weighted survival beyond each stopping depth
+
+    def probe(p):
+        k = int(np.searchsorted(surv, p))
+        return float(st_["z_stop"][order][min(k, len(order) - 1)])
+
+    def estimate(lg, depth):
+        deep = (lg["status"] == R.STOPPED) & (lg["z_stop"] >= depth)
+        per = np.zeros(n)
+        np.add.at(per, lg["lineage"][deep], lg["w"][deep])
+        bm = np.array([per[k::32].mean() for k in range(32)])
+        pr = per.mean()
+        rel = bm.std(ddof=1) / math.sqrt(32) / pr if pr > 0 else float("nan")
+        return pr, rel, int(deep.sum())
+
+    out = dict(workload="262,144 As at 100 keV along [001] into Si; 16 cloning depths to 1e-6; 5 A bins",
+               primaries=n, lanes_per_track=lanes, reed_s=runs["reed"][1], nosplit_s=runs["nosplit"][1],
+               reed_tracks=runs["reed"][2]["finished"], reed_force_evals_per_s=runs["reed"][2]["pair_evals"] / runs["reed"][1],
+               nosplit_force_evals_per_s=runs["nosplit"][2]["pair_evals"] / runs["nosplit"][1],
+               method="32 sub-batches (primary id mod 32), batch means; FOM = 1/(T s^2) with the run's wall time; "
+                      "probe depths where REED's weighted survival is 1e-4 and 1e-5")
+    for name, p in (("survival_1e-4", 1e-4), ("survival_1e-5", 1e-5)):
+        D = probe(p)
+        pr, rr, nr = estimate(reed, D)
+        pn, rn, nn = estimate(runs["nosplit"][0], D)
+        fr = 1.0 / (runs["reed"][1] * rr * rr) if rr > 0 else None
+        fn = 1.0 / (runs["nosplit"][1] * rn * rn) if (rn > 0 and rn == rn) else None
+        out[name] = dict(depth_A=D, reed_probability=pr, reed_rel_err=rr, reed_tracks_beyond=nr, reed_fom_per_s=fr,
+                         nosplit_probability=pn, nosplit_rel_err=rn, nosplit_tracks_beyond=nn, nosplit_fom_per_s=fn,
+                         fom_ratio=(fr / fn) if (fr and fn) else None)
+    ctx.close()
     return out
 
 
@@ -783,6 +847,9 @@ def main():
     if key != "c1" and not args.no_c1:
         progress("c1 leg")
         out["c1_as10kev"] = c1_leg(R, torch, np, args)
+    if not args.no_c4:
+        progress("c4 leg")
+        out["c4_as100kev_tail_accuracy"] = c4_leg(R, torch, np)
     if not args.no_domain:
         progress("interaction-set leg")
         out["interaction_set"] = domain_leg(R, torch)
