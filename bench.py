@@ -76,9 +76,11 @@ def parse():
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--waves", type=int, default=0, help="resident waves per CU with --lanes (0: by occupancy)")
     ap.add_argument("--queue", type=int, default=0, help="clone-queue capacity in records (0: library default)")
-    ap.add_argument("--refine-epochs", type=int, default=0,
-                    help="also time one run of the 10 keV As workload with the cloning depths re-placed "
-                         "between this many epochs (targets 2^-k, first table the stored depths); reported apart")
+    ap.add_argument("--refine-epochs", type=int, default=8,
+                    help="also time the 10 keV As workload with the cloning depths re-placed over this many "
+                         "epochs (targets 2^-k, first table the stored depths), once with one launch per "
+                         "epoch and once with every epoch inside one persistent launch; reported apart "
+                         "(0: skip)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-c1", action="store_true", help="skip the 10 keV As leg")
@@ -679,19 +681,27 @@ def c1_leg(R, torch, np, args):
                                                tail_depth)
     if args.refine_epochs > 0:
         from tests.workloads import C1_THRESHOLDS
-        b = R.sample_primaries(ctx, sampler, 0, n, stream=stream)
-        hist = torch.zeros(w["n_bins"], dtype=torch.float64, device="cuda")
-        stats = R.new_stats()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        _, _, depths = R.run_refined(ctx, w["species"], b, cfg, args.refine_epochs,
-                                     [2.0 ** -j for j in range(1, len(C1_THRESHOLDS) + 1)], 1.0,
-                                     hist=hist, stats=stats, stream=stream)
-        torch.cuda.synchronize()
-        tr = time.perf_counter() - t0
-        sr = R.parse_stats(stats)
-        out["refined"] = dict(epochs=args.refine_epochs, ms=1e3 * tr, force_evals_per_s=sr["pair_evals"] / tr,
-                              tracks=sr["finished"], last_depths=[round(x, 1) for x in depths[-1, 0].tolist()])
+        out["refined"] = dict(epochs=args.refine_epochs, fixed_depths_ms=k)
+        for name, inl in (("epoch_launches", False), ("in_launch", True)):
+            b = R.sample_primaries(ctx, sampler, 0, n, stream=stream)
+            hist = torch.zeros(w["n_bins"], dtype=torch.float64, device="cuda")
+            stats = R.new_stats()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, _, depths = R.run_refined(ctx, w["species"], b, cfg, args.refine_epochs,
+                                         [2.0 ** -j for j in range(1, len(C1_THRESHOLDS) + 1)], 1.0,
+                                         hist=hist, stats=stats, stream=stream, in_launch=inl)
+            torch.cuda.synchronize()
+            tr = time.perf_counter() - t0
+            sr = R.parse_stats(stats)
+            ledger = float(hist.sum().item()) + sr["w_underflow"] + sr["w_overflow"] + sr["w_backscattered"] + \
+                sr["w_quarantined"]
+            assert ledger == float(n) and sr["primaries"] == n, ("weight ledger broken", name, ledger)
+            out["refined"][name] = dict(ms=1e3 * tr, force_evals_per_s=sr["pair_evals"] / tr,
+                                        tracks=sr["finished"],
+                                        last_depths=[round(x, 1) for x in depths[-1, 0].tolist()])
+            progress(f"refined depths, {name}: {tr:.2f} s, {sr['finished']} tracks, "
+                     f"{sr['pair_evals'] / tr:.4g} force evals/s")
     if args.pipelined > 0:
         out["pipelined"] = pipelined_leg(R, torch, w, sampler, n, cfg, args.pipelined, w["species"])
     ctx.close()

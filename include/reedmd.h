@@ -303,10 +303,11 @@ reedmd_status reedmd_run_noalloc(reedmd_ctx* ctx, const reedmd_species* species,
 /* Adaptive cloning depths (Sec. 2: the depths are placed from the statistics
  * gathered so far; Sec. 3: criteria are updated between complete tracks). */
 typedef struct {
-    int32_t n_epochs;       /* the batch runs in n_epochs consecutive id ranges, 1..4096 */
-    int32_t reserved;
+    int32_t n_epochs;       /* the batch runs in n_epochs epochs, 1..4096 */
+    int32_t in_launch;      /* 0: one launch per epoch; 1: all epochs in one persistent launch */
     const double* probs;    /* host, n_thresh target survival probabilities, strictly decreasing in (0,1) */
     double min_gap;         /* minimum spacing of successive depths (A), >= 0 */
+    double* snapshots;      /* in_launch only: optional device [n_epochs][n_tables][n_bins + 2] */
 } reedmd_refine;
 
 /* Like reedmd_run, with the cloning depths refined between epochs.  Epoch e
@@ -322,8 +323,25 @@ typedef struct {
  * unbiased.  d_hist, d_stats and the optional track log accumulate over all
  * epochs as in reedmd_run; d_depths (device, optional, n_epochs x n_tables x
  * n_thresh doubles) receives the tables each epoch ran with; params->thresholds
- * is not modified.  Allocates its work buffers, synchronises the stream.
- * EINVAL for invalid settings (n_thresh >= 1 is required). */
+ * is not modified.
+ *
+ * in_launch = 1 runs every epoch inside one launch of the persistent form
+ * (params->form must be REEDMD_FORM_PERSISTENT, else EINVAL): epoch e is the
+ * claim positions [ceil(n e / E), ceil(n (e+1) / E)) of the primaries (claimed
+ * in the launch's longest-expected-first order), and the segment that claims
+ * the first position of epoch e > 0 re-places every table from the tracks
+ * booked by then (the same rule, starting from the depths of epoch 0, which is
+ * what a target not yet resolved keeps) while the other segments go on
+ * running; the epoch's other primaries start once its tables are published.
+ * No launch boundary drains the GPU between epochs; which tracks a table's
+ * statistics hold depends on timing, so the depths are not reproducible run
+ * to run (each family still keeps one table and the estimator stays unbiased).
+ * The statistics each table was placed from (per table: stopped weight of each
+ * bin, stopped weight beyond the last bin, all booked weight; zeros for epoch
+ * 0) go to snapshots when it is non-NULL.
+ *
+ * Allocates its work buffers, synchronises the stream.  EINVAL for invalid
+ * settings (n_thresh >= 1 is required). */
 reedmd_status reedmd_run_refined(reedmd_ctx* ctx, const reedmd_species* species, const reedmd_batch* batch,
                                  const reedmd_run_params* params, const reedmd_refine* rf, double* d_hist,
                                  reedmd_stats* d_stats, double* d_depths, hipStream_t stream);

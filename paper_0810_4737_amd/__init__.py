@@ -292,9 +292,12 @@ def _run_noalloc(ctx, species, batch, p, hist, stats, id0, stream):
 
 
 def run_refined(ctx: Context, species, batch, cfg: RunConfig, n_epochs: int, probs, min_gap: float = 1.0,
-                hist=None, stats=None, id0=0, log_cap=0, stream=None):
+                hist=None, stats=None, id0=0, log_cap=0, stream=None, in_launch=False, snapshots=None):
     """Runs the batch in n_epochs epochs with the cloning depths re-placed between epochs from
     the survival of the tracks booked so far (cfg.thresholds: the tables of epoch 0).
+    in_launch: every epoch inside one persistent launch (epochs by claim position, each
+    version placed from the caller's tables); snapshots: optional float64 device tensor
+    [n_epochs, n_tables, n_bins + 2] that receives the statistics each version was placed from.
     Returns (hist, stats, depths[n_epochs, n_tables, n_thresh][, log])."""
     dev = batch["energy"].device
     keep = []
@@ -316,6 +319,13 @@ def run_refined(ctx: Context, species, batch, cfg: RunConfig, n_epochs: int, pro
     rf.n_epochs = int(n_epochs)
     rf.probs = pr.ctypes.data_as(C.POINTER(C.c_double))
     rf.min_gap = float(min_gap)
+    rf.in_launch = 1 if in_launch else 0
+    if snapshots is not None:
+        E = max(1, min(int(n_epochs), int(batch["energy"].shape[0])))
+        if snapshots.dtype != torch.float64 or not snapshots.is_contiguous() or \
+                tuple(snapshots.shape) != (E, p.n_tables, p.n_bins + 2):
+            raise ValueError("snapshots must be a contiguous float64 tensor [n_epochs, n_tables, n_bins + 2]")
+        rf.snapshots = snapshots.data_ptr()
     with _on(stream):
         depths = torch.zeros((max(1, min(int(n_epochs), int(batch["energy"].shape[0]))), p.n_tables,
                               p.n_thresh), dtype=torch.float64, device=dev)

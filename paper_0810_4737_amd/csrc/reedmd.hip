@@ -783,9 +783,20 @@ Shape choose_shape(reedmd_ctx* ctx, const reedmd_run_params* p, const reedmd_bat
     return s;
 }
 
+// Depth refinement inside one persistent launch: E epochs of claim positions,
+// targets and spacing, the per-epoch statistics snapshots and publish flags.
+struct RefineLaunch {
+    int E;
+    const double* probs;
+    double min_gap;
+    double* snap;
+    int* ready;
+};
+
 reedmd_status run_impl(reedmd_ctx* ctx, const reedmd_species* sp, const reedmd_batch* b,
                        const reedmd_run_params* p, double* d_hist, reedmd_stats* d_stats, hipStream_t stream,
-                       const Shape* forced, double* d_tstat = nullptr, hipEvent_t ev_start = nullptr)
+                       const Shape* forced, double* d_tstat = nullptr, hipEvent_t ev_start = nullptr,
+                       const RefineLaunch* rl = nullptr)
 {
     Shape s = forced ? *forced : choose_shape(ctx, p, b);
     const int qcap = s.qcap > 0 ? s.qcap : 1;
@@ -811,6 +822,13 @@ reedmd_status run_impl(reedmd_ctx* ctx, const reedmd_species* sp, const reedmd_b
     A.handoff_live = s.tail_segs;
     A.cancel = p->cancel;
     A.seg_total = s.seg_total;
+    if (rl != nullptr) {
+        A.refine_E = rl->E;
+        A.r_probs = rl->probs;
+        A.r_min_gap = rl->min_gap;
+        A.r_snap = rl->snap;
+        A.r_ready = rl->ready;
+    }
 
     if (b->n == 0) return REEDMD_OK;
     st = ensure_order(ctx, b->n);
@@ -911,38 +929,17 @@ reedmd_status run_impl(reedmd_ctx* ctx, const reedmd_species* sp, const reedmd_b
 }
 
 // ---------------------------------------------------------------------------
-// Adaptive cloning depths (Sec. 2: depths placed from the statistics gathered
-// so far; Sec. 3: criteria updated between complete tracks).  For every depth
-// table t, from its booked tracks: S(z) = (stopped weight with z_stop >= z) /
-// (all weight booked for the table), evaluated at bin edges; depth k is where
-// S falls to probs[k], linear in S within the bin; a target the histogram does
-// not resolve (S at its end still above it) keeps the previous depth; the
-// depths are then made increasing by at least min_gap.  One thread per table.
+// Adaptive cloning depths between launches (Sec. 2: depths placed from the
+// statistics gathered so far; Sec. 3: criteria updated between complete
+// tracks): every table re-placed from its statistics by refine_table, starting
+// from its current depths.  One thread per table.
 __global__ void refine_kernel(const double* tstat, int n_bins, double bin_width, int n_tables, int n_thresh,
                               const double* probs, double min_gap, double* thr)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n_tables) return;
-    const double* h = tstat + static_cast<size_t>(t) * (n_bins + 2);
-    double* d = thr + static_cast<size_t>(t) * n_thresh;
-    const double total = h[n_bins + 1];
-    if (total > 0.0) {
-        double beyond = h[n_bins];                 // stopped weight at or beyond the lower edge of bin b
-        for (int b = n_bins - 1; b >= 0; --b) beyond += h[b];
-        double s_lo = beyond / total;
-        int k = 0;
-        for (int b = 0; b < n_bins && k < n_thresh; ++b) {
-            beyond -= h[b];
-            const double s_hi = beyond / total;
-            while (k < n_thresh && probs[k] >= s_hi) {
-                d[k] = (probs[k] < s_lo) ? (static_cast<double>(b) + (s_lo - probs[k]) / (s_lo - s_hi)) * bin_width
-                                         : static_cast<double>(b) * bin_width;
-                ++k;
-            }
-            s_lo = s_hi;
-        }
-    }
-    for (int k = 1; k < n_thresh; ++k) d[k] = fmax(d[k], d[k - 1] + min_gap);
+    refine_table(tstat + static_cast<size_t>(t) * (n_bins + 2), n_bins, bin_width, n_thresh, probs, min_gap,
+                 thr + static_cast<size_t>(t) * n_thresh);
 }
 
 // ---------------------------------------------------------------------------
@@ -1602,6 +1599,48 @@ reedmd_status reedmd_autotune_domain(reedmd_ctx* ctx, const reedmd_species* spec
     return st;
 }
 
+// All epochs of a refined run in one persistent launch (settings validated by the caller):
+// version e of the depth tables ([E][n_tables][n_thresh], version 0 the caller's) is
+// computed and published inside the launch by the first claimer of epoch e.
+static reedmd_status run_refined_in_launch(reedmd_ctx* ctx, const reedmd_species* species,
+                                           const reedmd_batch* batch, const reedmd_run_params* params,
+                                           const reedmd_refine* rf, int E, double* d_hist, reedmd_stats* d_stats,
+                                           double* d_depths, hipStream_t stream)
+{
+    const int nt = params->n_tables, nk = params->n_thresh, nb = params->n_bins;
+    const size_t thr_b = sizeof(double) * E * nt * nk, ts_b = sizeof(double) * nt * (nb + 2);
+    const size_t snap_b = ts_b * E, pr_b = sizeof(double) * nk, rd_b = sizeof(int) * E;
+    char* work = nullptr;
+    HIP_TRY(ctx, hipMalloc(reinterpret_cast<void**>(&work), thr_b + ts_b + snap_b + pr_b + rd_b + 256));
+    double* thr = reinterpret_cast<double*>(work);
+    double* tstat = thr + static_cast<size_t>(E) * nt * nk;
+    double* snap = tstat + static_cast<size_t>(nt) * (nb + 2);
+    double* probs = snap + static_cast<size_t>(E) * nt * (nb + 2);
+    int* ready = reinterpret_cast<int*>(probs + nk);
+    auto body = [&]() -> reedmd_status {
+        const int one = 1;
+        HIP_TRY(ctx, hipMemsetAsync(work, 0, thr_b + ts_b + snap_b + pr_b + rd_b, stream));
+        HIP_TRY(ctx, hipMemcpyAsync(thr, params->thresholds, sizeof(double) * nt * nk, hipMemcpyDeviceToDevice, stream));
+        HIP_TRY(ctx, hipMemcpyAsync(probs, rf->probs, pr_b, hipMemcpyHostToDevice, stream));
+        HIP_TRY(ctx, hipMemcpyAsync(ready, &one, sizeof(int), hipMemcpyHostToDevice, stream));
+        reedmd_run_params p = *params;
+        p.thresholds = thr;
+        p.r_cut = choose_shape(ctx, params, batch).r_cut;
+        const Shape shape = choose_shape(ctx, &p, batch);
+        const RefineLaunch rl{E, probs, rf->min_gap, snap, ready};
+        const reedmd_status rs = run_impl(ctx, species, batch, &p, d_hist, d_stats, stream, &shape, tstat, nullptr, &rl);
+        if (rs != REEDMD_OK) return rs;
+        if (d_depths) HIP_TRY(ctx, hipMemcpyAsync(d_depths, thr, thr_b, hipMemcpyDeviceToDevice, stream));
+        if (rf->snapshots) HIP_TRY(ctx, hipMemcpyAsync(rf->snapshots, snap, snap_b, hipMemcpyDeviceToDevice, stream));
+        HIP_TRY(ctx, hipStreamSynchronize(stream));
+        return REEDMD_OK;
+    };
+    const reedmd_status rs = body();
+    (void)hipStreamSynchronize(stream);
+    (void)hipFree(work);
+    return rs;
+}
+
 reedmd_status reedmd_run_refined(reedmd_ctx* ctx, const reedmd_species* species, const reedmd_batch* batch,
                                  const reedmd_run_params* params, const reedmd_refine* rf, double* d_hist,
                                  reedmd_stats* d_stats, double* d_depths, hipStream_t stream)
@@ -1621,10 +1660,14 @@ reedmd_status reedmd_run_refined(reedmd_ctx* ctx, const reedmd_species* species,
         if (!(pk > 0.0 && pk < 1.0) || (k > 0 && !(pk < rf->probs[k - 1])))
             return fail(ctx, REEDMD_EINVAL, "probs must decrease strictly inside (0, 1)");
     }
+    if (rf->in_launch != 0 && rf->in_launch != 1) return fail(ctx, REEDMD_EINVAL, "in_launch must be 0 or 1");
+    if (rf->in_launch && params->form != REEDMD_FORM_PERSISTENT)
+        return fail(ctx, REEDMD_EINVAL, "in-launch refinement needs the persistent form");
     const long long n = batch->n;
     if (n == 0) return REEDMD_OK;
     const int E = static_cast<int>(std::min<long long>(rf->n_epochs, n));
     const int nt = params->n_tables, nk = params->n_thresh, nb = params->n_bins;
+    if (rf->in_launch) return run_refined_in_launch(ctx, species, batch, params, rf, E, d_hist, d_stats, d_depths, stream);
     const long long m = (n + E - 1) / E;   // largest epoch
     // work buffers: depth tables, per-table statistics, targets, one epoch of primaries
     const size_t thr_b = sizeof(double) * nt * nk, ts_b = sizeof(double) * nt * (nb + 2), pr_b = sizeof(double) * nk;

@@ -96,6 +96,16 @@ struct KernelArgs {
     double bk_pref[kMaxSpecies];
     double bk_z13[kMaxSpecies];
     double bk_vF, bk_inv_vunit;
+    // cloning depths re-placed inside the launch (0: off): epoch e = claim positions
+    // [ceil(n e / E), ceil(n (e+1) / E)); the first claimer of epoch e computes table version e
+    // (thr holds [E][n_tables][n_thresh]) from a snapshot of tstat (snap: [E][n_tables][n_bins+2])
+    // and sets ready[e]; the epoch's other claims wait for it
+    int refine_E;
+    int pad_refine;
+    const double* r_probs;
+    double r_min_gap;
+    double* r_snap;
+    int* r_ready;
     const int* order;       // optional: batch entry of the i-th claimed primary (longest expected first)
     long long seg_total;
     // tail handoff (persistent form with fewer than 64 lanes per track): once every primary
@@ -873,15 +883,77 @@ __device__ __forceinline__ void add_i64(int64_t* p, long long v)
     atomicAdd(reinterpret_cast<unsigned long long*>(p), static_cast<unsigned long long>(v));
 }
 
+// Re-places one depth table (Sec. 2: depths from the statistics gathered so far; Sec. 3:
+// criteria updated between complete tracks).  h: the table's statistics, stopped weight per
+// depth bin, stopped weight beyond the last bin, all weight booked; d: on entry the previous
+// depths, on return the new ones.  S(z) = (stopped weight with z_stop >= z) / (all booked
+// weight) at the bin edges; depth k is where S falls to probs[k], linear in S inside the bin;
+// a target S does not reach within the histogram keeps its depth; then every depth is raised
+// to at least the previous one plus min_gap.
+__device__ inline void refine_table(const double* h, int n_bins, double bin_width, int n_thresh,
+                                    const double* probs, double min_gap, double* d)
+{
+    const double total = h[n_bins + 1];
+    if (total > 0.0) {
+        double beyond = h[n_bins];                 // stopped weight at or beyond the lower edge of bin b
+        for (int b = n_bins - 1; b >= 0; --b) beyond += h[b];
+        double s_lo = beyond / total;
+        int k = 0;
+        for (int b = 0; b < n_bins && k < n_thresh; ++b) {
+            beyond -= h[b];
+            const double s_hi = beyond / total;
+            while (k < n_thresh && probs[k] >= s_hi) {
+                d[k] = (probs[k] < s_lo) ? (static_cast<double>(b) + (s_lo - probs[k]) / (s_lo - s_hi)) * bin_width
+                                         : static_cast<double>(b) * bin_width;
+                ++k;
+            }
+            s_lo = s_hi;
+        }
+    }
+    for (int k = 1; k < n_thresh; ++k) d[k] = fmax(d[k], d[k - 1] + min_gap);
+}
+
+// First claim position of epoch e (ceil(n e / E)).
+__device__ __forceinline__ long long epoch_first(long long n, int E, int e)
+{
+    return (n * e + E - 1) / E;
+}
+
+// Table version e of an in-launch refinement, computed by the L lanes of one segment (lane
+// sl takes tables sl, sl + L, ...): copies each table's statistics as they stand into the
+// snapshot, re-places the table from the snapshot starting from version 0 (the caller's
+// depths; a version depends on no other version, so nothing waits while it is computed),
+// then publishes the version.  Kept out of line: a cold path whose registers stay out of
+// the track kernel's allocation.
+__device__ __noinline__ void compute_version(const double* tstat, double* snap_all, double* thr, const double* probs,
+                                             double min_gap, double bin_width, int nb, int nt, int nk, int e,
+                                             int sl, int L, int* ready)
+{
+    const size_t sw = static_cast<size_t>(nb + 2);
+    for (int tb = sl; tb < nt; tb += L) {
+        const double* live = tstat + static_cast<size_t>(tb) * sw;
+        double* snap = snap_all + (static_cast<size_t>(e) * nt + tb) * sw;
+        for (size_t i = 0; i < sw; ++i)
+            snap[i] = __hip_atomic_load(&live[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const double* first = thr + static_cast<size_t>(tb) * nk;
+        double* d = thr + (static_cast<size_t>(e) * nt + tb) * nk;
+        for (int k = 0; k < nk; ++k) d[k] = first[k];
+        refine_table(snap, nb, bin_width, nk, probs, min_gap, d);
+    }
+    __threadfence();
+    if (sl == 0) __hip_atomic_store(&ready[e], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Books a finished track (segment leader only).
 __device__ __forceinline__ void book_finished(const KernelArgs& A, int status, double w, double zstop,
                                               long long lineage, int next_k, long long steps, int table,
                                               unsigned long long key)
 {
     reedmd_stats* S = A.stats;
-    if (A.tstat != nullptr && table >= 0 && table < A.n_tables) {
-        // per-table survival statistics for adaptive cloning depths
-        double* ts = A.tstat + static_cast<size_t>(table) * (A.n_bins + 2);
+    if (A.tstat != nullptr && table >= 0) {
+        // per-table survival statistics for adaptive cloning depths (the table field of a
+        // track also carries its table version: version * n_tables + table)
+        double* ts = A.tstat + static_cast<size_t>(table % A.n_tables) * (A.n_bins + 2);
         add_f64(&ts[A.n_bins + 1], w);
         if (status == REEDMD_STOPPED && zstop >= 0.0) {
             const double fb = floor(zstop / A.bin_width);
@@ -1076,8 +1148,27 @@ __global__ void __launch_bounds__(256, REEDMD_WAVES_PER_SIMD(L, LAT)) track_kern
                     qi = __shfl(qi, leader, 64);
                     if (qi >= A.n) qi = -1;
                 }
+                int version = 0;
+                if (MODE == kModePersistent && A.refine_E > 1) {
+                    // in-launch refinement: the epoch of this claim position; its first claimer
+                    // computes the epoch's table version (which waits for nothing), then every
+                    // segment of a later epoch waits until its version is published (by this
+                    // segment, by another segment of this wave in the step above, or by
+                    // another wave)
+                    if (qi >= 0) version = static_cast<int>((qi * A.refine_E) / A.n);
+                    if (qi >= 0 && version > 0 && qi == epoch_first(A.n, A.refine_E, version))
+                        compute_version(A.tstat, A.r_snap, const_cast<double*>(A.thr), A.r_probs, A.r_min_gap,
+                                        A.bin_width, A.n_bins, A.n_tables, A.n_thresh, version, sl, L, A.r_ready);
+                    if (qi >= 0 && version > 0) {
+                        if (sl == 0)
+                            while (__hip_atomic_load(&A.r_ready[version], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0)
+                                __builtin_amdgcn_s_sleep(4);
+                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                    }
+                }
                 if (qi >= 0) {
                     start_primary<L, LAT>(t, A, sp, A.order != nullptr ? A.order[qi] : qi);
+                    if (t.status != REEDMD_LOST) t.table += version * A.n_tables;
                     if (t.status != REEDMD_LOST) refresh_threshold(t, A);
                     if (sl == 0) add_i64(&A.stats->primaries, 1);
                     fresh = true;

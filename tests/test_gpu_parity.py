@@ -378,6 +378,55 @@ def test_adaptive_depths_follow_the_oracle_rule_and_statistics(R, ctx):
     assert p > 0.01
 
 
+def test_in_launch_depths_follow_the_oracle_rule_and_statistics(R, ctx):
+    """The same refinement inside one persistent launch (16,384 B at 1 keV, 6 depths, 4 epochs
+    of claim positions, 32 lanes per track with the 64-lane tail, one block per CU: 2,048
+    segments, so every later epoch starts after thousands of families have finished): every
+    table version equals the
+    oracle's rule applied to the statistics snapshot it was placed from, starting from the
+    first table, to 1e-6 A; each snapshot is exactly a part of the run's final per-table
+    statistics (dyadic weights: sums are exact); the ledger is exact; the weighted stopping
+    depths match the stored oracle run of the epoch procedure (KS p > 0.01).  The plain form
+    is rejected."""
+    meta, zo, wo = _load_golden("c0_refined")
+    w = WORKLOADS["c0_b1kev"]
+    m = meta["workload"]
+    n, E, probs, first, gap = 16384, m["n_epochs"], m["probs"], m["first"], m["min_gap"]
+    nb, bw = w["n_bins"], w["bin_width"]
+    batch = R.sample_primaries(ctx, R.SamplerConfig(**w["sampler"]), 0, n)
+    cfg = rcfg(R, n_bins=nb, thresholds=[first], form=R.FORM_PERSISTENT, lanes_per_track=32, waves_per_cu=1)
+    shape = R.launch_shape(ctx, batch, cfg)
+    _say(f"in-launch refinement shape {shape}")
+    assert shape["segments"] <= n // (2 * E)
+    snaps = torch.zeros((E, 1, nb + 2), dtype=torch.float64, device="cuda")
+    hist, stats, depths, log = R.run_refined(ctx, w["species"], batch, cfg, E, probs, gap, log_cap=1000000,
+                                             in_launch=True, snapshots=snaps)
+    torch.cuda.synchronize()
+    st = R.parse_stats(stats)
+    _say(f"in-launch refinement stats {st}")
+    assert st["primaries"] == n and st["error_flags"] == 0
+    assert st["w_stopped"] + st["w_backscattered"] + st["w_quarantined"] == n
+    assert float(hist.sum()) + st["w_underflow"] + st["w_overflow"] == st["w_stopped"]
+    lg = R.parse_log(log, st["log_count"])
+    assert len(lg) == st["finished"]
+    d, S = depths.cpu().numpy(), snaps.cpu().numpy()
+    assert np.array_equal(d[0], [first]) and not S[0].any()
+    final = oracle.table_stats(lg, batch["table"].cpu().numpy(), 1, nb, bw)
+    for e in range(1, E):
+        assert S[e, 0, nb + 1] > 0.0, e
+        assert np.all(S[e] <= final), e
+        ref = oracle.refine_depths(S[e], nb, bw, probs, d[0], gap)
+        assert np.allclose(d[e], ref, rtol=0, atol=1e-6), (e, d[e], ref)
+    s = lg[lg["status"] == R.STOPPED]
+    D, p = physref.weighted_ks(s["z_stop"], s["w"], zo, wo)
+    _say(f"in-launch depths {np.round(d[:, 0], 1).tolist()} from booked weight "
+         f"{S[:, 0, nb + 1].tolist()}; KS D={D:.4g} p={p:.3g}")
+    assert p > 0.01
+    with pytest.raises(R.ReedmdError, match="persistent"):
+        R.run_refined(ctx, w["species"], batch, rcfg(R, n_bins=nb, thresholds=[first]), E, probs, gap,
+                      in_launch=True)
+
+
 def _c1_subset_batches(R, ctx):
     w = WORKLOADS["c1_as10kev"]
     sc = R.SamplerConfig(**w["sampler"])
