@@ -44,9 +44,9 @@ FLOP_PER_PAIR_F32_PART = 38
 # launch match the ones the counters were taken on.
 MEASURED_TRAFFIC = {
     "sources_sha256_prefix": "534c6a647a68fcc4",
-    "workload": "c2", "form": "persistent", "lanes": 32, "primaries": 1048576, "slice": 52429,
-    "fetch_bytes": 2287511.4 * 1024 * 2.000,
-    "write_bytes": 4466904.0 * 1024 * 1.000,
+    "workload": "c2", "form": "persistent", "lanes": 32, "blocks": 256, "primaries": 1048576, "slice": 52429,
+    "fetch_bytes": 1738149.6 * 1024 * 2.000,
+    "write_bytes": 3731298.2 * 1024 * 1.000,
 }
 
 
@@ -91,6 +91,9 @@ def parse():
     ap.add_argument("--no-c4", action="store_true", help="skip the 100 keV As deep-tail accuracy leg")
     ap.add_argument("--no-fkbk", action="store_true", help="skip the Firsov + Brandt-Kitagawa stopping leg")
     ap.add_argument("--uo2-n", type=int, default=0, help="primaries of the UO2 leg (default: the workload's 5,120)")
+    ap.add_argument("--grid-share", choices=["half", "full"], default="half",
+                    help="with several streams and no --waves: each step's persistent grid takes half of the "
+                         "resident workgroups (half) or all of them (full)")
     ap.add_argument("--streams", type=int, default=3,
                     help="sliced workloads: steps go round-robin to this many streams, each with its own "
                          "context, with no host synchronisation between them (1: one stream, one step at a time)")
@@ -766,9 +769,17 @@ def main():
         f, lanes, waves = (R.FORM_PLAIN if args.form == "plain" else R.FORM_PERSISTENT), args.lanes, args.waves
     cfg = R.RunConfig(form=f, lanes_per_track=lanes, waves_per_cu=waves, **base)
     shape = R.launch_shape(ctx, tb, cfg)
+    S = max(1, args.streams) if not whole else 1
+    if S > 1 and args.waves == 0 and f == R.FORM_PERSISTENT and args.grid_share == "half":
+        # steps on several streams share the GPU: each persistent grid takes half of the
+        # workgroups that fit (at least one per CU), so that the bulk of the next steps and the
+        # tail launches of the earlier ones run side by side
+        bpc = max(1, waves // 4) if waves > 0 else shape["blocks_per_cu"]
+        waves = 4 * max(1, bpc // 2)
+        cfg = R.RunConfig(form=f, lanes_per_track=lanes, waves_per_cu=waves, **base)
+        shape = R.launch_shape(ctx, tb, cfg)
 
     progress(f"workload {key}: {N} primaries, {sl} per step, shape {shape}")
-    S = max(1, args.streams) if not whole else 1
     if S == 1:
         if warm:
             progress("warm-up")
@@ -799,7 +810,8 @@ def main():
     m = MEASURED_TRAFFIC
     traffic = None
     if (kernel_sources_hash() == m["sources_sha256_prefix"] and key == m["workload"] and not whole
-            and cfg.form == R.FORM_PERSISTENT and shape["lanes"] == m["lanes"] and N == m["primaries"]
+            and cfg.form == R.FORM_PERSISTENT and shape["lanes"] == m["lanes"] and shape["blocks"] == m["blocks"]
+            and N == m["primaries"]
             and sl == m["slice"]):
         traffic = m["fetch_bytes"] + m["write_bytes"]
     out = {
