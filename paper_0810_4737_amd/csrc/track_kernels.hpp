@@ -502,6 +502,9 @@ __device__ __forceinline__ void track_step(TrackRegs<L, LAT>& t, const KernelArg
     constexpr bool CUT = (VAR & kVarCut) != 0;
     constexpr bool FK = (VAR & kVarFirsov) != 0;
     static_assert(!(FK && F32), "the Firsov stopping variant has FP64 pair terms");
+    // the run's scalar settings re-read from the argument segment at every step (scalar
+    // loads), instead of registers held across the persistent loop that the allocator spills
+    const KernelArgs C = cold_args();
     const SpeciesConst& c = sp[t.species];
     const PairConst& c1 = pair_table2(sp)[t.species];
     const double M1 = c.M1;
@@ -509,19 +512,19 @@ __device__ __forceinline__ void track_step(TrackRegs<L, LAT>& t, const KernelArg
     const double f2 = t.Fx * t.Fx + t.Fy * t.Fy + t.Fz * t.Fz;
     const double vmax2 = fmax(v2, t.vmax2a);
     const double amax2 = fmax(f2 * c.inv_M1sq, t.amax2a);
-    double dt = A.dt_max;
-    if (vmax2 > 0.0) dt = fmin(dt, A.dx_max * rsqrt_pos(vmax2));
-    if (amax2 > 0.0) dt = fmin(dt, sqrt(2.0 * A.dx_max * rsqrt_pos(amax2)));
+    double dt = C.dt_max;
+    if (vmax2 > 0.0) dt = fmin(dt, C.dx_max * rsqrt_pos(vmax2));
+    if (amax2 > 0.0) dt = fmin(dt, sqrt(2.0 * C.dx_max * rsqrt_pos(amax2)));
     if (fresh) dt = 0.0;
     if (info != nullptr) {
-        const bool by_a = amax2 > 0.0 && dt == sqrt(2.0 * A.dx_max * rsqrt_pos(amax2));
-        const bool by_v = vmax2 > 0.0 && dt == A.dx_max * rsqrt_pos(vmax2);
+        const bool by_a = amax2 > 0.0 && dt == sqrt(2.0 * C.dx_max * rsqrt_pos(amax2));
+        const bool by_v = vmax2 > 0.0 && dt == C.dx_max * rsqrt_pos(vmax2);
         info->dt = dt;
         info->code = (by_a ? 2 : (by_v ? 1 : 0)) | ((v2 >= t.vmax2a) ? 4 : 0) |
                      ((f2 * c.inv_M1sq >= t.amax2a) ? 8 : 0);
     }
     ke0 = 0.5 * M1 * v2;
-    z0 = range_coord(t, A.range_mode);
+    z0 = range_coord(t, C.range_mode);
 
     const double h1 = dt * c.half_inv_M1;
     double g1 = c.g_const + c.g_rho * t.rho;
@@ -537,9 +540,9 @@ __device__ __forceinline__ void track_step(TrackRegs<L, LAT>& t, const KernelArg
     t.y += t.vy * dt;
     t.z += t.vz * dt;
 
-    if (fresh || !inside_cell(t.x, t.cx, A.a, A.inv_a) || !inside_cell(t.y, t.cy, A.a, A.inv_a) ||
-        !inside_cell(t.z, t.cz, A.a, A.inv_a)) {
-        const int ncx = floor_cell(t.x, A.a), ncy = floor_cell(t.y, A.a), ncz = floor_cell(t.z, A.a);
+    if (fresh || !inside_cell(t.x, t.cx, C.a, C.inv_a) || !inside_cell(t.y, t.cy, C.a, C.inv_a) ||
+        !inside_cell(t.z, t.cz, C.a, C.inv_a)) {
+        const int ncx = floor_cell(t.x, C.a), ncy = floor_cell(t.y, C.a), ncz = floor_cell(t.z, C.a);
         if (fresh || ncx != t.cx || ncy != t.cy || ncz != t.cz) regenerate<L, LAT>(t, A, sl, ncx, ncy, ncz, fresh, drop);
     }
 
@@ -547,8 +550,8 @@ __device__ __forceinline__ void track_step(TrackRegs<L, LAT>& t, const KernelArg
     // atom kick and drift, pair term at the new positions, second atom kick
     // (fluorite: register slot i holds anions from slot 128 on, a whole lane row
     // of one target species, so the choice of constants and mass is static)
-    const double h2a = dt * A.half_inv_M2;
-    const double h2b = FL ? dt * A.half_inv_M2b : h2a;
+    const double h2a = dt * C.half_inv_M2;
+    const double h2b = FL ? dt * C.half_inv_M2b : h2a;
     constexpr int G = SegReduce<L>::G;
     double Fx[G], Fy[G], Fz[G], rho[G], rho1[G];
 #pragma unroll
@@ -578,7 +581,7 @@ __device__ __forceinline__ void track_step(TrackRegs<L, LAT>& t, const KernelArg
             t.avx[i] = vx; t.avy[i] = vy; t.avz[i] = vz;
             t.ax[i] = px; t.ay[i] = py; t.az[i] = pz;
             const double dx = t.x - px, dy = t.y - py, dz = t.z - pz;
-            const bool in = dx * dx + dy * dy + dz * dz <= A.rc2;
+            const bool in = dx * dx + dy * dy + dz * dz <= C.rc2;
             f[0 * FS] = in ? px : 0.0;
             f[1 * FS] = in ? py : 0.0;
             f[2 * FS] = in ? pz : 0.0;
@@ -600,7 +603,7 @@ __device__ __forceinline__ void track_step(TrackRegs<L, LAT>& t, const KernelArg
             const int j = k * L + sl;
             const bool valid = j < count;
             const int s = valid ? list[j] : 0;
-            double dx = 0.0, dy = 0.0, dz = A.park;
+            double dx = 0.0, dy = 0.0, dz = C.park;
             if (valid) {
                 dx = t.x - t.fl[0 * FS + s];
                 dy = t.y - t.fl[1 * FS + s];
@@ -663,7 +666,7 @@ __device__ __forceinline__ void track_step(TrackRegs<L, LAT>& t, const KernelArg
             t.avx[i] = vx; t.avy[i] = vy; t.avz[i] = vz;
             f[0 * FS] = fx; f[1 * FS] = fy; f[2 * FS] = fz;
             vm = fmax(vm, vx * vx + vy * vy + vz * vz);
-            if constexpr (FL) fm = fmax(fm, (fx * fx + fy * fy + fz * fz) * (anion ? A.inv_M2bsq : A.inv_M2sq));
+            if constexpr (FL) fm = fmax(fm, (fx * fx + fy * fy + fz * fz) * (anion ? C.inv_M2bsq : C.inv_M2sq));
             else fm = fmax(fm, fx * fx + fy * fy + fz * fz);
     #if REEDMD_PAIR_BARRIER
             __builtin_amdgcn_sched_barrier(0);
@@ -680,7 +683,7 @@ __device__ __forceinline__ void track_step(TrackRegs<L, LAT>& t, const KernelArg
     } else {
         t.rho = SegReduce<L>::csum(rho) * c.wnorm;
         t.vmax2a = SegReduce<L>::max(vm);
-        t.amax2a = SegReduce<L>::max(fm) * A.inv_M2sq;
+        t.amax2a = SegReduce<L>::max(fm) * C.inv_M2sq;
     }
 
     // second half kick, then the friction at the kicked speed
@@ -859,17 +862,18 @@ template <int L, int LAT>
 __device__ __forceinline__ int track_events(TrackRegs<L, LAT>& t, const KernelArgs& A, const SpeciesConst* sp,
                                             double ke0, double z0)
 {
+    const KernelArgs C = cold_args();
     const bool finite = isfinite(t.x) && isfinite(t.y) && isfinite(t.z) && isfinite(t.vx) &&
                         isfinite(t.vy) && isfinite(t.vz);
     if (!finite) return REEDMD_NONFINITE;
     const double ke = 0.5 * sp[t.species].M1 * (t.vx * t.vx + t.vy * t.vy + t.vz * t.vz);
-    if (ke < A.E_stop) {
-        const double zr = range_coord(t, A.range_mode);
-        t.zstop = (ke0 > A.E_stop) ? z0 + (zr - z0) * (ke0 - A.E_stop) / (ke0 - ke) : z0;
+    if (ke < C.E_stop) {
+        const double zr = range_coord(t, C.range_mode);
+        t.zstop = (ke0 > C.E_stop) ? z0 + (zr - z0) * (ke0 - C.E_stop) / (ke0 - ke) : z0;
         return REEDMD_STOPPED;
     }
-    if (t.z < A.z_start && t.vz < 0.0) return REEDMD_BACKSCATTERED;
-    if (A.max_steps > 0 && t.steps >= A.max_steps) return REEDMD_STEPCAP;
+    if (t.z < C.z_start && t.vz < 0.0) return REEDMD_BACKSCATTERED;
+    if (C.max_steps > 0 && t.steps >= C.max_steps) return REEDMD_STEPCAP;
     return REEDMD_ACTIVE;
 }
 
