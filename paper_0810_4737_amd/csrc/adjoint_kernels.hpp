@@ -103,13 +103,14 @@ template <int L>
 __device__ __forceinline__ void pair_state(const TrackRegs<L>& t, const KernelArgs& A, const SpeciesConst& c,
                                            PairState<L>& P)
 {
+    const KernelArgs K = cold_args();
 #pragma unroll
     for (int i = 0; i < TrackRegs<L>::SL; ++i) {
         P.c[i] = 0.0; P.cr[i] = 0.0; P.cs[i] = 0.0; P.w[i] = 0.0; P.ir[i] = 0.0;
         if (!((t.exist >> i) & 1u)) continue;
         const double dx = t.x - t.ax[i], dy = t.y - t.ay[i], dz = t.z - t.az[i];
         double r;
-        zbl_pair_adjoint(c, A.inv_s, dx * dx + dy * dy + dz * dz, r, P.ir[i],
+        zbl_pair_adjoint(c, K.inv_s, dx * dx + dy * dy + dz * dz, r, P.ir[i],
                          P.c[i], P.cr[i], P.cs[i], P.w[i]);
         __builtin_amdgcn_sched_barrier(0);
     }
@@ -129,6 +130,9 @@ __device__ __forceinline__ void reverse_step_regs(AdjIon& ai, AdjAtoms<L>& aa, P
 {
     constexpr int SL = TrackRegs<L>::SL;
     constexpr int FS = TrackRegs<L>::FS;
+    // the run's scalar settings re-read from the argument segment at every step (scalar loads)
+    // instead of registers held across the reverse sweep that the allocator spills
+    const KernelArgs K = cold_args();
     // centres of S_{n+1} and S_n; parking place of S_n's empty slots
     const int c1x = t.cx, c1y = t.cy, c1z = t.cz;
     int cnx = c1x, cny = c1y, cnz = c1z;
@@ -147,7 +151,7 @@ __device__ __forceinline__ void reverse_step_regs(AdjIon& ai, AdjAtoms<L>& aa, P
     const double dt = lgn[0];
     const int code = static_cast<int>(reinterpret_cast<const long long*>(lgn)[1]);
     const double h1 = dt * c.half_inv_M1;
-    const double h2 = dt * A.half_inv_M2;
+    const double h2 = dt * K.half_inv_M2;
     // ---- ion of S_{n+1}; the ion of S_n is the logged one (the chaotic part of the
     //      state is never run backwards)
     const double x1[3] = {t.x, t.y, t.z};
@@ -222,7 +226,7 @@ __device__ __forceinline__ void reverse_step_regs(AdjIon& ai, AdjAtoms<L>& aa, P
         if (en) {
             double dn[3], rn;
             for (int k = 0; k < 3; ++k) dn[k] = x[k] - X[k];
-            zbl_pair_adjoint(c, A.inv_s, dn[0] * dn[0] + dn[1] * dn[1] + dn[2] * dn[2],
+            zbl_pair_adjoint(c, K.inv_s, dn[0] * dn[0] + dn[1] * dn[1] + dn[2] * dn[2],
                              rn, irn, cn, crn, csn, wn);
             for (int k = 0; k < 3; ++k) {
                 fn[k] = -cn * dn[k];
@@ -288,7 +292,7 @@ __device__ __forceinline__ void reverse_step_regs(AdjIon& ai, AdjAtoms<L>& aa, P
     const double vm = (branch == 1 && !(code & 4)) ? SegReduce<L>::max(vm_l) : 0.0;
     const double fm = (branch == 2 && !(code & 8)) ? SegReduce<L>::max(fm_l) : 0.0;
     // d/dt through the atoms' drifts and, via h2 = dt / 2M2, their kicks: one reduction
-    double dtb = SegReduce<L>::sum(dtb_l + h2b_l * A.half_inv_M2);
+    double dtb = SegReduce<L>::sum(dtb_l + h2b_l * K.half_inv_M2);
 
     // ---- first friction half and kick of the step
     const double g1 = c.g_const + c.g_rho * rho;
@@ -343,7 +347,7 @@ __device__ __forceinline__ void reverse_step_regs(AdjIon& ai, AdjAtoms<L>& aa, P
     } else if (branch == 2) {
         const bool ion = (code & 8) != 0;
         const double f2 = F[0] * F[0] + F[1] * F[1] + F[2] * F[2];
-        const double amax2b = -0.25 * dtb * dt / (ion ? f2 * c.inv_M1sq : fm * A.inv_M2sq);
+        const double amax2b = -0.25 * dtb * dt / (ion ? f2 * c.inv_M1sq : fm * K.inv_M2sq);
         if (ion) {
             for (int k = 0; k < 3; ++k) ai.Fb[k] += 2.0 * amax2b * F[k] * c.inv_M1sq;
         } else {
@@ -352,9 +356,9 @@ __device__ __forceinline__ void reverse_step_regs(AdjIon& ai, AdjAtoms<L>& aa, P
                 if (f2s[i] == fm) {
                     const double* f = t.fl + (sl + L * i);
                     const double fx = f[0], fy = f[FS], fz = f[2 * FS];
-                    aa.fb[0][i] += 2.0 * amax2b * fx * A.inv_M2sq;
-                    aa.fb[1][i] += 2.0 * amax2b * fy * A.inv_M2sq;
-                    aa.fb[2][i] += 2.0 * amax2b * fz * A.inv_M2sq;
+                    aa.fb[0][i] += 2.0 * amax2b * fx * K.inv_M2sq;
+                    aa.fb[1][i] += 2.0 * amax2b * fy * K.inv_M2sq;
+                    aa.fb[2][i] += 2.0 * amax2b * fz * K.inv_M2sq;
                 }
             }
         }
