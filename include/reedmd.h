@@ -308,6 +308,8 @@ typedef struct {
     const double* probs;    /* host, n_thresh target survival probabilities, strictly decreasing in (0,1) */
     double min_gap;         /* minimum spacing of successive depths (A), >= 0 */
     double* snapshots;      /* in_launch only: optional device [n_epochs][n_tables][n_bins + 2] */
+    double min_weight;      /* a target k is placed only if probs[k] x booked weight >= min_weight
+                               (primaries' worth; 1 is a good default), finite, >= 0 */
 } reedmd_refine;
 
 /* Like reedmd_run, with the cloning depths refined between epochs.  Epoch e
@@ -316,8 +318,11 @@ typedef struct {
  * Before epoch e > 0 every table is re-placed from all tracks of that table
  * booked so far: with S(z) = (weight stopped at z_stop >= z) / (all weight
  * booked for the table) on the histogram's bin edges, depth k is where S falls
- * to probs[k] (linear in S within the bin); a target that S does not reach
- * within the histogram keeps its previous depth; the depths are then made
+ * to probs[k] (linear in S within the bin); the targets placed so are the
+ * leading ones, and the rest (S does not reach them within the histogram, or
+ * the statistics are too thin for them: probs[k] times the booked weight
+ * below min_weight) keep their previous depths shifted by the move of the last
+ * placed depth (unshifted when none is placed); the depths are then made
  * increasing by at least min_gap.  New depths apply only to primaries started
  * later, so every primary family keeps one depth table and the estimator stays
  * unbiased.  d_hist, d_stats and the optional track log accumulate over all

@@ -512,12 +512,22 @@ def run(cfg: Config, prim: dict, nthreads: int | None = None, log: bool = False,
     cnt = C.c_int64(0)
     if nthreads is None:
         nthreads = os.cpu_count() or 1
-    rc = L.or_run(C.byref(p), n, species.ctypes.data, E0.ctypes.data, pos.ctypes.data,
-                  dr.ctypes.data, key.ctypes.data, table.ctypes.data,
-                  None if lin is None else lin.ctypes.data, int(nthreads), hist.ctypes.data,
-                  C.byref(st), C.cast(logbuf, C.c_void_p) if log else None, cap, C.byref(cnt))
-    if rc != 0:
-        raise RuntimeError(f"oracle run failed ({rc})")
+    while True:
+        rc = L.or_run(C.byref(p), n, species.ctypes.data, E0.ctypes.data, pos.ctypes.data,
+                      dr.ctypes.data, key.ctypes.data, table.ctypes.data,
+                      None if lin is None else lin.ctypes.data, int(nthreads), hist.ctypes.data,
+                      C.byref(st), C.cast(logbuf, C.c_void_p) if log else None, cap, C.byref(cnt))
+        if rc != 0:
+            raise RuntimeError(f"oracle run failed ({rc})")
+        if not log or cnt.value <= cap:
+            break
+        # the families split more often than the first guess of the log's size: run again (every
+        # track is deterministic) with room for every finished track
+        cap = int(cnt.value) + 16
+        logbuf = (Result * cap)()
+        hist[:] = 0.0
+        st = Stats()
+        cnt = C.c_int64(0)
     out = dict(hist=hist, stats=st.as_dict(), nthreads=int(nthreads))
     if log:
         m = min(cnt.value, cap)
@@ -527,31 +537,41 @@ def run(cfg: Config, prim: dict, nthreads: int | None = None, log: bool = False,
 
 
 # --------------------------------------------------------------------------- adaptive depths
-def refine_depths(tstat, n_bins: int, bin_width: float, probs, old, min_gap: float):
+def refine_depths(tstat, n_bins: int, bin_width: float, probs, old, min_gap: float, min_weight: float = 1.0):
     """Cloning depths re-placed from the statistics gathered so far (Sec. 2: depths from the
     ongoing statistics; Sec. 3: criteria updated between complete tracks).
 
     tstat[t] = (stopped weight in each of the n_bins depth bins, stopped weight beyond the
     last bin, all weight booked for table t).  The survival S(z) = (stopped weight with
     z_stop >= z) / (all booked weight) is taken at the bin edges; depth k of table t is where
-    S falls to probs[k], linear in S inside the bin; a target that S does not reach within
-    the histogram keeps the old depth; finally each depth is raised to at least the previous
-    one plus min_gap."""
+    S falls to probs[k], linear in S inside the bin.  The targets placed this way are the
+    leading ones; the rest, those S does not reach within the histogram or that the statistics
+    are too thin for (probs[k] times the booked weight below min_weight: less than that much
+    weight is expected beyond the depth), keep their old depths shifted by the move of the last
+    placed depth (all of them unshifted when none is placed); finally each depth is raised to
+    at least the previous one plus min_gap."""
     tstat = np.asarray(tstat, dtype=np.float64)
     new = np.array(np.atleast_2d(old), dtype=np.float64, copy=True)
     for t in range(new.shape[0]):
+        old_t = np.array(new[t])
         h = tstat[t, :n_bins]
         over, total = tstat[t, n_bins], tstat[t, n_bins + 1]
         if total > 0.0:
             beyond = np.append(np.cumsum(h[::-1])[::-1], 0.0) + over   # at edges 0 .. n_bins
             S = beyond / total
+            placed = 0
             for k, pk in enumerate(probs):
+                if pk * total < min_weight:
+                    break
                 below = np.nonzero(S[1:] <= pk)[0]      # bins whose upper edge is at or below pk
                 if below.size == 0:
-                    continue
+                    break
                 b = int(below[0])
                 lo, hi = S[b], S[b + 1]
                 new[t, k] = (b + (lo - pk) / (lo - hi)) * bin_width if pk < lo else b * bin_width
+                placed = k + 1
+            if placed > 0:
+                new[t, placed:] += new[t, placed - 1] - old_t[placed - 1]
         for k in range(1, new.shape[1]):
             new[t, k] = max(new[t, k], new[t, k - 1] + min_gap)
     return new
@@ -571,7 +591,7 @@ def table_stats(log, tables, n_tables: int, n_bins: int, bin_width: float):
 
 
 def run_refined(cfg: Config, prim: dict, n_epochs: int, probs, min_gap: float = 1.0,
-                nthreads: int | None = None):
+                nthreads: int | None = None, min_weight: float = 1.0):
     """The batch in n_epochs consecutive id ranges (epoch e: ids [n e / E, n (e+1) / E)), the
     depth tables re-placed before every epoch after the first from all tracks finished so far
     (refine_depths); cfg.thresholds are the tables of epoch 0.  Returns dict(hist, stats,
@@ -585,7 +605,7 @@ def run_refined(cfg: Config, prim: dict, n_epochs: int, probs, min_gap: float = 
     for e in range(E):
         lo, hi = n * e // E, n * (e + 1) // E
         if e > 0:
-            thr = refine_depths(ts, cfg.n_bins, cfg.bin_width, probs, thr, min_gap)
+            thr = refine_depths(ts, cfg.n_bins, cfg.bin_width, probs, thr, min_gap, min_weight)
         depths.append(thr.copy())
         sub = {k: v[..., lo:hi] for k, v in prim.items()}
         c = Config(**{**cfg.__dict__, "thresholds": thr})

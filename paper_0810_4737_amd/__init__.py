@@ -292,12 +292,14 @@ def _run_noalloc(ctx, species, batch, p, hist, stats, id0, stream):
 
 
 def run_refined(ctx: Context, species, batch, cfg: RunConfig, n_epochs: int, probs, min_gap: float = 1.0,
-                hist=None, stats=None, id0=0, log_cap=0, stream=None, in_launch=False, snapshots=None):
+                hist=None, stats=None, id0=0, log_cap=0, stream=None, in_launch=False, snapshots=None,
+                min_weight=1.0):
     """Runs the batch in n_epochs epochs with the cloning depths re-placed between epochs from
     the survival of the tracks booked so far (cfg.thresholds: the tables of epoch 0).
     in_launch: every epoch inside one persistent launch (epochs by claim position, each
     version placed from the caller's tables); snapshots: optional float64 device tensor
-    [n_epochs, n_tables, n_bins + 2] that receives the statistics each version was placed from.
+    [n_epochs, n_tables, n_bins + 2] that receives the statistics each version was placed from;
+    min_weight: a target is placed only if target x booked weight (primaries' worth) reaches it.
     Returns (hist, stats, depths[n_epochs, n_tables, n_thresh][, log])."""
     dev = batch["energy"].device
     keep = []
@@ -320,6 +322,7 @@ def run_refined(ctx: Context, species, batch, cfg: RunConfig, n_epochs: int, pro
     rf.probs = pr.ctypes.data_as(C.POINTER(C.c_double))
     rf.min_gap = float(min_gap)
     rf.in_launch = 1 if in_launch else 0
+    rf.min_weight = float(min_weight)
     if snapshots is not None:
         E = max(1, min(int(n_epochs), int(batch["energy"].shape[0])))
         if snapshots.dtype != torch.float64 or not snapshots.is_contiguous() or \

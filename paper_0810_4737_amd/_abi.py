@@ -71,7 +71,7 @@ class RunParams(C.Structure):
 
 class Refine(C.Structure):
     _fields_ = [("n_epochs", C.c_int32), ("in_launch", C.c_int32), ("probs", C.POINTER(C.c_double)),
-                ("min_gap", C.c_double), ("snapshots", C.c_void_p)]
+                ("min_gap", C.c_double), ("snapshots", C.c_void_p), ("min_weight", C.c_double)]
 
 
 class Result(C.Structure):

@@ -788,7 +788,7 @@ Shape choose_shape(reedmd_ctx* ctx, const reedmd_run_params* p, const reedmd_bat
 struct RefineLaunch {
     int E;
     const double* probs;
-    double min_gap;
+    double min_gap, min_weight;
     double* snap;
     int* ready;
 };
@@ -826,6 +826,7 @@ reedmd_status run_impl(reedmd_ctx* ctx, const reedmd_species* sp, const reedmd_b
         A.refine_E = rl->E;
         A.r_probs = rl->probs;
         A.r_min_gap = rl->min_gap;
+        A.r_min_weight = rl->min_weight;
         A.r_snap = rl->snap;
         A.r_ready = rl->ready;
     }
@@ -932,13 +933,18 @@ reedmd_status run_impl(reedmd_ctx* ctx, const reedmd_species* sp, const reedmd_b
 // Adaptive cloning depths between launches (Sec. 2: depths placed from the
 // statistics gathered so far; Sec. 3: criteria updated between complete
 // tracks): every table re-placed from its statistics by refine_table, starting
-// from its current depths.  One thread per table.
+// from its current depths; a row holds each booked track's weight in one entry (its
+// depth bin, beyond the last bin, or not stopped in the crystal), so its sum is
+// all weight booked.  One thread per table.
 __global__ void refine_kernel(const double* tstat, int n_bins, double bin_width, int n_tables, int n_thresh,
-                              const double* probs, double min_gap, double* thr)
+                              const double* probs, double min_gap, double min_weight, double* thr)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n_tables) return;
-    refine_table(tstat + static_cast<size_t>(t) * (n_bins + 2), n_bins, bin_width, n_thresh, probs, min_gap,
+    const double* h = tstat + static_cast<size_t>(t) * (n_bins + 2);
+    double total = 0.0;
+    for (int i = 0; i < n_bins + 2; ++i) total += h[i];
+    refine_table(h, total, n_bins, bin_width, n_thresh, probs, min_gap, min_weight,
                  thr + static_cast<size_t>(t) * n_thresh);
 }
 
@@ -1627,7 +1633,7 @@ static reedmd_status run_refined_in_launch(reedmd_ctx* ctx, const reedmd_species
         p.thresholds = thr;
         p.r_cut = choose_shape(ctx, params, batch).r_cut;
         const Shape shape = choose_shape(ctx, &p, batch);
-        const RefineLaunch rl{E, probs, rf->min_gap, snap, ready};
+        const RefineLaunch rl{E, probs, rf->min_gap, rf->min_weight, snap, ready};
         const reedmd_status rs = run_impl(ctx, species, batch, &p, d_hist, d_stats, stream, &shape, tstat, nullptr, &rl);
         if (rs != REEDMD_OK) return rs;
         if (d_depths) HIP_TRY(ctx, hipMemcpyAsync(d_depths, thr, thr_b, hipMemcpyDeviceToDevice, stream));
@@ -1655,6 +1661,8 @@ reedmd_status reedmd_run_refined(reedmd_ctx* ctx, const reedmd_species* species,
     if (params->n_thresh < 1) return fail(ctx, REEDMD_EINVAL, "adaptive depths need n_thresh >= 1");
     if (rf->n_epochs < 1 || rf->n_epochs > 4096) return fail(ctx, REEDMD_EINVAL, "n_epochs must be in 1..4096");
     if (!(rf->min_gap >= 0.0) || !std::isfinite(rf->min_gap)) return fail(ctx, REEDMD_EINVAL, "min_gap must be >= 0");
+    if (!(rf->min_weight >= 0.0) || !std::isfinite(rf->min_weight))
+        return fail(ctx, REEDMD_EINVAL, "min_weight must be finite and >= 0");
     for (int k = 0; k < params->n_thresh; ++k) {
         const double pk = rf->probs[k];
         if (!(pk > 0.0 && pk < 1.0) || (k > 0 && !(pk < rf->probs[k - 1])))
@@ -1701,7 +1709,7 @@ reedmd_status reedmd_run_refined(reedmd_ctx* ctx, const reedmd_species* species,
             const long long lo = n * e / E, hi = n * (e + 1) / E, ne = hi - lo;
             if (e > 0)
                 hipLaunchKernelGGL(refine_kernel, dim3((nt + 63) / 64), dim3(64), 0, stream, tstat, nb,
-                                   params->bin_width, nt, nk, probs, rf->min_gap, thr);
+                                   params->bin_width, nt, nk, probs, rf->min_gap, rf->min_weight, thr);
             HIP_TRY(ctx, hipGetLastError());
             if (d_depths)
                 HIP_TRY(ctx, hipMemcpyAsync(d_depths + static_cast<size_t>(e) * nt * nk, thr, thr_b,

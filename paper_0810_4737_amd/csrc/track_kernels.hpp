@@ -103,7 +103,7 @@ struct KernelArgs {
     int refine_E;
     int pad_refine;
     const double* r_probs;
-    double r_min_gap;
+    double r_min_gap, r_min_weight;
     double* r_snap;
     int* r_ready;
     const int* order;       // optional: batch entry of the i-th claimed primary (longest expected first)
@@ -888,31 +888,41 @@ __device__ __forceinline__ void add_i64(int64_t* p, long long v)
 }
 
 // Re-places one depth table (Sec. 2: depths from the statistics gathered so far; Sec. 3:
-// criteria updated between complete tracks).  h: the table's statistics, stopped weight per
-// depth bin, stopped weight beyond the last bin, all weight booked; d: on entry the previous
-// depths, on return the new ones.  S(z) = (stopped weight with z_stop >= z) / (all booked
-// weight) at the bin edges; depth k is where S falls to probs[k], linear in S inside the bin;
-// a target S does not reach within the histogram keeps its depth; then every depth is raised
-// to at least the previous one plus min_gap.
-__device__ inline void refine_table(const double* h, int n_bins, double bin_width, int n_thresh,
-                                    const double* probs, double min_gap, double* d)
+// criteria updated between complete tracks).  h: the table's stopped weight per depth bin and
+// beyond the last bin (n_bins + 1 entries); total: all weight booked for the table; d: on entry
+// the previous depths, on return the new ones.  S(z) = (stopped weight with z_stop >= z) / (all booked
+// weight) at the bin edges; depth k is where S falls to probs[k], linear in S inside the bin.
+// The targets placed this way are the leading ones; the rest, those S does not reach within the
+// histogram or that the statistics are too thin for (probs[k] * booked weight < min_weight: less
+// than that much weight is expected beyond it; the targets decrease, so the rest are too), keep
+// their depths shifted by the move of the last placed depth (unshifted when none is placed);
+// then every depth is raised to at least the previous one plus min_gap.
+__device__ inline void refine_table(const double* h, double total, int n_bins, double bin_width, int n_thresh,
+                                    const double* probs, double min_gap, double min_weight, double* d)
 {
-    const double total = h[n_bins + 1];
-    if (total > 0.0) {
+    int resolvable = 0;
+    while (resolvable < n_thresh && probs[resolvable] * total >= min_weight) ++resolvable;
+    if (total > 0.0 && resolvable > 0) {
         double beyond = h[n_bins];                 // stopped weight at or beyond the lower edge of bin b
         for (int b = n_bins - 1; b >= 0; --b) beyond += h[b];
         double s_lo = beyond / total;
         int k = 0;
-        for (int b = 0; b < n_bins && k < n_thresh; ++b) {
+        double moved = 0.0;                        // move of the last placed depth
+        for (int b = 0; b < n_bins && k < resolvable; ++b) {
             beyond -= h[b];
             const double s_hi = beyond / total;
-            while (k < n_thresh && probs[k] >= s_hi) {
-                d[k] = (probs[k] < s_lo) ? (static_cast<double>(b) + (s_lo - probs[k]) / (s_lo - s_hi)) * bin_width
-                                         : static_cast<double>(b) * bin_width;
+            while (k < resolvable && probs[k] >= s_hi) {
+                const double nd = (probs[k] < s_lo)
+                                      ? (static_cast<double>(b) + (s_lo - probs[k]) / (s_lo - s_hi)) * bin_width
+                                      : static_cast<double>(b) * bin_width;
+                moved = nd - d[k];
+                d[k] = nd;
                 ++k;
             }
             s_lo = s_hi;
         }
+        if (k > 0)
+            for (int j = k; j < n_thresh; ++j) d[j] += moved;
     }
     for (int k = 1; k < n_thresh; ++k) d[k] = fmax(d[k], d[k - 1] + min_gap);
 }
@@ -923,26 +933,41 @@ __device__ __forceinline__ long long epoch_first(long long n, int E, int e)
     return (n * e + E - 1) / E;
 }
 
-// Table version e of an in-launch refinement, computed by the L lanes of one segment (lane
-// sl takes tables sl, sl + L, ...): copies each table's statistics as they stand into the
-// snapshot, re-places the table from the snapshot starting from version 0 (the caller's
-// depths; a version depends on no other version, so nothing waits while it is computed),
-// then publishes the version.  Kept out of line: a cold path whose registers stay out of
-// the track kernel's allocation.
+// Table version e of an in-launch refinement, computed by the L lanes of one segment:
+// copies every table's statistics as they stand into the snapshot (the lanes take the entries
+// in turn; each finished track is booked into exactly one entry of its table's row, so a
+// snapshot taken while tracks finish still holds only whole tracks' weights, and its total, the
+// sum of the row, is what the row was made of), then lane sl re-places tables sl, sl + L, ...
+// from the snapshot starting from version 0 (the caller's depths; a version depends on no other
+// version, so nothing waits while it is computed), and publishes the version.  The snapshot
+// rows are zero on entry; their last entry receives the total.  Kept out of line: a cold path
+// whose registers stay out of the track kernel's allocation.
 __device__ __noinline__ void compute_version(const double* tstat, double* snap_all, double* thr, const double* probs,
-                                             double min_gap, double bin_width, int nb, int nt, int nk, int e,
-                                             int sl, int L, int* ready)
+                                             double min_gap, double min_weight, double bin_width, int nb, int nt,
+                                             int nk, int e, int sl, int L, int* ready)
 {
     const size_t sw = static_cast<size_t>(nb + 2);
-    for (int tb = sl; tb < nt; tb += L) {
+    for (int tb = 0; tb < nt; ++tb) {
         const double* live = tstat + static_cast<size_t>(tb) * sw;
         double* snap = snap_all + (static_cast<size_t>(e) * nt + tb) * sw;
-        for (size_t i = 0; i < sw; ++i)
-            snap[i] = __hip_atomic_load(&live[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        double part = 0.0;
+        for (size_t i = static_cast<size_t>(sl); i < sw; i += static_cast<size_t>(L)) {
+            const double v = __hip_atomic_load(&live[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (i + 1 < sw) snap[i] = v;
+            part += v;
+        }
+        // weights are sums of powers of two: the total is exact in any order
+        if (part != 0.0) unsafeAtomicAdd(&snap[sw - 1], part);
+    }
+    __threadfence();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    for (int tb = sl; tb < nt; tb += L) {
+        double* snap = snap_all + (static_cast<size_t>(e) * nt + tb) * sw;
+        const double total = __hip_atomic_load(&snap[sw - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const double* first = thr + static_cast<size_t>(tb) * nk;
         double* d = thr + (static_cast<size_t>(e) * nt + tb) * nk;
         for (int k = 0; k < nk; ++k) d[k] = first[k];
-        refine_table(snap, nb, bin_width, nk, probs, min_gap, d);
+        refine_table(snap, total, nb, bin_width, nk, probs, min_gap, min_weight, d);
     }
     __threadfence();
     if (sl == 0) __hip_atomic_store(&ready[e], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
@@ -955,14 +980,17 @@ __device__ __forceinline__ void book_finished(const KernelArgs& A, int status, d
 {
     reedmd_stats* S = A.stats;
     if (A.tstat != nullptr && table >= 0) {
-        // per-table survival statistics for adaptive cloning depths (the table field of a
-        // track also carries its table version: version * n_tables + table)
+        // per-table survival statistics for adaptive cloning depths, each track's weight in
+        // exactly one entry: its depth bin, beyond the last bin, or (not stopped in the crystal)
+        // the last entry; the row's sum is all weight booked for the table (the table field of
+        // a track also carries its table version: version * n_tables + table)
         double* ts = A.tstat + static_cast<size_t>(table % A.n_tables) * (A.n_bins + 2);
-        add_f64(&ts[A.n_bins + 1], w);
         if (status == REEDMD_STOPPED && zstop >= 0.0) {
             const double fb = floor(zstop / A.bin_width);
             if (!(fb < static_cast<double>(A.n_bins))) add_f64(&ts[A.n_bins], w);
             else add_f64(&ts[static_cast<int>(fb)], w);
+        } else {
+            add_f64(&ts[A.n_bins + 1], w);
         }
     }
     add_i64(&S->finished, 1);
@@ -1162,7 +1190,8 @@ __global__ void __launch_bounds__(256, REEDMD_WAVES_PER_SIMD(L, LAT)) track_kern
                     if (qi >= 0) version = static_cast<int>((qi * A.refine_E) / A.n);
                     if (qi >= 0 && version > 0 && qi == epoch_first(A.n, A.refine_E, version))
                         compute_version(A.tstat, A.r_snap, const_cast<double*>(A.thr), A.r_probs, A.r_min_gap,
-                                        A.bin_width, A.n_bins, A.n_tables, A.n_thresh, version, sl, L, A.r_ready);
+                                        A.r_min_weight, A.bin_width, A.n_bins, A.n_tables, A.n_thresh, version, sl,
+                                        L, A.r_ready);
                     if (qi >= 0 && version > 0) {
                         if (sl == 0)
                             while (__hip_atomic_load(&A.r_ready[version], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0)

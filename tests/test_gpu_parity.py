@@ -427,6 +427,50 @@ def test_in_launch_depths_follow_the_oracle_rule_and_statistics(R, ctx):
                       in_launch=True)
 
 
+def test_in_launch_depths_on_the_mixed_workload_six_tables(R, ctx):
+    """In-launch refinement with several tables (16,384 mixed B/P/As primaries at 1-100 keV,
+    the six (species, energy decade) tables of 12 depths as the first versions, targets
+    10^(-5k/12), 4 epochs, 32 lanes, one workgroup per CU): every version of every table is the
+    oracle's rule applied to its snapshot (1e-6 A), each snapshot is bounded by the run's final
+    per-table statistics element by element, and the ledger is exact."""
+    from tests.workloads import C2_THRESHOLDS
+    w = WORKLOADS["c2_mixed"]
+    n, E, gap = 16384, 4, 1.0
+    nb, bw = w["n_bins"], w["bin_width"]
+    probs = [10.0 ** (-5.0 * k / 12.0) for k in range(1, 13)]
+    first = [list(t) for t in C2_THRESHOLDS]
+    batch = R.sample_primaries(ctx, R.SamplerConfig(**w["sampler"]), 0, n)
+    cfg = rcfg(R, n_bins=nb, bin_width=bw, thresholds=first, form=R.FORM_PERSISTENT, lanes_per_track=32,
+               waves_per_cu=4)
+    shape = R.launch_shape(ctx, batch, cfg)
+    assert shape["segments"] <= n // (2 * E)
+    snaps = torch.zeros((E, 6, nb + 2), dtype=torch.float64, device="cuda")
+    hist, stats, depths, log = R.run_refined(ctx, w["species"], batch, cfg, E, probs, gap, log_cap=1000000,
+                                             in_launch=True, snapshots=snaps)
+    torch.cuda.synchronize()
+    st = R.parse_stats(stats)
+    _say(f"in-launch refinement, six tables: {st}")
+    assert st["primaries"] == n and st["error_flags"] == 0
+    assert float(hist.sum()) + st["w_underflow"] + st["w_overflow"] + st["w_backscattered"] + \
+        st["w_quarantined"] == float(n)
+    lg = R.parse_log(log, st["log_count"])
+    assert len(lg) == st["finished"]
+    d, S = depths.cpu().numpy(), snaps.cpu().numpy()
+    assert np.array_equal(d[0], np.array(first)) and not S[0].any()
+    final = oracle.table_stats(lg, batch["table"].cpu().numpy(), 6, nb, bw)
+    moved = 0
+    for e in range(1, E):
+        assert np.all(S[e] <= final), e
+        # claims run longest-expected first, so a table of short tracks may have booked nothing
+        # when the first epochs begin (its depths then stay); some table always has
+        assert S[e][:, nb + 1].max() > 0.0, e
+        ref = oracle.refine_depths(S[e], nb, bw, probs, d[0], gap)
+        assert np.allclose(d[e], ref, rtol=0, atol=1e-6), (e, np.abs(d[e] - ref).max())
+        moved += int(np.sum(np.abs(d[e] - d[0]) > 1.0))
+    _say(f"six-table versions: {moved} depths moved by more than 1 A; last {np.round(d[-1][:, :3], 1).tolist()}")
+    assert moved > 0
+
+
 def _c1_subset_batches(R, ctx):
     w = WORKLOADS["c1_as10kev"]
     sc = R.SamplerConfig(**w["sampler"])

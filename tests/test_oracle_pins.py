@@ -574,29 +574,51 @@ def test_refined_depths_match_exponential_quantiles():
     S = np.exp(-np.arange(nb + 1) * dz / mu)
     ts = np.array([np.concatenate([S[:-1] - S[1:], [S[-1]], [1.0]])])
     probs = [2.0 ** -k for k in range(1, 9)]
-    d = oracle.refine_depths(ts, nb, dz, probs, np.zeros((1, 8)), 1.0)
+    d = oracle.refine_depths(ts, nb, dz, probs, np.zeros((1, 8)), 1.0, min_weight=0.0)
     assert np.allclose(d[0], [-mu * math.log(p) for p in probs], atol=dz * dz / (8 * mu) + 1e-9)
 
 
 def test_refined_depths_keep_unresolved_targets_and_spacing():
-    """A target the histogram does not resolve keeps its old depth, an empty table keeps its
-    depths, and the depths are raised to the previous one plus min_gap."""
+    """A target the histogram does not resolve keeps its old depth shifted by the move of the
+    last placed one, an empty table keeps its depths, and the depths are raised to the
+    previous one plus min_gap."""
     nb = 10
     ts = np.zeros((2, nb + 2))
     ts[0, :nb] = 1.0            # 10 units stopped uniformly in [0, 10) A
     ts[0, nb + 1] = 10.0        # everything booked for table 0; table 1 has no data
     old = np.array([[1.0, 2.0, 50.0], [7.0, 8.0, 9.0]])
-    d = oracle.refine_depths(ts, nb, 1.0, [0.5, 0.25, 1e-4], old, 0.0)
+    d = oracle.refine_depths(ts, nb, 1.0, [0.5, 0.25, 1e-4], old, 0.0, min_weight=0.0)
     # S(z) = (10 - z) / 10: 0.5 at 5 A, 0.25 at 7.5 A, 1e-4 at 9.999 A
     assert np.allclose(d[0], [5.0, 7.5, 9.999], rtol=0, atol=1e-12)
     assert np.array_equal(d[1], old[1])
     ts[0, nb] = 5.0             # 5 more units stopped beyond the histogram
     ts[0, nb + 1] = 15.0
-    d = oracle.refine_depths(ts, nb, 1.0, [0.5, 0.25, 1e-4], old, 3.0)
-    # S(z) = (15 - z) / 15 on [0, 10]: 0.5 at 7.5 A; S never falls below 1/3, so the deeper
-    # targets keep 2.0 and 50.0, raised by the 3 A spacing where needed
-    assert np.allclose(d[0], [7.5, 10.5, 50.0], rtol=0, atol=1e-12)
+    d = oracle.refine_depths(ts, nb, 1.0, [0.5, 0.25, 1e-4], old, 3.0, min_weight=0.0)
+    # S(z) = (15 - z) / 15 on [0, 10]: 0.5 at 7.5 A (moved by 6.5 A); S never falls below 1/3,
+    # so the deeper targets keep 2.0 and 50.0 shifted by 6.5 A, raised by the 3 A spacing
+    assert np.allclose(d[0], [7.5, 10.5, 56.5], rtol=0, atol=1e-12)
     assert np.array_equal(d[1], [7.0, 10.0, 13.0])
+
+
+def test_refined_depths_hold_targets_the_statistics_are_too_thin_for():
+    """A target is placed only where target x booked weight reaches min_weight (less than that
+    much weight expected beyond the depth: the depth moves with the last placed one); scaling
+    the statistics up resolves the deeper targets at the same places, since S does not change."""
+    nb = 10
+    ts = np.zeros((1, nb + 2))
+    ts[0, :nb] = 1.0            # 10 units stopped uniformly in [0, 10) A
+    ts[0, nb + 1] = 10.0
+    old = np.array([[1.0, 2.0, 30.0, 40.0]])
+    probs = [0.5, 0.25, 0.05, 1e-4]
+    # S(z) = (10 - z) / 10: 0.5 at 5 A, 0.25 at 7.5 A, 0.05 at 9.5 A, 1e-4 at 9.999 A
+    d = oracle.refine_depths(ts, nb, 1.0, probs, old, 0.0)           # min_weight 1: two placed
+    assert np.allclose(d[0], [5.0, 7.5, 35.5, 45.5], rtol=0, atol=1e-12)
+    d = oracle.refine_depths(ts, nb, 1.0, probs, old, 0.0, min_weight=2.6)   # one placed
+    assert np.allclose(d[0], [5.0, 6.0, 34.0, 44.0], rtol=0, atol=1e-12)
+    d = oracle.refine_depths(ts * 100.0, nb, 1.0, probs, old, 0.0)   # 1,000 units booked
+    assert np.allclose(d[0], [5.0, 7.5, 9.5, 19.5], rtol=0, atol=1e-12)
+    d = oracle.refine_depths(ts * 1e4, nb, 1.0, probs, old, 0.0)     # 1e5 units
+    assert np.allclose(d[0], [5.0, 7.5, 9.5, 9.999], rtol=0, atol=1e-12)
 
 
 def test_family_moment_errors_reduce_to_textbook_forms():
@@ -666,3 +688,18 @@ def test_cutoff_keeps_exactly_the_atoms_within_range(rc):
         assert 10 < n_in < int(ex.sum())
         assert np.allclose(st["F"], F, rtol=1e-12, atol=1e-12 * np.abs(full["F"]).max())
         assert abs(st["rho"] / rho - 1.0) < 1e-12
+
+
+def test_track_log_holds_every_finished_track():
+    """A shallow depth table makes the families split far more often than the log's first size
+    guess (1 + n_clones x n_thresh tracks per primary): the log still holds every finished
+    track once, and each family's weights sum to 1."""
+    n = 16
+    prim = oracle.sample_primaries(oracle.SamplerCfg(choice=(0,), E_min=1000.0, E_max=1000.0), 7, n)
+    cfg = oracle.Config(species=("B",), thresholds=[[10.0, 20.0, 30.0, 40.0, 50.0, 60.0]])
+    r = oracle.run(cfg, prim, nthreads=4, log=True)
+    lg = r["log"]
+    assert r["stats"]["finished"] > n * 13
+    assert len(lg) == r["stats"]["finished"]
+    per_family = np.bincount(lg["lineage"], weights=lg["w"], minlength=n)
+    assert np.array_equal(per_family, np.ones(n))
