@@ -940,9 +940,10 @@ __device__ __forceinline__ long long epoch_first(long long n, int E, int e)
 // sum of the row, is what the row was made of), then lane sl re-places tables sl, sl + L, ...
 // from the snapshot starting from version 0 (the caller's depths; a version depends on no other
 // version, so nothing waits while it is computed), and publishes the version.  The snapshot
-// rows are zero on entry; their last entry receives the total.  Kept out of line: a cold path
-// whose registers stay out of the track kernel's allocation.
-__device__ __noinline__ void compute_version(const double* tstat, double* snap_all, double* thr, const double* probs,
+// rows are zero on entry; their last entry receives the total.  Inlined: as a call, the
+// registers the call clobbers changed the allocation of the whole kernel and put spill stores
+// into the step loop's pair pass.
+__device__ __forceinline__ void compute_version(const double* tstat, double* snap_all, double* thr, const double* probs,
                                              double min_gap, double min_weight, double bin_width, int nb, int nt,
                                              int nk, int e, int sl, int L, int* ready)
 {
@@ -985,13 +986,12 @@ __device__ __forceinline__ void book_finished(const KernelArgs& A, int status, d
         // the last entry; the row's sum is all weight booked for the table (the table field of
         // a track also carries its table version: version * n_tables + table)
         double* ts = A.tstat + static_cast<size_t>(table % A.n_tables) * (A.n_bins + 2);
+        int entry = A.n_bins + 1;
         if (status == REEDMD_STOPPED && zstop >= 0.0) {
             const double fb = floor(zstop / A.bin_width);
-            if (!(fb < static_cast<double>(A.n_bins))) add_f64(&ts[A.n_bins], w);
-            else add_f64(&ts[static_cast<int>(fb)], w);
-        } else {
-            add_f64(&ts[A.n_bins + 1], w);
+            entry = (fb < static_cast<double>(A.n_bins)) ? static_cast<int>(fb) : A.n_bins;
         }
+        add_f64(&ts[entry], w);
     }
     add_i64(&S->finished, 1);
     if (status == REEDMD_STOPPED) {
