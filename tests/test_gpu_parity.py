@@ -427,6 +427,35 @@ def test_in_launch_depths_follow_the_oracle_rule_and_statistics(R, ctx):
                       in_launch=True)
 
 
+def test_in_launch_refinement_edge_cases(R, ctx):
+    """One epoch in one launch is the plain persistent run (histogram and totals bitwise, the
+    caller's table reported); more epochs than primaries run one primary per epoch (exact
+    ledger, a table version per epoch); a snapshot tensor of the wrong shape is rejected."""
+    w = WORKLOADS["c0_b1kev"]
+    first = [10.0, 20.0, 30.0, 40.0]
+    probs = [0.5, 0.25, 0.125, 0.0625]
+    cfg = rcfg(R, n_bins=w["n_bins"], thresholds=[first], form=R.FORM_PERSISTENT, lanes_per_track=32)
+    batch = R.sample_primaries(ctx, R.SamplerConfig(**w["sampler"]), 0, 512)
+    h1, s1, d1 = R.run_refined(ctx, w["species"], batch, cfg, 1, probs, 1.0, in_launch=True)
+    h0, s0, _ = R.run(ctx, w["species"], batch, cfg)
+    torch.cuda.synchronize()
+    assert torch.equal(h1, h0)
+    a, b = R.parse_stats(s1), R.parse_stats(s0)
+    for k in ("finished", "clones", "track_steps", "pair_evals", "n_stopped", "w_stopped"):
+        assert a[k] == b[k], k
+    assert np.array_equal(d1.cpu().numpy(), [[first]])
+    small = R.sample_primaries(ctx, R.SamplerConfig(**w["sampler"]), 0, 8)
+    h, st, d = R.run_refined(ctx, w["species"], small, cfg, 64, probs, 1.0, in_launch=True)
+    torch.cuda.synchronize()
+    st = R.parse_stats(st)
+    assert d.shape == (8, 1, 4) and st["primaries"] == 8
+    assert float(h.sum()) + st["w_underflow"] + st["w_overflow"] + st["w_backscattered"] + \
+        st["w_quarantined"] == 8.0
+    with pytest.raises(ValueError, match="snapshots"):
+        R.run_refined(ctx, w["species"], small, cfg, 2, probs, 1.0, in_launch=True,
+                      snapshots=torch.zeros((2, 1, 7), dtype=torch.float64, device="cuda"))
+
+
 def test_in_launch_depths_on_the_mixed_workload_six_tables(R, ctx):
     """In-launch refinement with several tables (16,384 mixed B/P/As primaries at 1-100 keV,
     the six (species, energy decade) tables of 12 depths as the first versions, targets
