@@ -329,6 +329,46 @@ __device__ __forceinline__ void zbl_pair(const PC& c, double dx, double dy, doub
     else ew = exp2_neg_pair(r, c.lam2);
 }
 
+// ln x for finite normal x > 0, written from the mathematics: x = m 2^k with m in
+// [sqrt(1/2), sqrt(2)); ln m = 2 atanh(s), s = (m - 1) / (m + 1) (m - 1 exact), |s| <= 0.1716,
+// from the odd series 2 s (1 + s^2/3 + s^4/5 + ... + s^22/23) (the first term left out is below
+// 1e-19 of the sum); k ln 2 with ln 2 split so that k times its leading part is exact.
+__device__ __forceinline__ double log_pos(double x)
+{
+    constexpr double kLn2Hi = 6.93147180369123816490e-01;   // ln 2 to 32 bits
+    constexpr double kLn2Lo = 1.90821492927058770002e-10;   // ln 2 - kLn2Hi
+    double m = __builtin_amdgcn_frexp_mant(x);               // [1/2, 1)
+    int k = __builtin_amdgcn_frexp_exp(x);
+    if (m < 0.70710678118654752440) {
+        m += m;
+        --k;
+    }
+    const double s = (m - 1.0) / (m + 1.0);
+    const double z = s * s;
+    double q = 1.0 / 23.0;
+    q = fma(q, z, 1.0 / 21.0);
+    q = fma(q, z, 1.0 / 19.0);
+    q = fma(q, z, 1.0 / 17.0);
+    q = fma(q, z, 1.0 / 15.0);
+    q = fma(q, z, 1.0 / 13.0);
+    q = fma(q, z, 1.0 / 11.0);
+    q = fma(q, z, 1.0 / 9.0);
+    q = fma(q, z, 1.0 / 7.0);
+    q = fma(q, z, 1.0 / 5.0);
+    q = fma(q, z, 1.0 / 3.0);
+    q = fma(q, z, 1.0);
+    const double kd = static_cast<double>(k);
+    return fma(kd, kLn2Hi, fma(kd, kLn2Lo, 2.0 * s * q));
+}
+
+// ln(1 + x) for finite x >= 0 with its relative accuracy kept for small x: with u = 1 + x
+// rounded, ln u scaled by x / (u - 1), the ratio of the exact to the rounded argument.
+__device__ __forceinline__ double log1p_pos(double x)
+{
+    const double u = 1.0 + x;
+    return (u == 1.0) ? x : log_pos(u) * (x / (u - 1.0));
+}
+
 // Brandt-Kitagawa friction of the ion at speed squared v2 (sqrt(eV/amu))^2:
 // pref zeta^2 with pref = k Z1^2 gamma_p (the slow-proton friction of the
 // electron gas), zeta the effective-charge fraction in atomic units,
@@ -350,13 +390,16 @@ __device__ __noinline__ double bk_friction(double v2, double pref, double z13, d
         vr = 0.75 * vF * (1.0 + (2.0 / 3.0) * s - s * s / 15.0);
     }
     const double y = vr / (z13 * z13);
-    const double y3 = pow(y, 0.3);
-    double q = 1.0 - exp(0.803 * y3 - 1.3167 * y3 * y3 - 0.38157 * y - 0.008983 * y * y);
+    // the powers as exponentials of logarithms (exp_neg takes arguments of either sign here:
+    // its reduction holds for |argument| below 700)
+    const double y3 = exp_neg(-0.3 * log_pos(y));                                 // y^0.3
+    double q = 1.0 - exp_neg(-(0.803 * y3 - 1.3167 * y3 * y3 - 0.38157 * y - 0.008983 * y * y));
     q = fmin(fmax(q, 0.0), 1.0);
     const double nb = 1.0 - q;
-    const double lam = 0.48 * cbrt(nb * nb) / (z13 * (1.0 - nb / 7.0));
+    const double nb23 = nb > 0.0 ? exp_neg(-(2.0 / 3.0) * log_pos(nb)) : 0.0;      // nb^(2/3)
+    const double lam = 0.48 * nb23 / (z13 * (1.0 - nb / 7.0));
     const double a = 2.0 * lam * vF;
-    const double zeta = q + nb / (2.0 * vF2) * log1p(a * a);
+    const double zeta = q + nb / (2.0 * vF2) * log1p_pos(a * a);
     return pref * zeta * zeta;
 }
 
