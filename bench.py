@@ -727,7 +727,7 @@ DESCR = {
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+        print(json.dumps({"error": "the benchmark runs on one GPU only; --gpus must be 1 "
                                    "(multi-GPU sharding is a design note, not built)"}))
         sys.exit(2)
     import numpy as np
