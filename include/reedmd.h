@@ -418,6 +418,16 @@ reedmd_status reedmd_grad(reedmd_ctx* ctx, const reedmd_species* species, const 
 reedmd_status reedmd_eval_exp_neg(const double* d_y, double* d_out, int64_t n, hipStream_t stream);
 reedmd_status reedmd_eval_exp_neg_pair(const double* d_y, double* d_out, int64_t n, hipStream_t stream);
 
+/* Evaluates the library's natural logarithm (used by the Brandt-Kitagawa
+ * stopping, Sec. 2 "Third": its powers y^0.3 and (1-q)^(2/3) are taken as
+ * exponentials of logarithms, and ln(1 + x)) into out (device, n doubles):
+ * one_plus = 0: ln x for normal finite x > 0 (x = m 2^k, ln m = 2 atanh((m-1)/(m+1))
+ * from its series); one_plus = 1: ln(1 + x) for finite x >= 0, with its
+ * relative accuracy kept for small x.  Other inputs give unspecified values.
+ * For accuracy tests.  Enqueued on stream; EINVAL for n < 0, NULL arrays or
+ * one_plus not 0 or 1. */
+reedmd_status reedmd_eval_log(const double* d_x, double* d_out, int64_t n, int32_t one_plus, hipStream_t stream);
+
 /* Chooses the launch shape for runs like this one.  Each candidate (lanes per
  * track 64, 32, 16; for the persistent form also one workgroup per CU fewer
  * than the occupancy allows) runs on the first `pilot` primaries of the batch

@@ -455,6 +455,18 @@ class ReedMDRange(torch.autograd.Function):
         return g * d[0], g * d[1], None, None, None, None
 
 
+def eval_log(x: torch.Tensor, stream=None, one_plus=False):
+    """The library's ln x (or ln(1 + x) with one_plus=True) on a float64 device tensor."""
+    L = _abi.load()
+    with _on(stream):
+        x = x.contiguous()
+        out = torch.empty_like(x)
+    rc = L.reedmd_eval_log(_ptr(x), _ptr(out), int(x.numel()), 1 if one_plus else 0, _stream(stream))
+    if rc != 0:
+        raise ReedmdError(f"reedmd_eval_log failed ({rc})")
+    return out
+
+
 def eval_exp_neg(y: torch.Tensor, stream=None, pair=False):
     """The library's exp(-y) on a float64 device tensor: the friction factors' exponential, or
     with pair=True the one of the ion-atom pair terms."""

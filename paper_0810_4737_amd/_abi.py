@@ -92,7 +92,7 @@ STATS_WORDS = len(STATS_INT_A) + len(STATS_DBL) + len(STATS_INT_B)
 # every entry point declared in include/reedmd.h
 EXPORTS = ("reedmd_version", "reedmd_create", "reedmd_destroy", "reedmd_last_error",
            "reedmd_sample_primaries", "reedmd_run", "reedmd_track_init", "reedmd_debug_step",
-           "reedmd_autotune", "reedmd_grad", "reedmd_eval_exp_neg", "reedmd_eval_exp_neg_pair", "reedmd_launch_shape",
+           "reedmd_autotune", "reedmd_grad", "reedmd_eval_exp_neg", "reedmd_eval_exp_neg_pair", "reedmd_eval_log", "reedmd_launch_shape",
            "reedmd_run_refined", "reedmd_cached_graphs", "reedmd_run_noalloc", "reedmd_autotune_domain")
 
 _lib = None
@@ -140,6 +140,8 @@ def load():
     L.reedmd_eval_exp_neg.restype = C.c_int
     L.reedmd_eval_exp_neg_pair.argtypes = [V, V, C.c_int64, V]
     L.reedmd_eval_exp_neg_pair.restype = C.c_int
+    L.reedmd_eval_log.argtypes = [V, V, C.c_int64, C.c_int32, V]
+    L.reedmd_eval_log.restype = C.c_int
     L.reedmd_launch_shape.argtypes = [V, P(Batch), P(RunParams), P(C.c_int64)]
     L.reedmd_launch_shape.restype = C.c_int
     L.reedmd_run_refined.argtypes = [V, P(Species), P(Batch), P(RunParams), P(Refine), V, V, V, V]

@@ -1032,6 +1032,12 @@ __global__ void exp_neg_kernel(const double* y, double* out, long long n, int pa
     if (i < n) out[i] = pair ? exp_neg_pair(y[i]) : exp_neg(y[i]);
 }
 
+__global__ void log_kernel(const double* x, double* out, long long n, int one_plus)
+{
+    const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = one_plus ? log1p_pos(x[i]) : log_pos(x[i]);
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -1389,6 +1395,18 @@ reedmd_status reedmd_eval_exp_neg(const double* d_y, double* d_out, int64_t n, h
 reedmd_status reedmd_eval_exp_neg_pair(const double* d_y, double* d_out, int64_t n, hipStream_t stream)
 {
     return eval_exp(d_y, d_out, n, 1, stream);
+}
+
+reedmd_status reedmd_eval_log(const double* d_x, double* d_out, int64_t n, int32_t one_plus, hipStream_t stream)
+{
+    if (n < 0 || (n > 0 && (!d_x || !d_out)) || (one_plus != 0 && one_plus != 1))
+        return fail(nullptr, REEDMD_EINVAL, "bad arguments");
+    if (n == 0) return REEDMD_OK;
+    hipLaunchKernelGGL(log_kernel, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, stream, d_x, d_out,
+                       static_cast<long long>(n), static_cast<int>(one_plus));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(nullptr, REEDMD_EHIP, hipGetErrorString(e));
+    return REEDMD_OK;
 }
 
 reedmd_status reedmd_autotune(reedmd_ctx* ctx, const reedmd_species* species, const reedmd_batch* batch,

@@ -123,6 +123,28 @@ def test_library_exponential_is_accurate(R, pair):
     assert np.all(np.abs(got[sub] - ref[sub]) <= bound * ref[sub] + 4 * 5e-324)
 
 
+def test_library_logarithm_is_accurate(R):
+    """The logarithm of the Brandt-Kitagawa stopping (atanh series after the binary exponent
+    is split off) against numpy over the normal range and around 1, and ln(1 + x) down to
+    x = 1e-300: within 4 ulp of the value (the series' truncation is below 1e-19, the rest is
+    the rounding of the division, the series and the final sums)."""
+    x = np.concatenate([np.geomspace(2.3e-308, 1.7e308, 200001), 1.0 + np.linspace(-0.3, 0.3, 100001),
+                        np.linspace(0.5, 4.0, 100001)])
+    got = R.eval_log(torch.as_tensor(x, device="cuda")).cpu().numpy()
+    ref = np.log(x)
+    scale = np.maximum(np.abs(ref), 1e-300)
+    rel = np.abs(got - ref) / scale
+    _say(f"log: worst relative error {rel.max():.3g}")
+    assert rel.max() <= 4 * 2.0 ** -52
+    assert got[x == 1.0].max() == 0.0 and np.count_nonzero(x == 1.0) == 1
+    y = np.concatenate([np.geomspace(1e-300, 1e300, 200001), np.linspace(0.0, 10.0, 100001)])
+    got1 = R.eval_log(torch.as_tensor(y, device="cuda"), one_plus=True).cpu().numpy()
+    ref1 = np.log1p(y)
+    rel1 = np.abs(got1 - ref1) / np.maximum(np.abs(ref1), 1e-300)
+    _say(f"log1p: worst relative error {rel1.max():.3g}")
+    assert rel1[y > 0].max() <= 4 * 2.0 ** -52 and got1[y == 0.0].max() == 0.0
+
+
 # ----------------------------------------------------------------------------- sampler
 def test_sampler_matches_oracle(R, ctx):
     sc = dict(choice=(0, 1, 2), E_min=1000.0, E_max=100000.0, n_energy_tables=2, dir_mode=2,
