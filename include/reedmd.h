@@ -335,9 +335,10 @@ typedef struct {
  * claim positions [ceil(n e / E), ceil(n (e+1) / E)) of the primaries (claimed
  * in the launch's longest-expected-first order), and the segment that claims
  * the first position of epoch e > 0 re-places every table from the tracks
- * booked by then (the same rule, starting from the depths of epoch 0, which is
- * what a target not yet resolved keeps) while the other segments go on
- * running; the epoch's other primaries start once its tables are published.
+ * booked by then (the same rule applied to the depths of epoch 0, so a target
+ * not placed keeps its epoch-0 depth shifted by the last placed one's move)
+ * while the other segments go on running; the epoch's other primaries start
+ * once its tables are published.
  * No launch boundary drains the GPU between epochs; which tracks a table's
  * statistics hold depends on timing, so the depths are not reproducible run
  * to run (each family still keeps one table and the estimator stays unbiased).
